@@ -1,0 +1,257 @@
+"""ctypes wrapper of the FP64 CPU oracle (``rpba_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg; the product path never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["rpba_oracle.cpp", "rpba_oracle_solvers.cpp"]
+LIB = os.path.join(HERE, "liboracle.so")
+
+ST_OK, ST_NOT_CONVERGED, ST_BEHIND, ST_ILL, ST_ELIMINATED = 0, 1, 2, 3, 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, OpenMP)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        _lib = ctypes.CDLL(LIB)
+        _declare(_lib)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_up = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _declare(L):
+    L.orc_create.restype = ctypes.c_void_p
+    L.orc_create.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 4 + [_dp] * 4 + [_ip, _ip, _dp, _ip,
+                                                                                     ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    L.orc_destroy.argtypes = [ctypes.c_void_p]
+    L.orc_intersect.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_robust_reweight.restype = ctypes.c_int
+    L.orc_robust_reweight.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
+    L.orc_lm_step.restype = ctypes.c_int
+    L.orc_lm_step.argtypes = [ctypes.c_void_p, _up, _dp]
+    L.orc_consensus.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_get_cameras.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.orc_set_cameras.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.orc_get_points.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_get_intersection.argtypes = [ctypes.c_void_p, _dp, _dp, _ip]
+    L.orc_num_copies.restype = ctypes.c_int
+    L.orc_num_copies.argtypes = [ctypes.c_void_p]
+    L.orc_get_copies.argtypes = [ctypes.c_void_p, _ip, _ip, _dp, _dp]
+    L.orc_get_weights.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_get_residuals.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_block_rcs.restype = ctypes.c_int
+    L.orc_block_rcs.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+    L.orc_block_step.restype = ctypes.c_int
+    L.orc_block_step.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+    L.orc_linearise.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    L.orc_rodrigues.argtypes = [_dp, _dp]
+    L.orc_cholesky.restype = ctypes.c_int
+    L.orc_cholesky.argtypes = [ctypes.c_int, _dp]
+    L.orc_num_threads.restype = ctypes.c_int
+    _declare_solvers(L)
+
+
+def _declare_solvers(L):
+    if not hasattr(L, "orc_pcg"):
+        return
+    L.orc_pcg.restype = ctypes.c_int
+    L.orc_pcg.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp]
+    L.orc_mlp_features.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
+    L.orc_mlp_blocks.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.orc_mlp_loss_grad.restype = ctypes.c_double
+    L.orc_mlp_loss_grad.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_mlp_num_params.restype = ctypes.c_int
+    L.orc_mlp_num_params.argtypes = []
+
+
+def _p(a, t=_dp):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class OracleProblem:
+    """Stateful oracle run on one scene (same call sequence as the library)."""
+
+    def __init__(self, scene, lam=1e-4, int_tol=1e-12, int_maxit=20, obs_info=None):
+        L = lib()
+        self._keep = dict(R=f64(scene.cam_R), C=f64(scene.cam_C), X=f64(scene.pts), xy=f64(scene.obs_xy),
+                          cam=i32(scene.obs_cam), pt=i32(scene.obs_pt), blk=i32(scene.cam_block),
+                          info=None if obs_info is None else f64(obs_info))
+        k = self._keep
+        self.M, self.N, self.K, self.L = scene.M, scene.N, scene.K, scene.L
+        self.h = L.orc_create(self.M, self.N, self.K, self.L, scene.f, scene.cx, scene.cy, scene.sigma_px,
+                              _p(k["R"]), _p(k["C"]), _p(k["X"]), _p(k["xy"]), _p(k["cam"], _ip), _p(k["pt"], _ip),
+                              _p(k["info"]), _p(k["blk"], _ip), lam, int_tol, int_maxit)
+        self._lib = L
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self._lib.orc_destroy(self.h)
+            self.h = None
+
+    def intersect(self):
+        s = np.zeros(4)
+        self._lib.orc_intersect(self.h, _p(s))
+        return s
+
+    def robust_reweight(self, t_v=4.0, down_weight=1e-4, eliminate=False):
+        sc = np.zeros(self.M)
+        n = self._lib.orc_robust_reweight(self.h, t_v, down_weight, int(eliminate), _p(sc))
+        return n, sc
+
+    def lm_step(self, active=None):
+        bs = np.zeros((self.L, 4))
+        act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+        fails = self._lib.orc_lm_step(self.h, _p(act, _up), _p(bs))
+        return bs, fails
+
+    def consensus(self):
+        s = np.zeros(2)
+        self._lib.orc_consensus(self.h, _p(s))
+        return s
+
+    def cameras(self):
+        R = np.zeros((self.M, 9))
+        C = np.zeros((3, self.M))
+        self._lib.orc_get_cameras(self.h, _p(R), _p(C))
+        return R, C
+
+    def set_cameras(self, R, C):
+        R, C = f64(R), f64(C)
+        self._lib.orc_set_cameras(self.h, _p(R), _p(C))
+
+    def points(self):
+        X = np.zeros((3, self.N))
+        self._lib.orc_get_points(self.h, _p(X))
+        return X
+
+    def intersection(self):
+        X = np.zeros((3, self.N))
+        cov = np.zeros((6, self.N))
+        st = np.zeros(self.N, dtype=np.int32)
+        self._lib.orc_get_intersection(self.h, _p(X), _p(cov), _p(st, _ip))
+        return X, cov, st
+
+    def copies(self):
+        n = self._lib.orc_num_copies(self.h)
+        blk = np.zeros(n, dtype=np.int32)
+        pt = np.zeros(n, dtype=np.int32)
+        X = np.zeros((n, 3))
+        om = np.zeros((n, 6))
+        self._lib.orc_get_copies(self.h, _p(blk, _ip), _p(pt, _ip), _p(X), _p(om))
+        return blk, pt, X, om
+
+    def weights(self):
+        w = np.zeros(self.K)
+        self._lib.orc_get_weights(self.h, _p(w))
+        return w
+
+    def residuals(self):
+        r = np.zeros((2, self.K))
+        self._lib.orc_get_residuals(self.h, _p(r))
+        return r
+
+    def block_rcs(self, l, n6):
+        S = np.zeros((n6, n6))
+        e = np.zeros(n6)
+        n = self._lib.orc_block_rcs(self.h, l, _p(S), _p(e))
+        if n < 0:
+            raise RuntimeError("singular point block")
+        return S, e
+
+    def block_step(self, l, n6, n_copies):
+        dC = np.zeros(n6)
+        dX = np.zeros(3 * n_copies)
+        nc = self._lib.orc_block_step(self.h, l, _p(dC), _p(dX))
+        if nc < 0:
+            raise RuntimeError(f"block step failed {nc}")
+        return dC, dX[: 3 * nc].reshape(-1, 3)
+
+
+def linearise(R9, C3, X3, f=1000.0, cx=500.0, cy=500.0):
+    R9, C3, X3 = f64(R9), f64(C3), f64(X3)
+    g = np.zeros(2)
+    A = np.zeros((2, 6))
+    B = np.zeros((2, 3))
+    lib().orc_linearise(_p(R9), _p(C3), _p(X3), f, cx, cy, _p(g), _p(A), _p(B))
+    return g, A, B
+
+
+def rodrigues(w):
+    w = f64(w)
+    R = np.zeros(9)
+    lib().orc_rodrigues(_p(w), _p(R))
+    return R.reshape(3, 3)
+
+
+def cholesky(A):
+    A = f64(A).copy()
+    n = A.shape[0]
+    rc = lib().orc_cholesky(n, _p(A))
+    if rc:
+        raise np.linalg.LinAlgError("not SPD")
+    return np.tril(A)
+
+
+def run_schedule(scene, T=6, I=4, robust=False, t_r=2, t_v=4.0, down_weight=1e-4, callback=None, **kw):
+    """Fixed schedule: T outer iterations of (intersect [, robust, re-intersect],
+    I LM steps, consensus), then a final intersection.  Returns the oracle
+    problem and a list of per-iteration records."""
+    op = OracleProblem(scene, **kw)
+    hist = []
+    for t in range(T):
+        st = op.intersect()
+        if robust and t >= t_r:
+            op.robust_reweight(t_v, down_weight, eliminate=False)
+            st = op.intersect()
+        rec = dict(t=t, int_stats=st, steps=[])
+        for s in range(I):
+            bs, fails = op.lm_step()
+            rec["steps"].append((bs, fails))
+        rec["consensus"] = op.consensus()
+        hist.append(rec)
+        if callback:
+            callback(op, rec)
+    if robust:
+        op.intersect()
+        op.robust_reweight(t_v, down_weight, eliminate=True)
+    final = op.intersect()
+    hist.append(dict(t=T, int_stats=final))
+    return op, hist
