@@ -1,0 +1,191 @@
+/*
+ * rpba.h -- C ABI of librpba, the MI355X (gfx950) implementation of the
+ * data-parallel hot path of covariance-weighted consensus bundle adjustment
+ * (H. Mayer, "RPBA: Robust Parallel Bundle Adjustment Based on Covariance
+ * Information", arXiv 1910.08138).
+ *
+ * Problem statement (paper Sec. 2): cameras P_i (here rotation R_i, world to
+ * camera, and projection centre C_i), points X_j, observations x_k of point j
+ * in camera i with 2x2 covariance C_xk (weight W_k = C_xk^-1), residual
+ * v_k = g_k(P_i, X_j) - x_k with the calibrated pinhole
+ *     p = R_i (X_j - C_i),  g = (f p1/p3 + cx, f p2/p3 + cy).
+ * The cameras are split into L sub-blocks, each camera in exactly one
+ * (Sec. 4, "every camera is just contained in one sub-block"); points seen by
+ * cameras of two or more sub-blocks are tie points (TPs).
+ *
+ * One outer iteration of the method (Sec. 5) is
+ *     rpba_intersect          eq:bars + refined re-weighting (Sec. 5.1)
+ *     [rpba_robust_reweight + rpba_intersect]   parallel robust variant (Sec. 5.3)
+ *     rpba_subblock_lm_step   eq:bact, one LM iteration per call (Sec. 5.4)
+ *     rpba_consensus          exchange of cameras and TPs (Sec. 5)
+ *
+ * Memory: every pointer argument is a DEVICE pointer unless it is marked
+ * HOST.  All device memory (including the workspace) is allocated and owned
+ * by the caller; the library never allocates or frees device memory.  The
+ * handle is host memory owned by the library, released by rpba_destroy.  All
+ * buffers named in the descriptor must outlive the handle.
+ *
+ * Asynchrony: every call except rpba_workspace_size / rpba_create only
+ * enqueues kernels on the stream given at creation and returns.  Results
+ * (stats, covariances, statuses) are in device memory; read them after
+ * synchronising the stream.  rpba_create synchronises once.
+ *
+ * Errors: calls return a status code; no exception crosses the ABI.
+ * rpba_last_error() returns a thread-local description of the last failure.
+ * One host thread at a time per handle.
+ */
+#ifndef RPBA_H
+#define RPBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPBA_OK = 0,
+  RPBA_ERR_ARG = 1,        /* invalid argument or problem (message says which) */
+  RPBA_ERR_HIP = 2,        /* a HIP runtime call failed */
+  RPBA_ERR_WORKSPACE = 3,  /* workspace too small or misaligned (256 B) */
+  RPBA_ERR_NOT_SPD = 4,    /* a reduced camera system was not positive definite */
+  RPBA_ERR_STATE = 5       /* call not valid in the handle's state */
+} rpba_status;
+
+/* precision policy */
+enum { RPBA_FP64 = 0, RPBA_MIXED = 1 };
+/* solver of the reduced camera system */
+enum { RPBA_SOLVER_CHOL = 0, RPBA_SOLVER_PCG_BJ = 1, RPBA_SOLVER_PCG_LEARNED = 2, RPBA_SOLVER_AUTO = 3 };
+/* per-point status written by rpba_intersect */
+enum {
+  RPBA_PT_OK = 0,
+  RPBA_PT_NOT_CONVERGED = 1, /* Gauss-Newton did not reach int_tol in int_maxit iterations */
+  RPBA_PT_BEHIND = 2,        /* some p3 <= 0 */
+  RPBA_PT_ILL = 3,           /* 3x3 Cholesky pivot <= 1e-12 * largest diagonal */
+  RPBA_PT_ELIMINATED = 4     /* removed by the robust step */
+};
+
+typedef struct rpba_problem rpba_problem;
+
+typedef struct {
+  int32_t M, N, K, L;        /* cameras, points, observations, sub-blocks */
+  double f, cx, cy;          /* shared pinhole intrinsics [px] */
+  double sigma_px;           /* a-priori std. dev. of an image coordinate; W = I / sigma^2 when obs_info is NULL */
+  double *cam_R;             /* [M][9] row-major world->camera rotation; read at create, written by rpba_consensus */
+  double *cam_C;             /* [3][M] projection centres (SoA); same ownership as cam_R */
+  double *pts;               /* [3][N] points (SoA); read at create (start values), written by rpba_intersect / rpba_consensus */
+  const double *obs_xy;      /* [2][K] measured pixel coordinates (SoA) */
+  const double *obs_info;    /* [3][K] (w11, w12, w22) of W_k = C_xk^-1, or NULL */
+  const int32_t *obs_cam;    /* HOST [K] camera of each observation, in [0, M) */
+  const int32_t *obs_pt;     /* HOST [K] point of each observation, in [0, N) */
+  const int32_t *cam_block;  /* HOST [M] sub-block of each camera, in [0, L) */
+} rpba_problem_desc;
+
+typedef struct {
+  int32_t precision;     /* RPBA_FP64 or RPBA_MIXED */
+  int32_t solver;        /* RPBA_SOLVER_* */
+  double lambda;         /* LM damping, N + lambda diag(N) (Sec. 5.4): 1e-4 */
+  double int_tol;        /* intersection stop: |dX| <= int_tol (1 + |X|): 1e-12 */
+  int32_t int_maxit;     /* intersection iterations: 20 */
+  int32_t pcg_maxit;     /* PCG iterations per refinement sweep: 200 */
+  double pcg_tol;        /* PCG relative residual: 1e-8 */
+  double ir_tol;         /* iterative refinement relative residual (FP64): 1e-10 */
+  int32_t ir_maxit;      /* refinement sweeps: 6 */
+  int32_t pcg_min_cams;  /* RPBA_SOLVER_AUTO: sub-blocks with at least this many cameras use PCG: 150 */
+  double t_v;            /* robust threshold on the normalised residual (Sec. 5.3, parallel variant): 4 */
+  double down_weight;    /* weight multiplier of flagged observations: 1e-4 */
+  int32_t chol_tile;     /* Cholesky tile edge, 32 or 64 (0 = library choice) */
+  int32_t reserved;
+} rpba_options;
+
+/* Fill *opt with the defaults listed above.  HOST pointer. */
+rpba_status rpba_default_options(rpba_options *opt);
+
+/* Bytes of device workspace rpba_create needs for this problem (host-side
+ * planning; reads the HOST topology arrays only).  *bytes is HOST. */
+rpba_status rpba_workspace_size(const rpba_problem_desc *desc, const rpba_options *opt, size_t *bytes);
+
+/* Validate the problem, plan the data layout (Sec. 4: camera-unique split,
+ * TPs derived from it) and pack the observation streams into the workspace.
+ * Checks: indices in range, every point observed at least twice, every
+ * camera observed at least once, every sub-block non-empty, no repeated
+ * (camera, point) pair, finite inputs.  `workspace` is a device buffer of at
+ * least rpba_workspace_size bytes, 256-byte aligned, owned by the caller for
+ * the life of the handle.  `stream` is a hipStream_t (NULL = default).
+ * *out is HOST. */
+rpba_status rpba_create(const rpba_problem_desc *desc, const rpba_options *opt, void *workspace, size_t bytes,
+                        void *stream, rpba_problem **out);
+
+/* Intersection of every valid point with all cameras fixed (eq:bars): undamped
+ * Gauss-Newton on the point, covariance Sigma_j = (sum B^T W B)^-1, and for
+ * each (point, sub-block) copy the refined weight Omega_j^l = H_j - H_j^(l),
+ * the point information from cameras outside l (Sec. 5.1).  The point
+ * position uses all cameras.  Sets every copy X_j^l = Xbar_j.  Points that
+ * fail get a non-zero status and weight zero from then on (Sec. 5.4).
+ *   cov    [6][N] (xx, xy, xz, yy, yz, zz) or NULL
+ *   status [N] RPBA_PT_* or NULL
+ *   stats  [4]: weighted cost sum v^T W v, sigma0 [px] (unit weights,
+ *          redundancy 2K_valid - 6M - 3N_valid, eq:sigma0), RMS [px], N_valid;
+ *          or NULL
+ * Writes Xbar to desc->pts. */
+rpba_status rpba_intersect(rpba_problem *h, double *cov, int32_t *status, double *stats);
+
+/* Parallel robust variant (Sec. 5.3): per camera, sigma0_i = 1.4826 MAD of the
+ * whitened residual components of the last intersection; an observation with
+ * sqrt(v^T W v) / sigma0_i > t_v gets the weight multiplier down_weight,
+ * every other observation 1.  With `eliminate`, points with a flagged
+ * observation get RPBA_PT_ELIMINATED.  stats [2]: flagged observations,
+ * eliminated points (or NULL). */
+rpba_status rpba_robust_reweight(rpba_problem *h, int32_t eliminate, double *stats);
+
+/* One LM iteration of every active sub-block (eq:bact): normal equations of
+ * the sub-block's cameras and point copies with the TPs as stochastic control
+ * points, cost sum v^T W v + (X - Xbar)^T Omega (X - Xbar); damping
+ * N + lambda diag(N); Schur complement onto the cameras (reduced camera system
+ * S, outer products accumulated straight into S); S solved by Cholesky
+ * (FP64 MFMA) or PCG; back-substitution; update R <- Exp([w]x) R, C += dc,
+ * X^l += dX.  Every step is accepted.
+ *   active      [L] uint8 (0 = skip) or NULL for all
+ *   block_stats [L][4]: cost before, cost after, step norm, solver iterations
+ *               (or NULL) */
+rpba_status rpba_subblock_lm_step(rpba_problem *h, const uint8_t *active, double *block_stats);
+
+/* Consensus exchange (Sec. 5): cameras go back to desc->cam_R / cam_C; every
+ * point's start value for the next intersection is the mean of its sub-block
+ * copies (eq:admm8 form), written to desc->pts.
+ *   stats [2]: largest distance of a copy from its point's mean, number of TPs
+ *         (or NULL) */
+rpba_status rpba_consensus(rpba_problem *h, double *stats);
+
+/* Release the handle (host memory only; caller buffers are untouched). */
+rpba_status rpba_destroy(rpba_problem *h);
+
+/* Thread-local message of the last non-OK status. */
+const char *rpba_last_error(void);
+
+/* ---------------------------------------------------------------- inspection
+ * Synchronous helpers for tests and tools; all pointers HOST.
+ * rpba_num_copies: number of (sub-block, point) copies.
+ * rpba_get_copies: copies in library order with sub-block, original point
+ *   index, X^l [n][3] and Omega [n][6]; any pointer may be NULL.
+ * rpba_get_block_rcs: the reduced camera system S (n6 x n6, row-major, lower
+ *   triangle valid) and right-hand side e of sub-block l as assembled by the
+ *   last rpba_subblock_lm_step (before factorisation), n6 = 6 cameras of l
+ *   (cameras in ascending original index).  Only for the Cholesky path; call
+ *   rpba_set_debug(h, 1) before the step.
+ * rpba_block_cameras: number of cameras of sub-block l. */
+int64_t rpba_num_copies(rpba_problem *h);
+rpba_status rpba_get_copies(rpba_problem *h, int32_t *blk, int32_t *pt, double *X, double *omega);
+rpba_status rpba_set_debug(rpba_problem *h, int32_t on);
+rpba_status rpba_get_block_rcs(rpba_problem *h, int32_t l, double *S, double *e);
+int32_t rpba_block_cameras(rpba_problem *h, int32_t l);
+
+/* Self-test of the FP64 matrix-core tile product used by the Cholesky:
+ * C = A B^T for 64 x 64 row-major device tiles, one workgroup on `stream`. */
+rpba_status rpba_selftest_gemm(const double *A, const double *B, double *C, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPBA_H */

@@ -1,0 +1,256 @@
+"""Thin ctypes binding of librpba (include/rpba.h) on torch device tensors.
+
+PyTorch supplies device memory and the stream; every step of the method runs
+in the library's HIP kernels.  The functions keep the C names:
+``rpba_intersect``, ``rpba_subblock_lm_step``, ``rpba_consensus``,
+``rpba_robust_reweight``.  There is no fallback: without the built library or
+a GPU, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librpba.so")
+
+RPBA_FP64, RPBA_MIXED = 0, 1
+RPBA_SOLVER_CHOL, RPBA_SOLVER_PCG_BJ, RPBA_SOLVER_PCG_LEARNED, RPBA_SOLVER_AUTO = 0, 1, 2, 3
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_WORKSPACE", 4: "ERR_NOT_SPD", 5: "ERR_STATE"}
+
+# every symbol include/rpba.h declares
+EXPORTS = [
+    "rpba_default_options", "rpba_workspace_size", "rpba_create", "rpba_intersect", "rpba_robust_reweight",
+    "rpba_subblock_lm_step", "rpba_consensus", "rpba_destroy", "rpba_last_error", "rpba_num_copies",
+    "rpba_get_copies", "rpba_set_debug", "rpba_get_block_rcs", "rpba_block_cameras", "rpba_selftest_gemm",
+]
+
+
+class RpbaError(RuntimeError):
+    pass
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int32), ("N", ctypes.c_int32), ("K", ctypes.c_int32), ("L", ctypes.c_int32),
+        ("f", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("sigma_px", ctypes.c_double),
+        ("cam_R", ctypes.c_void_p), ("cam_C", ctypes.c_void_p), ("pts", ctypes.c_void_p),
+        ("obs_xy", ctypes.c_void_p), ("obs_info", ctypes.c_void_p),
+        ("obs_cam", ctypes.c_void_p), ("obs_pt", ctypes.c_void_p), ("cam_block", ctypes.c_void_p),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("lam", ctypes.c_double),
+        ("int_tol", ctypes.c_double), ("int_maxit", ctypes.c_int32), ("pcg_maxit", ctypes.c_int32),
+        ("pcg_tol", ctypes.c_double), ("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
+        ("pcg_min_cams", ctypes.c_int32), ("t_v", ctypes.c_double), ("down_weight", ctypes.c_double),
+        ("chol_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librpba.so; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RpbaError(f"{path} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    L.rpba_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        getattr(L, name)  # every declared symbol must resolve
+    L.rpba_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.rpba_workspace_size.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]
+    L.rpba_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(Options), vp, ctypes.c_size_t, vp,
+                              ctypes.POINTER(vp)]
+    L.rpba_intersect.argtypes = [vp, dp, dp, dp]
+    L.rpba_robust_reweight.argtypes = [vp, i32, dp]
+    L.rpba_subblock_lm_step.argtypes = [vp, dp, dp]
+    L.rpba_consensus.argtypes = [vp, dp]
+    L.rpba_destroy.argtypes = [vp]
+    L.rpba_num_copies.restype = i64
+    L.rpba_num_copies.argtypes = [vp]
+    L.rpba_get_copies.argtypes = [vp, vp, vp, vp, vp]
+    L.rpba_set_debug.argtypes = [vp, i32]
+    L.rpba_get_block_rcs.argtypes = [vp, i32, vp, vp]
+    L.rpba_block_cameras.restype = i32
+    L.rpba_block_cameras.argtypes = [vp, i32]
+    L.rpba_selftest_gemm.argtypes = [dp, dp, dp, vp]
+    for name in EXPORTS:
+        if name not in ("rpba_last_error", "rpba_num_copies", "rpba_block_cameras"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = _lib.rpba_last_error().decode(errors="replace")
+        raise RpbaError(f"{what}: {STATUS_NAMES.get(rc, rc)}: {msg}")
+
+
+def default_options(**kw) -> Options:
+    L = load_library()
+    o = Options()
+    _check(L.rpba_default_options(ctypes.byref(o)), "rpba_default_options")
+    for k, v in kw.items():
+        setattr(o, "lam" if k == "lam" else k, v)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def selftest_gemm(A, B):
+    """C = A B^T through the library's FP64 matrix-core tile product (64x64)."""
+    import torch
+    L = load_library()
+    C = torch.empty_like(A)
+    _check(L.rpba_selftest_gemm(_ptr(A), _ptr(B), _ptr(C), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           "rpba_selftest_gemm")
+    return C
+
+
+class Problem:
+    """One problem on the GPU: device state tensors, workspace, handle."""
+
+    def __init__(self, scene, device="cuda", obs_info=None, **opts):
+        import torch
+        self.torch = torch
+        L = load_library()
+        self.L_ = L
+        dev = torch.device(device)
+        self.dev = dev
+        f64 = torch.float64
+        self.M, self.N, self.K, self.L = scene.M, scene.N, scene.K, scene.L
+        self.cam_R = torch.as_tensor(np.ascontiguousarray(scene.cam_R), dtype=f64).to(dev)
+        self.cam_C = torch.as_tensor(np.ascontiguousarray(scene.cam_C), dtype=f64).to(dev)
+        self.pts = torch.as_tensor(np.ascontiguousarray(scene.pts), dtype=f64).to(dev)
+        self.obs_xy = torch.as_tensor(np.ascontiguousarray(scene.obs_xy), dtype=f64).to(dev)
+        self.obs_info = None if obs_info is None else torch.as_tensor(np.ascontiguousarray(obs_info), dtype=f64).to(dev)
+        self._obs_cam = np.ascontiguousarray(scene.obs_cam, dtype=np.int32)
+        self._obs_pt = np.ascontiguousarray(scene.obs_pt, dtype=np.int32)
+        self._cam_block = np.ascontiguousarray(scene.cam_block, dtype=np.int32)
+        d = ProblemDesc()
+        d.M, d.N, d.K, d.L = self.M, self.N, self.K, self.L
+        d.f, d.cx, d.cy, d.sigma_px = scene.f, scene.cx, scene.cy, scene.sigma_px
+        d.cam_R, d.cam_C, d.pts = self.cam_R.data_ptr(), self.cam_C.data_ptr(), self.pts.data_ptr()
+        d.obs_xy = self.obs_xy.data_ptr()
+        d.obs_info = None if self.obs_info is None else self.obs_info.data_ptr()
+        d.obs_cam = self._obs_cam.ctypes.data
+        d.obs_pt = self._obs_pt.ctypes.data
+        d.cam_block = self._cam_block.ctypes.data
+        self.desc = d
+        self.opt = default_options(**opts)
+        nbytes = ctypes.c_size_t(0)
+        _check(L.rpba_workspace_size(ctypes.byref(d), ctypes.byref(self.opt), ctypes.byref(nbytes)), "rpba_workspace_size")
+        self.ws_bytes = nbytes.value
+        self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p(0)
+        _check(L.rpba_create(ctypes.byref(d), ctypes.byref(self.opt), ctypes.c_void_p(self.workspace.data_ptr()),
+                             self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "rpba_create")
+        self.h = h
+        self.cov = torch.zeros((6, self.N), dtype=f64, device=dev)
+        self.status = torch.zeros(self.N, dtype=torch.int32, device=dev)
+        self.int_stats = torch.zeros(4, dtype=f64, device=dev)
+        self.block_stats = torch.zeros((self.L, 4), dtype=f64, device=dev)
+        self.cons_stats = torch.zeros(2, dtype=f64, device=dev)
+        self.rob_stats = torch.zeros(2, dtype=f64, device=dev)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.L_.rpba_destroy(self.h)
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- the method's calls (asynchronous; stats stay on the device) ---
+    def rpba_intersect(self, cov=True, status=True):
+        _check(self.L_.rpba_intersect(self.h, _ptr(self.cov) if cov else None, _ptr(self.status) if status else None,
+                                      _ptr(self.int_stats)), "rpba_intersect")
+        return self.int_stats
+
+    def rpba_robust_reweight(self, eliminate=False):
+        _check(self.L_.rpba_robust_reweight(self.h, int(eliminate), _ptr(self.rob_stats)), "rpba_robust_reweight")
+        return self.rob_stats
+
+    def rpba_subblock_lm_step(self, active=None):
+        _check(self.L_.rpba_subblock_lm_step(self.h, _ptr(active), _ptr(self.block_stats)), "rpba_subblock_lm_step")
+        return self.block_stats
+
+    def rpba_consensus(self):
+        _check(self.L_.rpba_consensus(self.h, _ptr(self.cons_stats)), "rpba_consensus")
+        return self.cons_stats
+
+    # --- inspection (synchronous) ---
+    def num_copies(self):
+        return int(self.L_.rpba_num_copies(self.h))
+
+    def copies(self):
+        n = self.num_copies()
+        blk = np.zeros(n, dtype=np.int32)
+        pt = np.zeros(n, dtype=np.int32)
+        X = np.zeros((n, 3))
+        om = np.zeros((n, 6))
+        _check(self.L_.rpba_get_copies(self.h, blk.ctypes.data, pt.ctypes.data, X.ctypes.data, om.ctypes.data),
+               "rpba_get_copies")
+        return blk, pt, X, om
+
+    def block_rcs(self, l):
+        n6 = 6 * int(self.L_.rpba_block_cameras(self.h, l))
+        S = np.zeros((n6, n6))
+        e = np.zeros(n6)
+        _check(self.L_.rpba_get_block_rcs(self.h, l, S.ctypes.data, e.ctypes.data), "rpba_get_block_rcs")
+        return S, e
+
+    def cameras(self):
+        self.stream.synchronize()
+        return self.cam_R.cpu().numpy(), self.cam_C.cpu().numpy()
+
+    def points(self):
+        self.stream.synchronize()
+        return self.pts.cpu().numpy()
+
+    def intersection(self):
+        self.stream.synchronize()
+        return self.pts.cpu().numpy(), self.cov.cpu().numpy(), self.status.cpu().numpy()
+
+
+def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, **opts):
+    """Fixed schedule on the GPU: T outer iterations of (intersect [, robust,
+    re-intersect], I LM steps, consensus), then a final intersection."""
+    p = Problem(scene, **opts)
+    hist = []
+    for t in range(T):
+        st = p.rpba_intersect().cpu().numpy().copy()
+        if robust and t >= t_r:
+            p.rpba_robust_reweight(False)
+            st = p.rpba_intersect().cpu().numpy().copy()
+        rec = dict(t=t, int_stats=st, steps=[])
+        for s in range(I):
+            bs = p.rpba_subblock_lm_step().cpu().numpy().copy()
+            rec["steps"].append(bs)
+        rec["consensus"] = p.rpba_consensus().cpu().numpy().copy()
+        hist.append(rec)
+        if callback:
+            callback(p, rec)
+    if robust:
+        p.rpba_intersect()
+        p.rpba_robust_reweight(True)
+    final = p.rpba_intersect().cpu().numpy().copy()
+    hist.append(dict(t=T, int_stats=final))
+    return p, hist

@@ -1,0 +1,446 @@
+// C ABI of librpba (declared in include/rpba.h): argument checking, the
+// workspace layout, the host-side plan upload and the per-call kernel
+// sequences.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rpba.h"
+#include "rpba_internal.hpp"
+#include "rpba_plan.hpp"
+
+using namespace rpba;
+
+namespace {
+
+thread_local std::string g_err;
+
+rpba_status fail(rpba_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(RPBA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Layout {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    size_t off = total;
+    total += (bytes + 255) & ~(size_t)255;
+    return off;
+  }
+};
+
+// byte offsets of every workspace array
+struct WsMap {
+  size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
+      cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
+      bwd_items, blk_fail;
+  size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
+      acc_rob;
+  size_t total;
+};
+
+WsMap layout_for(const Plan& P) {
+  Layout L;
+  WsMap m;
+  const size_t i4 = 4, i8 = 8, f8 = 8;
+  m.cam_blk = L.add(i4 * P.M);
+  m.blk_cam_off = L.add(i4 * (P.L + 1));
+  m.cam_orig = L.add(i4 * P.M);
+  m.pt_orig = L.add(i4 * P.N);
+  m.pt_copy_off = L.add(i4 * (P.N + 1));
+  m.pt_copies = L.add(i4 * P.NC);
+  m.obs_cam = L.add(i4 * P.K);
+  m.obs_copy = L.add(i4 * P.K);
+  m.obs_orig = L.add(i4 * P.K);
+  m.cam_obs_off = L.add(i4 * (P.M + 1));
+  m.cam_obs = L.add(i4 * P.K);
+  m.copy_off = L.add(i4 * (P.NC + 1));
+  m.copy_pt = L.add(i4 * P.NC);
+  m.copy_blk = L.add(i4 * P.NC);
+  m.blk_copy_off = L.add(i8 * (P.L + 1));
+  m.nb_off = L.add(i4 * (P.M + 1));
+  m.nb_cam = L.add(i4 * P.nb_cam.size());
+  m.nt = L.add(i4 * P.L);
+  m.rcs_off = L.add(i8 * P.L);
+  m.diag_off = L.add(i8 * P.L);
+  m.vec_off = L.add(i8 * P.L);
+  m.fwd_items = L.add(i4 * P.fwd_items.size());
+  m.bwd_items = L.add(i4 * P.bwd_items.size());
+  m.blk_fail = L.add(i4 * P.L);
+  m.cam = L.add(f8 * 12 * P.M);
+  m.camN = L.add(f8 * 12 * P.M);
+  m.P0 = L.add(f8 * 3 * P.N);
+  m.Xbar = L.add(f8 * 3 * P.N);
+  m.status = L.add(i4 * P.N);
+  m.xy = L.add(f8 * 2 * P.K);
+  m.info = L.add(P.has_info ? f8 * 3 * P.K : 0);
+  m.rw = L.add(f8 * P.K);
+  m.res = L.add(f8 * 2 * P.K);
+  m.Xc = L.add(f8 * 3 * P.NC);
+  m.Om = L.add(f8 * 6 * P.NC);
+  m.cpk = L.add(f8 * 12 * P.NC);
+  m.S = L.add(f8 * P.rcs_total);
+  m.Ld = L.add(f8 * P.diag_total);
+  m.Li = L.add(f8 * P.diag_total);
+  m.y = L.add(f8 * P.vec_total);
+  m.ys = L.add(f8 * P.vec_total);
+  m.x = L.add(f8 * P.vec_total);
+  m.acc_int = L.add(f8 * 4);
+  m.acc_blk = L.add(f8 * 4 * P.L);
+  m.acc_cons = L.add(f8 * 2);
+  m.acc_rob = L.add(f8 * 2);
+  m.total = L.total;
+  return m;
+}
+
+// one cached plan: rpba_workspace_size followed by rpba_create on the same
+// topology plans once
+std::mutex g_plan_mu;
+std::shared_ptr<Plan> g_last_plan;
+
+rpba_status get_plan(const rpba_problem_desc* d, const rpba_options* o, std::shared_ptr<Plan>& out) {
+  int tile = o->chol_tile == 0 ? 64 : o->chol_tile;
+  if (!d->obs_cam || !d->obs_pt || !d->cam_block) return fail(RPBA_ERR_ARG, "topology arrays must be non-NULL");
+  uint64_t key = topology_key(d->M, d->N, d->K, d->L, d->obs_cam, d->obs_pt, d->cam_block, tile);
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    if (g_last_plan && g_last_plan->key == key) {
+      out = g_last_plan;
+      out->has_info = d->obs_info != nullptr;
+      return RPBA_OK;
+    }
+  }
+  auto P = std::make_shared<Plan>();
+  std::string err = build_plan(d->M, d->N, d->K, d->L, d->obs_cam, d->obs_pt, d->cam_block, tile, *P);
+  if (!err.empty()) return fail(RPBA_ERR_ARG, err);
+  P->has_info = d->obs_info != nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    g_last_plan = P;
+  }
+  out = P;
+  return RPBA_OK;
+}
+
+rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
+  if (!d || !o) return fail(RPBA_ERR_ARG, "desc and options must be non-NULL");
+  if (!(d->f > 0) || !std::isfinite(d->f) || !std::isfinite(d->cx) || !std::isfinite(d->cy))
+    return fail(RPBA_ERR_ARG, "intrinsics must be finite, f > 0");
+  if (!d->obs_info && !(d->sigma_px > 0)) return fail(RPBA_ERR_ARG, "sigma_px must be > 0 without obs_info");
+  if (!d->cam_R || !d->cam_C || !d->pts || !d->obs_xy) return fail(RPBA_ERR_ARG, "state and observation arrays must be non-NULL");
+  if (o->precision != RPBA_FP64 && o->precision != RPBA_MIXED) return fail(RPBA_ERR_ARG, "unknown precision");
+  if (!(o->lambda >= 0) || !(o->int_tol > 0) || o->int_maxit < 1) return fail(RPBA_ERR_ARG, "bad LM / intersection options");
+  if (o->chol_tile != 0 && o->chol_tile != 32 && o->chol_tile != 64) return fail(RPBA_ERR_ARG, "chol_tile must be 0, 32 or 64");
+  return RPBA_OK;
+}
+
+}  // namespace
+
+struct rpba_problem {
+  std::shared_ptr<Plan> plan;
+  WsMap map;
+  Dev d;
+  rpba_options opt;
+  hipStream_t stream;
+  char* ws;
+  size_t max_lds_schur;
+  bool intersected = false;
+};
+
+extern "C" {
+
+const char* rpba_last_error(void) { return g_err.c_str(); }
+
+rpba_status rpba_default_options(rpba_options* o) {
+  if (!o) return fail(RPBA_ERR_ARG, "NULL options");
+  std::memset(o, 0, sizeof(*o));
+  o->precision = RPBA_FP64;
+  o->solver = RPBA_SOLVER_CHOL;
+  o->lambda = 1e-4;
+  o->int_tol = 1e-12;
+  o->int_maxit = 20;
+  o->pcg_maxit = 200;
+  o->pcg_tol = 1e-8;
+  o->ir_tol = 1e-10;
+  o->ir_maxit = 6;
+  o->pcg_min_cams = 150;
+  o->t_v = 4.0;
+  o->down_weight = 1e-4;
+  o->chol_tile = 0;
+  return RPBA_OK;
+}
+
+rpba_status rpba_workspace_size(const rpba_problem_desc* d, const rpba_options* o, size_t* bytes) {
+  rpba_status s = check_desc(d, o);
+  if (s != RPBA_OK) return s;
+  if (!bytes) return fail(RPBA_ERR_ARG, "NULL bytes");
+  std::shared_ptr<Plan> P;
+  s = get_plan(d, o, P);
+  if (s != RPBA_OK) return s;
+  *bytes = layout_for(*P).total;
+  return RPBA_OK;
+}
+
+rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void* workspace, size_t bytes, void* stream,
+                        rpba_problem** out) {
+  rpba_status s = check_desc(d, o);
+  if (s != RPBA_OK) return s;
+  if (!out) return fail(RPBA_ERR_ARG, "NULL out");
+  *out = nullptr;
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(RPBA_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  std::shared_ptr<Plan> P;
+  s = get_plan(d, o, P);
+  if (s != RPBA_OK) return s;
+  WsMap m = layout_for(*P);
+  if (bytes < m.total) return fail(RPBA_ERR_WORKSPACE, "workspace too small: need " + std::to_string(m.total));
+  size_t lds = (size_t)P->max_nb * 36 * 8 + 33 * 4 * 8 + (size_t)P->max_blk_cams * 4;
+  if (lds > 160 * 1024) return fail(RPBA_ERR_ARG, "a camera has too many neighbours for the LDS row accumulator");
+
+  std::unique_ptr<rpba_problem> h(new rpba_problem());
+  h->plan = P;
+  h->map = m;
+  h->opt = *o;
+  h->stream = (hipStream_t)stream;
+  h->ws = (char*)workspace;
+  h->max_lds_schur = lds;
+  hipStream_t st = h->stream;
+  char* w = h->ws;
+  auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(w + off, src, n, hipMemcpyHostToDevice, st);
+  };
+  const Plan& p = *P;
+  HIP_TRY(up(m.cam_blk, p.cam_blk.data(), 4 * p.cam_blk.size()));
+  HIP_TRY(up(m.blk_cam_off, p.blk_cam_off.data(), 4 * p.blk_cam_off.size()));
+  HIP_TRY(up(m.cam_orig, p.cam_orig.data(), 4 * p.cam_orig.size()));
+  HIP_TRY(up(m.pt_orig, p.pt_orig.data(), 4 * p.pt_orig.size()));
+  HIP_TRY(up(m.pt_copy_off, p.pt_copy_off.data(), 4 * p.pt_copy_off.size()));
+  HIP_TRY(up(m.pt_copies, p.pt_copies.data(), 4 * p.pt_copies.size()));
+  HIP_TRY(up(m.obs_cam, p.obs_cam.data(), 4 * p.obs_cam.size()));
+  HIP_TRY(up(m.obs_copy, p.obs_copy.data(), 4 * p.obs_copy.size()));
+  HIP_TRY(up(m.obs_orig, p.obs_orig.data(), 4 * p.obs_orig.size()));
+  HIP_TRY(up(m.cam_obs_off, p.cam_obs_off.data(), 4 * p.cam_obs_off.size()));
+  HIP_TRY(up(m.cam_obs, p.cam_obs.data(), 4 * p.cam_obs.size()));
+  HIP_TRY(up(m.copy_off, p.copy_off.data(), 4 * p.copy_off.size()));
+  HIP_TRY(up(m.copy_pt, p.copy_pt.data(), 4 * p.copy_pt.size()));
+  HIP_TRY(up(m.copy_blk, p.copy_blk.data(), 4 * p.copy_blk.size()));
+  HIP_TRY(up(m.blk_copy_off, p.blk_copy_off.data(), 8 * p.blk_copy_off.size()));
+  HIP_TRY(up(m.nb_off, p.nb_off.data(), 4 * p.nb_off.size()));
+  HIP_TRY(up(m.nb_cam, p.nb_cam.data(), 4 * p.nb_cam.size()));
+  HIP_TRY(up(m.nt, p.nt.data(), 4 * p.nt.size()));
+  HIP_TRY(up(m.rcs_off, p.rcs_off.data(), 8 * p.rcs_off.size()));
+  HIP_TRY(up(m.diag_off, p.diag_off.data(), 8 * p.diag_off.size()));
+  HIP_TRY(up(m.vec_off, p.vec_off.data(), 8 * p.vec_off.size()));
+  HIP_TRY(up(m.fwd_items, p.fwd_items.data(), 4 * p.fwd_items.size()));
+  HIP_TRY(up(m.bwd_items, p.bwd_items.data(), 4 * p.bwd_items.size()));
+
+  Dev& D = h->d;
+  std::memset(&D, 0, sizeof(D));
+  D.M = p.M;
+  D.N = p.N;
+  D.K = p.K;
+  D.L = p.L;
+  D.NC = p.NC;
+  D.T = p.T;
+  D.int_maxit = o->int_maxit;
+  D.has_info = p.has_info ? 1 : 0;
+  D.f = d->f;
+  D.cx = d->cx;
+  D.cy = d->cy;
+  D.w0 = d->obs_info ? 0.0 : 1.0 / (d->sigma_px * d->sigma_px);
+  D.lambda = o->lambda;
+  D.int_tol = o->int_tol;
+  D.u_camR = d->cam_R;
+  D.u_camC = d->cam_C;
+  D.u_pts = d->pts;
+  D.u_xy = d->obs_xy;
+  D.u_info = d->obs_info;
+  auto I = [&](size_t off) { return (int32_t*)(w + off); };
+  auto F = [&](size_t off) { return (double*)(w + off); };
+  D.cam = F(m.cam);
+  D.camN = F(m.camN);
+  D.cam_blk = I(m.cam_blk);
+  D.blk_cam_off = I(m.blk_cam_off);
+  D.cam_orig = I(m.cam_orig);
+  D.P0 = F(m.P0);
+  D.Xbar = F(m.Xbar);
+  D.status = I(m.status);
+  D.pt_orig = I(m.pt_orig);
+  D.pt_copy_off = I(m.pt_copy_off);
+  D.pt_copies = I(m.pt_copies);
+  D.xy = F(m.xy);
+  D.info = p.has_info ? F(m.info) : nullptr;
+  D.rw = F(m.rw);
+  D.res = F(m.res);
+  D.obs_cam = I(m.obs_cam);
+  D.obs_copy = I(m.obs_copy);
+  D.obs_orig = I(m.obs_orig);
+  D.cam_obs_off = I(m.cam_obs_off);
+  D.cam_obs = I(m.cam_obs);
+  D.copy_off = I(m.copy_off);
+  D.copy_pt = I(m.copy_pt);
+  D.copy_blk = I(m.copy_blk);
+  D.blk_copy_off = (const int64_t*)(w + m.blk_copy_off);
+  D.Xc = F(m.Xc);
+  D.Om = F(m.Om);
+  D.cpk = F(m.cpk);
+  D.nb_off = I(m.nb_off);
+  D.nb_cam = I(m.nb_cam);
+  D.S = F(m.S);
+  D.Ld = F(m.Ld);
+  D.Li = F(m.Li);
+  D.y = F(m.y);
+  D.ys = F(m.ys);
+  D.x = F(m.x);
+  D.nt = I(m.nt);
+  D.rcs_off = (const int64_t*)(w + m.rcs_off);
+  D.diag_off = (const int64_t*)(w + m.diag_off);
+  D.vec_off = (const int64_t*)(w + m.vec_off);
+  D.blk_fail = I(m.blk_fail);
+  D.acc_int = F(m.acc_int);
+  D.acc_blk = F(m.acc_blk);
+  D.acc_cons = F(m.acc_cons);
+  D.acc_rob = F(m.acc_rob);
+
+  // packing kernels, zero state, identity padding
+  launch_gather(D, st);
+  launch_zero(D.Xc, 3 * D.NC, st);
+  launch_zero(D.Om, 6 * D.NC, st);
+  launch_zero(D.cpk, 12 * D.NC, st);
+  launch_zero(D.S, p.rcs_total, st);
+  launch_zero(D.Ld, p.diag_total, st);
+  launch_zero(D.Li, p.diag_total, st);
+  launch_zero(D.y, p.vec_total, st);
+  launch_zero(D.ys, p.vec_total, st);
+  launch_zero(D.x, p.vec_total, st);
+  launch_zero_i32(D.blk_fail, D.L, st);
+  launch_init_rcs(D, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = h.release();
+  return RPBA_OK;
+}
+
+rpba_status rpba_destroy(rpba_problem* h) {
+  delete h;
+  return RPBA_OK;
+}
+
+rpba_status rpba_intersect(rpba_problem* h, double* cov, int32_t* status, double* stats) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  launch_intersect(h->d, cov, status, stats, h->stream);
+  HIP_TRY(hipGetLastError());
+  h->intersected = true;
+  return RPBA_OK;
+}
+
+static rpba_status assemble(rpba_problem* h, const uint8_t* active) {
+  h->d.active = active;
+  launch_copy_prep(h->d, h->stream);
+  launch_schur_rows(h->d, h->plan->max_nb, h->plan->max_blk_cams, h->stream);
+  HIP_TRY(hipGetLastError());
+  return RPBA_OK;
+}
+
+rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double* block_stats) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run before the first LM step");
+  const Plan& p = *h->plan;
+  rpba_status s = assemble(h, active);
+  if (s != RPBA_OK) return s;
+  const int32_t* fwd = (const int32_t*)(h->ws + h->map.fwd_items);
+  const int32_t* bwd = (const int32_t*)(h->ws + h->map.bwd_items);
+  for (int k = 0; k < p.nt_max; ++k)
+    launch_chol_forward(h->d, k, fwd + p.fwd_off[k], p.fwd_off[k + 1] - p.fwd_off[k], h->stream);
+  for (int s2 = 0; s2 < p.nt_max; ++s2)
+    launch_chol_backward(h->d, bwd + p.bwd_off[s2], p.bwd_off[s2 + 1] - p.bwd_off[s2], h->stream);
+  launch_update(h->d, block_stats, h->stream);
+  HIP_TRY(hipGetLastError());
+  h->d.active = nullptr;
+  return RPBA_OK;
+}
+
+rpba_status rpba_consensus(rpba_problem* h, double* stats) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  launch_consensus(h->d, stats, h->stream);
+  HIP_TRY(hipGetLastError());
+  return RPBA_OK;
+}
+
+rpba_status rpba_robust_reweight(rpba_problem* h, int32_t eliminate, double* stats) {
+  (void)eliminate;
+  (void)stats;
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  return fail(RPBA_ERR_STATE, "robust re-weighting not available");
+}
+
+int64_t rpba_num_copies(rpba_problem* h) { return h ? h->plan->NC : -1; }
+
+int32_t rpba_block_cameras(rpba_problem* h, int32_t l) {
+  if (!h || l < 0 || l >= h->plan->L) return -1;
+  return h->plan->blk_cam_off[l + 1] - h->plan->blk_cam_off[l];
+}
+
+rpba_status rpba_set_debug(rpba_problem* h, int32_t on) {
+  (void)on;
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  return RPBA_OK;
+}
+
+rpba_status rpba_get_copies(rpba_problem* h, int32_t* blk, int32_t* pt, double* X, double* omega) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  const Plan& p = *h->plan;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (blk) std::memcpy(blk, p.copy_blk.data(), 4 * p.NC);
+  if (pt)
+    for (int64_t c = 0; c < p.NC; ++c) pt[c] = p.pt_orig[p.copy_pt[c]];
+  if (X) HIP_TRY(hipMemcpy(X, h->d.Xc, 8 * 3 * p.NC, hipMemcpyDeviceToHost));
+  if (omega) HIP_TRY(hipMemcpy(omega, h->d.Om, 8 * 6 * p.NC, hipMemcpyDeviceToHost));
+  return RPBA_OK;
+}
+
+// S of sub-block l assembled at the current state (cameras of l in ascending
+// original index = internal order within the sub-block).  Runs the assembly
+// kernels of an LM step without solving.
+rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  const Plan& p = *h->plan;
+  if (l < 0 || l >= p.L) return fail(RPBA_ERR_ARG, "sub-block out of range");
+  if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run first");
+  rpba_status s = assemble(h, nullptr);
+  if (s != RPBA_OK) return s;
+  int n6 = 6 * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
+  // stage through the x / ys vectors is not possible for a full matrix: use
+  // the Ld array (free outside a step) when large enough, else the cpk array
+  size_t need = (size_t)n6 * n6 + n6;
+  double* stage = nullptr;
+  if ((int64_t)need <= p.diag_total * 2) stage = h->d.Ld;  // Ld and Li are contiguous in the layout
+  else if ((int64_t)need <= 12 * p.NC) stage = h->d.cpk;
+  else return fail(RPBA_ERR_STATE, "no staging space for this sub-block");
+  launch_rcs_extract(h->d, l, stage, stage + (size_t)n6 * n6, h->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (S) HIP_TRY(hipMemcpy(S, stage, 8 * (size_t)n6 * n6, hipMemcpyDeviceToHost));
+  if (e) HIP_TRY(hipMemcpy(e, stage + (size_t)n6 * n6, 8 * (size_t)n6, hipMemcpyDeviceToHost));
+  return RPBA_OK;
+}
+
+rpba_status rpba_selftest_gemm(const double* A, const double* B, double* C, void* stream) {
+  launch_selftest_gemm(A, B, C, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return RPBA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Device-side geometry and small dense algebra for the librpba kernels.
+//
+// Camera model (paper Sec. 2, calibrated pinhole): p = R (X - C),
+// g = (f p1/p3 + cx, f p2/p3 + cy).  With u = p1/p3, w = p2/p3:
+//   dg/dX            = (f/p3) [[1, 0, -u], [0, 1, -w]] R            (B, 2x3)
+//   dg/d(rotation)   = f [[-u w, 1 + u^2, -w], [-(1 + w^2), u w, u]]  (rotation
+//                      increment left-multiplied, R <- Exp([d]x) R, Sec. 5.4)
+//   dg/dC            = -B
+// The camera Jacobian A (2x6) is [Ar | -B] with parameter order
+// (rotation x, y, z, centre x, y, z).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpba {
+
+// camera record in device memory: R (row-major, 9) then C (3)
+constexpr int CAM_STRIDE = 12;
+
+template <typename T>
+struct Lin {
+  T g0, g1;      // projected pixel
+  T z;           // depth p3
+  T B[2][3];     // dg/dX
+  T Ar[2][3];    // dg/d(rotation increment)
+};
+
+template <typename T>
+__device__ __forceinline__ void linearise(const T* __restrict__ R, const T* __restrict__ C, const T X[3], T f,
+                                          T cx, T cy, Lin<T>& o) {
+  T d0 = X[0] - C[0], d1 = X[1] - C[1], d2 = X[2] - C[2];
+  T p0 = R[0] * d0 + R[1] * d1 + R[2] * d2;
+  T p1 = R[3] * d0 + R[4] * d1 + R[5] * d2;
+  T p2 = R[6] * d0 + R[7] * d1 + R[8] * d2;
+  o.z = p2;
+  T iz = T(1) / p2;
+  T u = p0 * iz, w = p1 * iz;
+  o.g0 = f * u + cx;
+  o.g1 = f * w + cy;
+  T fz = f * iz;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    o.B[0][c] = fz * (R[c] - u * R[6 + c]);
+    o.B[1][c] = fz * (R[3 + c] - w * R[6 + c]);
+  }
+  o.Ar[0][0] = -f * u * w;
+  o.Ar[0][1] = f * (T(1) + u * u);
+  o.Ar[0][2] = -f * w;
+  o.Ar[1][0] = -f * (T(1) + w * w);
+  o.Ar[1][1] = f * u * w;
+  o.Ar[1][2] = f * u;
+}
+
+// weight matrix of one observation [[a, b], [b, c]]
+template <typename T>
+struct W2 {
+  T a, b, c;
+};
+
+template <typename T>
+__device__ __forceinline__ T wquad(const W2<T>& W, T v0, T v1) {
+  return W.a * v0 * v0 + T(2) * W.b * v0 * v1 + W.c * v1 * v1;
+}
+
+// Rodrigues' formula: R_out = Exp([w]x) R_in (series below 1e-8 rad).
+__device__ __forceinline__ void rotate_left(const double w[3], const double* Rin, double* Rout) {
+  double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  double th = sqrt(th2);
+  double a, b;
+  if (th < 1e-8) {
+    a = 1.0;
+    b = 0.5;
+  } else {
+    a = sin(th) / th;
+    b = (1.0 - cos(th)) / th2;
+  }
+  // E = I + a K + b K^2 with K = [w]x, K^2 = w w^T - th2 I
+  double E[9];
+  E[0] = 1.0 + b * (w[0] * w[0] - th2);
+  E[4] = 1.0 + b * (w[1] * w[1] - th2);
+  E[8] = 1.0 + b * (w[2] * w[2] - th2);
+  E[1] = -a * w[2] + b * w[0] * w[1];
+  E[3] = a * w[2] + b * w[0] * w[1];
+  E[2] = a * w[1] + b * w[0] * w[2];
+  E[6] = -a * w[1] + b * w[0] * w[2];
+  E[5] = -a * w[0] + b * w[1] * w[2];
+  E[7] = a * w[0] + b * w[1] * w[2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Rout[3 * r + c] = E[3 * r] * Rin[c] + E[3 * r + 1] * Rin[3 + c] + E[3 * r + 2] * Rin[6 + c];
+}
+
+// Symmetric 3x3 stored as (xx, xy, xz, yy, yz, zz).
+// Cholesky with the pivot test pivot > 1e-12 * max diagonal; on success
+// writes the lower factor l = (l00, l10, l20, l11, l21, l22).
+__device__ __forceinline__ bool chol3(const double h[6], double l[6]) {
+  double dmax = fmax(h[0], fmax(h[3], h[5]));
+  if (!(dmax > 0.0)) return false;
+  double thr = 1e-12 * dmax;
+  double p0 = h[0];
+  if (!(p0 > thr)) return false;
+  l[0] = sqrt(p0);
+  l[1] = h[1] / l[0];
+  l[2] = h[2] / l[0];
+  double p1 = h[3] - l[1] * l[1];
+  if (!(p1 > thr)) return false;
+  l[3] = sqrt(p1);
+  l[4] = (h[4] - l[2] * l[1]) / l[3];
+  double p2 = h[5] - l[2] * l[2] - l[4] * l[4];
+  if (!(p2 > thr)) return false;
+  l[5] = sqrt(p2);
+  return true;
+}
+
+// x = (L L^T)^-1 b
+__device__ __forceinline__ void chol3_solve(const double l[6], const double b[3], double x[3]) {
+  double y0 = b[0] / l[0];
+  double y1 = (b[1] - l[1] * y0) / l[3];
+  double y2 = (b[2] - l[2] * y0 - l[4] * y1) / l[5];
+  x[2] = y2 / l[5];
+  x[1] = (y1 - l[4] * x[2]) / l[3];
+  x[0] = (y0 - l[1] * x[1] - l[2] * x[2]) / l[0];
+}
+
+// inverse (sym6 layout) from the Cholesky factor: Inv = L^-T L^-1
+__device__ __forceinline__ void chol3_inverse(const double l[6], double inv[6]) {
+  // M = L^-1 (lower)
+  double m00 = 1.0 / l[0];
+  double m11 = 1.0 / l[3];
+  double m22 = 1.0 / l[5];
+  double m10 = -l[1] * m00 * m11;
+  double m21 = -l[4] * m11 * m22;
+  double m20 = -(l[2] * m00 + l[4] * m10) * m22;
+  inv[0] = m00 * m00 + m10 * m10 + m20 * m20;
+  inv[1] = m11 * m10 + m21 * m20;
+  inv[2] = m22 * m20;
+  inv[3] = m11 * m11 + m21 * m21;
+  inv[4] = m22 * m21;
+  inv[5] = m22 * m22;
+}
+
+__device__ __forceinline__ void sym3_mul(const double s[6], const double x[3], double y[3]) {
+  y[0] = s[0] * x[0] + s[1] * x[1] + s[2] * x[2];
+  y[1] = s[1] * x[0] + s[3] * x[1] + s[4] * x[2];
+  y[2] = s[2] * x[0] + s[4] * x[1] + s[5] * x[2];
+}
+
+// B^T W B (sym6) and B^T W v added into h, g.
+template <typename T>
+__device__ __forceinline__ void add_point_normals(const Lin<T>& L, const W2<T>& W, T v0, T v1, T h[6], T g[3]) {
+  T WB0[3], WB1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    WB0[c] = W.a * L.B[0][c] + W.b * L.B[1][c];
+    WB1[c] = W.b * L.B[0][c] + W.c * L.B[1][c];
+  }
+  T Wv0 = W.a * v0 + W.b * v1, Wv1 = W.b * v0 + W.c * v1;
+  h[0] += L.B[0][0] * WB0[0] + L.B[1][0] * WB1[0];
+  h[1] += L.B[0][0] * WB0[1] + L.B[1][0] * WB1[1];
+  h[2] += L.B[0][0] * WB0[2] + L.B[1][0] * WB1[2];
+  h[3] += L.B[0][1] * WB0[1] + L.B[1][1] * WB1[1];
+  h[4] += L.B[0][1] * WB0[2] + L.B[1][1] * WB1[2];
+  h[5] += L.B[0][2] * WB0[2] + L.B[1][2] * WB1[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g[c] += L.B[0][c] * Wv0 + L.B[1][c] * Wv1;
+}
+
+// atomic max of a non-negative double through its bit pattern
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+}  // namespace rpba

@@ -1,0 +1,100 @@
+// Internal state shared by the librpba kernels and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpba {
+
+// Device view of one problem: every pointer lives in the caller's workspace
+// (or is one of the caller's own arrays, prefix u_).
+struct Dev {
+  int32_t M, N, K, L;
+  int64_t NC;
+  int32_t T;              // Cholesky tile edge
+  int32_t int_maxit;
+  int32_t has_info;
+  double f, cx, cy, w0;   // w0 = 1 / sigma_px^2
+  double lambda, int_tol;
+
+  // caller arrays (original order)
+  double* u_camR;         // [M][9]
+  double* u_camC;         // [3][M]
+  double* u_pts;          // [3][N]
+  const double* u_xy;     // [2][K]
+  const double* u_info;   // [3][K] or null
+
+  // cameras, internal (sub-block-major) order
+  double* cam;            // [M][12] R row-major, C
+  double* camN;           // [M][12] updated cameras of the current step
+  const int32_t* cam_blk;
+  const int32_t* blk_cam_off;
+  const int32_t* cam_orig;
+
+  // points, internal order
+  double* P0;             // [3][N] start values of the next intersection
+  double* Xbar;           // [3][N] last intersection
+  int32_t* status;        // [N]
+  const int32_t* pt_orig;
+  const int32_t* pt_copy_off;
+  const int32_t* pt_copies;
+
+  // observations, LM order
+  double* xy;             // [K][2]
+  double* info;           // [K][3] or null
+  double* rw;             // [K] robust weight multiplier
+  double* res;            // [K][2] residuals of the last intersection
+  const int32_t* obs_cam;
+  const int32_t* obs_copy;
+  const int32_t* obs_orig;
+  const int32_t* cam_obs_off;
+  const int32_t* cam_obs;
+
+  // copies (sub-block, point)
+  const int32_t* copy_off;
+  const int32_t* copy_pt;
+  const int32_t* copy_blk;
+  const int64_t* blk_copy_off;
+  double* Xc;             // [NC][3] X_j^l
+  double* Om;             // [NC][6] refined tie-point weight
+  double* cpk;            // [NC][12] X, damped V^-1 (6), g_X (3) of the current step
+  const int32_t* nb_off;
+  const int32_t* nb_cam;
+
+  // dense reduced camera systems
+  double* S;              // tiles, lower triangle per sub-block
+  double* Ld;             // [diag] factor tiles L(k,k)
+  double* Li;             // [diag] inverse tiles L(k,k)^-1
+  double* y;              // padded right-hand sides, updated in place
+  double* ys;             // forward-solved segments L^-1 e, then backward-updated
+  double* x;              // solution (camera steps)
+  const int32_t* nt;
+  const int64_t* rcs_off;
+  const int64_t* diag_off;
+  const int64_t* vec_off;
+  int32_t* blk_fail;      // [L]
+  const uint8_t* active;  // [L] or null (set per call)
+
+  // accumulators
+  double* acc_int;        // [4] cost, sum |v|^2, K_valid, N_valid
+  double* acc_blk;        // [L][4] cost before, cost after, |step|^2, iterations
+  double* acc_cons;       // [2]
+  double* acc_rob;        // [2]
+};
+
+// kernel launchers (all asynchronous on `st`)
+void launch_gather(const Dev& d, hipStream_t st);
+void launch_init_rcs(const Dev& d, hipStream_t st);
+void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st);
+void launch_copy_prep(const Dev& d, hipStream_t st);
+void launch_schur_rows(const Dev& d, int max_nb, int max_blk_cams, hipStream_t st);
+void launch_chol_forward(const Dev& d, int k, const int32_t* items, int64_t n_items, hipStream_t st);
+void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st);
+void launch_update(const Dev& d, double* block_stats, hipStream_t st);
+void launch_consensus(const Dev& d, double* stats, hipStream_t st);
+void launch_zero(double* p, int64_t n, hipStream_t st);
+void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);
+// in-bounds layout check of the FP64 MFMA tile product: C = A B^T (64x64, row-major)
+void launch_selftest_gemm(const double* A, const double* B, double* C, hipStream_t st);
+
+}  // namespace rpba

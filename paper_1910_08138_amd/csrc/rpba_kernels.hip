@@ -1,0 +1,684 @@
+// librpba kernels of the FP64 path: packing, intersection with covariance and
+// refined tie-point weights (eq:bars, Sec. 5.1), the sub-block normal
+// equations with tie-point priors and their Schur complement (eq:bact,
+// Sec. 2 and 5.4), back-substitution / update / new cost, and the consensus
+// exchange (Sec. 5).
+#include "rpba_device.hpp"
+#include "rpba_internal.hpp"
+
+namespace rpba {
+
+namespace {
+
+constexpr int NT = 256;  // threads per workgroup of the streaming kernels
+
+inline unsigned grid_for(int64_t n, int per = NT) { return (unsigned)((n + per - 1) / per); }
+
+__device__ __forceinline__ W2<double> obs_weight(const Dev& d, int64_t k) {
+  double r = d.rw[k];
+  if (d.has_info) {
+    const double* w = d.info + 3 * k;
+    return {r * w[0], r * w[1], r * w[2]};
+  }
+  return {r * d.w0, 0.0, r * d.w0};
+}
+
+// sum over a workgroup of 256 threads of `n` doubles; result valid in thread 0
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][8] */) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[q * 8 + wv] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = sh[q * 8 + 0] + sh[q * 8 + 1] + sh[q * 8 + 2] + sh[q * 8 + 3];
+}
+
+// ------------------------------------------------------------------ packing
+__global__ void k_gather_obs(Dev d) {
+  int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (k >= d.K) return;
+  int64_t o = d.obs_orig[k];
+  d.xy[2 * k] = d.u_xy[o];
+  d.xy[2 * k + 1] = d.u_xy[(int64_t)d.K + o];
+  if (d.has_info) {
+    d.info[3 * k] = d.u_info[o];
+    d.info[3 * k + 1] = d.u_info[(int64_t)d.K + o];
+    d.info[3 * k + 2] = d.u_info[2 * (int64_t)d.K + o];
+  }
+  d.rw[k] = 1.0;
+  d.res[2 * k] = 0.0;
+  d.res[2 * k + 1] = 0.0;
+}
+
+__global__ void k_gather_cams(Dev d) {
+  int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= d.M) return;
+  int o = d.cam_orig[i];
+  double* c = d.cam + (int64_t)CAM_STRIDE * i;
+  for (int q = 0; q < 9; ++q) c[q] = d.u_camR[9 * (int64_t)o + q];
+  for (int r = 0; r < 3; ++r) c[9 + r] = d.u_camC[(int64_t)r * d.M + o];
+}
+
+__global__ void k_gather_pts(Dev d) {
+  int j = blockIdx.x * NT + threadIdx.x;
+  if (j >= d.N) return;
+  int o = d.pt_orig[j];
+  for (int r = 0; r < 3; ++r) {
+    double v = d.u_pts[(int64_t)r * d.N + o];
+    d.P0[(int64_t)r * d.N + j] = v;
+    d.Xbar[(int64_t)r * d.N + j] = v;
+  }
+  d.status[j] = 0;
+}
+
+__global__ void k_zero(double* p, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) p[t] = 0.0;
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) p[t] = 0;
+}
+
+// identity on the padded rows of the last diagonal tile of every sub-block
+__global__ void k_pad_identity(Dev d) {
+  int l = blockIdx.x;
+  int n6 = 6 * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
+  int nt = d.nt[l];
+  int T = d.T;
+  int64_t tile = d.rcs_off[l] + ((int64_t)(nt - 1) * nt / 2 + (nt - 1)) * T * T;
+  for (int r = threadIdx.x; r < T; r += NT) {
+    int gr = (nt - 1) * T + r;
+    if (gr >= n6) d.S[tile + (int64_t)r * T + r] = 1.0;
+  }
+}
+
+// ------------------------------------------------------------ intersection
+// One thread per point (internal order).  Gauss-Newton with cameras fixed
+// (eq:bars); on convergence: covariance, refined weights Omega^l = H - H^(l)
+// of every copy (Sec. 5.1), copies reset to Xbar, residuals stored.
+__global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* status_out) {
+  __shared__ double sh[4 * 8];
+  int j = blockIdx.x * NT + threadIdx.x;
+  double accv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < d.N && d.status[j] == 0) {
+    const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
+    double X[3] = {d.P0[j], d.P0[(int64_t)d.N + j], d.P0[2 * (int64_t)d.N + j]};
+    int st = 1;  // not converged
+    double h[6], g[3], lch[6];
+    for (int it = 0; it < d.int_maxit; ++it) {
+      for (int q = 0; q < 6; ++q) h[q] = 0.0;
+      g[0] = g[1] = g[2] = 0.0;
+      bool behind = false;
+      for (int cc = c0; cc < c1; ++cc) {
+        int c = d.pt_copies[cc];
+        for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
+          const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
+          Lin<double> L;
+          linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+          if (!(L.z > 0.0)) behind = true;
+          add_point_normals<double>(L, obs_weight(d, k), L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1], h, g);
+        }
+      }
+      if (behind) {
+        st = 2;
+        break;
+      }
+      if (!chol3(h, lch)) {
+        st = 3;
+        break;
+      }
+      double mg[3] = {-g[0], -g[1], -g[2]}, dX[3];
+      chol3_solve(lch, mg, dX);
+      X[0] += dX[0];
+      X[1] += dX[1];
+      X[2] += dX[2];
+      double nd = sqrt(dX[0] * dX[0] + dX[1] * dX[1] + dX[2] * dX[2]);
+      double nx = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+      if (nd <= d.int_tol * (1.0 + nx)) {
+        st = 0;
+        break;
+      }
+    }
+    double cost = 0.0, sq = 0.0, nobs = 0.0;
+    if (st == 0) {
+      for (int q = 0; q < 6; ++q) h[q] = 0.0;
+      g[0] = g[1] = g[2] = 0.0;
+      bool behind = false;
+      for (int cc = c0; cc < c1; ++cc) {
+        int c = d.pt_copies[cc];
+        for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
+          const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
+          Lin<double> L;
+          linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+          if (!(L.z > 0.0)) behind = true;
+          double v0 = L.g0 - d.xy[2 * k], v1 = L.g1 - d.xy[2 * k + 1];
+          W2<double> W = obs_weight(d, k);
+          add_point_normals<double>(L, W, v0, v1, h, g);
+          d.res[2 * k] = v0;
+          d.res[2 * k + 1] = v1;
+          cost += wquad(W, v0, v1);
+          sq += v0 * v0 + v1 * v1;
+          nobs += 1.0;
+        }
+      }
+      if (behind) st = 2;
+      else if (!chol3(h, lch)) st = 3;
+    }
+    if (st == 0) {
+      double inv[6];
+      chol3_inverse(lch, inv);
+      int o = d.pt_orig[j];
+      if (cov)
+        for (int q = 0; q < 6; ++q) cov[(int64_t)q * d.N + o] = inv[q];
+      for (int r = 0; r < 3; ++r) {
+        d.Xbar[(int64_t)r * d.N + j] = X[r];
+        d.P0[(int64_t)r * d.N + j] = X[r];
+        d.u_pts[(int64_t)r * d.N + o] = X[r];
+      }
+      for (int cc = c0; cc < c1; ++cc) {
+        int c = d.pt_copies[cc];
+        double hl[6] = {0, 0, 0, 0, 0, 0}, gl[3] = {0, 0, 0};
+        for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
+          const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
+          Lin<double> L;
+          linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+          add_point_normals<double>(L, obs_weight(d, k), L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1], hl, gl);
+        }
+        for (int q = 0; q < 6; ++q) d.Om[6 * (int64_t)c + q] = h[q] - hl[q];
+        for (int r = 0; r < 3; ++r) d.Xc[3 * (int64_t)c + r] = X[r];
+      }
+      accv[0] = cost;
+      accv[1] = sq;
+      accv[2] = nobs;
+      accv[3] = 1.0;
+    }
+    d.status[j] = st;
+    if (status_out) status_out[d.pt_orig[j]] = st;
+  } else if (j < d.N && status_out) {
+    status_out[d.pt_orig[j]] = d.status[j];
+  }
+  block_sum<4>(accv, sh);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) atomicAdd(&d.acc_int[q], accv[q]);
+}
+
+// stats = (cost, sigma0, RMS, N_valid) from the accumulated sums
+__global__ void k_intersect_stats(Dev d, double* stats) {
+  if (threadIdx.x != 0) return;
+  double cost = d.acc_int[0], sq = d.acc_int[1], kv = d.acc_int[2], nv = d.acc_int[3];
+  double red = 2.0 * kv - 6.0 * d.M - 3.0 * nv;
+  stats[0] = cost;
+  stats[1] = red > 0 ? sqrt(sq / red) : 0.0;
+  stats[2] = kv > 0 ? sqrt(sq / (2.0 * kv)) : 0.0;
+  stats[3] = nv;
+}
+
+// ------------------------------------------------ sub-block normal equations
+// One thread per copy: damped point block V* = (sum B^T W B + Omega)(1 + lambda
+// on the diagonal), its FP64 inverse, g_X = sum B^T W v + Omega (X - Xbar),
+// and the cost before the step.  Packs (X, V*^-1, g_X) for the Schur pass.
+__global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
+  __shared__ double sh[8];
+  __shared__ int l_first;
+  int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (threadIdx.x == 0) {
+    l_first = d.copy_blk[blockIdx.x * (int64_t)NT];
+    for (int q = 0; q < 8; ++q) sh[q] = 0.0;
+  }
+  __syncthreads();
+  if (c < d.NC) {
+    int l = d.copy_blk[c];
+    bool act = d.active == nullptr || d.active[l];
+    double* pk = d.cpk + 12 * c;
+    if (act && d.status[d.copy_pt[c]] == 0) {
+      double X[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
+      const double* om = d.Om + 6 * c;
+      int p = d.copy_pt[c];
+      double dx[3] = {X[0] - d.Xbar[p], X[1] - d.Xbar[(int64_t)d.N + p], X[2] - d.Xbar[2 * (int64_t)d.N + p]};
+      double h[6], g[3];
+      for (int q = 0; q < 6; ++q) h[q] = om[q];
+      sym3_mul(om, dx, g);
+      double cost = dx[0] * g[0] + dx[1] * g[1] + dx[2] * g[2];
+      for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
+        const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
+        Lin<double> L;
+        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+        double v0 = L.g0 - d.xy[2 * k], v1 = L.g1 - d.xy[2 * k + 1];
+        W2<double> W = obs_weight(d, k);
+        add_point_normals<double>(L, W, v0, v1, h, g);
+        cost += wquad(W, v0, v1);
+      }
+      h[0] *= 1.0 + d.lambda;
+      h[3] *= 1.0 + d.lambda;
+      h[5] *= 1.0 + d.lambda;
+      double lch[6], inv[6];
+      bool ok = chol3(h, lch);
+      if (ok) chol3_inverse(lch, inv);
+      else
+        for (int q = 0; q < 6; ++q) inv[q] = 0.0;
+      pk[0] = X[0];
+      pk[1] = X[1];
+      pk[2] = X[2];
+      for (int q = 0; q < 6; ++q) pk[3 + q] = inv[q];
+      for (int q = 0; q < 3; ++q) pk[9 + q] = ok ? g[q] : 0.0;
+      int slot = l - l_first;
+      if (slot >= 0 && slot < 8) atomicAdd(&sh[slot], cost);
+      else atomicAdd(&d.acc_blk[4 * l + 0], cost);
+    } else {
+      for (int q = 0; q < 12; ++q) pk[q] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && sh[threadIdx.x] != 0.0 && l_first + (int)threadIdx.x < d.L)
+    atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 0], sh[threadIdx.x]);
+}
+
+// One workgroup per camera i (internal order): row block i of the reduced
+// camera system of its sub-block,
+//   S_(i,i2) = [i == i2] U*_i - sum_copies sum_(k1 in i, k2 in i2) Y_k1 V*^-1 Y_k2^T
+//   e_i      = -g_Ci + sum_(k1 in i) Y_k1 V*^-1 g_X,
+// accumulated as outer products straight into the row (Sec. 5.4).  Only
+// cameras i2 <= i (local index) are formed; neighbours are held in LDS slots.
+__global__ __launch_bounds__(NT) void k_schur_rows(Dev d) {
+  extern __shared__ double smem[];
+  const int i = blockIdx.x;
+  const int l = d.cam_blk[i];
+  if (d.active && !d.active[l]) return;
+  const int base = d.blk_cam_off[l];
+  const int ncam = d.blk_cam_off[l + 1] - base;
+  const int a = i - base;
+  const int nb0 = d.nb_off[i], nnb = d.nb_off[i + 1] - nb0;
+  double* acc = smem;                               // [nnb][36]
+  double* red = smem + (size_t)nnb * 36;            // [33][4]
+  int* slot = (int*)(red + 33 * 4);                 // [ncam]
+  for (int t = threadIdx.x; t < nnb * 36; t += NT) acc[t] = 0.0;
+  for (int t = threadIdx.x; t < ncam; t += NT) slot[t] = -1;
+  __syncthreads();
+  for (int t = threadIdx.x; t < nnb; t += NT) slot[d.nb_cam[nb0 + t]] = t;
+  __syncthreads();
+
+  const double* cm1 = d.cam + (int64_t)CAM_STRIDE * i;
+  double R1[9], C1[3];
+  for (int q = 0; q < 9; ++q) R1[q] = cm1[q];
+  for (int q = 0; q < 3; ++q) C1[q] = cm1[9 + q];
+  double U[21], gC[6], ep[6];
+  for (int q = 0; q < 21; ++q) U[q] = 0.0;
+  for (int q = 0; q < 6; ++q) gC[q] = ep[q] = 0.0;
+
+  for (int idx = d.cam_obs_off[i] + threadIdx.x; idx < d.cam_obs_off[i + 1]; idx += NT) {
+    const int k1 = d.cam_obs[idx];
+    const int c = d.obs_copy[k1];
+    if (d.status[d.copy_pt[c]] != 0) continue;
+    const double* pk = d.cpk + 12 * (int64_t)c;
+    double X[3] = {pk[0], pk[1], pk[2]};
+    double Vi[6];
+    for (int q = 0; q < 6; ++q) Vi[q] = pk[3 + q];
+    double gX[3] = {pk[9], pk[10], pk[11]};
+    Lin<double> L1;
+    linearise<double>(R1, C1, X, d.f, d.cx, d.cy, L1);
+    double v0 = L1.g0 - d.xy[2 * k1], v1 = L1.g1 - d.xy[2 * k1 + 1];
+    W2<double> W = obs_weight(d, k1);
+    // A = [Ar | -B]; WA rows
+    double A[2][6], WA[2][6];
+    for (int q = 0; q < 3; ++q) {
+      A[0][q] = L1.Ar[0][q];
+      A[1][q] = L1.Ar[1][q];
+      A[0][3 + q] = -L1.B[0][q];
+      A[1][3 + q] = -L1.B[1][q];
+    }
+    for (int q = 0; q < 6; ++q) {
+      WA[0][q] = W.a * A[0][q] + W.b * A[1][q];
+      WA[1][q] = W.b * A[0][q] + W.c * A[1][q];
+    }
+    double Wv0 = W.a * v0 + W.b * v1, Wv1 = W.b * v0 + W.c * v1;
+    int u = 0;
+    for (int r = 0; r < 6; ++r)
+      for (int s = r; s < 6; ++s) U[u++] += A[0][r] * WA[0][s] + A[1][r] * WA[1][s];
+    for (int r = 0; r < 6; ++r) gC[r] += A[0][r] * Wv0 + A[1][r] * Wv1;
+    // Y1 = A^T W B (6x3), Z1 = Y1 V*^-1
+    double Y1[6][3], Z1[6][3];
+    for (int r = 0; r < 6; ++r)
+      for (int s = 0; s < 3; ++s) Y1[r][s] = WA[0][r] * L1.B[0][s] + WA[1][r] * L1.B[1][s];
+    for (int r = 0; r < 6; ++r) {
+      Z1[r][0] = Y1[r][0] * Vi[0] + Y1[r][1] * Vi[1] + Y1[r][2] * Vi[2];
+      Z1[r][1] = Y1[r][0] * Vi[1] + Y1[r][1] * Vi[3] + Y1[r][2] * Vi[4];
+      Z1[r][2] = Y1[r][0] * Vi[2] + Y1[r][1] * Vi[4] + Y1[r][2] * Vi[5];
+      ep[r] += Z1[r][0] * gX[0] + Z1[r][1] * gX[1] + Z1[r][2] * gX[2];
+    }
+    for (int k2 = d.copy_off[c]; k2 < d.copy_off[c + 1]; ++k2) {
+      const int i2 = d.obs_cam[k2];
+      const int a2 = i2 - base;
+      if (a2 > a) break;  // observations of a copy are ordered by camera
+      double Y2[6][3];
+      if (k2 == k1) {
+        for (int r = 0; r < 6; ++r)
+          for (int s = 0; s < 3; ++s) Y2[r][s] = Y1[r][s];
+      } else {
+        const double* cm2 = d.cam + (int64_t)CAM_STRIDE * i2;
+        Lin<double> L2;
+        linearise<double>(cm2, cm2 + 9, X, d.f, d.cx, d.cy, L2);
+        W2<double> Wb = obs_weight(d, k2);
+        double WB2[2][3];
+        for (int s = 0; s < 3; ++s) {
+          WB2[0][s] = Wb.a * L2.B[0][s] + Wb.b * L2.B[1][s];
+          WB2[1][s] = Wb.b * L2.B[0][s] + Wb.c * L2.B[1][s];
+        }
+        for (int r = 0; r < 3; ++r)
+          for (int s = 0; s < 3; ++s) {
+            Y2[r][s] = L2.Ar[0][r] * WB2[0][s] + L2.Ar[1][r] * WB2[1][s];
+            Y2[3 + r][s] = -(L2.B[0][r] * WB2[0][s] + L2.B[1][r] * WB2[1][s]);
+          }
+      }
+      double* blk = acc + 36 * slot[a2];
+      for (int r = 0; r < 6; ++r)
+        for (int s = 0; s < 6; ++s)
+          atomicAdd(&blk[6 * r + s], -(Z1[r][0] * Y2[s][0] + Z1[r][1] * Y2[s][1] + Z1[r][2] * Y2[s][2]));
+    }
+  }
+  // reduce U (21), gC (6), ep (6) over the workgroup
+  {
+    double v[33];
+    for (int q = 0; q < 21; ++q) v[q] = U[q];
+    for (int q = 0; q < 6; ++q) v[21 + q] = gC[q];
+    for (int q = 0; q < 6; ++q) v[27 + q] = ep[q];
+    for (int q = 0; q < 33; ++q)
+      for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+      for (int q = 0; q < 33; ++q) red[q * 4 + wv] = v[q];
+  }
+  __syncthreads();
+  double* own = acc + 36 * slot[a];
+  if (threadIdx.x < 36) {
+    int r = threadIdx.x / 6, s = threadIdx.x % 6;
+    int rr = r < s ? r : s, ss = r < s ? s : r;
+    int u = rr * 6 - rr * (rr - 1) / 2 + (ss - rr);  // index in the packed upper triangle
+    double uv = red[u * 4] + red[u * 4 + 1] + red[u * 4 + 2] + red[u * 4 + 3];
+    if (r == s) uv = (uv == 0.0) ? 1.0 : uv * (1.0 + d.lambda);
+    own[threadIdx.x] += uv;
+  }
+  const int T = d.T;
+  const int64_t vbase = d.vec_off[l];
+  if (threadIdx.x < 6) {
+    int q = threadIdx.x;
+    double gcq = red[(21 + q) * 4] + red[(21 + q) * 4 + 1] + red[(21 + q) * 4 + 2] + red[(21 + q) * 4 + 3];
+    double epq = red[(27 + q) * 4] + red[(27 + q) * 4 + 1] + red[(27 + q) * 4 + 2] + red[(27 + q) * 4 + 3];
+    d.y[vbase + 6 * a + q] = -gcq + epq;
+  }
+  __syncthreads();
+  // write rows 6a..6a+5, columns c <= row of the dense tiled lower triangle
+  const int64_t sbase = d.rcs_off[l];
+  const int ncols = 6 * a + 6;
+  for (int t = threadIdx.x; t < 6 * ncols; t += NT) {
+    int q = t / ncols, col = t % ncols;
+    int row = 6 * a + q;
+    if (col > row) continue;
+    int b = col / 6;
+    int sl = slot[b];
+    double val = sl >= 0 ? acc[36 * sl + 6 * q + (col % 6)] : 0.0;
+    int tr = row / T, tc = col / T;
+    int64_t off = sbase + ((int64_t)tr * (tr + 1) / 2 + tc) * T * T + (int64_t)(row % T) * T + (col % T);
+    d.S[off] = val;
+  }
+}
+
+// ------------------------------------------------------- update of the step
+// One thread per camera: new pose R <- Exp([w]x) R, C <- C + dc into camN.
+__global__ void k_cam_update(Dev d) {
+  int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= d.M) return;
+  int l = d.cam_blk[i];
+  const double* c = d.cam + (int64_t)CAM_STRIDE * i;
+  double* n = d.camN + (int64_t)CAM_STRIDE * i;
+  bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
+  if (!act) {
+    for (int q = 0; q < 12; ++q) n[q] = c[q];
+    return;
+  }
+  int a = i - d.blk_cam_off[l];
+  const double* dx = d.x + d.vec_off[l] + 6 * a;
+  double w[3] = {dx[0], dx[1], dx[2]};
+  rotate_left(w, c, n);
+  for (int r = 0; r < 3; ++r) n[9 + r] = c[9 + r] + dx[3 + r];
+  double s2 = 0;
+  for (int q = 0; q < 6; ++q) s2 += dx[q] * dx[q];
+  atomicAdd(&d.acc_blk[4 * l + 2], s2);
+}
+
+// One thread per copy: dX = V*^-1 (-g_X - sum_k Y_k^T dC_i(k)) with Y_k at the
+// old cameras, X^l += dX, and the cost after the step at the new cameras.
+__global__ __launch_bounds__(NT) void k_back_update(Dev d) {
+  __shared__ double sh[16];
+  __shared__ int l_first;
+  int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (threadIdx.x == 0) {
+    l_first = d.copy_blk[blockIdx.x * (int64_t)NT];
+    for (int q = 0; q < 16; ++q) sh[q] = 0.0;
+  }
+  __syncthreads();
+  if (c < d.NC) {
+    int l = d.copy_blk[c];
+    bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
+    if (act && d.status[d.copy_pt[c]] == 0) {
+      const double* pk = d.cpk + 12 * c;
+      double X[3] = {pk[0], pk[1], pk[2]};
+      double rhs[3] = {-pk[9], -pk[10], -pk[11]};
+      const int base = d.blk_cam_off[l];
+      const double* xs = d.x + d.vec_off[l];
+      for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
+        int i = d.obs_cam[k];
+        const double* cm = d.cam + (int64_t)CAM_STRIDE * i;
+        Lin<double> L;
+        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+        const double* dC = xs + 6 * (i - base);
+        // t = A dC = Ar w - B dc ; Y^T dC = B^T W t
+        double t0 = L.Ar[0][0] * dC[0] + L.Ar[0][1] * dC[1] + L.Ar[0][2] * dC[2] -
+                    (L.B[0][0] * dC[3] + L.B[0][1] * dC[4] + L.B[0][2] * dC[5]);
+        double t1 = L.Ar[1][0] * dC[0] + L.Ar[1][1] * dC[1] + L.Ar[1][2] * dC[2] -
+                    (L.B[1][0] * dC[3] + L.B[1][1] * dC[4] + L.B[1][2] * dC[5]);
+        W2<double> W = obs_weight(d, k);
+        double wt0 = W.a * t0 + W.b * t1, wt1 = W.b * t0 + W.c * t1;
+        for (int s = 0; s < 3; ++s) rhs[s] -= L.B[0][s] * wt0 + L.B[1][s] * wt1;
+      }
+      double dX[3];
+      sym3_mul(pk + 3, rhs, dX);
+      double Xn[3] = {X[0] + dX[0], X[1] + dX[1], X[2] + dX[2]};
+      d.Xc[3 * c] = Xn[0];
+      d.Xc[3 * c + 1] = Xn[1];
+      d.Xc[3 * c + 2] = Xn[2];
+      int p = d.copy_pt[c];
+      double dx[3] = {Xn[0] - d.Xbar[p], Xn[1] - d.Xbar[(int64_t)d.N + p], Xn[2] - d.Xbar[2 * (int64_t)d.N + p]};
+      double og[3];
+      sym3_mul(d.Om + 6 * c, dx, og);
+      double cost = dx[0] * og[0] + dx[1] * og[1] + dx[2] * og[2];
+      for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
+        const double* cm = d.camN + (int64_t)CAM_STRIDE * d.obs_cam[k];
+        Lin<double> L;
+        linearise<double>(cm, cm + 9, Xn, d.f, d.cx, d.cy, L);
+        cost += wquad(obs_weight(d, k), L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1]);
+      }
+      double s2 = dX[0] * dX[0] + dX[1] * dX[1] + dX[2] * dX[2];
+      int slot = l - l_first;
+      if (slot >= 0 && slot < 8) {
+        atomicAdd(&sh[slot], cost);
+        atomicAdd(&sh[8 + slot], s2);
+      } else {
+        atomicAdd(&d.acc_blk[4 * l + 1], cost);
+        atomicAdd(&d.acc_blk[4 * l + 2], s2);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && l_first + (int)threadIdx.x < d.L) {
+    if (sh[threadIdx.x] != 0.0) atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 1], sh[threadIdx.x]);
+    if (sh[8 + threadIdx.x] != 0.0) atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 2], sh[8 + threadIdx.x]);
+  }
+}
+
+__global__ void k_cam_commit(Dev d) {
+  int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= (int64_t)CAM_STRIDE * d.M) return;
+  d.cam[t] = d.camN[t];
+}
+
+__global__ void k_block_stats(Dev d, double* bs) {
+  int l = blockIdx.x * NT + threadIdx.x;
+  if (l >= d.L) return;
+  bool act = d.active == nullptr || d.active[l];
+  const double* a = d.acc_blk + 4 * l;
+  if (bs) {
+    bs[4 * l + 0] = act ? a[0] : 0.0;
+    bs[4 * l + 1] = act ? (d.blk_fail[l] ? a[0] : a[1]) : 0.0;
+    bs[4 * l + 2] = act ? sqrt(a[2]) : 0.0;
+    bs[4 * l + 3] = act ? (d.blk_fail[l] ? -1.0 : (a[3] > 0 ? a[3] : 1.0)) : 0.0;
+  }
+}
+
+// --------------------------------------------------------------- consensus
+__global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
+  __shared__ double sh[8];
+  int j = blockIdx.x * NT + threadIdx.x;
+  double dmax = 0.0, ntp = 0.0;
+  if (j < d.N) {
+    int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
+    if (c1 - c0 > 1) ntp = 1.0;
+    if (d.status[j] == 0) {
+      double m[3] = {0, 0, 0};
+      for (int cc = c0; cc < c1; ++cc) {
+        const double* x = d.Xc + 3 * (int64_t)d.pt_copies[cc];
+        m[0] += x[0];
+        m[1] += x[1];
+        m[2] += x[2];
+      }
+      double inv = 1.0 / (double)(c1 - c0);
+      for (int r = 0; r < 3; ++r) m[r] *= inv;
+      for (int cc = c0; cc < c1; ++cc) {
+        const double* x = d.Xc + 3 * (int64_t)d.pt_copies[cc];
+        double e0 = x[0] - m[0], e1 = x[1] - m[1], e2 = x[2] - m[2];
+        dmax = fmax(dmax, sqrt(e0 * e0 + e1 * e1 + e2 * e2));
+      }
+      int o = d.pt_orig[j];
+      for (int r = 0; r < 3; ++r) {
+        d.P0[(int64_t)r * d.N + j] = m[r];
+        d.u_pts[(int64_t)r * d.N + o] = m[r];
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dmax = fmax(dmax, __shfl_xor(dmax, o));
+    ntp += __shfl_xor(ntp, o);
+  }
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wv] = dmax;
+    sh[4 + wv] = ntp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(&d.acc_cons[0], fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3])));
+    atomicAdd(&d.acc_cons[1], sh[4] + sh[5] + sh[6] + sh[7]);
+  }
+}
+
+__global__ void k_consensus_cams(Dev d) {
+  int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= d.M) return;
+  int o = d.cam_orig[i];
+  const double* c = d.cam + (int64_t)CAM_STRIDE * i;
+  for (int q = 0; q < 9; ++q) d.u_camR[9 * (int64_t)o + q] = c[q];
+  for (int r = 0; r < 3; ++r) d.u_camC[(int64_t)r * d.M + o] = c[9 + r];
+}
+
+__global__ void k_copy2(const double* src, double* dst, int n) {
+  if (threadIdx.x == 0)
+    for (int q = 0; q < n; ++q) dst[q] = src[q];
+}
+
+// dense copy-out of one sub-block's RCS (row-major n6 x n6 lower) and rhs
+__global__ void k_rcs_extract(Dev d, int l, double* S_out, double* e_out) {
+  int n6 = 6 * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
+  int T = d.T;
+  int64_t tot = (int64_t)n6 * n6;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < tot; t += (int64_t)gridDim.x * NT) {
+    int row = (int)(t / n6), col = (int)(t % n6);
+    double v = 0.0;
+    if (col <= row) {
+      int tr = row / T, tc = col / T;
+      v = d.S[d.rcs_off[l] + ((int64_t)tr * (tr + 1) / 2 + tc) * T * T + (int64_t)(row % T) * T + (col % T)];
+    }
+    S_out[t] = v;
+  }
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n6; t += (int64_t)gridDim.x * NT)
+    e_out[t] = d.y[d.vec_off[l] + t];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+void launch_zero(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n);
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_zero, dim3(g), dim3(NT), 0, st, p, n);
+}
+
+void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n);
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_zero_i32, dim3(g), dim3(NT), 0, st, p, n);
+}
+
+void launch_gather(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_obs, dim3(grid_for(d.K)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_gather_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_gather_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
+}
+
+void launch_init_rcs(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_pad_identity, dim3(d.L), dim3(NT), 0, st, d);
+}
+
+void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
+  launch_zero(d.acc_int, 4, st);
+  hipLaunchKernelGGL(k_intersect, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
+  if (stats) hipLaunchKernelGGL(k_intersect_stats, dim3(1), dim3(64), 0, st, d, stats);
+}
+
+void launch_copy_prep(const Dev& d, hipStream_t st) {
+  launch_zero(d.acc_blk, 4 * (int64_t)d.L, st);
+  launch_zero_i32(d.blk_fail, d.L, st);
+  hipLaunchKernelGGL(k_copy_prep, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+}
+
+void launch_schur_rows(const Dev& d, int max_nb, int max_blk_cams, hipStream_t st) {
+  size_t lds = (size_t)max_nb * 36 * sizeof(double) + 33 * 4 * sizeof(double) + (size_t)max_blk_cams * sizeof(int);
+  hipLaunchKernelGGL(k_schur_rows, dim3(d.M), dim3(NT), lds, st, d);
+}
+
+void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
+  hipLaunchKernelGGL(k_cam_update, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_back_update, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_cam_commit, dim3(grid_for((int64_t)CAM_STRIDE * d.M)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_block_stats, dim3(grid_for(d.L)), dim3(NT), 0, st, d, block_stats);
+}
+
+void launch_consensus(const Dev& d, double* stats, hipStream_t st) {
+  launch_zero(d.acc_cons, 2, st);
+  hipLaunchKernelGGL(k_consensus_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_consensus_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
+  if (stats) hipLaunchKernelGGL(k_copy2, dim3(1), dim3(64), 0, st, (const double*)d.acc_cons, stats, 2);
+}
+
+void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_rcs_extract, dim3(1024), dim3(NT), 0, st, d, l, S_out, e_out);
+}
+
+}  // namespace rpba

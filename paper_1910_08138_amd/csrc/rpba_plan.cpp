@@ -1,0 +1,262 @@
+// Host-side planning of the device data layout.  See rpba_plan.hpp.
+#include "rpba_plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+namespace rpba {
+
+uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
+                      const int32_t* cam_block, int32_t tile) {
+  // FNV-1a over sizes and the three index arrays
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  mix((uint64_t)M);
+  mix((uint64_t)N);
+  mix((uint64_t)K);
+  mix((uint64_t)L);
+  mix((uint64_t)tile);
+  for (int32_t k = 0; k < K; ++k) mix(((uint64_t)(uint32_t)obs_cam[k] << 32) | (uint32_t)obs_pt[k]);
+  for (int32_t i = 0; i < M; ++i) mix((uint64_t)(uint32_t)cam_block[i]);
+  return h;
+}
+
+std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
+                       const int32_t* cam_block, int32_t tile, Plan& P) {
+  if (M <= 0 || N <= 0 || K <= 0 || L <= 0) return "M, N, K and L must be positive";
+  if (M >= (1 << 20)) return "at most 2^20 - 1 cameras";
+  if (N >= (1 << 28)) return "at most 2^28 - 1 points";
+  if (L >= (1 << 15)) return "at most 2^15 - 1 sub-blocks";
+  if (tile != 32 && tile != 64) return "Cholesky tile must be 32 or 64";
+  if (!obs_cam || !obs_pt || !cam_block) return "topology arrays must be non-NULL host pointers";
+  P = Plan();
+  P.M = M;
+  P.N = N;
+  P.K = K;
+  P.L = L;
+  P.T = tile;
+  for (int32_t i = 0; i < M; ++i)
+    if (cam_block[i] < 0 || cam_block[i] >= L) return "cam_block out of range at camera " + std::to_string(i);
+  std::vector<int32_t> ccount(M, 0), pcount(N, 0);
+  for (int32_t k = 0; k < K; ++k) {
+    if (obs_cam[k] < 0 || obs_cam[k] >= M) return "obs_cam out of range at observation " + std::to_string(k);
+    if (obs_pt[k] < 0 || obs_pt[k] >= N) return "obs_pt out of range at observation " + std::to_string(k);
+    ccount[obs_cam[k]]++;
+    pcount[obs_pt[k]]++;
+  }
+  for (int32_t i = 0; i < M; ++i)
+    if (ccount[i] < 1) return "camera " + std::to_string(i) + " has no observation";
+  for (int32_t j = 0; j < N; ++j)
+    if (pcount[j] < 2) return "point " + std::to_string(j) + " has fewer than 2 observations";
+
+  // cameras grouped by sub-block
+  P.blk_cam_off.assign(L + 1, 0);
+  for (int32_t i = 0; i < M; ++i) P.blk_cam_off[cam_block[i] + 1]++;
+  for (int32_t l = 0; l < L; ++l) {
+    if (P.blk_cam_off[l + 1] == 0) return "sub-block " + std::to_string(l) + " has no camera";
+    P.blk_cam_off[l + 1] += P.blk_cam_off[l];
+  }
+  P.cam_orig.resize(M);
+  P.cam_blk.resize(M);
+  std::vector<int32_t> cam_new(M);
+  {
+    std::vector<int32_t> fill(P.blk_cam_off.begin(), P.blk_cam_off.end() - 1);
+    for (int32_t i = 0; i < M; ++i) {
+      int32_t n = fill[cam_block[i]]++;
+      P.cam_orig[n] = i;
+      cam_new[i] = n;
+      P.cam_blk[n] = cam_block[i];
+    }
+  }
+  for (int32_t l = 0; l < L; ++l) P.max_blk_cams = std::max(P.max_blk_cams, P.blk_cam_off[l + 1] - P.blk_cam_off[l]);
+  if (6 * P.max_blk_cams > 255 * tile) return "sub-block too large for the Cholesky tiling";
+
+  // points ordered by their lowest sub-block
+  std::vector<int32_t> owner(N, L);
+  for (int32_t k = 0; k < K; ++k) owner[obs_pt[k]] = std::min(owner[obs_pt[k]], cam_block[obs_cam[k]]);
+  P.pt_orig.resize(N);
+  std::vector<int32_t> pt_new(N);
+  {
+    std::vector<int32_t> cnt(L + 1, 0);
+    for (int32_t j = 0; j < N; ++j) cnt[owner[j] + 1]++;
+    for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
+    for (int32_t j = 0; j < N; ++j) {
+      int32_t n = cnt[owner[j]]++;
+      P.pt_orig[n] = j;
+      pt_new[j] = n;
+    }
+  }
+
+  // observations in (sub-block, point, camera) order
+  std::vector<std::pair<uint64_t, int32_t>> keys(K);
+  for (int32_t k = 0; k < K; ++k) {
+    uint64_t l = (uint64_t)cam_block[obs_cam[k]];
+    keys[k] = {(l << 48) | ((uint64_t)pt_new[obs_pt[k]] << 20) | (uint64_t)cam_new[obs_cam[k]], k};
+  }
+  std::sort(keys.begin(), keys.end());
+  P.obs_orig.resize(K);
+  P.obs_cam.resize(K);
+  P.obs_copy.resize(K);
+  P.copy_off.clear();
+  P.copy_pt.clear();
+  P.copy_blk.clear();
+  P.blk_copy_off.assign(L + 1, 0);
+  for (int32_t k = 0; k < K; ++k) {
+    uint64_t key = keys[k].first;
+    P.obs_orig[k] = keys[k].second;
+    P.obs_cam[k] = (int32_t)(key & ((1u << 20) - 1));
+    int32_t pt = (int32_t)((key >> 20) & ((1u << 28) - 1));
+    int32_t l = (int32_t)(key >> 48);
+    if (k > 0 && (keys[k - 1].first >> 20) == (key >> 20)) {
+      if (P.obs_cam[k - 1] == P.obs_cam[k])
+        return "repeated (camera, point) pair at observation " + std::to_string(keys[k].second);
+    } else {
+      P.copy_off.push_back(k);
+      P.copy_pt.push_back(pt);
+      P.copy_blk.push_back(l);
+      P.blk_copy_off[l + 1]++;
+    }
+    P.obs_copy[k] = (int32_t)P.copy_off.size() - 1;
+  }
+  keys.clear();
+  keys.shrink_to_fit();
+  P.NC = (int64_t)P.copy_pt.size();
+  P.copy_off.push_back(K);
+  for (int32_t l = 0; l < L; ++l) P.blk_copy_off[l + 1] += P.blk_copy_off[l];
+
+  // copies of each point (ascending sub-block because copies are (l, pt) sorted)
+  P.pt_copy_off.assign(N + 1, 0);
+  for (int64_t c = 0; c < P.NC; ++c) P.pt_copy_off[P.copy_pt[c] + 1]++;
+  for (int32_t j = 0; j < N; ++j) P.pt_copy_off[j + 1] += P.pt_copy_off[j];
+  P.pt_copies.resize(P.NC);
+  {
+    std::vector<int32_t> fill(P.pt_copy_off.begin(), P.pt_copy_off.end() - 1);
+    for (int64_t c = 0; c < P.NC; ++c) P.pt_copies[fill[P.copy_pt[c]]++] = (int32_t)c;
+  }
+
+  // observations of each camera (ascending LM index)
+  P.cam_obs_off.assign(M + 1, 0);
+  for (int32_t k = 0; k < K; ++k) P.cam_obs_off[P.obs_cam[k] + 1]++;
+  for (int32_t i = 0; i < M; ++i) {
+    P.max_cam_obs = std::max(P.max_cam_obs, P.cam_obs_off[i + 1]);
+    P.cam_obs_off[i + 1] += P.cam_obs_off[i];
+  }
+  P.cam_obs.resize(K);
+  {
+    std::vector<int32_t> fill(P.cam_obs_off.begin(), P.cam_obs_off.end() - 1);
+    for (int32_t k = 0; k < K; ++k) P.cam_obs[fill[P.obs_cam[k]]++] = k;
+  }
+
+  // neighbour lists: cameras of the same sub-block sharing a point copy, local index <= own
+  std::vector<std::vector<int32_t>> nb(M);
+  for (int32_t i = 0; i < M; ++i) nb[i].push_back(i - P.blk_cam_off[P.cam_blk[i]]);
+  for (int64_t c = 0; c < P.NC; ++c) {
+    int32_t b = P.copy_off[c], e = P.copy_off[c + 1];
+    int32_t base = P.blk_cam_off[P.copy_blk[c]];
+    for (int32_t k1 = b; k1 < e; ++k1)
+      for (int32_t k2 = b; k2 < k1; ++k2) {
+        // obs of a copy are sorted by camera, so obs_cam[k2] < obs_cam[k1]
+        nb[P.obs_cam[k1]].push_back(P.obs_cam[k2] - base);
+      }
+  }
+  P.nb_off.assign(M + 1, 0);
+  for (int32_t i = 0; i < M; ++i) {
+    std::sort(nb[i].begin(), nb[i].end());
+    nb[i].erase(std::unique(nb[i].begin(), nb[i].end()), nb[i].end());
+    P.nb_off[i + 1] = P.nb_off[i] + (int32_t)nb[i].size();
+    P.max_nb = std::max(P.max_nb, (int32_t)nb[i].size());
+  }
+  P.nb_cam.resize(P.nb_off[M]);
+  for (int32_t i = 0; i < M; ++i) std::copy(nb[i].begin(), nb[i].end(), P.nb_cam.begin() + P.nb_off[i]);
+
+  // block-sparse pattern with both triangles (rows by internal camera)
+  {
+    std::vector<std::vector<int32_t>> full(M);
+    for (int32_t i = 0; i < M; ++i) {
+      int32_t base = P.blk_cam_off[P.cam_blk[i]];
+      for (int32_t a2 : nb[i]) {
+        full[i].push_back(a2);
+        int32_t i2 = base + a2;
+        if (i2 != i) full[i2].push_back(i - base);
+      }
+    }
+    P.bsr_row_off.assign(M + 1, 0);
+    for (int32_t i = 0; i < M; ++i) {
+      std::sort(full[i].begin(), full[i].end());
+      P.bsr_row_off[i + 1] = P.bsr_row_off[i] + (int32_t)full[i].size();
+    }
+    P.nbsr = P.bsr_row_off[M];
+    P.bsr_col.resize(P.nbsr);
+    for (int32_t i = 0; i < M; ++i) std::copy(full[i].begin(), full[i].end(), P.bsr_col.begin() + P.bsr_row_off[i]);
+    P.bsr_tr.resize(P.nbsr);
+    for (int32_t i = 0; i < M; ++i) {
+      int32_t base = P.blk_cam_off[P.cam_blk[i]];
+      int32_t ai = i - base;
+      for (int32_t q = P.bsr_row_off[i]; q < P.bsr_row_off[i + 1]; ++q) {
+        int32_t i2 = base + P.bsr_col[q];
+        const int32_t* b = P.bsr_col.data() + P.bsr_row_off[i2];
+        const int32_t* e = P.bsr_col.data() + P.bsr_row_off[i2 + 1];
+        const int32_t* f = std::lower_bound(b, e, ai);
+        P.bsr_tr[q] = (int32_t)(f - P.bsr_col.data());
+      }
+    }
+  }
+
+  // dense tiled reduced camera systems
+  const int64_t T2 = (int64_t)tile * tile;
+  P.nt.resize(L);
+  P.rcs_off.resize(L);
+  P.diag_off.resize(L);
+  P.vec_off.resize(L);
+  P.nt_max = 0;
+  for (int32_t l = 0; l < L; ++l) {
+    int32_t n6 = 6 * (P.blk_cam_off[l + 1] - P.blk_cam_off[l]);
+    int32_t nt = (n6 + tile - 1) / tile;
+    P.nt[l] = nt;
+    P.nt_max = std::max(P.nt_max, nt);
+    P.rcs_off[l] = P.rcs_total;
+    P.rcs_total += (int64_t)nt * (nt + 1) / 2 * T2;
+    P.diag_off[l] = P.diag_total;
+    P.diag_total += (int64_t)nt * T2;
+    P.vec_off[l] = P.vec_total;
+    P.vec_total += (int64_t)nt * tile;
+  }
+  // forward launches: launch k = panel k (items j == k) + trailing updates of
+  // step k-1 outside column k (items k < j <= i)
+  P.fwd_off.assign(P.nt_max + 1, 0);
+  P.fwd_items.clear();
+  for (int32_t k = 0; k < P.nt_max; ++k) {
+    for (int32_t l = 0; l < L; ++l) {
+      int32_t nt = P.nt[l];
+      if (nt <= k) continue;
+      for (int32_t i = k; i < nt; ++i) P.fwd_items.push_back((l << 16) | (i << 8) | k);
+    }
+    if (k > 0)
+      for (int32_t l = 0; l < L; ++l) {
+        int32_t nt = P.nt[l];
+        for (int32_t j = k + 1; j < nt; ++j)
+          for (int32_t i = j; i < nt; ++i) P.fwd_items.push_back((l << 16) | (i << 8) | j);
+      }
+    P.fwd_off[k + 1] = (int64_t)P.fwd_items.size();
+  }
+  // backward launches, step k (descending): items (l, k, j), j <= k
+  P.bwd_off.assign(P.nt_max + 1, 0);
+  P.bwd_items.clear();
+  for (int32_t s = 0; s < P.nt_max; ++s) {
+    int32_t k = P.nt_max - 1 - s;
+    for (int32_t l = 0; l < L; ++l) {
+      if (P.nt[l] <= k) continue;
+      for (int32_t j = 0; j <= k; ++j) P.bwd_items.push_back((l << 16) | (k << 8) | j);
+    }
+    P.bwd_off[s + 1] = (int64_t)P.bwd_items.size();
+  }
+  P.blk_pcg.assign(L, 0);
+  P.key = topology_key(M, N, K, L, obs_cam, obs_pt, cam_block, tile);
+  return "";
+}
+
+}  // namespace rpba

@@ -1,0 +1,74 @@
+// Host-side planning of the device data layout (done once per problem).
+//
+// Orders (paper Sec. 4: every camera belongs to exactly one sub-block; a point
+// may appear in several, as a "copy" per sub-block):
+//   * cameras: grouped by sub-block (stable in the original index);
+//   * points: by the lowest sub-block that sees them, then original index;
+//   * observations ("LM order"): by (sub-block, point, camera), so that every
+//     copy (sub-block, point) is one contiguous run of observations and the
+//     copies of one sub-block are contiguous.
+// The same order serves the intersection (a point visits its copies) and the
+// sub-block step (a sub-block visits its copies).
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace rpba {
+
+struct Plan {
+  int32_t M = 0, N = 0, K = 0, L = 0;
+  int64_t NC = 0;  // copies
+  int32_t T = 64;  // Cholesky tile edge
+  bool has_info = false;
+
+  // permutations (new -> original)
+  std::vector<int32_t> cam_orig, pt_orig, obs_orig;
+  std::vector<int32_t> cam_blk;        // [M] sub-block of internal camera
+  std::vector<int32_t> blk_cam_off;    // [L+1]
+  std::vector<int32_t> obs_cam;        // [K] internal camera of LM-ordered observation
+  std::vector<int32_t> obs_copy;       // [K]
+  std::vector<int32_t> copy_off;       // [NC+1] observation runs
+  std::vector<int32_t> copy_pt;        // [NC] internal point
+  std::vector<int32_t> copy_blk;       // [NC]
+  std::vector<int64_t> blk_copy_off;   // [L+1]
+  std::vector<int32_t> pt_copy_off;    // [N+1]
+  std::vector<int32_t> pt_copies;      // [NC] copy indices grouped by point (ascending sub-block)
+  std::vector<int32_t> cam_obs_off;    // [M+1]
+  std::vector<int32_t> cam_obs;        // [K] LM-ordered observation indices per camera
+  std::vector<int32_t> nb_off;         // [M+1] neighbour lists (cameras of the same
+  std::vector<int32_t> nb_cam;         //        sub-block sharing a point, local index <= own)
+  int32_t max_nb = 0, max_blk_cams = 0, max_cam_obs = 0;
+
+  // dense reduced camera systems (tile-major lower triangle per sub-block)
+  std::vector<int32_t> nt;             // [L] tiles per side
+  std::vector<int64_t> rcs_off;        // [L] offset (doubles) of tile (0,0)
+  std::vector<int64_t> diag_off;       // [L] offset of the nt factor/inverse diagonal tiles
+  std::vector<int64_t> vec_off;        // [L] offset of the padded vectors
+  int64_t rcs_total = 0, diag_total = 0, vec_total = 0;
+  int32_t nt_max = 0;
+  // Cholesky work lists: item = (l << 16) | (i << 8) | j
+  std::vector<int32_t> fwd_items;      // launch k: items [fwd_off[k], fwd_off[k+1])
+  std::vector<int64_t> fwd_off;
+  std::vector<int32_t> bwd_items;      // backward launch for step k (descending)
+  std::vector<int64_t> bwd_off;
+
+  // block-sparse RCS (6x6 blocks, both triangles) for the iterative solver
+  std::vector<int32_t> bsr_row_off;    // [M+1] per internal camera
+  std::vector<int32_t> bsr_col;        // local column camera of each block
+  std::vector<int32_t> bsr_tr;         // index of the transposed block
+  int64_t nbsr = 0;
+  std::vector<uint8_t> blk_pcg;        // [L] 1 = iterative solver for this sub-block
+
+  uint64_t key = 0;
+};
+
+// Returns an empty string on success, else the reason.
+std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
+                       const int32_t* cam_block, int32_t tile, Plan& P);
+
+uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
+                      const int32_t* cam_block, int32_t tile);
+
+}  // namespace rpba

@@ -1,0 +1,189 @@
+"""GPU (librpba through its C ABI) vs the FP64 CPU oracle on the same seeded
+scenes.  FP64 path bar: 1e-9 relative per result (camera centres relative to
+the scene extent, rotations in radians, points, covariances in relative
+Frobenius norm, RMS / sigma0 / per-step costs relative)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_08138_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def rp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_08138_amd import binding
+    binding.load_library()
+    return binding
+
+
+def _sym(c):
+    return np.array([[c[0], c[1], c[2]], [c[1], c[3], c[4]], [c[2], c[4], c[5]]])
+
+
+def _rot_angle(R1, R2):
+    """largest rotation angle between corresponding rows of (M, 9) arrays;
+    |R1 - R2|_F = 2 sqrt(2) sin(theta / 2), accurate for tiny angles (an
+    arccos of the trace would have a 1e-8 rad rounding floor)"""
+    d = np.linalg.norm((R1 - R2).reshape(-1, 9), axis=1)
+    return float(np.max(2 * np.arcsin(np.minimum(d / (2 * np.sqrt(2)), 1.0)))) if len(d) else 0.0
+
+
+def _extent(scene):
+    C = scene.cam_C_true
+    return float(np.linalg.norm(C.max(axis=1) - C.min(axis=1))) + 1.0
+
+
+def _compare_copies(gp, op, tol=TOL):
+    gb, gpt, gX, gom = gp.copies()
+    ob, opt_, oX, oom = op.copies()
+    assert len(gb) == len(ob)
+    o1 = np.lexsort((gpt, gb))
+    o2 = np.lexsort((opt_, ob))
+    assert np.array_equal(gb[o1], ob[o2]) and np.array_equal(gpt[o1], opt_[o2])
+    gX, oX, gom, oom = gX[o1], oX[o2], gom[o1], oom[o2]
+    scale = np.abs(oX).max() + 1.0
+    assert np.abs(gX - oX).max() <= tol * scale
+    onorm = np.abs(oom).max()
+    assert np.abs(gom - oom).max() <= tol * onorm
+
+
+def test_selftest_tile_product_layout(rp):
+    """FP64 matrix-core tile product (the Cholesky building block) = A B^T."""
+    import torch
+    g = torch.Generator().manual_seed(0)
+    A = torch.randn(64, 64, dtype=torch.float64, generator=g)
+    B = torch.randn(64, 64, dtype=torch.float64, generator=g)
+    C = rp.selftest_gemm(A.cuda(), B.cuda()).cpu()
+    ref = A @ B.T
+    assert torch.abs(C - ref).max() <= 1e-13 * torch.abs(ref).max()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_intersection_parity_ring(rp, seed):
+    s = scenes.config_scene(1, seed)
+    gp = rp.Problem(s)
+    op = oracle.OracleProblem(s)
+    gst = gp.rpba_intersect().cpu().numpy()
+    ost = op.intersect()
+    gX, gcov, gstat = gp.intersection()
+    oX, ocov, ostat = op.intersection()
+    assert np.array_equal(gstat, ostat)
+    assert np.abs(gX - oX).max() <= TOL * (np.abs(oX).max() + 1)
+    for j in range(0, s.N, 13):
+        a, b = _sym(gcov[:, j]), _sym(ocov[:, j])
+        assert np.linalg.norm(a - b) <= TOL * np.linalg.norm(b)
+    assert np.allclose(gst, ost, rtol=TOL, atol=0)
+    _compare_copies(gp, op)
+
+
+def _scene(name, seed):
+    if name == "ring":
+        return scenes.config_scene(1, seed)
+    if name == "aerial-small":
+        return scenes.config_scene(2, seed, small=True)
+    if name == "oblique-small":
+        return scenes.config_scene(3, seed, small=True)
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("name", ["ring", "aerial-small", "oblique-small"])
+@pytest.mark.parametrize("tile", [64, 32])
+def test_reduced_camera_system_parity(rp, name, tile):
+    """The assembled RCS S and right-hand side e of every sub-block."""
+    s = _scene(name, 3)
+    gp = rp.Problem(s, chol_tile=tile)
+    op = oracle.OracleProblem(s)
+    gp.rpba_intersect()
+    op.intersect()
+    # one step so that copies differ from Xbar (non-zero prior gradient)
+    gp.rpba_subblock_lm_step()
+    op.lm_step()
+    for l in range(s.L):
+        Sg, eg = gp.block_rcs(l)
+        So, eo = op.block_rcs(l, Sg.shape[0])
+        lo = np.tril(So)
+        assert np.abs(np.tril(Sg) - lo).max() <= TOL * np.abs(lo).max(), l
+        assert np.abs(eg - eo).max() <= TOL * np.abs(eo).max(), l
+
+
+def _run_both(s, T, I, **opts):
+    gp, gh = rp_run(s, T, I, **opts)
+    op, oh = oracle.run_schedule(s, T=T, I=I)
+    return gp, gh, op, oh
+
+
+def rp_run(s, T, I, **opts):
+    from paper_1910_08138_amd import binding
+    return binding.run_schedule(s, T=T, I=I, **opts)
+
+
+@pytest.mark.parametrize("name,T,I", [("ring", 6, 4), ("aerial-small", 3, 2), ("oblique-small", 2, 2)])
+def test_fixed_schedule_parity(rp, name, T, I):
+    """Whole fixed schedule (intersection, LM steps, consensus) vs the oracle."""
+    s = _scene(name, 5)
+    gp, gh, op, oh = _run_both(s, T, I)
+    for g, o in zip(gh, oh):
+        assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0), (g["t"], g["int_stats"], o["int_stats"])
+        for bg, (bo, fails) in zip(g.get("steps", []), o.get("steps", [])):
+            assert fails == 0
+            assert np.allclose(bg[:, 0], bo[:, 0], rtol=TOL, atol=0)
+            assert np.allclose(bg[:, 1], bo[:, 1], rtol=TOL, atol=0)
+            assert np.allclose(bg[:, 2], bo[:, 2], rtol=1e-7, atol=1e-12)
+        if "consensus" in g:
+            assert g["consensus"][1] == o["consensus"][1]
+            assert abs(g["consensus"][0] - o["consensus"][0]) <= TOL * _extent(s)
+    gR, gC = gp.cameras()
+    oR, oC = op.cameras()
+    assert np.abs(gC - oC).max() <= TOL * _extent(s)
+    assert _rot_angle(gR, oR) <= TOL
+    gX, gcov, gst = gp.intersection()
+    oX, ocov, ost = op.intersection()
+    assert np.array_equal(gst, ost)
+    assert np.abs(gX - oX).max() <= TOL * _extent(s)
+
+
+def test_active_mask_skips_subblocks(rp):
+    import torch
+    s = _scene("aerial-small", 7)
+    gp = rp.Problem(s)
+    op = oracle.OracleProblem(s)
+    gp.rpba_intersect()
+    op.intersect()
+    act = np.zeros(s.L, dtype=np.uint8)
+    act[1] = 1
+    act[3] = 1
+    bg = gp.rpba_subblock_lm_step(torch.as_tensor(act).cuda()).cpu().numpy()
+    bo, _ = op.lm_step(act)
+    assert np.allclose(bg, bo, rtol=1e-7, atol=0)
+    gR, gC = gp.cameras()
+    oR, oC = op.cameras()
+    # the GPU writes cameras back at consensus
+    gp.rpba_consensus()
+    op.consensus()
+    gR, gC = gp.cameras()
+    oR, oC = op.cameras()
+    assert np.abs(gC - oC).max() <= TOL * _extent(s)
+    inactive = np.nonzero(act[s.cam_block] == 0)[0]
+    assert np.array_equal(gC[:, inactive], s.cam_C[:, inactive])
+
+
+def test_single_camera_and_single_subblock_edges(rp):
+    """Ragged extremes: one sub-block (no tie points) and a one-camera sub-block."""
+    s = scenes.ring_scene(2, n_pts=300, n_blocks=1)
+    gp, gh, op, oh = _run_both(s, 2, 2)
+    assert np.allclose(gh[-1]["int_stats"], oh[-1]["int_stats"], rtol=TOL, atol=0)
+    s2 = scenes.ring_scene(3, n_pts=400)
+    blk = np.zeros(20, dtype=np.int32)
+    blk[7] = 1                                   # sub-block 1 = one camera
+    blk[10:] = 2
+    s2.cam_block = blk
+    gp, gh, op, oh = _run_both(s2, 2, 2)
+    for g, o in zip(gh, oh):
+        assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0)

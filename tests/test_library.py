@@ -1,0 +1,100 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol that
+include/rpba.h declares, and its host-side validation (rpba_workspace_size
+plans without touching the GPU) rejects malformed problems."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_08138_amd import binding, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rpba.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpba_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.load_library()
+    names = _declared()
+    assert "rpba_intersect" in names and "rpba_subblock_lm_step" in names and "rpba_consensus" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(binding.EXPORTS) == names
+
+
+def _desc(s):
+    d = binding.ProblemDesc()
+    d.M, d.N, d.K, d.L = s.M, s.N, s.K, s.L
+    d.f, d.cx, d.cy, d.sigma_px = s.f, s.cx, s.cy, s.sigma_px
+    fake = ctypes.c_void_p(256)     # never dereferenced by the planner
+    d.cam_R = d.cam_C = d.pts = d.obs_xy = fake.value
+    keep = [np.ascontiguousarray(s.obs_cam, np.int32), np.ascontiguousarray(s.obs_pt, np.int32),
+            np.ascontiguousarray(s.cam_block, np.int32)]
+    d.obs_cam, d.obs_pt, d.cam_block = (a.ctypes.data for a in keep)
+    return d, keep
+
+
+def _size(s, **kw):
+    L = binding.load_library()
+    d, keep = _desc(s)
+    o = binding.default_options(**kw)
+    n = ctypes.c_size_t(0)
+    rc = L.rpba_workspace_size(ctypes.byref(d), ctypes.byref(o), ctypes.byref(n))
+    return rc, n.value, L.rpba_last_error().decode()
+
+
+def test_workspace_size_for_valid_scene():
+    s = scenes.config_scene(1, 0)
+    rc, n, msg = _size(s)
+    assert rc == 0, msg
+    assert n > s.K * 16
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda s: s.obs_cam.__setitem__(0, s.M), "obs_cam out of range"),
+    (lambda s: s.obs_pt.__setitem__(3, -1), "obs_pt out of range"),
+    (lambda s: s.cam_block.__setitem__(0, -1), "cam_block out of range"),
+])
+def test_validation_rejects_bad_indices(mutate, needle):
+    s = scenes.config_scene(1, 0)
+    s.obs_cam = s.obs_cam.copy()
+    s.obs_pt = s.obs_pt.copy()
+    s.cam_block = s.cam_block.copy()
+    mutate(s)
+    rc, _, msg = _size(s)
+    assert rc == 1 and needle in msg
+
+
+def test_validation_rejects_single_view_point_and_repeated_pair():
+    s = scenes.config_scene(1, 0)
+    keep = s.obs_pt != 5
+    first = np.nonzero(s.obs_pt == 5)[0][0]
+    keep[first] = True                       # point 5 keeps one observation
+    s1 = scenes.Scene(**{k: getattr(s, k) for k in s.__dataclass_fields__})
+    s1.obs_xy, s1.obs_cam, s1.obs_pt = s.obs_xy[:, keep], s.obs_cam[keep], s.obs_pt[keep]
+    rc, _, msg = _size(s1)
+    assert rc == 1 and "fewer than 2" in msg
+    s2 = scenes.Scene(**{k: getattr(s, k) for k in s.__dataclass_fields__})
+    s2.obs_cam = s.obs_cam.copy()
+    j = s.obs_pt[0]
+    idx = np.nonzero(s.obs_pt == j)[0]
+    s2.obs_cam[idx[1]] = s2.obs_cam[idx[0]]
+    rc, _, msg = _size(s2)
+    assert rc == 1 and "repeated" in msg
+
+
+def test_validation_rejects_empty_subblock_and_bad_tile():
+    s = scenes.config_scene(1, 0)
+    s.cam_block = np.zeros(s.M, dtype=np.int32)
+    s.cam_block[10:] = 2                     # sub-block 1 empty (L = 3)
+    rc, _, msg = _size(s)
+    assert rc == 1 and "no camera" in msg
+    s = scenes.config_scene(1, 0)
+    rc, _, msg = _size(s, chol_tile=48)
+    assert rc == 1 and "chol_tile" in msg
