@@ -181,6 +181,21 @@ rpba_status rpba_set_debug(rpba_problem *h, int32_t on);
 rpba_status rpba_get_block_rcs(rpba_problem *h, int32_t l, double *S, double *e);
 int32_t rpba_block_cameras(rpba_problem *h, int32_t l);
 
+/* ---------------------------------------------------------------- execution
+ * rpba_set_graph: when on, each of rpba_intersect, rpba_subblock_lm_step and
+ *   rpba_consensus is captured into a HIP graph on its first call and replayed
+ *   on later calls with the same pointer arguments (re-captured when they
+ *   change).  The stream given at creation must then not be the NULL stream.
+ * rpba_set_timing: when on (graphs are bypassed), every phase is bracketed by
+ *   HIP events on the handle's stream and the call synchronises; counters are
+ *   reset.  rpba_get_timing copies (HOST) per-phase milliseconds, kernel
+ *   launches and calls for phases 0..n-1: intersection, point blocks, Schur
+ *   rows, Cholesky forward, Cholesky backward, update, consensus, robust,
+ *   iterative solver; returns the number of phases. */
+rpba_status rpba_set_graph(rpba_problem *h, int32_t on);
+rpba_status rpba_set_timing(rpba_problem *h, int32_t on);
+int32_t rpba_get_timing(rpba_problem *h, double *ms, int64_t *launches, int64_t *calls, int32_t n);
+
 /* Self-test of the FP64 matrix-core tile product used by the Cholesky:
  * C = A B^T for 64 x 64 row-major device tiles, one workgroup on `stream`. */
 rpba_status rpba_selftest_gemm(const double *A, const double *B, double *C, void *stream);

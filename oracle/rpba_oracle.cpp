@@ -51,7 +51,6 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
-#include <map>
 #include <vector>
 
 #ifdef _OPENMP
@@ -630,23 +629,32 @@ orc_problem* orc_create(int M, int N, int K, int L, double f, double cx, double 
   }
   P.pt_obs.assign(N, {});
   for (int k = 0; k < K; ++k) P.pt_obs[P.opt[k]].push_back(k);
-  // copies: one per (sub-block, point) pair, sorted by (sub-block, point)
-  std::map<std::pair<int, int>, std::vector<int>> cm;
-  for (int k = 0; k < K; ++k) cm[{P.cblk[P.ocam[k]], P.opt[k]}].push_back(k);
+  // copies: one per (sub-block, point) pair, sorted by (sub-block, point);
+  // the observations of a copy sorted by camera
+  std::vector<int> ord(K);
+  for (int k = 0; k < K; ++k) ord[k] = k;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+    int la = P.cblk[P.ocam[a]], lb = P.cblk[P.ocam[b]];
+    if (la != lb) return la < lb;
+    if (P.opt[a] != P.opt[b]) return P.opt[a] < P.opt[b];
+    if (P.ocam[a] != P.ocam[b]) return P.ocam[a] < P.ocam[b];
+    return a < b;
+  });
   P.blk_copies.assign(L, {});
   P.pt_copies.assign(N, {});
-  for (auto& kv : cm) {
+  for (int q = 0; q < K;) {
+    int k0 = ord[q];
+    int l = P.cblk[P.ocam[k0]], j = P.opt[k0];
     Copy c;
-    c.blk = kv.first.first;
-    c.pt = kv.first.second;
-    c.obs = kv.second;
-    std::sort(c.obs.begin(), c.obs.end(), [&](int a, int b) { return P.ocam[a] < P.ocam[b] || (P.ocam[a] == P.ocam[b] && a < b); });
+    c.blk = l;
+    c.pt = j;
+    while (q < K && P.cblk[P.ocam[ord[q]]] == l && P.opt[ord[q]] == j) c.obs.push_back(ord[q++]);
     for (int r = 0; r < 3; ++r) c.X[r] = P.X[3 * c.pt + r];
     std::memset(c.Om, 0, sizeof(c.Om));
     int id = (int)P.copies.size();
     P.copies.push_back(std::move(c));
-    P.blk_copies[kv.first.first].push_back(id);
-    P.pt_copies[kv.first.second].push_back(id);
+    P.blk_copies[l].push_back(id);
+    P.pt_copies[j].push_back(id);
   }
   return h;
 }

@@ -25,7 +25,10 @@ EXPORTS = [
     "rpba_default_options", "rpba_workspace_size", "rpba_create", "rpba_intersect", "rpba_robust_reweight",
     "rpba_subblock_lm_step", "rpba_consensus", "rpba_destroy", "rpba_last_error", "rpba_num_copies",
     "rpba_get_copies", "rpba_set_debug", "rpba_get_block_rcs", "rpba_block_cameras", "rpba_selftest_gemm",
+    "rpba_set_graph", "rpba_set_timing", "rpba_get_timing",
 ]
+PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
+          "robust", "iterative_solve"]
 
 
 class RpbaError(RuntimeError):
@@ -84,8 +87,12 @@ def load_library(path: str = LIB_PATH):
     L.rpba_block_cameras.restype = i32
     L.rpba_block_cameras.argtypes = [vp, i32]
     L.rpba_selftest_gemm.argtypes = [dp, dp, dp, vp]
+    L.rpba_set_graph.argtypes = [vp, i32]
+    L.rpba_set_timing.argtypes = [vp, i32]
+    L.rpba_get_timing.restype = i32
+    L.rpba_get_timing.argtypes = [vp, vp, vp, vp, i32]
     for name in EXPORTS:
-        if name not in ("rpba_last_error", "rpba_num_copies", "rpba_block_cameras"):
+        if name not in ("rpba_last_error", "rpba_num_copies", "rpba_block_cameras", "rpba_get_timing"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -155,7 +162,8 @@ class Problem:
         _check(L.rpba_workspace_size(ctypes.byref(d), ctypes.byref(self.opt), ctypes.byref(nbytes)), "rpba_workspace_size")
         self.ws_bytes = nbytes.value
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
-        self.stream = torch.cuda.current_stream(dev)
+        # a dedicated stream: graph capture is not possible on the NULL stream
+        self.stream = torch.cuda.Stream(dev)
         h = ctypes.c_void_p(0)
         _check(L.rpba_create(ctypes.byref(d), ctypes.byref(self.opt), ctypes.c_void_p(self.workspace.data_ptr()),
                              self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "rpba_create")
@@ -178,21 +186,47 @@ class Problem:
         except Exception:
             pass
 
-    # --- the method's calls (asynchronous; stats stay on the device) ---
+    def sync(self):
+        self.stream.synchronize()
+
+    def set_graph(self, on=True):
+        _check(self.L_.rpba_set_graph(self.h, int(on)), "rpba_set_graph")
+
+    def set_timing(self, on=True):
+        _check(self.L_.rpba_set_timing(self.h, int(on)), "rpba_set_timing")
+
+    def timing(self):
+        n = len(PHASES)
+        ms = np.zeros(n)
+        la = np.zeros(n, dtype=np.int64)
+        ca = np.zeros(n, dtype=np.int64)
+        self.L_.rpba_get_timing(self.h, ms.ctypes.data, la.ctypes.data, ca.ctypes.data, n)
+        return {PHASES[q]: dict(ms=float(ms[q]), launches=int(la[q]), calls=int(ca[q])) for q in range(n)}
+
+    # --- the method's calls (asynchronous on self.stream; stats stay on the device) ---
+    def _order(self):
+        # work queued by torch on the caller's stream (e.g. an `active` mask
+        # copy) must land before the library's kernels read it
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.dev))
+
     def rpba_intersect(self, cov=True, status=True):
+        self._order()
         _check(self.L_.rpba_intersect(self.h, _ptr(self.cov) if cov else None, _ptr(self.status) if status else None,
                                       _ptr(self.int_stats)), "rpba_intersect")
         return self.int_stats
 
     def rpba_robust_reweight(self, eliminate=False):
+        self._order()
         _check(self.L_.rpba_robust_reweight(self.h, int(eliminate), _ptr(self.rob_stats)), "rpba_robust_reweight")
         return self.rob_stats
 
     def rpba_subblock_lm_step(self, active=None):
+        self._order()
         _check(self.L_.rpba_subblock_lm_step(self.h, _ptr(active), _ptr(self.block_stats)), "rpba_subblock_lm_step")
         return self.block_stats
 
     def rpba_consensus(self):
+        self._order()
         _check(self.L_.rpba_consensus(self.h, _ptr(self.cons_stats)), "rpba_consensus")
         return self.cons_stats
 
@@ -230,27 +264,34 @@ class Problem:
         return self.pts.cpu().numpy(), self.cov.cpu().numpy(), self.status.cpu().numpy()
 
 
-def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, **opts):
+def _host(p, t):
+    p.sync()
+    return t.cpu().numpy().copy()
+
+
+def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, graph=False, **opts):
     """Fixed schedule on the GPU: T outer iterations of (intersect [, robust,
     re-intersect], I LM steps, consensus), then a final intersection."""
     p = Problem(scene, **opts)
+    if graph:
+        p.set_graph(True)
     hist = []
     for t in range(T):
-        st = p.rpba_intersect().cpu().numpy().copy()
+        st = _host(p, p.rpba_intersect())
         if robust and t >= t_r:
             p.rpba_robust_reweight(False)
-            st = p.rpba_intersect().cpu().numpy().copy()
+            st = _host(p, p.rpba_intersect())
         rec = dict(t=t, int_stats=st, steps=[])
         for s in range(I):
-            bs = p.rpba_subblock_lm_step().cpu().numpy().copy()
+            bs = _host(p, p.rpba_subblock_lm_step())
             rec["steps"].append(bs)
-        rec["consensus"] = p.rpba_consensus().cpu().numpy().copy()
+        rec["consensus"] = _host(p, p.rpba_consensus())
         hist.append(rec)
         if callback:
             callback(p, rec)
     if robust:
         p.rpba_intersect()
         p.rpba_robust_reweight(True)
-    final = p.rpba_intersect().cpu().numpy().copy()
+    final = _host(p, p.rpba_intersect())
     hist.append(dict(t=T, int_stats=final))
     return p, hist

@@ -148,6 +148,21 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
 
 }  // namespace
 
+// A captured call, replayed while its pointer arguments stay the same.
+struct CallGraph {
+  hipGraphExec_t exec = nullptr;
+  const void* args[3] = {nullptr, nullptr, nullptr};
+  bool valid = false;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    valid = false;
+  }
+};
+
+enum Phase { PH_INTERSECT = 0, PH_COPY_PREP, PH_SCHUR, PH_CHOL_FWD, PH_CHOL_BWD, PH_UPDATE, PH_CONSENSUS, PH_ROBUST,
+             PH_SOLVE_IT, NPHASE };
+
 struct rpba_problem {
   std::shared_ptr<Plan> plan;
   WsMap map;
@@ -157,7 +172,80 @@ struct rpba_problem {
   char* ws;
   size_t max_lds_schur;
   bool intersected = false;
+  bool use_graph = false;
+  CallGraph g_int, g_step, g_cons;
+  bool timing = false;
+  hipEvent_t ev[NPHASE + 1] = {};
+  double ms[NPHASE] = {};
+  int64_t launches[NPHASE] = {};
+  int64_t calls[NPHASE] = {};
+  ~rpba_problem() {
+    g_int.reset();
+    g_step.reset();
+    g_cons.reset();
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
+
+namespace {
+
+// Runs `body` on the handle's stream: eagerly, or through a graph captured on
+// the first call with these pointer arguments and replayed afterwards.
+template <typename F>
+rpba_status run_call(rpba_problem* h, CallGraph& g, const void* a0, const void* a1, const void* a2, F body) {
+  if (!h->use_graph || h->timing) {
+    rpba_status s = body();
+    if (s != RPBA_OK) return s;
+    HIP_TRY(hipGetLastError());
+    return RPBA_OK;
+  }
+  if (!(g.valid && g.args[0] == a0 && g.args[1] == a1 && g.args[2] == a2)) {
+    g.reset();
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    rpba_status s = body();
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (s != RPBA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(RPBA_ERR_HIP, std::string("stream capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(RPBA_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    g.args[0] = a0;
+    g.args[1] = a1;
+    g.args[2] = a2;
+    g.valid = true;
+  }
+  HIP_TRY(hipGraphLaunch(g.exec, h->stream));
+  return RPBA_OK;
+}
+
+// event-timed phase (timing mode only)
+struct PhaseTimer {
+  rpba_problem* h;
+  int ph;
+  PhaseTimer(rpba_problem* h_, int ph_, int64_t nlaunch) : h(h_), ph(ph_) {
+    if (h->timing) {
+      (void)hipEventRecord(h->ev[0], h->stream);
+      h->launches[ph] += nlaunch;
+      h->calls[ph] += 1;
+    }
+  }
+  ~PhaseTimer() {
+    if (h->timing) {
+      (void)hipEventRecord(h->ev[1], h->stream);
+      (void)hipEventSynchronize(h->ev[1]);
+      float t = 0;
+      (void)hipEventElapsedTime(&t, h->ev[0], h->ev[1]);
+      h->ms[ph] += t;
+    }
+  }
+};
+
+}  // namespace
 
 extern "C" {
 
@@ -340,16 +428,26 @@ rpba_status rpba_destroy(rpba_problem* h) {
 
 rpba_status rpba_intersect(rpba_problem* h, double* cov, int32_t* status, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
-  launch_intersect(h->d, cov, status, stats, h->stream);
-  HIP_TRY(hipGetLastError());
+  rpba_status s = run_call(h, h->g_int, cov, status, stats, [&]() -> rpba_status {
+    PhaseTimer t(h, PH_INTERSECT, stats ? 3 : 2);
+    launch_intersect(h->d, cov, status, stats, h->stream);
+    return RPBA_OK;
+  });
+  if (s != RPBA_OK) return s;
   h->intersected = true;
   return RPBA_OK;
 }
 
 static rpba_status assemble(rpba_problem* h, const uint8_t* active) {
   h->d.active = active;
-  launch_copy_prep(h->d, h->stream);
-  launch_schur_rows(h->d, h->plan->max_nb, h->plan->max_blk_cams, h->stream);
+  {
+    PhaseTimer t(h, PH_COPY_PREP, 3);
+    launch_copy_prep(h->d, h->stream);
+  }
+  {
+    PhaseTimer t(h, PH_SCHUR, 1);
+    launch_schur_rows(h->d, h->plan->max_nb, h->plan->max_blk_cams, h->stream);
+  }
   HIP_TRY(hipGetLastError());
   return RPBA_OK;
 }
@@ -358,25 +456,74 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run before the first LM step");
   const Plan& p = *h->plan;
-  rpba_status s = assemble(h, active);
-  if (s != RPBA_OK) return s;
-  const int32_t* fwd = (const int32_t*)(h->ws + h->map.fwd_items);
-  const int32_t* bwd = (const int32_t*)(h->ws + h->map.bwd_items);
-  for (int k = 0; k < p.nt_max; ++k)
-    launch_chol_forward(h->d, k, fwd + p.fwd_off[k], p.fwd_off[k + 1] - p.fwd_off[k], h->stream);
-  for (int s2 = 0; s2 < p.nt_max; ++s2)
-    launch_chol_backward(h->d, bwd + p.bwd_off[s2], p.bwd_off[s2 + 1] - p.bwd_off[s2], h->stream);
-  launch_update(h->d, block_stats, h->stream);
-  HIP_TRY(hipGetLastError());
+  rpba_status s = run_call(h, h->g_step, active, block_stats, nullptr, [&]() -> rpba_status {
+    rpba_status s1 = assemble(h, active);
+    if (s1 != RPBA_OK) return s1;
+    const int32_t* fwd = (const int32_t*)(h->ws + h->map.fwd_items);
+    const int32_t* bwd = (const int32_t*)(h->ws + h->map.bwd_items);
+    {
+      PhaseTimer t(h, PH_CHOL_FWD, p.nt_max);
+      for (int k = 0; k < p.nt_max; ++k)
+        launch_chol_forward(h->d, k, fwd + p.fwd_off[k], p.fwd_off[k + 1] - p.fwd_off[k], h->stream);
+    }
+    {
+      PhaseTimer t(h, PH_CHOL_BWD, p.nt_max);
+      for (int s2 = 0; s2 < p.nt_max; ++s2)
+        launch_chol_backward(h->d, bwd + p.bwd_off[s2], p.bwd_off[s2 + 1] - p.bwd_off[s2], h->stream);
+    }
+    {
+      PhaseTimer t(h, PH_UPDATE, 4);
+      launch_update(h->d, block_stats, h->stream);
+    }
+    return RPBA_OK;
+  });
   h->d.active = nullptr;
-  return RPBA_OK;
+  return s;
 }
 
 rpba_status rpba_consensus(rpba_problem* h, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
-  launch_consensus(h->d, stats, h->stream);
-  HIP_TRY(hipGetLastError());
+  return run_call(h, h->g_cons, stats, nullptr, nullptr, [&]() -> rpba_status {
+    PhaseTimer t(h, PH_CONSENSUS, stats ? 4 : 3);
+    launch_consensus(h->d, stats, h->stream);
+    return RPBA_OK;
+  });
+}
+
+rpba_status rpba_set_graph(rpba_problem* h, int32_t on) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  h->use_graph = on != 0;
+  if (!h->use_graph) {
+    h->g_int.reset();
+    h->g_step.reset();
+    h->g_cons.reset();
+  }
   return RPBA_OK;
+}
+
+rpba_status rpba_set_timing(rpba_problem* h, int32_t on) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  if (on && !h->ev[0]) {
+    HIP_TRY(hipEventCreate(&h->ev[0]));
+    HIP_TRY(hipEventCreate(&h->ev[1]));
+  }
+  h->timing = on != 0;
+  for (int q = 0; q < NPHASE; ++q) {
+    h->ms[q] = 0;
+    h->launches[q] = 0;
+    h->calls[q] = 0;
+  }
+  return RPBA_OK;
+}
+
+int32_t rpba_get_timing(rpba_problem* h, double* ms, int64_t* launches, int64_t* calls, int32_t n) {
+  if (!h) return -1;
+  for (int q = 0; q < NPHASE && q < n; ++q) {
+    if (ms) ms[q] = h->ms[q];
+    if (launches) launches[q] = h->launches[q];
+    if (calls) calls[q] = h->calls[q];
+  }
+  return NPHASE;
 }
 
 rpba_status rpba_robust_reweight(rpba_problem* h, int32_t eliminate, double* stats) {

@@ -394,7 +394,7 @@ def _rig_rotations(tilt_deg=45.0):
 
 def oblique_scene(seed=0, n_strips=12, n_stations=100, H=100.0, along=40.0, across=60.0,
                   n_pts=2_500_000, views=(3, 7), sigma=0.5, n_blocks=64, size_range=(20, 400),
-                  outlier_frac=0.0, draws_per_round=64, max_rounds=12, chunk=250_000,
+                  outlier_frac=0.0, draws_per_round=24, max_rounds=16, chunk=250_000,
                   noise=None) -> Scene:
     geo, nrng, pert, part = _streams(seed)
     rig = _rig_rotations()
@@ -411,10 +411,19 @@ def oblique_scene(seed=0, n_strips=12, n_stations=100, H=100.0, along=40.0, acro
     x_range = (-margin, sx[-1] + margin)
     y_range = (-margin, sy[-1] + margin)
     terrain = Terrain(geo, x_range, y_range)
-    # horizontal reach of an oblique view at the lowest terrain point
-    reach = (H + 10.0) * math.tan(math.radians(45.0) + math.atan(0.5 * IMG_W / F_PX)) + 10.0
-    ra = int(math.ceil(reach / along))
-    rc = int(math.ceil(reach / across))
+    # ground footprints of the rig cameras relative to the station, from the
+    # depth range over the terrain: nadir |dx|, |dy| <= d/2; a 45 degree oblique
+    # with a +-26.57 degree field sees (1/3 .. 3) d along its tilt and
+    # +-sqrt(2) d across it.  Candidate stations per camera are the stations
+    # whose footprint box can contain the point.
+    gx_s = np.linspace(*x_range, 200)
+    gy_s = np.linspace(*y_range, 60)
+    hz = terrain(*np.meshgrid(gx_s, gy_s))
+    dmin = H - hz.max() - 5.0
+    dmax = H - hz.min() + 5.0
+    boxes = [(-0.5 * dmax - 1, 0.5 * dmax + 1, -0.5 * dmax - 1, 0.5 * dmax + 1)]  # (xlo, xhi, ylo, yhi) of point - station
+    near, far, side = dmin / 3.0 - 1, 3.0 * dmax + 1, math.sqrt(2.0) * dmax + 1
+    boxes += [(near, far, -side, side), (-far, -near, -side, side), (-side, side, near, far), (-side, side, -far, -near)]
 
     X_list, obs_pt_l, obs_cam_l = [], [], []
     have = 0
@@ -424,29 +433,51 @@ def oblique_scene(seed=0, n_strips=12, n_stations=100, H=100.0, along=40.0, acro
         y = geo.uniform(*y_range, size=nb)
         Xb = np.stack([x, y, terrain(x, y)], axis=1)
         want = geo.integers(views[0], views[1] + 1, size=nb)
-        ia0 = np.rint(x / along).astype(np.int64)
-        ic0 = np.rint(y / across).astype(np.int64)
+        # per point and rig: station index windows and candidate counts
+        lo_a = np.empty((nb, n_rig), np.int64)
+        lo_c = np.empty((nb, n_rig), np.int64)
+        na_ = np.empty((nb, n_rig), np.int64)
+        nc_ = np.empty((nb, n_rig), np.int64)
+        for r, (xl, xh, yl, yh) in enumerate(boxes):
+            a0 = np.maximum(np.ceil((x - xh) / along), 0).astype(np.int64)
+            a1 = np.minimum(np.floor((x - xl) / along), n_stations - 1).astype(np.int64)
+            c0 = np.maximum(np.ceil((y - yh) / across), 0).astype(np.int64)
+            c1 = np.minimum(np.floor((y - yl) / across), n_strips - 1).astype(np.int64)
+            lo_a[:, r], lo_c[:, r] = a0, c0
+            na_[:, r] = np.maximum(a1 - a0 + 1, 0)
+            nc_[:, r] = np.maximum(c1 - c0 + 1, 0)
+        ncand = na_ * nc_
+        cum = np.cumsum(ncand, axis=1)
+        tot = cum[:, -1]
         chosen = np.full((nb, views[1]), -1, dtype=np.int64)
         nchosen = np.zeros(nb, dtype=np.int64)
-        active = np.arange(nb)
+        active = np.nonzero(tot > 0)[0]
         for _ in range(max_rounds):
             if active.size == 0:
                 break
             na = active.size
             D = draws_per_round
-            da = geo.integers(-ra, ra + 1, size=(na, D))
-            dc = geo.integers(-rc, rc + 1, size=(na, D))
-            rr = geo.integers(0, n_rig, size=(na, D))
-            ia = ia0[active, None] + da
-            ic = ic0[active, None] + dc
-            ok = (ia >= 0) & (ia < n_stations) & (ic >= 0) & (ic < n_strips)
-            cam = np.where(ok, (ic * n_stations + ia) * n_rig + rr, -1)
+            u = (geo.random((na, D)) * tot[active, None]).astype(np.int64)
+            cact = cum[active]
+            rig_id = (u[:, :, None] >= cact[:, None, :]).sum(axis=2)
+            prev_cum = np.where(rig_id > 0, np.take_along_axis(cact, np.maximum(rig_id - 1, 0), axis=1), 0)
+            w = u - prev_cum
+            ncr = np.take_along_axis(nc_[active], rig_id, axis=1)
+            ia = np.take_along_axis(lo_a[active], rig_id, axis=1) + w // ncr
+            ic = np.take_along_axis(lo_c[active], rig_id, axis=1) + w % ncr
+            cam = (ic * n_stations + ia) * n_rig + rig_id
             flat_p = np.repeat(active, D)
             flat_c = cam.ravel()
-            m = flat_c >= 0
             vis = np.zeros(flat_c.shape[0], dtype=bool)
-            u, v, d = render(R[flat_c[m]], C[flat_c[m]], Xb[flat_p[m]])
-            vis[m] = _in_image(u, v, d)
+            dxyz = Xb[flat_p] - C[flat_c]
+            rig_of = rig_id.ravel()
+            for r in range(n_rig):
+                sel = np.nonzero(rig_of == r)[0]
+                pr = dxyz[sel] @ rig[r].T
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    uu = F_PX * pr[:, 0] / pr[:, 2] + CX
+                    vv = F_PX * pr[:, 1] / pr[:, 2] + CY
+                vis[sel] = _in_image(uu, vv, pr[:, 2])
             cam = np.where(vis.reshape(na, D), cam, -1)
             # drop draws that repeat an earlier draw or an already chosen camera
             prev = chosen[active]
@@ -459,14 +490,12 @@ def oblique_scene(seed=0, n_strips=12, n_stations=100, H=100.0, along=40.0, acro
             np.put_along_axis(dup, o, dup_sorted, axis=1)
             newc = np.where(dup[:, prev.shape[1]:], -1, cam)
             # append the new distinct visible cameras in draw order, up to `want`
-            for col in range(D):
-                c = newc[:, col]
-                take = (c >= 0) & (nchosen[active] < want[active])
-                if not take.any():
-                    continue
-                rows = active[take]
-                chosen[rows, nchosen[rows]] = c[take]
-                nchosen[rows] += 1
+            valid = newc >= 0
+            pos = nchosen[active][:, None] + np.cumsum(valid, axis=1) - 1
+            take = valid & (pos < want[active][:, None])
+            rr, cc = np.nonzero(take)
+            chosen[active[rr], pos[rr, cc]] = newc[rr, cc]
+            nchosen[active] = np.minimum(nchosen[active] + valid.sum(axis=1), want[active])
             active = active[nchosen[active] < want[active]]
         good = nchosen >= 2
         good_idx = np.nonzero(good)[0][: n_pts - have]

@@ -70,7 +70,9 @@ def test_intersection_parity_ring(rp, seed):
     s = scenes.config_scene(1, seed)
     gp = rp.Problem(s)
     op = oracle.OracleProblem(s)
-    gst = gp.rpba_intersect().cpu().numpy()
+    gst = gp.rpba_intersect()
+    gp.sync()
+    gst = gst.cpu().numpy()
     ost = op.intersect()
     gX, gcov, gstat = gp.intersection()
     oX, ocov, ostat = op.intersection()
@@ -124,11 +126,13 @@ def rp_run(s, T, I, **opts):
     return binding.run_schedule(s, T=T, I=I, **opts)
 
 
-@pytest.mark.parametrize("name,T,I", [("ring", 6, 4), ("aerial-small", 3, 2), ("oblique-small", 2, 2)])
-def test_fixed_schedule_parity(rp, name, T, I):
-    """Whole fixed schedule (intersection, LM steps, consensus) vs the oracle."""
+@pytest.mark.parametrize("name,T,I,graph", [("ring", 6, 4, False), ("ring", 6, 4, True), ("aerial-small", 3, 2, True),
+                                            ("oblique-small", 2, 2, False)])
+def test_fixed_schedule_parity(rp, name, T, I, graph):
+    """Whole fixed schedule (intersection, LM steps, consensus) vs the oracle,
+    eager and through replayed HIP graphs."""
     s = _scene(name, 5)
-    gp, gh, op, oh = _run_both(s, T, I)
+    gp, gh, op, oh = _run_both(s, T, I, graph=graph)
     for g, o in zip(gh, oh):
         assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0), (g["t"], g["int_stats"], o["int_stats"])
         for bg, (bo, fails) in zip(g.get("steps", []), o.get("steps", [])):
@@ -159,7 +163,9 @@ def test_active_mask_skips_subblocks(rp):
     act = np.zeros(s.L, dtype=np.uint8)
     act[1] = 1
     act[3] = 1
-    bg = gp.rpba_subblock_lm_step(torch.as_tensor(act).cuda()).cpu().numpy()
+    bg = gp.rpba_subblock_lm_step(torch.as_tensor(act).cuda())
+    gp.sync()
+    bg = bg.cpu().numpy()
     bo, _ = op.lm_step(act)
     assert np.allclose(bg, bo, rtol=1e-7, atol=0)
     gR, gC = gp.cameras()
