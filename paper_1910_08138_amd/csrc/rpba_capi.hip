@@ -45,7 +45,7 @@ struct Layout {
 struct WsMap {
   size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
-      bwd_items, blk_fail;
+      bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -78,7 +78,19 @@ WsMap layout_for(const Plan& P) {
   m.vec_off = L.add(i8 * P.L);
   m.fwd_items = L.add(i4 * P.fwd_items.size());
   m.bwd_items = L.add(i4 * P.bwd_items.size());
+  m.upd_items = L.add(i4 * P.upd_items.size());
+  m.pot_items = L.add(i4 * P.pot_items.size());
   m.blk_fail = L.add(i4 * P.L);
+  m.pb_row = L.add(i4 * P.pb_row.size());
+  m.pb_ent_off = L.add(i8 * P.pb_ent_off.size());
+  m.pb_ent = L.add(i4 * P.pb_ent.size());
+  m.od_pb = L.add(i4 * P.od_pb.size());
+  m.pb_bsr = L.add(i4 * P.pb_bsr.size());
+  m.pb_bsr_t = L.add(i4 * P.pb_bsr_t.size());
+  m.blk_pcg = L.add(P.L);
+  m.bsr_row_off = L.add(i4 * P.bsr_row_off.size());
+  m.bsr_col = L.add(i4 * P.bsr_col.size());
+  m.bsr = L.add(4 * 36 * (size_t)P.nbsr);
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -171,6 +183,7 @@ struct rpba_problem {
   hipStream_t stream;
   char* ws;
   size_t max_lds_schur;
+  std::vector<uint8_t> blk_pcg;
   bool intersected = false;
   bool use_graph = false;
   CallGraph g_int, g_step, g_cons;
@@ -293,8 +306,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   if (s != RPBA_OK) return s;
   WsMap m = layout_for(*P);
   if (bytes < m.total) return fail(RPBA_ERR_WORKSPACE, "workspace too small: need " + std::to_string(m.total));
-  size_t lds = (size_t)P->max_nb * 36 * 8 + 33 * 4 * 8 + (size_t)P->max_blk_cams * 4;
-  if (lds > 160 * 1024) return fail(RPBA_ERR_ARG, "a camera has too many neighbours for the LDS row accumulator");
+  size_t lds = 0;
 
   std::unique_ptr<rpba_problem> h(new rpba_problem());
   h->plan = P;
@@ -333,6 +345,18 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.vec_off, p.vec_off.data(), 8 * p.vec_off.size()));
   HIP_TRY(up(m.fwd_items, p.fwd_items.data(), 4 * p.fwd_items.size()));
   HIP_TRY(up(m.bwd_items, p.bwd_items.data(), 4 * p.bwd_items.size()));
+  HIP_TRY(up(m.upd_items, p.upd_items.data(), 4 * p.upd_items.size()));
+  HIP_TRY(up(m.pot_items, p.pot_items.data(), 4 * p.pot_items.size()));
+  HIP_TRY(up(m.pb_row, p.pb_row.data(), 4 * p.pb_row.size()));
+  HIP_TRY(up(m.pb_ent_off, p.pb_ent_off.data(), 8 * p.pb_ent_off.size()));
+  HIP_TRY(up(m.pb_ent, p.pb_ent.data(), 4 * p.pb_ent.size()));
+  HIP_TRY(up(m.od_pb, p.od_pb.data(), 4 * p.od_pb.size()));
+  HIP_TRY(up(m.pb_bsr, p.pb_bsr.data(), 4 * p.pb_bsr.size()));
+  HIP_TRY(up(m.pb_bsr_t, p.pb_bsr_t.data(), 4 * p.pb_bsr_t.size()));
+  HIP_TRY(up(m.bsr_row_off, p.bsr_row_off.data(), 4 * p.bsr_row_off.size()));
+  HIP_TRY(up(m.bsr_col, p.bsr_col.data(), 4 * p.bsr_col.size()));
+  h->blk_pcg.assign(p.L, 0);
+  HIP_TRY(up(m.blk_pcg, h->blk_pcg.data(), p.L));
 
   Dev& D = h->d;
   std::memset(&D, 0, sizeof(D));
@@ -386,6 +410,15 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.cpk = F(m.cpk);
   D.nb_off = I(m.nb_off);
   D.nb_cam = I(m.nb_cam);
+  D.pb_row = I(m.pb_row);
+  D.pb_ent_off = (const int64_t*)(w + m.pb_ent_off);
+  D.pb_ent = I(m.pb_ent);
+  D.od_pb = I(m.od_pb);
+  D.n_od = (int64_t)p.od_pb.size();
+  D.pb_bsr = I(m.pb_bsr);
+  D.pb_bsr_t = I(m.pb_bsr_t);
+  D.blk_pcg = (const uint8_t*)(w + m.blk_pcg);
+  D.bsr = (float*)(w + m.bsr);
   D.S = F(m.S);
   D.Ld = F(m.Ld);
   D.Li = F(m.Li);
@@ -445,8 +478,11 @@ static rpba_status assemble(rpba_problem* h, const uint8_t* active) {
     launch_copy_prep(h->d, h->stream);
   }
   {
-    PhaseTimer t(h, PH_SCHUR, 1);
-    launch_schur_rows(h->d, h->plan->max_nb, h->plan->max_blk_cams, h->stream);
+    const bool fp32 = h->opt.precision == RPBA_MIXED;
+    bool dense = false;
+    for (uint8_t b : h->blk_pcg) dense |= (b == 0);
+    PhaseTimer t(h, PH_SCHUR, (h->d.n_od ? 2 : 1) + (dense ? 2 : 0));
+    launch_schur(h->d, fp32, dense, h->plan->rcs_total, h->stream);
   }
   HIP_TRY(hipGetLastError());
   return RPBA_OK;
@@ -459,15 +495,20 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
   rpba_status s = run_call(h, h->g_step, active, block_stats, nullptr, [&]() -> rpba_status {
     rpba_status s1 = assemble(h, active);
     if (s1 != RPBA_OK) return s1;
+    const int32_t* pot = (const int32_t*)(h->ws + h->map.pot_items);
     const int32_t* fwd = (const int32_t*)(h->ws + h->map.fwd_items);
+    const int32_t* upd = (const int32_t*)(h->ws + h->map.upd_items);
     const int32_t* bwd = (const int32_t*)(h->ws + h->map.bwd_items);
     {
-      PhaseTimer t(h, PH_CHOL_FWD, p.nt_max);
+      PhaseTimer t(h, PH_CHOL_FWD, 3 * p.nt_max);
       for (int k = 0; k < p.nt_max; ++k)
-        launch_chol_forward(h->d, k, fwd + p.fwd_off[k], p.fwd_off[k + 1] - p.fwd_off[k], h->stream);
+        launch_chol_step(h->d, k, pot + p.pot_off[k], p.pot_off[k + 1] - p.pot_off[k], fwd + p.fwd_off[k],
+                         p.fwd_off[k + 1] - p.fwd_off[k], upd + p.upd_off[k], p.upd_off[k + 1] - p.upd_off[k],
+                         h->stream);
     }
     {
-      PhaseTimer t(h, PH_CHOL_BWD, p.nt_max);
+      PhaseTimer t(h, PH_CHOL_BWD, p.nt_max + 1);
+      launch_rhs_extract(h->d, h->stream);
       for (int s2 = 0; s2 < p.nt_max; ++s2)
         launch_chol_backward(h->d, bwd + p.bwd_off[s2], p.bwd_off[s2 + 1] - p.bwd_off[s2], h->stream);
     }

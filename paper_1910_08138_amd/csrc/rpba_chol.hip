@@ -1,21 +1,21 @@
 // Batched tiled Cholesky of the reduced camera systems of all sub-blocks
 // (paper Sec. 2: the RCS is solved by Cholesky factorisation instead of being
-// inverted), with the forward substitution of the right-hand side folded into
-// the factorisation and a tiled backward substitution.
+// inverted), with the forward substitution folded into the factorisation and
+// a tiled backward substitution.
 //
 // Storage per sub-block: the lower triangle of S in T x T tiles (tile (i, j),
-// i >= j, row-major inside, at (i (i + 1) / 2 + j) T^2), padded to nt T with
-// an identity block.  Off-diagonal factor tiles overwrite S in place; the
-// diagonal factor L(k,k) and its inverse go to separate arrays.
+// i >= j, at (i (i + 1) / 2 + j) T^2, in-tile layout mf_idx), padded to nt T
+// with an identity block, followed by one more tile row i = nt whose row 0
+// holds the right-hand side e^T.  Factorising the augmented matrix turns that
+// row into (L^-1 e)^T: the forward substitution comes for free.
 //
-// Right-looking schedule, one launch per panel step k for all sub-blocks at
-// once.  Launch k holds
-//   * panel items (l, i, k), i >= k: apply the step k-1 update to A(k,k) and
-//     A(i,k) in registers, factor A(k,k) in LDS (each item redundantly),
-//     invert it, L(i,k) = A(i,k) L(k,k)^-T as a tile product, and
-//     y_i -= L(i,k) L(k,k)^-1 y_k;
-//   * update items (l, i, j), k < j <= i: A(i,j) -= L(i,k-1) L(j,k-1)^T.
-// Every tile product runs on the FP64 matrix cores (v_mfma_f64_16x16x4).
+// Right-looking schedule, three launches per step k for all sub-blocks:
+//   potrf  (l):          L(k,k) and L(k,k)^-1 of the diagonal tile, one
+//                        workgroup per sub-block, tile held in registers;
+//   trsm   (l, i, k):    L(i,k) = A(i,k) L(k,k)^-T, k < i <= nt;
+//   update (l, i, j):    A(i,j) -= L(i,k) L(j,k)^T, k < j <= i, j < nt.
+// The tile products run on the FP64 matrix cores (v_mfma_f64_16x16x4) with
+// operands read straight from memory in the matrix-core layout.
 // Backward launch k: x_k = L(k,k)^-T z_k, z_j -= L(k,j)^T x_k for j < k.
 #include "rpba_internal.hpp"
 
@@ -48,21 +48,19 @@ __device__ __forceinline__ void acc_rc(int p, int q, int e, int& r, int& c) {
   c = (wv & 1) * (T / 2) + 16 * q + (lane & 15);
 }
 
-// acc += A B^T for T x T tiles in LDS (row stride T + 2)
+// acc += A B^T for T x T tiles stored in the matrix-core layout
 template <int T>
-__device__ __forceinline__ void gemm_nt(const double* __restrict__ A, const double* __restrict__ B, Acc<T>& acc) {
-  constexpr int LD = T + 2;
+__device__ __forceinline__ void gemm_nt_mf(const double* __restrict__ A, const double* __restrict__ B, Acc<T>& acc) {
   constexpr int NB = T / 32;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r0 = (wv >> 1) * (T / 2), c0 = (wv & 1) * (T / 2);
-  const int lr = lane & 15, lk = lane >> 4;
+  const int rb0 = (wv >> 1) * NB, cb0 = (wv & 1) * NB;
 #pragma unroll 4
-  for (int k = 0; k < T; k += 4) {
+  for (int kg = 0; kg < T / 4; ++kg) {
     double a[NB], b[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      a[q] = A[(r0 + 16 * q + lr) * LD + k + lk];
-      b[q] = B[(c0 + 16 * q + lr) * LD + k + lk];
+      a[q] = A[((rb0 + q) * (T / 4) + kg) * 64 + lane];
+      b[q] = B[((cb0 + q) * (T / 4) + kg) * 64 + lane];
     }
 #pragma unroll
     for (int p = 0; p < NB; ++p)
@@ -72,15 +70,128 @@ __device__ __forceinline__ void gemm_nt(const double* __restrict__ A, const doub
 }
 
 template <int T>
-__device__ __forceinline__ void load_tile(const double* __restrict__ g, double* s) {
-  constexpr int LD = T + 2;
-  for (int e = threadIdx.x; e < T * T; e += NT) s[(e / T) * LD + (e % T)] = g[e];
+__device__ __forceinline__ double* tile_ptr(const Dev& d, int l, int i, int j) {
+  return d.S + d.rcs_off[l] + ((int64_t)i * (i + 1) / 2 + j) * (int64_t)T * T;
 }
 
-// s = g - acc (element-wise), g global tile, s LDS
+// Diagonal tile of step k: Cholesky factor and its inverse.  The 256 threads
+// form a 16 x 16 grid, each holding a B x B block (B = T / 16) of the tile in
+// registers; one column (resp. row) is broadcast through LDS per step.
 template <int T>
-__device__ __forceinline__ void store_diff(const double* __restrict__ g, const Acc<T>& acc, double* s) {
-  constexpr int LD = T + 2;
+__global__ __launch_bounds__(NT) void k_chol_potrf(Dev d, int k, const int32_t* __restrict__ items) {
+  constexpr int B = T / 16;
+  __shared__ double Lsh[T][T + 1];
+  __shared__ double rowx[T];
+  __shared__ double piv;
+  __shared__ int fail;
+  const int l = items[blockIdx.x] >> 16;
+  if (d.active && !d.active[l]) return;
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  const double* A = tile_ptr<T>(d, l, k, k);
+  double a[B][B];
+#pragma unroll
+  for (int rr = 0; rr < B; ++rr)
+#pragma unroll
+    for (int ss = 0; ss < B; ++ss) a[rr][ss] = A[mf_idx(T, ti * B + rr, tj * B + ss)];
+  if (threadIdx.x == 0) fail = 0;
+  // right-looking factorisation; per column one pivot broadcast and one
+  // column broadcast through LDS, updates as predicated multiply-adds (no
+  // divergent branches: entries outside the active part are masked to zero
+  // or left untouched by selects)
+  for (int cb = 0; cb < 16; ++cb) {
+#pragma unroll
+    for (int cc = 0; cc < B; ++cc) {
+      const int c = cb * B + cc;
+      if (threadIdx.x == cb * 16 + cb) {
+        double dv = a[cc][cc];
+        if (!(dv > 0.0)) {
+          fail = 1;
+          dv = 1.0;
+        }
+        piv = sqrt(dv);
+      }
+      __syncthreads();
+      const double p = piv;
+      const double ip = 1.0 / p;
+      if (tj == cb) {
+#pragma unroll
+        for (int rr = 0; rr < B; ++rr) {
+          const int r = ti * B + rr;
+          const double v = a[rr][cc];
+          const double nv = r > c ? v * ip : (r == c ? p : v);
+          a[rr][cc] = nv;
+          Lsh[r][c] = nv;
+        }
+      }
+      __syncthreads();
+      double ls[B];
+#pragma unroll
+      for (int ss = 0; ss < B; ++ss) {
+        const int s = tj * B + ss;
+        ls[ss] = s > c ? Lsh[s][c] : 0.0;
+      }
+#pragma unroll
+      for (int rr = 0; rr < B; ++rr) {
+        const int r = ti * B + rr;
+        const double lr = r > c ? Lsh[r][c] : 0.0;
+#pragma unroll
+        for (int ss = 0; ss < B; ++ss) a[rr][ss] -= lr * ls[ss];
+      }
+    }
+  }
+  __syncthreads();
+  // inverse X = L^-1 by a right-looking forward substitution on X = I
+  double x[B][B];
+#pragma unroll
+  for (int rr = 0; rr < B; ++rr)
+#pragma unroll
+    for (int ss = 0; ss < B; ++ss) x[rr][ss] = (ti * B + rr == tj * B + ss) ? 1.0 : 0.0;
+  for (int cb = 0; cb < 16; ++cb) {
+#pragma unroll
+    for (int cc = 0; cc < B; ++cc) {
+      const int c = cb * B + cc;
+      if (ti == cb) {
+        const double inv = 1.0 / Lsh[c][c];
+#pragma unroll
+        for (int ss = 0; ss < B; ++ss) {
+          x[cc][ss] *= inv;
+          rowx[tj * B + ss] = x[cc][ss];
+        }
+      }
+      __syncthreads();
+      double xs[B];
+#pragma unroll
+      for (int ss = 0; ss < B; ++ss) xs[ss] = rowx[tj * B + ss];
+#pragma unroll
+      for (int rr = 0; rr < B; ++rr) {
+        const int r = ti * B + rr;
+        const double lr = r > c ? Lsh[r][c] : 0.0;
+#pragma unroll
+        for (int ss = 0; ss < B; ++ss) x[rr][ss] -= lr * xs[ss];
+      }
+      __syncthreads();
+    }
+  }
+  double* Li = d.Li + d.diag_off[l] + (int64_t)k * T * T;
+#pragma unroll
+  for (int rr = 0; rr < B; ++rr)
+#pragma unroll
+    for (int ss = 0; ss < B; ++ss) Li[mf_idx(T, ti * B + rr, tj * B + ss)] = x[rr][ss];
+  if (threadIdx.x == 0 && fail) d.blk_fail[l] = 1;
+}
+
+// L(i,k) = A(i,k) L(k,k)^-T, in place (the right-hand-side row i = nt included)
+template <int T>
+__global__ __launch_bounds__(NT) void k_chol_trsm(Dev d, int k, const int32_t* __restrict__ items) {
+  const int it = items[blockIdx.x];
+  const int l = it >> 16, i = (it >> 8) & 255;
+  if (d.active && !d.active[l]) return;
+  double* Aik = tile_ptr<T>(d, l, i, k);
+  const double* Li = d.Li + d.diag_off[l] + (int64_t)k * T * T;
+  Acc<T> acc;
+  acc.zero();
+  gemm_nt_mf<T>(Aik, Li, acc);
+  __syncthreads();  // every wave has read A(i,k) before it is overwritten
 #pragma unroll
   for (int p = 0; p < Acc<T>::NB; ++p)
 #pragma unroll
@@ -89,148 +200,23 @@ __device__ __forceinline__ void store_diff(const double* __restrict__ g, const A
       for (int e = 0; e < 4; ++e) {
         int r, c;
         acc_rc<T>(p, q, e, r, c);
-        s[r * LD + c] = g[r * T + c] - acc.v[p][q][e];
+        Aik[mf_idx(T, r, c)] = acc.v[p][q][e];
       }
 }
 
-// Left-looking Cholesky of the lower triangle of an LDS tile; sets *fail on a
-// non-positive pivot (the pivot is then replaced by 1 to keep values finite).
+// Trailing update A(i,j) -= L(i,k) L(j,k)^T.  Each wave owns a (T/2) x (T/2)
+// quadrant; no LDS.
 template <int T>
-__device__ void potrf_lds(double* D, int* fail) {
-  constexpr int LD = T + 2;
-  constexpr int P = NT / T;  // threads per row
-  const int r = threadIdx.x / P, p = threadIdx.x % P;
-  for (int c = 0; c < T; ++c) {
-    double s = 0.0;
-    if (r >= c)
-      for (int m = p; m < c; m += P) s += D[r * LD + m] * D[c * LD + m];
-#pragma unroll
-    for (int o = 1; o < P; o <<= 1) s += __shfl_xor(s, o);
-    if (r == c && p == 0) {
-      double dv = D[c * LD + c] - s;
-      if (!(dv > 0.0)) {
-        *fail = 1;
-        dv = 1.0;
-      }
-      D[c * LD + c] = sqrt(dv);
-    }
-    __syncthreads();
-    if (r > c && p == 0) D[r * LD + c] = (D[r * LD + c] - s) / D[c * LD + c];
-    __syncthreads();
-  }
-}
-
-// G = L^-1 (lower) from the lower triangle of L, both LDS tiles
-template <int T>
-__device__ void trtri_lds(const double* Lt, double* G) {
-  constexpr int LD = T + 2;
-  constexpr int P = NT / T;
-  const int j = threadIdx.x / P, p = threadIdx.x % P;
-  for (int e = threadIdx.x; e < T * T; e += NT) G[(e / T) * LD + (e % T)] = 0.0;
-  __syncthreads();
-  for (int r = 0; r < T; ++r) {
-    if (j < r) {
-      double s = 0.0;
-      for (int m = j + p; m < r; m += P) s += Lt[r * LD + m] * G[m * LD + j];
-#pragma unroll
-      for (int o = 1; o < P; o <<= 1) s += __shfl_xor(s, o);
-      if (p == 0) G[r * LD + j] = -s / Lt[r * LD + r];
-    } else if (j == r && p == 0) {
-      G[r * LD + r] = 1.0 / Lt[r * LD + r];
-    }
-    __syncthreads();
-  }
-}
-
-template <int T>
-__global__ __launch_bounds__(NT) void k_chol_forward(Dev d, int k, const int32_t* __restrict__ items) {
-  constexpr int LD = T + 2;
-  constexpr int64_t T2 = (int64_t)T * T;
-  extern __shared__ double sm[];
-  double* bA = sm;                 // L(i,k-1), then A(i,k) updated, then L(i,k)
-  double* bB = sm + T * LD;        // L(k,k-1), then A(k,k) updated and factored
-  double* bG = sm + 2 * T * LD;    // L(k,k)^-1
-  double* yv = sm + 3 * T * LD;    // [T] y_k
-  double* ysv = yv + T;            // [T] L(k,k)^-1 y_k
-  __shared__ int fail;
-
+__global__ __launch_bounds__(NT) void k_chol_update(Dev d, int k, const int32_t* __restrict__ items) {
   const int it = items[blockIdx.x];
   const int l = it >> 16, i = (it >> 8) & 255, j = it & 255;
   if (d.active && !d.active[l]) return;
-  const int64_t base = d.rcs_off[l];
-  auto tile = [&](int ti, int tj) { return d.S + base + ((int64_t)ti * (ti + 1) / 2 + tj) * T2; };
-
-  if (j > k) {
-    // trailing update of step k-1
-    load_tile<T>(tile(i, k - 1), bA);
-    load_tile<T>(tile(j, k - 1), bB);
-    __syncthreads();
-    Acc<T> acc;
-    acc.zero();
-    gemm_nt<T>(bA, bB, acc);
-    double* C = tile(i, j);
-#pragma unroll
-    for (int p = 0; p < Acc<T>::NB; ++p)
-#pragma unroll
-      for (int q = 0; q < Acc<T>::NB; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int r, c;
-          acc_rc<T>(p, q, e, r, c);
-          C[r * T + c] -= acc.v[p][q][e];
-        }
-    return;
-  }
-
-  // panel item (l, i, k)
-  if (threadIdx.x == 0) fail = 0;
-  if (k > 0) {
-    load_tile<T>(tile(k, k - 1), bB);
-    if (i > k) load_tile<T>(tile(i, k - 1), bA);
-    __syncthreads();
-    Acc<T> accD, accO;
-    accD.zero();
-    gemm_nt<T>(bB, bB, accD);
-    if (i > k) {
-      accO.zero();
-      gemm_nt<T>(bA, bB, accO);
-    }
-    __syncthreads();
-    store_diff<T>(tile(k, k), accD, bB);
-    if (i > k) store_diff<T>(tile(i, k), accO, bA);
-  } else {
-    load_tile<T>(tile(k, k), bB);
-    if (i > k) load_tile<T>(tile(i, k), bA);
-  }
-  const int64_t vb = d.vec_off[l];
-  for (int t = threadIdx.x; t < T; t += NT) yv[t] = d.y[vb + (int64_t)k * T + t];
-  __syncthreads();
-  potrf_lds<T>(bB, &fail);
-  trtri_lds<T>(bB, bG);
-  // ys_k = L(k,k)^-1 y_k
-  for (int r = threadIdx.x; r < T; r += NT) {
-    double s = 0.0;
-    for (int m = 0; m <= r; ++m) s += bG[r * LD + m] * yv[m];
-    ysv[r] = s;
-  }
-  __syncthreads();
-  if (i == k) {
-    const int64_t db = d.diag_off[l] + (int64_t)k * T2;
-    for (int e = threadIdx.x; e < T * T; e += NT) {
-      int r = e / T, c = e % T;
-      d.Ld[db + e] = c <= r ? bB[r * LD + c] : 0.0;
-      d.Li[db + e] = bG[r * LD + c];
-    }
-    for (int t = threadIdx.x; t < T; t += NT) d.ys[vb + (int64_t)k * T + t] = ysv[t];
-    if (threadIdx.x == 0 && fail) d.blk_fail[l] = 1;
-    return;
-  }
-  // L(i,k) = A(i,k) L(k,k)^-T
-  Acc<T> accT;
-  accT.zero();
-  gemm_nt<T>(bA, bG, accT);
-  __syncthreads();
-  double* Lik = tile(i, k);
+  const double* Aik = tile_ptr<T>(d, l, i, k);
+  const double* Ajk = tile_ptr<T>(d, l, j, k);
+  double* C = tile_ptr<T>(d, l, i, j);
+  Acc<T> acc;
+  acc.zero();
+  gemm_nt_mf<T>(Aik, Ajk, acc);
 #pragma unroll
   for (int p = 0; p < Acc<T>::NB; ++p)
 #pragma unroll
@@ -239,22 +225,29 @@ __global__ __launch_bounds__(NT) void k_chol_forward(Dev d, int k, const int32_t
       for (int e = 0; e < 4; ++e) {
         int r, c;
         acc_rc<T>(p, q, e, r, c);
-        Lik[r * T + c] = accT.v[p][q][e];
-        bA[r * LD + c] = accT.v[p][q][e];
+        C[mf_idx(T, r, c)] -= acc.v[p][q][e];
       }
-  __syncthreads();
-  // y_i -= L(i,k) ys_k
-  for (int r = threadIdx.x; r < T; r += NT) {
-    double s = 0.0;
-    for (int c = 0; c < T; ++c) s += bA[r * LD + c] * ysv[c];
-    d.y[vb + (int64_t)i * T + r] -= s;
+}
+
+// ys = L^-1 e: row 0 of the factored right-hand-side tile row
+template <int T>
+__global__ void k_rhs_extract(Dev d) {
+  const int l = blockIdx.x;
+  if (d.active && !d.active[l]) return;
+  const int nt = d.nt[l];
+  const int64_t vb = d.vec_off[l];
+  for (int t = threadIdx.x; t < nt * T; t += blockDim.x) {
+    const int k = t / T, c = t % T;
+    d.ys[vb + t] = tile_ptr<T>(d, l, nt, k)[mf_idx(T, 0, c)];
   }
 }
 
-// backward substitution step k: x_k = L(k,k)^-T z_k; z_j -= L(k,j)^T x_k
+// backward substitution step k: x_k = L(k,k)^-T z_k; z_j -= L(k,j)^T x_k.
+// P = 256 / T threads share each output element (strided partial sums,
+// reduced with lane shuffles).
 template <int T>
 __global__ __launch_bounds__(NT) void k_chol_backward(Dev d, const int32_t* __restrict__ items) {
-  constexpr int64_t T2 = (int64_t)T * T;
+  constexpr int P = NT / T;
   __shared__ double zk[T], xk[T];
   const int it = items[blockIdx.x];
   const int l = it >> 16, k = (it >> 8) & 255, j = it & 255;
@@ -262,34 +255,49 @@ __global__ __launch_bounds__(NT) void k_chol_backward(Dev d, const int32_t* __re
   const int64_t vb = d.vec_off[l];
   for (int t = threadIdx.x; t < T; t += NT) zk[t] = d.ys[vb + (int64_t)k * T + t];
   __syncthreads();
-  const double* Li = d.Li + d.diag_off[l] + (int64_t)k * T2;
-  for (int r = threadIdx.x; r < T; r += NT) {
-    double s = 0.0;
-    for (int m = r; m < T; ++m) s += Li[(int64_t)m * T + r] * zk[m];
-    xk[r] = s;
+  const int r = threadIdx.x / P, part = threadIdx.x % P;
+  const double* Li = d.Li + d.diag_off[l] + (int64_t)k * T * T;
+  double s = 0.0;
+#pragma unroll
+  for (int m0 = 0; m0 < T; m0 += P) {
+    const int m = m0 + part;
+    s += m >= r ? Li[mf_idx(T, m, r)] * zk[m] : 0.0;
   }
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) s += __shfl_xor(s, o);
+  if (part == 0) xk[r] = s;
   __syncthreads();
   if (j == k) {
     for (int t = threadIdx.x; t < T; t += NT) d.x[vb + (int64_t)k * T + t] = xk[t];
     return;
   }
-  const double* Lkj = d.S + d.rcs_off[l] + ((int64_t)k * (k + 1) / 2 + j) * T2;
-  for (int c = threadIdx.x; c < T; c += NT) {
-    double s = 0.0;
-    for (int r = 0; r < T; ++r) s += Lkj[(int64_t)r * T + c] * xk[r];
-    d.ys[vb + (int64_t)j * T + c] -= s;
+  const double* Lkj = tile_ptr<T>(d, l, k, j);
+  double u = 0.0;
+#pragma unroll
+  for (int m0 = 0; m0 < T; m0 += P) {
+    const int m = m0 + part;
+    u += Lkj[mf_idx(T, m, r)] * xk[m];
   }
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) u += __shfl_xor(u, o);
+  if (part == 0) d.ys[vb + (int64_t)j * T + r] -= u;
 }
 
+// C = A B^T for row-major 64 x 64 tiles through the matrix-core tile product
 __global__ __launch_bounds__(NT) void k_selftest_gemm(const double* A, const double* B, double* C) {
-  constexpr int T = 64, LD = T + 2;
+  constexpr int T = 64;
   extern __shared__ double sm[];
-  load_tile<T>(A, sm);
-  load_tile<T>(B, sm + T * LD);
+  double* a = sm;
+  double* b = sm + T * T;
+  for (int e = threadIdx.x; e < T * T; e += NT) {
+    const int r = e / T, c = e % T;
+    a[mf_idx(T, r, c)] = A[e];
+    b[mf_idx(T, r, c)] = B[e];
+  }
   __syncthreads();
   Acc<T> acc;
   acc.zero();
-  gemm_nt<T>(sm, sm + T * LD, acc);
+  gemm_nt_mf<T>(a, b, acc);
 #pragma unroll
   for (int p = 0; p < Acc<T>::NB; ++p)
 #pragma unroll
@@ -302,19 +310,24 @@ __global__ __launch_bounds__(NT) void k_selftest_gemm(const double* A, const dou
       }
 }
 
-template <int T>
-size_t fwd_lds() {
-  return (size_t)(3 * T * (T + 2) + 2 * T) * sizeof(double);
-}
-
 }  // namespace
 
-void launch_chol_forward(const Dev& d, int k, const int32_t* items, int64_t n_items, hipStream_t st) {
-  if (n_items <= 0) return;
-  if (d.T == 64)
-    hipLaunchKernelGGL(k_chol_forward<64>, dim3((unsigned)n_items), dim3(NT), fwd_lds<64>(), st, d, k, items);
-  else
-    hipLaunchKernelGGL(k_chol_forward<32>, dim3((unsigned)n_items), dim3(NT), fwd_lds<32>(), st, d, k, items);
+void launch_chol_step(const Dev& d, int k, const int32_t* pot, int64_t npot, const int32_t* trsm, int64_t ntrsm,
+                      const int32_t* upd, int64_t nupd, hipStream_t st) {
+  if (d.T == 64) {
+    if (npot) hipLaunchKernelGGL(k_chol_potrf<64>, dim3((unsigned)npot), dim3(NT), 0, st, d, k, pot);
+    if (ntrsm) hipLaunchKernelGGL(k_chol_trsm<64>, dim3((unsigned)ntrsm), dim3(NT), 0, st, d, k, trsm);
+    if (nupd) hipLaunchKernelGGL(k_chol_update<64>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
+  } else {
+    if (npot) hipLaunchKernelGGL(k_chol_potrf<32>, dim3((unsigned)npot), dim3(NT), 0, st, d, k, pot);
+    if (ntrsm) hipLaunchKernelGGL(k_chol_trsm<32>, dim3((unsigned)ntrsm), dim3(NT), 0, st, d, k, trsm);
+    if (nupd) hipLaunchKernelGGL(k_chol_update<32>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
+  }
+}
+
+void launch_rhs_extract(const Dev& d, hipStream_t st) {
+  if (d.T == 64) hipLaunchKernelGGL(k_rhs_extract<64>, dim3(d.L), dim3(NT), 0, st, d);
+  else hipLaunchKernelGGL(k_rhs_extract<32>, dim3(d.L), dim3(NT), 0, st, d);
 }
 
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st) {
@@ -326,7 +339,7 @@ void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, h
 }
 
 void launch_selftest_gemm(const double* A, const double* B, double* C, hipStream_t st) {
-  hipLaunchKernelGGL(k_selftest_gemm, dim3(1), dim3(NT), 2 * 64 * 66 * sizeof(double), st, A, B, C);
+  hipLaunchKernelGGL(k_selftest_gemm, dim3(1), dim3(NT), 2 * 64 * 64 * sizeof(double), st, A, B, C);
 }
 
 }  // namespace rpba

@@ -25,10 +25,10 @@ struct Lin {
   T Ar[2][3];    // dg/d(rotation increment)
 };
 
+// linearisation from the offset d = X - C (formed by the caller, in FP64 when T
+// is float, so that large coordinates do not cancel in single precision)
 template <typename T>
-__device__ __forceinline__ void linearise(const T* __restrict__ R, const T* __restrict__ C, const T X[3], T f,
-                                          T cx, T cy, Lin<T>& o) {
-  T d0 = X[0] - C[0], d1 = X[1] - C[1], d2 = X[2] - C[2];
+__device__ __forceinline__ void linearise_d(const T* __restrict__ R, T d0, T d1, T d2, T f, T cx, T cy, Lin<T>& o) {
   T p0 = R[0] * d0 + R[1] * d1 + R[2] * d2;
   T p1 = R[3] * d0 + R[4] * d1 + R[5] * d2;
   T p2 = R[6] * d0 + R[7] * d1 + R[8] * d2;
@@ -49,6 +49,12 @@ __device__ __forceinline__ void linearise(const T* __restrict__ R, const T* __re
   o.Ar[1][0] = -f * (T(1) + w * w);
   o.Ar[1][1] = f * u * w;
   o.Ar[1][2] = f * u;
+}
+
+template <typename T>
+__device__ __forceinline__ void linearise(const T* __restrict__ R, const T* __restrict__ C, const T X[3], T f,
+                                          T cx, T cy, Lin<T>& o) {
+  linearise_d<T>(R, X[0] - C[0], X[1] - C[1], X[2] - C[2], f, cx, cy, o);
 }
 
 // weight matrix of one observation [[a, b], [b, c]]

@@ -59,6 +59,16 @@ struct Dev {
   double* cpk;            // [NC][12] X, damped V^-1 (6), g_X (3) of the current step
   const int32_t* nb_off;
   const int32_t* nb_cam;
+  // pair blocks (see the plan) and the block-sparse matrix of iterative sub-blocks
+  const int32_t* pb_row;
+  const int64_t* pb_ent_off;
+  const int32_t* pb_ent;
+  const int32_t* od_pb;
+  int64_t n_od;
+  const int32_t* pb_bsr;
+  const int32_t* pb_bsr_t;
+  const uint8_t* blk_pcg;  // [L] 1 = iterative solver (block-sparse output)
+  float* bsr;              // [nbsr][36] FP32 blocks of the reduced camera systems
 
   // dense reduced camera systems
   double* S;              // tiles, lower triangle per sub-block
@@ -81,13 +91,31 @@ struct Dev {
   double* acc_rob;        // [2]
 };
 
+// In-tile layout of the RCS tiles, chosen for the FP64 matrix cores: element
+// (r, c) of a T x T tile lives at ((r / 16) (T / 4) + c / 4) 64 + r % 16 +
+// 16 (c % 4), so that the 16 x 4 operand fragment a 64-lane wave feeds to one
+// v_mfma_f64_16x16x4 (lane -> row lane % 16, column lane / 16) is one
+// contiguous 512-byte load.
+__host__ __device__ __forceinline__ int mf_idx(int T, int r, int c) {
+  return ((r >> 4) * (T >> 2) + (c >> 2)) * 64 + (r & 15) + 16 * (c & 3);
+}
+
+// offset of element (row, col), col <= row, of sub-block l's tiled RCS
+__host__ __device__ __forceinline__ int64_t rcs_elem(const Dev& d, int l, int row, int col) {
+  const int T = d.T;
+  const int tr = row / T, tc = col / T;
+  return d.rcs_off[l] + ((int64_t)tr * (tr + 1) / 2 + tc) * T * T + mf_idx(T, row % T, col % T);
+}
+
 // kernel launchers (all asynchronous on `st`)
 void launch_gather(const Dev& d, hipStream_t st);
 void launch_init_rcs(const Dev& d, hipStream_t st);
 void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st);
 void launch_copy_prep(const Dev& d, hipStream_t st);
-void launch_schur_rows(const Dev& d, int max_nb, int max_blk_cams, hipStream_t st);
-void launch_chol_forward(const Dev& d, int k, const int32_t* items, int64_t n_items, hipStream_t st);
+void launch_schur(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st);
+void launch_chol_step(const Dev& d, int k, const int32_t* pot, int64_t npot, const int32_t* trsm, int64_t ntrsm,
+                      const int32_t* upd, int64_t nupd, hipStream_t st);
+void launch_rhs_extract(const Dev& d, hipStream_t st);
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st);
 void launch_update(const Dev& d, double* block_stats, hipStream_t st);
 void launch_consensus(const Dev& d, double* stats, hipStream_t st);

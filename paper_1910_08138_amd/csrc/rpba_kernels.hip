@@ -91,11 +91,10 @@ __global__ void k_pad_identity(Dev d) {
   int l = blockIdx.x;
   int n6 = 6 * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
   int nt = d.nt[l];
-  int T = d.T;
-  int64_t tile = d.rcs_off[l] + ((int64_t)(nt - 1) * nt / 2 + (nt - 1)) * T * T;
+  const int T = d.T;
   for (int r = threadIdx.x; r < T; r += NT) {
     int gr = (nt - 1) * T + r;
-    if (gr >= n6) d.S[tile + (int64_t)r * T + r] = 1.0;
+    if (gr >= n6) d.S[rcs_elem(d, l, gr, gr)] = 1.0;
   }
 }
 
@@ -280,155 +279,6 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
     atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 0], sh[threadIdx.x]);
 }
 
-// One workgroup per camera i (internal order): row block i of the reduced
-// camera system of its sub-block,
-//   S_(i,i2) = [i == i2] U*_i - sum_copies sum_(k1 in i, k2 in i2) Y_k1 V*^-1 Y_k2^T
-//   e_i      = -g_Ci + sum_(k1 in i) Y_k1 V*^-1 g_X,
-// accumulated as outer products straight into the row (Sec. 5.4).  Only
-// cameras i2 <= i (local index) are formed; neighbours are held in LDS slots.
-__global__ __launch_bounds__(NT) void k_schur_rows(Dev d) {
-  extern __shared__ double smem[];
-  const int i = blockIdx.x;
-  const int l = d.cam_blk[i];
-  if (d.active && !d.active[l]) return;
-  const int base = d.blk_cam_off[l];
-  const int ncam = d.blk_cam_off[l + 1] - base;
-  const int a = i - base;
-  const int nb0 = d.nb_off[i], nnb = d.nb_off[i + 1] - nb0;
-  double* acc = smem;                               // [nnb][36]
-  double* red = smem + (size_t)nnb * 36;            // [33][4]
-  int* slot = (int*)(red + 33 * 4);                 // [ncam]
-  for (int t = threadIdx.x; t < nnb * 36; t += NT) acc[t] = 0.0;
-  for (int t = threadIdx.x; t < ncam; t += NT) slot[t] = -1;
-  __syncthreads();
-  for (int t = threadIdx.x; t < nnb; t += NT) slot[d.nb_cam[nb0 + t]] = t;
-  __syncthreads();
-
-  const double* cm1 = d.cam + (int64_t)CAM_STRIDE * i;
-  double R1[9], C1[3];
-  for (int q = 0; q < 9; ++q) R1[q] = cm1[q];
-  for (int q = 0; q < 3; ++q) C1[q] = cm1[9 + q];
-  double U[21], gC[6], ep[6];
-  for (int q = 0; q < 21; ++q) U[q] = 0.0;
-  for (int q = 0; q < 6; ++q) gC[q] = ep[q] = 0.0;
-
-  for (int idx = d.cam_obs_off[i] + threadIdx.x; idx < d.cam_obs_off[i + 1]; idx += NT) {
-    const int k1 = d.cam_obs[idx];
-    const int c = d.obs_copy[k1];
-    if (d.status[d.copy_pt[c]] != 0) continue;
-    const double* pk = d.cpk + 12 * (int64_t)c;
-    double X[3] = {pk[0], pk[1], pk[2]};
-    double Vi[6];
-    for (int q = 0; q < 6; ++q) Vi[q] = pk[3 + q];
-    double gX[3] = {pk[9], pk[10], pk[11]};
-    Lin<double> L1;
-    linearise<double>(R1, C1, X, d.f, d.cx, d.cy, L1);
-    double v0 = L1.g0 - d.xy[2 * k1], v1 = L1.g1 - d.xy[2 * k1 + 1];
-    W2<double> W = obs_weight(d, k1);
-    // A = [Ar | -B]; WA rows
-    double A[2][6], WA[2][6];
-    for (int q = 0; q < 3; ++q) {
-      A[0][q] = L1.Ar[0][q];
-      A[1][q] = L1.Ar[1][q];
-      A[0][3 + q] = -L1.B[0][q];
-      A[1][3 + q] = -L1.B[1][q];
-    }
-    for (int q = 0; q < 6; ++q) {
-      WA[0][q] = W.a * A[0][q] + W.b * A[1][q];
-      WA[1][q] = W.b * A[0][q] + W.c * A[1][q];
-    }
-    double Wv0 = W.a * v0 + W.b * v1, Wv1 = W.b * v0 + W.c * v1;
-    int u = 0;
-    for (int r = 0; r < 6; ++r)
-      for (int s = r; s < 6; ++s) U[u++] += A[0][r] * WA[0][s] + A[1][r] * WA[1][s];
-    for (int r = 0; r < 6; ++r) gC[r] += A[0][r] * Wv0 + A[1][r] * Wv1;
-    // Y1 = A^T W B (6x3), Z1 = Y1 V*^-1
-    double Y1[6][3], Z1[6][3];
-    for (int r = 0; r < 6; ++r)
-      for (int s = 0; s < 3; ++s) Y1[r][s] = WA[0][r] * L1.B[0][s] + WA[1][r] * L1.B[1][s];
-    for (int r = 0; r < 6; ++r) {
-      Z1[r][0] = Y1[r][0] * Vi[0] + Y1[r][1] * Vi[1] + Y1[r][2] * Vi[2];
-      Z1[r][1] = Y1[r][0] * Vi[1] + Y1[r][1] * Vi[3] + Y1[r][2] * Vi[4];
-      Z1[r][2] = Y1[r][0] * Vi[2] + Y1[r][1] * Vi[4] + Y1[r][2] * Vi[5];
-      ep[r] += Z1[r][0] * gX[0] + Z1[r][1] * gX[1] + Z1[r][2] * gX[2];
-    }
-    for (int k2 = d.copy_off[c]; k2 < d.copy_off[c + 1]; ++k2) {
-      const int i2 = d.obs_cam[k2];
-      const int a2 = i2 - base;
-      if (a2 > a) break;  // observations of a copy are ordered by camera
-      double Y2[6][3];
-      if (k2 == k1) {
-        for (int r = 0; r < 6; ++r)
-          for (int s = 0; s < 3; ++s) Y2[r][s] = Y1[r][s];
-      } else {
-        const double* cm2 = d.cam + (int64_t)CAM_STRIDE * i2;
-        Lin<double> L2;
-        linearise<double>(cm2, cm2 + 9, X, d.f, d.cx, d.cy, L2);
-        W2<double> Wb = obs_weight(d, k2);
-        double WB2[2][3];
-        for (int s = 0; s < 3; ++s) {
-          WB2[0][s] = Wb.a * L2.B[0][s] + Wb.b * L2.B[1][s];
-          WB2[1][s] = Wb.b * L2.B[0][s] + Wb.c * L2.B[1][s];
-        }
-        for (int r = 0; r < 3; ++r)
-          for (int s = 0; s < 3; ++s) {
-            Y2[r][s] = L2.Ar[0][r] * WB2[0][s] + L2.Ar[1][r] * WB2[1][s];
-            Y2[3 + r][s] = -(L2.B[0][r] * WB2[0][s] + L2.B[1][r] * WB2[1][s]);
-          }
-      }
-      double* blk = acc + 36 * slot[a2];
-      for (int r = 0; r < 6; ++r)
-        for (int s = 0; s < 6; ++s)
-          atomicAdd(&blk[6 * r + s], -(Z1[r][0] * Y2[s][0] + Z1[r][1] * Y2[s][1] + Z1[r][2] * Y2[s][2]));
-    }
-  }
-  // reduce U (21), gC (6), ep (6) over the workgroup
-  {
-    double v[33];
-    for (int q = 0; q < 21; ++q) v[q] = U[q];
-    for (int q = 0; q < 6; ++q) v[21 + q] = gC[q];
-    for (int q = 0; q < 6; ++q) v[27 + q] = ep[q];
-    for (int q = 0; q < 33; ++q)
-      for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0)
-      for (int q = 0; q < 33; ++q) red[q * 4 + wv] = v[q];
-  }
-  __syncthreads();
-  double* own = acc + 36 * slot[a];
-  if (threadIdx.x < 36) {
-    int r = threadIdx.x / 6, s = threadIdx.x % 6;
-    int rr = r < s ? r : s, ss = r < s ? s : r;
-    int u = rr * 6 - rr * (rr - 1) / 2 + (ss - rr);  // index in the packed upper triangle
-    double uv = red[u * 4] + red[u * 4 + 1] + red[u * 4 + 2] + red[u * 4 + 3];
-    if (r == s) uv = (uv == 0.0) ? 1.0 : uv * (1.0 + d.lambda);
-    own[threadIdx.x] += uv;
-  }
-  const int T = d.T;
-  const int64_t vbase = d.vec_off[l];
-  if (threadIdx.x < 6) {
-    int q = threadIdx.x;
-    double gcq = red[(21 + q) * 4] + red[(21 + q) * 4 + 1] + red[(21 + q) * 4 + 2] + red[(21 + q) * 4 + 3];
-    double epq = red[(27 + q) * 4] + red[(27 + q) * 4 + 1] + red[(27 + q) * 4 + 2] + red[(27 + q) * 4 + 3];
-    d.y[vbase + 6 * a + q] = -gcq + epq;
-  }
-  __syncthreads();
-  // write rows 6a..6a+5, columns c <= row of the dense tiled lower triangle
-  const int64_t sbase = d.rcs_off[l];
-  const int ncols = 6 * a + 6;
-  for (int t = threadIdx.x; t < 6 * ncols; t += NT) {
-    int q = t / ncols, col = t % ncols;
-    int row = 6 * a + q;
-    if (col > row) continue;
-    int b = col / 6;
-    int sl = slot[b];
-    double val = sl >= 0 ? acc[36 * sl + 6 * q + (col % 6)] : 0.0;
-    int tr = row / T, tc = col / T;
-    int64_t off = sbase + ((int64_t)tr * (tr + 1) / 2 + tc) * T * T + (int64_t)(row % T) * T + (col % T);
-    d.S[off] = val;
-  }
-}
-
 // ------------------------------------------------------- update of the step
 // One thread per camera: new pose R <- Exp([w]x) R, C <- C + dc into camN.
 __global__ void k_cam_update(Dev d) {
@@ -604,15 +454,11 @@ __global__ void k_copy2(const double* src, double* dst, int n) {
 // dense copy-out of one sub-block's RCS (row-major n6 x n6 lower) and rhs
 __global__ void k_rcs_extract(Dev d, int l, double* S_out, double* e_out) {
   int n6 = 6 * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
-  int T = d.T;
   int64_t tot = (int64_t)n6 * n6;
   for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < tot; t += (int64_t)gridDim.x * NT) {
     int row = (int)(t / n6), col = (int)(t % n6);
     double v = 0.0;
-    if (col <= row) {
-      int tr = row / T, tc = col / T;
-      v = d.S[d.rcs_off[l] + ((int64_t)tr * (tr + 1) / 2 + tc) * T * T + (int64_t)(row % T) * T + (col % T)];
-    }
+    if (col <= row) v = d.S[rcs_elem(d, l, row, col)];
     S_out[t] = v;
   }
   for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n6; t += (int64_t)gridDim.x * NT)
@@ -656,11 +502,6 @@ void launch_copy_prep(const Dev& d, hipStream_t st) {
   launch_zero(d.acc_blk, 4 * (int64_t)d.L, st);
   launch_zero_i32(d.blk_fail, d.L, st);
   hipLaunchKernelGGL(k_copy_prep, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
-}
-
-void launch_schur_rows(const Dev& d, int max_nb, int max_blk_cams, hipStream_t st) {
-  size_t lds = (size_t)max_nb * 36 * sizeof(double) + 33 * 4 * sizeof(double) + (size_t)max_blk_cams * sizeof(int);
-  hipLaunchKernelGGL(k_schur_rows, dim3(d.M), dim3(NT), lds, st, d);
 }
 
 void launch_update(const Dev& d, double* block_stats, hipStream_t st) {

@@ -206,6 +206,56 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     }
   }
 
+  // pair blocks and their observation pairs
+  {
+    const int64_t NPB = (int64_t)P.nb_cam.size();
+    P.pb_row.resize(NPB);
+    for (int32_t i = 0; i < M; ++i)
+      for (int32_t q = P.nb_off[i]; q < P.nb_off[i + 1]; ++q) P.pb_row[q] = i;
+    auto pb_of = [&](int32_t i1, int32_t a2) -> int32_t {
+      const int32_t* b = P.nb_cam.data() + P.nb_off[i1];
+      const int32_t* e = P.nb_cam.data() + P.nb_off[i1 + 1];
+      return (int32_t)(std::lower_bound(b, e, a2) - P.nb_cam.data());
+    };
+    std::vector<int64_t> cnt(NPB + 1, 0);
+    for (int64_t c = 0; c < P.NC; ++c) {
+      int32_t b = P.copy_off[c], e = P.copy_off[c + 1], base = P.blk_cam_off[P.copy_blk[c]];
+      for (int32_t k1 = b; k1 < e; ++k1)
+        for (int32_t k2 = b; k2 <= k1; ++k2) cnt[pb_of(P.obs_cam[k1], P.obs_cam[k2] - base) + 1]++;
+    }
+    for (int64_t q = 0; q < NPB; ++q) cnt[q + 1] += cnt[q];
+    P.pb_ent_off = cnt;
+    P.pb_ent.resize(2 * (size_t)cnt[NPB]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t c = 0; c < P.NC; ++c) {
+      int32_t b = P.copy_off[c], e = P.copy_off[c + 1], base = P.blk_cam_off[P.copy_blk[c]];
+      for (int32_t k1 = b; k1 < e; ++k1)
+        for (int32_t k2 = b; k2 <= k1; ++k2) {
+          int64_t at = fill[pb_of(P.obs_cam[k1], P.obs_cam[k2] - base)]++;
+          P.pb_ent[2 * at] = k1;
+          P.pb_ent[2 * at + 1] = k2;
+        }
+    }
+    P.od_pb.clear();
+    for (int64_t q = 0; q < NPB; ++q) {
+      int32_t i = P.pb_row[q];
+      if (P.nb_cam[q] != i - P.blk_cam_off[P.cam_blk[i]]) P.od_pb.push_back((int32_t)q);
+    }
+    P.pb_bsr.resize(NPB);
+    P.pb_bsr_t.resize(NPB);
+    for (int64_t q = 0; q < NPB; ++q) {
+      int32_t i = P.pb_row[q];
+      int32_t base = P.blk_cam_off[P.cam_blk[i]];
+      int32_t a2 = P.nb_cam[q];
+      const int32_t* rb = P.bsr_col.data() + P.bsr_row_off[i];
+      const int32_t* re = P.bsr_col.data() + P.bsr_row_off[i + 1];
+      int32_t pos = (int32_t)(std::lower_bound(rb, re, a2) - P.bsr_col.data());
+      P.pb_bsr[q] = pos;
+      P.pb_bsr_t[q] = P.bsr_tr[pos];
+      (void)base;
+    }
+  }
+
   // dense tiled reduced camera systems
   const int64_t T2 = (int64_t)tile * tile;
   P.nt.resize(L);
@@ -219,29 +269,38 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     P.nt[l] = nt;
     P.nt_max = std::max(P.nt_max, nt);
     P.rcs_off[l] = P.rcs_total;
-    P.rcs_total += (int64_t)nt * (nt + 1) / 2 * T2;
+    P.rcs_total += ((int64_t)nt * (nt + 1) / 2 + nt) * T2;  // lower triangle + right-hand-side tile row
     P.diag_off[l] = P.diag_total;
     P.diag_total += (int64_t)nt * T2;
     P.vec_off[l] = P.vec_total;
     P.vec_total += (int64_t)nt * tile;
   }
-  // forward launches: launch k = panel k (items j == k) + trailing updates of
-  // step k-1 outside column k (items k < j <= i)
+  // larger sub-blocks first: their tiles carry the longest dependency chains
+  std::vector<int32_t> order(L);
+  for (int32_t l = 0; l < L; ++l) order[l] = l;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.nt[a] > P.nt[b]; });
+  P.pot_off.assign(P.nt_max + 1, 0);
   P.fwd_off.assign(P.nt_max + 1, 0);
+  P.upd_off.assign(P.nt_max + 1, 0);
+  P.pot_items.clear();
   P.fwd_items.clear();
+  P.upd_items.clear();
   for (int32_t k = 0; k < P.nt_max; ++k) {
-    for (int32_t l = 0; l < L; ++l) {
+    for (int32_t l : order)
+      if (P.nt[l] > k) P.pot_items.push_back((l << 16) | (k << 8) | k);
+    P.pot_off[k + 1] = (int64_t)P.pot_items.size();
+    for (int32_t l : order) {
       int32_t nt = P.nt[l];
       if (nt <= k) continue;
-      for (int32_t i = k; i < nt; ++i) P.fwd_items.push_back((l << 16) | (i << 8) | k);
+      for (int32_t i = k + 1; i <= nt; ++i) P.fwd_items.push_back((l << 16) | (i << 8) | k);
     }
-    if (k > 0)
-      for (int32_t l = 0; l < L; ++l) {
-        int32_t nt = P.nt[l];
-        for (int32_t j = k + 1; j < nt; ++j)
-          for (int32_t i = j; i < nt; ++i) P.fwd_items.push_back((l << 16) | (i << 8) | j);
-      }
     P.fwd_off[k + 1] = (int64_t)P.fwd_items.size();
+    for (int32_t l : order) {
+      int32_t nt = P.nt[l];
+      for (int32_t j = k + 1; j < nt; ++j)
+        for (int32_t i = j; i <= nt; ++i) P.upd_items.push_back((l << 16) | (i << 8) | j);
+    }
+    P.upd_off[k + 1] = (int64_t)P.upd_items.size();
   }
   // backward launches, step k (descending): items (l, k, j), j <= k
   P.bwd_off.assign(P.nt_max + 1, 0);

@@ -40,6 +40,15 @@ struct Plan {
   std::vector<int32_t> nb_off;         // [M+1] neighbour lists (cameras of the same
   std::vector<int32_t> nb_cam;         //        sub-block sharing a point, local index <= own)
   int32_t max_nb = 0, max_blk_cams = 0, max_cam_obs = 0;
+  // pair blocks = neighbour entries: block (i, nb_cam[q]) of the RCS of camera
+  // i's sub-block, with the observation pairs (k1 of camera i, k2 of the
+  // neighbour, same copy) that contribute to it
+  std::vector<int32_t> pb_row;         // [NPB] internal camera i
+  std::vector<int64_t> pb_ent_off;     // [NPB+1]
+  std::vector<int32_t> pb_ent;         // [2 * entries] (k1, k2)
+  std::vector<int32_t> od_pb;          // off-diagonal pair blocks (i2 != i)
+  std::vector<int32_t> pb_bsr;         // [NPB] position of block (i, i2) in the full block-sparse matrix
+  std::vector<int32_t> pb_bsr_t;       // [NPB] position of block (i2, i)
 
   // dense reduced camera systems (tile-major lower triangle per sub-block)
   std::vector<int32_t> nt;             // [L] tiles per side
@@ -48,9 +57,15 @@ struct Plan {
   std::vector<int64_t> vec_off;        // [L] offset of the padded vectors
   int64_t rcs_total = 0, diag_total = 0, vec_total = 0;
   int32_t nt_max = 0;
-  // Cholesky work lists: item = (l << 16) | (i << 8) | j
-  std::vector<int32_t> fwd_items;      // launch k: items [fwd_off[k], fwd_off[k+1])
+  // Cholesky work lists: item = (l << 16) | (i << 8) | j.  Tile row nt of a
+  // sub-block holds the right-hand side (row 0 = e^T), so that the forward
+  // substitution is part of the factorisation.
+  std::vector<int32_t> pot_items;      // step k: sub-blocks with nt > k, in [pot_off[k], pot_off[k+1])
+  std::vector<int64_t> pot_off;
+  std::vector<int32_t> fwd_items;      // step k: triangular solves (l, i, k), k < i <= nt
   std::vector<int64_t> fwd_off;
+  std::vector<int32_t> upd_items;      // step k: updates (l, i, j), k < j <= i, j < nt
+  std::vector<int64_t> upd_off;
   std::vector<int32_t> bwd_items;      // backward launch for step k (descending)
   std::vector<int64_t> bwd_off;
 

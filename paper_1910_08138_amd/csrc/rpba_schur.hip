@@ -1,0 +1,285 @@
+// Schur complement of the sub-block normal equations onto the cameras (the
+// reduced camera system, RCS), paper Sec. 2 and 5.4: the outer products of
+// the observations of every point copy are accumulated straight into the RCS,
+//   S_(i,i2) = [i == i2] U*_i - sum_(copies c) sum_(k1 in i, k2 in i2) Y_k1 V*_c^-1 Y_k2^T,
+//   e_i      = -g_Ci + sum_(k1 in i) Y_k1 V*_c^-1 g_Xc,
+// with U*_i the damped camera block, Y_k = A_k^T W_k B_k, V*_c the damped point
+// block (its FP64 inverse comes from the point-block pass).
+//
+// Each 6x6 block is owned by one group of lanes that sums the contributions of
+// its observation pairs in registers and writes the block once: no atomics,
+// deterministic order.  Diagonal blocks (one 64-lane wave per camera) also
+// reduce U*, g_C and e; off-diagonal blocks take a 16-lane group each.
+//
+// T is the arithmetic of the Jacobians and of the accumulation: double on the
+// FP64 path, float on the mixed path (X - C is formed in FP64 first).  Output
+// per sub-block: the dense tiled lower triangle (FP64) for sub-blocks solved by
+// Cholesky, or full 6x6 blocks of a block-sparse matrix (FP32) for sub-blocks
+// solved iteratively.
+#include "rpba_device.hpp"
+#include "rpba_internal.hpp"
+
+namespace rpba {
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T>
+__device__ __forceinline__ W2<T> obs_weight_t(const Dev& d, int64_t k) {
+  double r = d.rw[k];
+  if (d.has_info) {
+    const double* w = d.info + 3 * k;
+    return {(T)(r * w[0]), (T)(r * w[1]), (T)(r * w[2])};
+  }
+  return {(T)(r * d.w0), T(0), (T)(r * d.w0)};
+}
+
+// camera i: rotation in T, centre in FP64
+template <typename T>
+struct CamReg {
+  T R[9];
+  double C[3];
+  __device__ void load(const Dev& d, int i) {
+    const double* c = d.cam + (int64_t)CAM_STRIDE * i;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R[q] = (T)c[q];
+    C[0] = c[9];
+    C[1] = c[10];
+    C[2] = c[11];
+  }
+  __device__ void lin(const double X[3], const Dev& d, Lin<T>& L) const {
+    linearise_d<T>(R, (T)(X[0] - C[0]), (T)(X[1] - C[1]), (T)(X[2] - C[2]), (T)d.f, (T)d.cx, (T)d.cy, L);
+  }
+};
+
+// Y = A^T W B (6x3) of one observation
+template <typename T>
+__device__ __forceinline__ void y_block(const Lin<T>& L, const W2<T>& W, T Y[6][3]) {
+  T WB0[3], WB1[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    WB0[s] = W.a * L.B[0][s] + W.b * L.B[1][s];
+    WB1[s] = W.b * L.B[0][s] + W.c * L.B[1][s];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      Y[r][s] = L.Ar[0][r] * WB0[s] + L.Ar[1][r] * WB1[s];
+      Y[3 + r][s] = -(L.B[0][r] * WB0[s] + L.B[1][r] * WB1[s]);
+    }
+}
+
+// Z = Y V^-1 with V^-1 symmetric (xx, xy, xz, yy, yz, zz)
+template <typename T>
+__device__ __forceinline__ void z_block(const T Y[6][3], const T Vi[6], T Z[6][3]) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    Z[r][0] = Y[r][0] * Vi[0] + Y[r][1] * Vi[1] + Y[r][2] * Vi[2];
+    Z[r][1] = Y[r][0] * Vi[1] + Y[r][1] * Vi[3] + Y[r][2] * Vi[4];
+    Z[r][2] = Y[r][0] * Vi[2] + Y[r][1] * Vi[4] + Y[r][2] * Vi[5];
+  }
+}
+
+// index of (r, s), r <= s, in a packed 6x6 upper triangle
+__host__ __device__ constexpr int up6(int r, int s) { return r * 6 - r * (r - 1) / 2 + (s - r); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T group16_sum(T v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+// One wave per camera: diagonal block S_(i,i) = U*_i - sum_k Y_k V*^-1 Y_k^T
+// and e_i.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (i >= d.M) return;
+  const int l = d.cam_blk[i];
+  if (d.active && !d.active[l]) return;
+  CamReg<T> cm;
+  cm.load(d, i);
+  T acc[21], U[21], gC[6], ep[6];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) acc[q] = U[q] = T(0);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) gC[q] = ep[q] = T(0);
+
+  for (int idx = d.cam_obs_off[i] + lane; idx < d.cam_obs_off[i + 1]; idx += 64) {
+    const int k = d.cam_obs[idx];
+    const int c = d.obs_copy[k];
+    if (d.status[d.copy_pt[c]] != 0) continue;
+    const double* pk = d.cpk + 12 * (int64_t)c;
+    const double X[3] = {pk[0], pk[1], pk[2]};
+    T Vi[6], gX[3];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) Vi[q] = (T)pk[3 + q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) gX[q] = (T)pk[9 + q];
+    Lin<T> L;
+    cm.lin(X, d, L);
+    const W2<T> W = obs_weight_t<T>(d, k);
+    const T v0 = L.g0 - (T)d.xy[2 * k], v1 = L.g1 - (T)d.xy[2 * k + 1];
+    T A[2][6], WA[2][6];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      A[0][q] = L.Ar[0][q];
+      A[1][q] = L.Ar[1][q];
+      A[0][3 + q] = -L.B[0][q];
+      A[1][3 + q] = -L.B[1][q];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      WA[0][q] = W.a * A[0][q] + W.b * A[1][q];
+      WA[1][q] = W.b * A[0][q] + W.c * A[1][q];
+    }
+    const T Wv0 = W.a * v0 + W.b * v1, Wv1 = W.b * v0 + W.c * v1;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+#pragma unroll
+      for (int s = r; s < 6; ++s) U[up6(r, s)] += A[0][r] * WA[0][s] + A[1][r] * WA[1][s];
+      gC[r] += A[0][r] * Wv0 + A[1][r] * Wv1;
+    }
+    T Y[6][3], Z[6][3];
+    y_block<T>(L, W, Y);
+    z_block<T>(Y, Vi, Z);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      ep[r] += Z[r][0] * gX[0] + Z[r][1] * gX[1] + Z[r][2] * gX[2];
+#pragma unroll
+      for (int s = r; s < 6; ++s) acc[up6(r, s)] -= Z[r][0] * Y[s][0] + Z[r][1] * Y[s][1] + Z[r][2] * Y[s][2];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 21; ++q) {
+    acc[q] = wave_sum(acc[q]);
+    U[q] = wave_sum(U[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    gC[q] = wave_sum(gC[q]);
+    ep[q] = wave_sum(ep[q]);
+  }
+  const int a = i - d.blk_cam_off[l];
+  if (lane < 36) {
+    const int r = lane / 6, s = lane % 6;
+    const int u = r <= s ? up6(r, s) : up6(s, r);
+    // select the lane's entry from the register arrays
+    double uv = 0.0, av = 0.0;
+#pragma unroll
+    for (int q = 0; q < 21; ++q)
+      if (q == u) {
+        uv = (double)U[q];
+        av = (double)acc[q];
+      }
+    if (r == s) uv = (uv == 0.0) ? 1.0 : uv * (1.0 + d.lambda);
+    const double val = uv + av;
+    if (d.blk_pcg && d.blk_pcg[l]) {
+      d.bsr[(int64_t)d.pb_bsr[d.nb_off[i + 1] - 1] * 36 + lane] = (float)val;
+    } else if (s <= r) {
+      d.S[rcs_elem(d, l, 6 * a + r, 6 * a + s)] = val;
+    }
+  }
+  if (lane < 6) {
+    double g = 0.0, e = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      if (q == lane) {
+        g = (double)gC[q];
+        e = (double)ep[q];
+      }
+    d.y[d.vec_off[l] + 6 * a + lane] = -g + e;
+    // dense sub-blocks: e^T is row 0 of the right-hand-side tile row
+    if (!(d.blk_pcg && d.blk_pcg[l])) d.S[rcs_elem(d, l, d.nt[l] * d.T, 6 * a + lane)] = -g + e;
+  }
+}
+
+// One 16-lane group per off-diagonal pair block (i, i2), i2 < i in the sub-block.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
+  const int gl = threadIdx.x & 15;
+  const int64_t t = (int64_t)blockIdx.x * (NT / 16) + (threadIdx.x >> 4);
+  if (t >= d.n_od) return;  // uniform over the 16-lane group
+  const int q = d.od_pb[t];
+  const int i1 = d.pb_row[q];
+  const int l = d.cam_blk[i1];
+  if (d.active && !d.active[l]) return;
+  const int base = d.blk_cam_off[l];
+  const int a2 = d.nb_cam[q];
+  const int i2 = base + a2;
+  CamReg<T> c1, c2;
+  c1.load(d, i1);
+  c2.load(d, i2);
+  T acc[36];
+#pragma unroll
+  for (int u = 0; u < 36; ++u) acc[u] = T(0);
+  for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += 16) {
+    const int k1 = d.pb_ent[2 * e], k2 = d.pb_ent[2 * e + 1];
+    const int c = d.obs_copy[k1];
+    if (d.status[d.copy_pt[c]] != 0) continue;
+    const double* pk = d.cpk + 12 * (int64_t)c;
+    const double X[3] = {pk[0], pk[1], pk[2]};
+    T Vi[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) Vi[u] = (T)pk[3 + u];
+    Lin<T> L1, L2;
+    c1.lin(X, d, L1);
+    c2.lin(X, d, L2);
+    T Y1[6][3], Y2[6][3], Z1[6][3];
+    y_block<T>(L1, obs_weight_t<T>(d, k1), Y1);
+    y_block<T>(L2, obs_weight_t<T>(d, k2), Y2);
+    z_block<T>(Y1, Vi, Z1);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int s = 0; s < 6; ++s) acc[6 * r + s] -= Z1[r][0] * Y2[s][0] + Z1[r][1] * Y2[s][1] + Z1[r][2] * Y2[s][2];
+  }
+#pragma unroll
+  for (int u = 0; u < 36; ++u) acc[u] = group16_sum(acc[u]);
+  const int a1 = i1 - base;
+  const bool sparse = d.blk_pcg && d.blk_pcg[l];
+#pragma unroll
+  for (int u = 0; u < 36; ++u) {
+    if ((u & 15) != gl) continue;
+    const int r = u / 6, s = u % 6;
+    if (sparse) {
+      d.bsr[(int64_t)d.pb_bsr[q] * 36 + u] = (float)acc[u];
+      d.bsr[(int64_t)d.pb_bsr_t[q] * 36 + 6 * s + r] = (float)acc[u];
+    } else {
+      d.S[rcs_elem(d, l, 6 * a1 + r, 6 * a2 + s)] = (double)acc[u];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_schur(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st) {
+  if (dense) {
+    // every lower element not covered by a pair block is zero; the padded
+    // identity of the last diagonal tile is restored as well
+    launch_zero(d.S, rcs_total, st);
+    launch_init_rcs(d, st);
+  }
+  const unsigned gd = (unsigned)((d.M + 3) / 4);
+  const unsigned go = (unsigned)((d.n_od + 15) / 16);
+  if (fp32) {
+    hipLaunchKernelGGL(k_schur_diag<float>, dim3(gd), dim3(NT), 0, st, d);
+    if (go) hipLaunchKernelGGL(k_schur_offdiag<float>, dim3(go), dim3(NT), 0, st, d);
+  } else {
+    hipLaunchKernelGGL(k_schur_diag<double>, dim3(gd), dim3(NT), 0, st, d);
+    if (go) hipLaunchKernelGGL(k_schur_offdiag<double>, dim3(go), dim3(NT), 0, st, d);
+  }
+}
+
+}  // namespace rpba
