@@ -85,9 +85,9 @@ def _declare_solvers(L):
     L.orc_pcg.restype = ctypes.c_int
     L.orc_pcg.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp]
     L.orc_mlp_features.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
-    L.orc_mlp_blocks.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.orc_mlp_blocks.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
     L.orc_mlp_loss_grad.restype = ctypes.c_double
-    L.orc_mlp_loss_grad.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_mlp_loss_grad.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
     L.orc_mlp_num_params.restype = ctypes.c_int
     L.orc_mlp_num_params.argtypes = []
 
@@ -228,6 +228,57 @@ def cholesky(A):
     if rc:
         raise np.linalg.LinAlgError("not SPD")
     return np.tril(A)
+
+
+def pcg(S, e, P=None, tol=1e-8, maxit=1000):
+    """Block-preconditioned CG (x0 = 0) on a dense symmetric system; P: (n/6, 6, 6)
+    blocks or None for block-Jacobi.  Returns (x, iterations, relative residuals)."""
+    S, e = f64(S), f64(e)
+    n = S.shape[0]
+    x = np.zeros(n)
+    hist = np.zeros(maxit)
+    Pp = None if P is None else f64(P)
+    it = lib().orc_pcg(n, _p(S), _p(e), _p(Pp), tol, maxit, _p(x), _p(hist))
+    if it < 0:
+        raise np.linalg.LinAlgError("diagonal block not positive definite")
+    return x, it, hist[:it]
+
+
+MLP_NF, MLP_NH, MLP_NO = 26, 64, 21
+
+
+def mlp_num_params():
+    return int(lib().orc_mlp_num_params())
+
+
+def mlp_features(S, obs_tp, lam=1e-4):
+    S = f64(S)
+    n = S.shape[0]
+    obs_tp = f64(obs_tp)
+    feat = np.zeros((n // 6, MLP_NF))
+    lib().orc_mlp_features(n, _p(S), _p(obs_tp), lam, _p(feat))
+    return feat
+
+
+def mlp_blocks(S, feat, params=None):
+    """(P blocks (nb, 6, 6), G^-1 blocks (nb, 6, 6))"""
+    S = f64(S)
+    n = S.shape[0]
+    feat = f64(feat)
+    P = np.zeros((n // 6, 6, 6))
+    Gi = np.zeros((n // 6, 6, 6))
+    pp = None if params is None else f64(params)
+    lib().orc_mlp_blocks(n, _p(S), _p(feat), _p(pp), _p(P), _p(Gi))
+    return P, Gi
+
+
+def mlp_loss_grad(Ginv, feat, params, zw):
+    """Hutchinson SPAI loss and gradient; zw: (nz, 2, n) probe pairs (z, S z)."""
+    Ginv, feat, params, zw = f64(Ginv), f64(feat), f64(params), f64(zw)
+    nb = Ginv.shape[0]
+    grad = np.zeros(mlp_num_params())
+    loss = lib().orc_mlp_loss_grad(nb, zw.shape[0], _p(Ginv), _p(feat), _p(params), _p(zw), _p(grad))
+    return loss, grad
 
 
 def run_schedule(scene, T=6, I=4, robust=False, t_r=2, t_v=4.0, down_weight=1e-4, callback=None, **kw):
