@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="small oblique block (smoke-sized)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=64)
+    ap.add_argument("--path", default="fp64", choices=["fp64", "mixed", "mixed-pcg", "mixed-learned"])
+    ap.add_argument("--pcg-min-cams", type=int, default=150)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -82,7 +84,12 @@ def main():
     scene = scenes.config_scene(3, args.seed, small=args.small)
     log(f"scene: M={scene.M} N={scene.N} K={scene.K} L={scene.L} ({time.time() - t0:.1f} s)")
     t0 = time.time()
-    prob = binding.Problem(scene, chol_tile=args.tile)
+    opts = dict(chol_tile=args.tile)
+    if args.path != "fp64":
+        opts["precision"] = binding.RPBA_MIXED
+    if args.path == "mixed-pcg":
+        opts.update(solver=binding.RPBA_SOLVER_AUTO, pcg_min_cams=args.pcg_min_cams)
+    prob = binding.Problem(scene, **opts)
     log(f"plan + pack: {time.time() - t0:.1f} s, workspace {prob.ws_bytes / 2**30:.2f} GiB")
 
     prob.set_graph(True)
@@ -123,7 +130,8 @@ def main():
     ph = prob.timing()
     prob.set_timing(False)
     per_step = {k: v["ms"] / max(args.steps, 1) for k, v in ph.items()}
-    lm_ms = sum(per_step[k] for k in ("point_blocks", "schur_rows", "chol_forward", "chol_backward", "update"))
+    lm_ms = sum(per_step[k] for k in ("point_blocks", "schur_rows", "chol_forward", "chol_backward", "update",
+                                      "iterative_solve"))
     dom = max(("chol_forward", "schur_rows", "intersect", "point_blocks", "chol_backward", "update"),
               key=lambda k: per_step[k])
     chol_flops, _ = rcs_flops(scene)
@@ -171,11 +179,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.path == "fp64" else "f32+f64",
         "data": "synthetic (seeded oblique strip block)",
         "config": {"workload": "oblique-strips-6000cam-2.5Mpt-64subblocks" if not args.small else "oblique-small",
                    "cameras": scene.M, "points": scene.N, "observations": scene.K, "subblocks": scene.L,
-                   "path": "fp64-cholesky", "step": "intersect + subblock LM step + consensus (HIP graphs)",
+                   "path": args.path, "step": "intersect + subblock LM step + consensus (HIP graphs)",
                    "seed": args.seed},
         "roofline": roof,
         "cpu_baseline": cpu,

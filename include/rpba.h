@@ -169,17 +169,55 @@ const char *rpba_last_error(void);
  * rpba_num_copies: number of (sub-block, point) copies.
  * rpba_get_copies: copies in library order with sub-block, original point
  *   index, X^l [n][3] and Omega [n][6]; any pointer may be NULL.
- * rpba_get_block_rcs: the reduced camera system S (n6 x n6, row-major, lower
- *   triangle valid) and right-hand side e of sub-block l as assembled by the
- *   last rpba_subblock_lm_step (before factorisation), n6 = 6 cameras of l
- *   (cameras in ascending original index).  Only for the Cholesky path; call
- *   rpba_set_debug(h, 1) before the step.
+ * rpba_get_block_rcs: assembles the reduced camera system of every sub-block at
+ *   the current state (as an LM step would, without solving) and copies S of
+ *   sub-block l (n6 x n6 row-major; the lower triangle for Cholesky
+ *   sub-blocks, both triangles of the stored FP32 blocks for iterative ones)
+ *   and e; n6 = 6 cameras of l, cameras in ascending original index.
  * rpba_block_cameras: number of cameras of sub-block l. */
 int64_t rpba_num_copies(rpba_problem *h);
 rpba_status rpba_get_copies(rpba_problem *h, int32_t *blk, int32_t *pt, double *X, double *omega);
 rpba_status rpba_set_debug(rpba_problem *h, int32_t on);
 rpba_status rpba_get_block_rcs(rpba_problem *h, int32_t l, double *S, double *e);
 int32_t rpba_block_cameras(rpba_problem *h, int32_t l);
+/* rpba_get_block_solution: the camera step (n6 values) of sub-block l from the
+ * last rpba_subblock_lm_step.  rpba_block_solver: 0 = Cholesky, 1 = iterative. */
+rpba_status rpba_get_block_solution(rpba_problem *h, int32_t l, double *x);
+int32_t rpba_block_solver(rpba_problem *h, int32_t l);
+
+/* ------------------------------------------------ learned block preconditioner
+ * With RPBA_SOLVER_PCG_LEARNED the CG preconditioner keeps the block-diagonal
+ * form of block-Jacobi (paper Sec. 3 and 5.4) with blocks
+ * P_i = G^-T L L^T G^-1, S_ii = G G^T, L = I + strict lower part from a
+ * 26 -> 64 -> 64 -> 21 network (tanh) on per-camera features, exp(.) on the
+ * diagonal: SPD for any output, block-Jacobi for a zero output (the default
+ * until weights are set).
+ * rpba_precond_num_params: number of FP32 network parameters (W1[64][26],
+ *   b1[64], W2[64][64], b2[64], W3[21][64], b3[21]).
+ * rpba_set_precond_weights: copy the parameters (DEVICE, FP32) into the
+ *   workspace.
+ * rpba_precond_num_samples: cameras of the iterative sub-blocks.
+ * rpba_precond_sample_stride: floats per training sample for nz probes:
+ *   features (26), G^-1 (36, row-major lower), z_i (6 nz), (S z)_i (6 nz).
+ * rpba_precond_harvest: assemble the systems at the current state and write one
+ *   sample per camera of the iterative sub-blocks; z: DEVICE [nz][M][6] probe
+ *   vectors indexed by the library's camera order (random signs supplied by
+ *   the caller); out: DEVICE [samples][stride].
+ * rpba_precond_train_scratch: bytes of DEVICE scratch for rpba_precond_train_step.
+ * rpba_precond_train_step: on `stream`, the loss
+ *   (1 / (nz nsamp)) sum |z_i - P_i (S z)_i|^2 of the samples and its gradient
+ *   (grad[NPAR], DEVICE); with `apply`, one Adam step (beta 0.9 / 0.999,
+ *   eps 1e-8, step count t >= 1) on W with moments m, v (DEVICE).  loss: DEVICE
+ *   [1] or NULL. */
+int32_t rpba_precond_num_params(void);
+rpba_status rpba_set_precond_weights(rpba_problem *h, const float *W);
+int32_t rpba_precond_num_samples(rpba_problem *h);
+int32_t rpba_precond_sample_stride(int32_t nz);
+rpba_status rpba_precond_harvest(rpba_problem *h, const float *z, int32_t nz, float *out);
+size_t rpba_precond_train_scratch(int32_t nsamp);
+rpba_status rpba_precond_train_step(const float *samples, int32_t nsamp, int32_t nz, float *W, float *m, float *v,
+                                    int32_t t, float lr, void *scratch, float *grad, float *loss, int32_t apply,
+                                    void *stream);
 
 /* ---------------------------------------------------------------- execution
  * rpba_set_graph: when on, each of rpba_intersect, rpba_subblock_lm_step and

@@ -25,7 +25,9 @@ EXPORTS = [
     "rpba_default_options", "rpba_workspace_size", "rpba_create", "rpba_intersect", "rpba_robust_reweight",
     "rpba_subblock_lm_step", "rpba_consensus", "rpba_destroy", "rpba_last_error", "rpba_num_copies",
     "rpba_get_copies", "rpba_set_debug", "rpba_get_block_rcs", "rpba_block_cameras", "rpba_selftest_gemm",
-    "rpba_set_graph", "rpba_set_timing", "rpba_get_timing",
+    "rpba_set_graph", "rpba_set_timing", "rpba_get_timing", "rpba_get_block_solution", "rpba_block_solver",
+    "rpba_precond_num_params", "rpba_set_precond_weights", "rpba_precond_num_samples", "rpba_precond_sample_stride",
+    "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step",
 ]
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
           "robust", "iterative_solve"]
@@ -87,12 +89,28 @@ def load_library(path: str = LIB_PATH):
     L.rpba_block_cameras.restype = i32
     L.rpba_block_cameras.argtypes = [vp, i32]
     L.rpba_selftest_gemm.argtypes = [dp, dp, dp, vp]
+    L.rpba_precond_num_params.restype = i32
+    L.rpba_precond_num_params.argtypes = []
+    L.rpba_set_precond_weights.argtypes = [vp, vp]
+    L.rpba_precond_num_samples.restype = i32
+    L.rpba_precond_num_samples.argtypes = [vp]
+    L.rpba_precond_sample_stride.restype = i32
+    L.rpba_precond_sample_stride.argtypes = [i32]
+    L.rpba_precond_harvest.argtypes = [vp, vp, i32, vp]
+    L.rpba_precond_train_scratch.restype = ctypes.c_size_t
+    L.rpba_precond_train_scratch.argtypes = [i32]
+    L.rpba_precond_train_step.argtypes = [vp, i32, i32, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, i32, vp]
+    L.rpba_get_block_solution.argtypes = [vp, i32, vp]
+    L.rpba_block_solver.restype = i32
+    L.rpba_block_solver.argtypes = [vp, i32]
     L.rpba_set_graph.argtypes = [vp, i32]
     L.rpba_set_timing.argtypes = [vp, i32]
     L.rpba_get_timing.restype = i32
     L.rpba_get_timing.argtypes = [vp, vp, vp, vp, i32]
     for name in EXPORTS:
-        if name not in ("rpba_last_error", "rpba_num_copies", "rpba_block_cameras", "rpba_get_timing"):
+        if name not in ("rpba_last_error", "rpba_num_copies", "rpba_block_cameras", "rpba_get_timing",
+                        "rpba_block_solver", "rpba_precond_num_params", "rpba_precond_num_samples",
+                        "rpba_precond_sample_stride", "rpba_precond_train_scratch"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -115,6 +133,25 @@ def default_options(**kw) -> Options:
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def precond_num_params():
+    return int(load_library().rpba_precond_num_params())
+
+
+def precond_train_step(samples, nz, W, m, v, t, lr, scratch, grad, loss, apply=True, stream=None):
+    """One training step of the preconditioner network on `samples` (FP32
+    device tensor [n][stride]); with apply=False only loss and gradient."""
+    import torch
+    L = load_library()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.rpba_precond_train_step(_ptr(samples), int(samples.shape[0]), nz, _ptr(W), _ptr(m), _ptr(v), int(t),
+                                     float(lr), _ptr(scratch), _ptr(grad), _ptr(loss), int(apply),
+                                     ctypes.c_void_p(st.cuda_stream)), "rpba_precond_train_step")
+
+
+def precond_train_scratch_bytes(nsamp):
+    return int(load_library().rpba_precond_train_scratch(int(nsamp)))
 
 
 def selftest_gemm(A, B):
@@ -250,6 +287,31 @@ class Problem:
         e = np.zeros(n6)
         _check(self.L_.rpba_get_block_rcs(self.h, l, S.ctypes.data, e.ctypes.data), "rpba_get_block_rcs")
         return S, e
+
+    def block_solution(self, l):
+        n6 = 6 * int(self.L_.rpba_block_cameras(self.h, l))
+        x = np.zeros(n6)
+        _check(self.L_.rpba_get_block_solution(self.h, l, x.ctypes.data), "rpba_get_block_solution")
+        return x
+
+    def set_precond_weights(self, W):
+        """W: FP32 device tensor of rpba_precond_num_params() parameters."""
+        self._order()
+        _check(self.L_.rpba_set_precond_weights(self.h, _ptr(W)), "rpba_set_precond_weights")
+
+    def precond_harvest(self, z):
+        """Training samples of the systems at the current state; z: FP32 device
+        tensor (nz, M, 6) of probe vectors."""
+        nz = int(z.shape[0])
+        ns = int(self.L_.rpba_precond_num_samples(self.h))
+        stride = int(self.L_.rpba_precond_sample_stride(nz))
+        out = self.torch.empty((ns, stride), dtype=self.torch.float32, device=self.dev)
+        self._order()
+        _check(self.L_.rpba_precond_harvest(self.h, _ptr(z), nz, _ptr(out)), "rpba_precond_harvest")
+        return out
+
+    def block_solver(self, l):
+        return int(self.L_.rpba_block_solver(self.h, l))
 
     def cameras(self):
         self.stream.synchronize()

@@ -45,7 +45,8 @@ struct Layout {
 struct WsMap {
   size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
-      bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr;
+      bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
+      Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -91,6 +92,12 @@ WsMap layout_for(const Plan& P) {
   m.bsr_row_off = L.add(i4 * P.bsr_row_off.size());
   m.bsr_col = L.add(i4 * P.bsr_col.size());
   m.bsr = L.add(4 * 36 * (size_t)P.nbsr);
+  m.Pblk = L.add(4 * 36 * (size_t)P.M);
+  m.pcg_list = L.add(i4 * P.L);
+  m.mean_diag = L.add(4 * (size_t)P.L);
+  m.cam_tpfrac = L.add(4 * (size_t)P.M);
+  m.mlp_w = L.add(4 * (size_t)mlp_num_params());
+  m.pcg_cams = L.add(i4 * P.M);
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -158,6 +165,8 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
   return RPBA_OK;
 }
 
+bool pcg_bytes_ok(int max_n) { return pcg_lds_bytes(max_n) <= 150 * 1024; }
+
 }  // namespace
 
 // A captured call, replayed while its pointer arguments stay the same.
@@ -184,6 +193,12 @@ struct rpba_problem {
   char* ws;
   size_t max_lds_schur;
   std::vector<uint8_t> blk_pcg;
+  // Cholesky work lists restricted to the sub-blocks solved densely
+  std::vector<int64_t> pot_off, fwd_off, upd_off, bwd_off;
+  int32_t nt_max_dense = 0;
+  int32_t n_pcg = 0, max_pcg_n = 0, n_pcg_cams = 0;
+  bool have_weights = false;
+  bool any_dense = true;
   bool intersected = false;
   bool use_graph = false;
   CallGraph g_int, g_step, g_cons;
@@ -343,10 +358,6 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.rcs_off, p.rcs_off.data(), 8 * p.rcs_off.size()));
   HIP_TRY(up(m.diag_off, p.diag_off.data(), 8 * p.diag_off.size()));
   HIP_TRY(up(m.vec_off, p.vec_off.data(), 8 * p.vec_off.size()));
-  HIP_TRY(up(m.fwd_items, p.fwd_items.data(), 4 * p.fwd_items.size()));
-  HIP_TRY(up(m.bwd_items, p.bwd_items.data(), 4 * p.bwd_items.size()));
-  HIP_TRY(up(m.upd_items, p.upd_items.data(), 4 * p.upd_items.size()));
-  HIP_TRY(up(m.pot_items, p.pot_items.data(), 4 * p.pot_items.size()));
   HIP_TRY(up(m.pb_row, p.pb_row.data(), 4 * p.pb_row.size()));
   HIP_TRY(up(m.pb_ent_off, p.pb_ent_off.data(), 8 * p.pb_ent_off.size()));
   HIP_TRY(up(m.pb_ent, p.pb_ent.data(), 4 * p.pb_ent.size()));
@@ -355,8 +366,76 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.pb_bsr_t, p.pb_bsr_t.data(), 4 * p.pb_bsr_t.size()));
   HIP_TRY(up(m.bsr_row_off, p.bsr_row_off.data(), 4 * p.bsr_row_off.size()));
   HIP_TRY(up(m.bsr_col, p.bsr_col.data(), 4 * p.bsr_col.size()));
+  // solver of every sub-block
   h->blk_pcg.assign(p.L, 0);
+  std::vector<int32_t> pcg_list;
+  for (int l = 0; l < p.L; ++l) {
+    const int ncam = p.blk_cam_off[l + 1] - p.blk_cam_off[l];
+    bool it = o->solver == RPBA_SOLVER_PCG_BJ || o->solver == RPBA_SOLVER_PCG_LEARNED ||
+              (o->solver == RPBA_SOLVER_AUTO && ncam >= o->pcg_min_cams);
+    if (it) {
+      h->blk_pcg[l] = 1;
+      pcg_list.push_back(l);
+      h->max_pcg_n = std::max(h->max_pcg_n, 6 * ncam);
+    }
+  }
+  h->n_pcg = (int32_t)pcg_list.size();
+  {
+    std::vector<int32_t> cams;
+    for (int32_t l : pcg_list)
+      for (int32_t i = p.blk_cam_off[l]; i < p.blk_cam_off[l + 1]; ++i) cams.push_back(i);
+    h->n_pcg_cams = (int32_t)cams.size();
+    HIP_TRY(up(m.pcg_cams, cams.data(), 4 * cams.size()));
+    // tie-point fraction of every camera's observations (a feature of the
+    // learned preconditioner)
+    std::vector<float> tpf(p.M, 0.f);
+    for (int32_t i = 0; i < p.M; ++i) {
+      int32_t n = 0, tp = 0;
+      for (int32_t q = p.cam_obs_off[i]; q < p.cam_obs_off[i + 1]; ++q) {
+        const int32_t pt = p.copy_pt[p.obs_copy[p.cam_obs[q]]];
+        ++n;
+        tp += (p.pt_copy_off[pt + 1] - p.pt_copy_off[pt]) > 1;
+      }
+      tpf[i] = n ? (float)tp / (float)n : 0.f;
+    }
+    HIP_TRY(up(m.cam_tpfrac, tpf.data(), 4 * tpf.size()));
+    std::vector<float> w0(mlp_num_params(), 0.f);  // zero network: block-Jacobi
+    HIP_TRY(up(m.mlp_w, w0.data(), 4 * w0.size()));
+  }
+  if (pcg_bytes_ok(h->max_pcg_n) == false)
+    return fail(RPBA_ERR_ARG, "a sub-block is too large for the single-workgroup iterative solver");
   HIP_TRY(up(m.blk_pcg, h->blk_pcg.data(), p.L));
+  HIP_TRY(up(m.pcg_list, pcg_list.data(), 4 * pcg_list.size()));
+  // Cholesky work lists without the iterative sub-blocks (same order, same
+  // positions in the workspace arrays)
+  {
+    auto filt = [&](const std::vector<int32_t>& items, const std::vector<int64_t>& off, std::vector<int32_t>& out,
+                    std::vector<int64_t>& out_off) {
+      out.clear();
+      out_off.assign(off.size(), 0);
+      for (size_t k = 0; k + 1 < off.size(); ++k) {
+        for (int64_t t = off[k]; t < off[k + 1]; ++t)
+          if (!h->blk_pcg[items[t] >> 16]) out.push_back(items[t]);
+        out_off[k + 1] = (int64_t)out.size();
+      }
+    };
+    std::vector<int32_t> tmp;
+    filt(p.pot_items, p.pot_off, tmp, h->pot_off);
+    HIP_TRY(up(m.pot_items, tmp.data(), 4 * tmp.size()));
+    filt(p.fwd_items, p.fwd_off, tmp, h->fwd_off);
+    HIP_TRY(up(m.fwd_items, tmp.data(), 4 * tmp.size()));
+    filt(p.upd_items, p.upd_off, tmp, h->upd_off);
+    HIP_TRY(up(m.upd_items, tmp.data(), 4 * tmp.size()));
+    filt(p.bwd_items, p.bwd_off, tmp, h->bwd_off);
+    HIP_TRY(up(m.bwd_items, tmp.data(), 4 * tmp.size()));
+    h->any_dense = false;
+    h->nt_max_dense = 0;
+    for (int l = 0; l < p.L; ++l)
+      if (!h->blk_pcg[l]) {
+        h->any_dense = true;
+        h->nt_max_dense = std::max(h->nt_max_dense, p.nt[l]);
+      }
+  }
 
   Dev& D = h->d;
   std::memset(&D, 0, sizeof(D));
@@ -419,6 +498,9 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.pb_bsr_t = I(m.pb_bsr_t);
   D.blk_pcg = (const uint8_t*)(w + m.blk_pcg);
   D.bsr = (float*)(w + m.bsr);
+  D.bsr_row_off = I(m.bsr_row_off);
+  D.bsr_col = I(m.bsr_col);
+  D.Pblk = (float*)(w + m.Pblk);
   D.S = F(m.S);
   D.Ld = F(m.Ld);
   D.Li = F(m.Li);
@@ -479,10 +561,8 @@ static rpba_status assemble(rpba_problem* h, const uint8_t* active) {
   }
   {
     const bool fp32 = h->opt.precision == RPBA_MIXED;
-    bool dense = false;
-    for (uint8_t b : h->blk_pcg) dense |= (b == 0);
-    PhaseTimer t(h, PH_SCHUR, (h->d.n_od ? 2 : 1) + (dense ? 2 : 0));
-    launch_schur(h->d, fp32, dense, h->plan->rcs_total, h->stream);
+    PhaseTimer t(h, PH_SCHUR, (h->d.n_od ? 2 : 1) + (h->any_dense ? 2 : 0));
+    launch_schur(h->d, fp32, h->any_dense, h->plan->rcs_total, h->stream);
   }
   HIP_TRY(hipGetLastError());
   return RPBA_OK;
@@ -499,18 +579,30 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
     const int32_t* fwd = (const int32_t*)(h->ws + h->map.fwd_items);
     const int32_t* upd = (const int32_t*)(h->ws + h->map.upd_items);
     const int32_t* bwd = (const int32_t*)(h->ws + h->map.bwd_items);
-    {
-      PhaseTimer t(h, PH_CHOL_FWD, 3 * p.nt_max);
-      for (int k = 0; k < p.nt_max; ++k)
-        launch_chol_step(h->d, k, pot + p.pot_off[k], p.pot_off[k + 1] - p.pot_off[k], fwd + p.fwd_off[k],
-                         p.fwd_off[k + 1] - p.fwd_off[k], upd + p.upd_off[k], p.upd_off[k + 1] - p.upd_off[k],
-                         h->stream);
+    if (h->any_dense) {
+      {
+        PhaseTimer t(h, PH_CHOL_FWD, 3 * h->nt_max_dense);
+        for (int k = 0; k < h->nt_max_dense; ++k)
+          launch_chol_step(h->d, k, pot + h->pot_off[k], h->pot_off[k + 1] - h->pot_off[k], fwd + h->fwd_off[k],
+                           h->fwd_off[k + 1] - h->fwd_off[k], upd + h->upd_off[k], h->upd_off[k + 1] - h->upd_off[k],
+                           h->stream);
+      }
+      {
+        PhaseTimer t(h, PH_CHOL_BWD, h->nt_max_dense + 1);
+        launch_rhs_extract(h->d, h->stream);
+        for (int s2 = 0; s2 < p.nt_max; ++s2)
+          launch_chol_backward(h->d, bwd + h->bwd_off[s2], h->bwd_off[s2 + 1] - h->bwd_off[s2], h->stream);
+      }
     }
-    {
-      PhaseTimer t(h, PH_CHOL_BWD, p.nt_max + 1);
-      launch_rhs_extract(h->d, h->stream);
-      for (int s2 = 0; s2 < p.nt_max; ++s2)
-        launch_chol_backward(h->d, bwd + p.bwd_off[s2], p.bwd_off[s2 + 1] - p.bwd_off[s2], h->stream);
+    if (h->n_pcg) {
+      const bool learned = h->opt.solver == RPBA_SOLVER_PCG_LEARNED;
+      PhaseTimer t(h, PH_SOLVE_IT, learned ? 3 : 2);
+      if (learned) launch_mean_diag(h->d, (float*)(h->ws + h->map.mean_diag), h->stream);
+      launch_precond_learned(h->d, learned ? (const float*)(h->ws + h->map.mlp_w) : nullptr,
+                             (const float*)(h->ws + h->map.mean_diag), (const float*)(h->ws + h->map.cam_tpfrac),
+                             h->stream);
+      launch_pcg(h->d, (const int32_t*)(h->ws + h->map.pcg_list), h->n_pcg, h->max_pcg_n, h->opt.pcg_maxit,
+                 h->opt.pcg_tol, h->opt.ir_tol, h->opt.ir_maxit, h->stream);
     }
     {
       PhaseTimer t(h, PH_UPDATE, 4);
@@ -617,11 +709,74 @@ rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e)
   if ((int64_t)need <= p.diag_total * 2) stage = h->d.Ld;  // Ld and Li are contiguous in the layout
   else if ((int64_t)need <= 12 * p.NC) stage = h->d.cpk;
   else return fail(RPBA_ERR_STATE, "no staging space for this sub-block");
-  launch_rcs_extract(h->d, l, stage, stage + (size_t)n6 * n6, h->stream);
+  if (h->blk_pcg[l]) {
+    launch_zero(stage, (int64_t)n6 * n6, h->stream);
+    launch_bsr_extract(h->d, l, stage, stage + (size_t)n6 * n6, h->stream);
+  } else {
+    launch_rcs_extract(h->d, l, stage, stage + (size_t)n6 * n6, h->stream);
+  }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (S) HIP_TRY(hipMemcpy(S, stage, 8 * (size_t)n6 * n6, hipMemcpyDeviceToHost));
   if (e) HIP_TRY(hipMemcpy(e, stage + (size_t)n6 * n6, 8 * (size_t)n6, hipMemcpyDeviceToHost));
+  return RPBA_OK;
+}
+
+rpba_status rpba_get_block_solution(rpba_problem* h, int32_t l, double* x) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  const Plan& p = *h->plan;
+  if (l < 0 || l >= p.L) return fail(RPBA_ERR_ARG, "sub-block out of range");
+  int n6 = 6 * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(x, h->d.x + p.vec_off[l], 8 * (size_t)n6, hipMemcpyDeviceToHost));
+  return RPBA_OK;
+}
+
+int32_t rpba_block_solver(rpba_problem* h, int32_t l) {
+  if (!h || l < 0 || l >= h->plan->L) return -1;
+  return h->blk_pcg[l] ? 1 : 0;
+}
+
+int32_t rpba_precond_num_params(void) { return mlp_num_params(); }
+
+int32_t rpba_precond_sample_stride(int32_t nz) { return mlp_num_features() + 36 + 12 * nz; }
+
+int32_t rpba_precond_num_samples(rpba_problem* h) { return h ? h->n_pcg_cams : -1; }
+
+rpba_status rpba_set_precond_weights(rpba_problem* h, const float* W) {
+  if (!h || !W) return fail(RPBA_ERR_ARG, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(h->ws + h->map.mlp_w, W, 4 * (size_t)mlp_num_params(), hipMemcpyDeviceToDevice, h->stream));
+  h->have_weights = true;
+  return RPBA_OK;
+}
+
+rpba_status rpba_precond_harvest(rpba_problem* h, const float* z, int32_t nz, float* out) {
+  if (!h || !z || !out || nz < 1) return fail(RPBA_ERR_ARG, "bad harvest arguments");
+  if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run first");
+  if (h->n_pcg == 0) return fail(RPBA_ERR_STATE, "no sub-block uses the iterative solver");
+  rpba_status s = assemble(h, nullptr);
+  if (s != RPBA_OK) return s;
+  launch_mean_diag(h->d, (float*)(h->ws + h->map.mean_diag), h->stream);
+  launch_harvest(h->d, (const float*)(h->ws + h->map.mean_diag), (const float*)(h->ws + h->map.cam_tpfrac), z, nz,
+                 (const int32_t*)(h->ws + h->map.pcg_cams), h->n_pcg_cams, out, h->stream);
+  HIP_TRY(hipGetLastError());
+  return RPBA_OK;
+}
+
+size_t rpba_precond_train_scratch(int32_t nsamp) {
+  return 4 * ((size_t)nsamp * mlp_scratch_per_sample() + (size_t)((nsamp + 255) / 256) + 64);
+}
+
+rpba_status rpba_precond_train_step(const float* samples, int32_t nsamp, int32_t nz, float* W, float* m, float* v,
+                                    int32_t t, float lr, void* scratch, float* grad, float* loss, int32_t apply,
+                                    void* stream) {
+  if (!samples || nsamp < 1 || nz < 1 || !W || !grad || !scratch || (apply && (!m || !v || t < 1)))
+    return fail(RPBA_ERR_ARG, "bad training arguments");
+  float* sc = (float*)scratch;
+  float* parts = sc + (size_t)nsamp * mlp_scratch_per_sample();
+  launch_train_step(samples, nsamp, nz, W, m, v, t, lr, sc, grad, parts, apply != 0, (hipStream_t)stream);
+  if (loss) launch_sum_f32(parts, (nsamp + 255) / 256, loss, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
   return RPBA_OK;
 }
 

@@ -69,6 +69,9 @@ struct Dev {
   const int32_t* pb_bsr_t;
   const uint8_t* blk_pcg;  // [L] 1 = iterative solver (block-sparse output)
   float* bsr;              // [nbsr][36] FP32 blocks of the reduced camera systems
+  const int32_t* bsr_row_off;  // [M+1]
+  const int32_t* bsr_col;      // local column camera of each block
+  float* Pblk;             // [M][36] preconditioner blocks (row-major 6x6)
 
   // dense reduced camera systems
   double* S;              // tiles, lower triangle per sub-block
@@ -122,6 +125,21 @@ void launch_consensus(const Dev& d, double* stats, hipStream_t st);
 void launch_zero(double* p, int64_t n, hipStream_t st);
 void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);
+void launch_bsr_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);
+size_t pcg_lds_bytes(int max_n);
+int mlp_num_params();
+int mlp_num_features();
+int mlp_scratch_per_sample();
+void launch_mean_diag(const Dev& d, float* mean_diag, hipStream_t st);
+void launch_precond_learned(const Dev& d, const float* W, const float* mean_diag, const float* cam_tpfrac,
+                            hipStream_t st);
+void launch_harvest(const Dev& d, const float* mean_diag, const float* cam_tpfrac, const float* z, int nz,
+                    const int32_t* cams, int ncams, float* out, hipStream_t st);
+void launch_train_step(const float* samples, int nsamp, int nz, float* W, float* m, float* v, int t, float lr,
+                       float* scratch, float* grad, float* loss_part, bool apply, hipStream_t st);
+void launch_sum_f32(const float* parts, int n, float* out, hipStream_t st);
+void launch_pcg(const Dev& d, const int32_t* blocks, int nblocks, int max_n, int pcg_maxit, double pcg_tol,
+                double ir_tol, int ir_maxit, hipStream_t st);
 // in-bounds layout check of the FP64 MFMA tile product: C = A B^T (64x64, row-major)
 void launch_selftest_gemm(const double* A, const double* B, double* C, hipStream_t st);
 

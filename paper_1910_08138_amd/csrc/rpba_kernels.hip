@@ -465,6 +465,22 @@ __global__ void k_rcs_extract(Dev d, int l, double* S_out, double* e_out) {
     e_out[t] = d.y[d.vec_off[l] + t];
 }
 
+// dense copy-out of an iterative sub-block's block-sparse RCS (output zeroed first)
+__global__ void k_bsr_extract(Dev d, int l, double* S_out, double* e_out) {
+  const int base = d.blk_cam_off[l];
+  const int ncam = d.blk_cam_off[l + 1] - base;
+  const int n6 = 6 * ncam;
+  for (int a = blockIdx.x; a < ncam; a += gridDim.x) {
+    const int i = base + a;
+    for (int b = d.bsr_row_off[i]; b < d.bsr_row_off[i + 1]; ++b) {
+      const int a2 = d.bsr_col[b];
+      for (int t = threadIdx.x; t < 36; t += NT)
+        S_out[(int64_t)(6 * a + t / 6) * n6 + 6 * a2 + t % 6] = (double)d.bsr[(int64_t)b * 36 + t];
+    }
+    if (threadIdx.x < 6) e_out[6 * a + threadIdx.x] = d.y[d.vec_off[l] + 6 * a + threadIdx.x];
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
@@ -516,6 +532,10 @@ void launch_consensus(const Dev& d, double* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_consensus_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_consensus_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
   if (stats) hipLaunchKernelGGL(k_copy2, dim3(1), dim3(64), 0, st, (const double*)d.acc_cons, stats, 2);
+}
+
+void launch_bsr_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_bsr_extract, dim3(256), dim3(NT), 0, st, d, l, S_out, e_out);
 }
 
 void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st) {
