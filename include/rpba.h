@@ -139,6 +139,13 @@ rpba_status rpba_intersect(rpba_problem *h, double *cov, int32_t *status, double
  * eliminated points (or NULL). */
 rpba_status rpba_robust_reweight(rpba_problem *h, int32_t eliminate, double *stats);
 
+/* Result of the last rpba_robust_reweight: sigma_cam [M] the per-camera
+ * scales sigma0_i (0 for a camera without a valid observation), obs_weight
+ * [K] the weight multipliers (1 or down_weight), both HOST, in the caller's
+ * camera and observation order; either may be NULL.  Synchronises the
+ * handle's stream. */
+rpba_status rpba_get_robust(rpba_problem *h, double *sigma_cam, double *obs_weight);
+
 /* One LM iteration of every active sub-block (eq:bact): normal equations of
  * the sub-block's cameras and point copies with the TPs as stochastic control
  * points, cost sum v^T W v + (X - Xbar)^T Omega (X - Xbar); damping

@@ -27,7 +27,7 @@ EXPORTS = [
     "rpba_get_copies", "rpba_set_debug", "rpba_get_block_rcs", "rpba_block_cameras", "rpba_selftest_gemm",
     "rpba_set_graph", "rpba_set_timing", "rpba_get_timing", "rpba_get_block_solution", "rpba_block_solver",
     "rpba_precond_num_params", "rpba_set_precond_weights", "rpba_precond_num_samples", "rpba_precond_sample_stride",
-    "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step",
+    "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
 ]
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
           "robust", "iterative_solve"]
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
                               ctypes.POINTER(vp)]
     L.rpba_intersect.argtypes = [vp, dp, dp, dp]
     L.rpba_robust_reweight.argtypes = [vp, i32, dp]
+    L.rpba_get_robust.argtypes = [vp, vp, vp]
     L.rpba_subblock_lm_step.argtypes = [vp, dp, dp]
     L.rpba_consensus.argtypes = [vp, dp]
     L.rpba_destroy.argtypes = [vp]
@@ -256,6 +257,14 @@ class Problem:
         self._order()
         _check(self.L_.rpba_robust_reweight(self.h, int(eliminate), _ptr(self.rob_stats)), "rpba_robust_reweight")
         return self.rob_stats
+
+    def robust_result(self):
+        """(sigma_cam [M], obs_weight [K]) of the last robust re-weighting,
+        caller order, on the host."""
+        sc = np.zeros(self.M)
+        w = np.zeros(self.K)
+        _check(self.L_.rpba_get_robust(self.h, sc.ctypes.data, w.ctypes.data), "rpba_get_robust")
+        return sc, w
 
     def rpba_subblock_lm_step(self, active=None):
         self._order()

@@ -46,11 +46,26 @@ struct WsMap {
   size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
-      Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams;
+      Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
 };
+
+// doubles of global staging for the robust medians: cameras whose residual
+// components do not fit the workgroup's LDS
+int64_t robust_spill_values(const Plan& P, std::vector<int64_t>* off = nullptr) {
+  int64_t tot = 0;
+  if (off) off->assign(P.M, 0);
+  for (int i = 0; i < P.M; ++i) {
+    const int64_t n2 = 2 * (int64_t)(P.cam_obs_off[i + 1] - P.cam_obs_off[i]);
+    if (n2 > robust_lds_values()) {
+      if (off) (*off)[i] = tot;
+      tot += n2;
+    }
+  }
+  return tot;
+}
 
 WsMap layout_for(const Plan& P) {
   Layout L;
@@ -98,6 +113,10 @@ WsMap layout_for(const Plan& P) {
   m.cam_tpfrac = L.add(4 * (size_t)P.M);
   m.mlp_w = L.add(4 * (size_t)mlp_num_params());
   m.pcg_cams = L.add(i4 * P.M);
+  m.rob_bad = L.add(i4 * P.N);
+  m.rob_off = L.add(i8 * P.M);
+  m.rob_vals = L.add(f8 * robust_spill_values(P));
+  m.rob_sigma = L.add(f8 * P.M);
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -201,7 +220,7 @@ struct rpba_problem {
   bool any_dense = true;
   bool intersected = false;
   bool use_graph = false;
-  CallGraph g_int, g_step, g_cons;
+  CallGraph g_int, g_step, g_cons, g_rob, g_rob_elim;
   bool timing = false;
   hipEvent_t ev[NPHASE + 1] = {};
   double ms[NPHASE] = {};
@@ -211,6 +230,8 @@ struct rpba_problem {
     g_int.reset();
     g_step.reset();
     g_cons.reset();
+    g_rob.reset();
+    g_rob_elim.reset();
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
   }
@@ -405,6 +426,11 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   if (pcg_bytes_ok(h->max_pcg_n) == false)
     return fail(RPBA_ERR_ARG, "a sub-block is too large for the single-workgroup iterative solver");
   HIP_TRY(up(m.blk_pcg, h->blk_pcg.data(), p.L));
+  {
+    std::vector<int64_t> roff;
+    robust_spill_values(p, &roff);
+    HIP_TRY(up(m.rob_off, roff.data(), 8 * roff.size()));
+  }
   HIP_TRY(up(m.pcg_list, pcg_list.data(), 4 * pcg_list.size()));
   // Cholesky work lists without the iterative sub-blocks (same order, same
   // positions in the workspace arrays)
@@ -529,6 +555,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero(D.ys, p.vec_total, st);
   launch_zero(D.x, p.vec_total, st);
   launch_zero_i32(D.blk_fail, D.L, st);
+  launch_zero_i32((int32_t*)(w + m.rob_bad), D.N, st);
+  launch_zero((double*)(w + m.rob_sigma), D.M, st);
   launch_init_rcs(D, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
@@ -660,10 +688,33 @@ int32_t rpba_get_timing(rpba_problem* h, double* ms, int64_t* launches, int64_t*
 }
 
 rpba_status rpba_robust_reweight(rpba_problem* h, int32_t eliminate, double* stats) {
-  (void)eliminate;
-  (void)stats;
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
-  return fail(RPBA_ERR_STATE, "robust re-weighting not available");
+  if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run before rpba_robust_reweight");
+  CallGraph& g = eliminate ? h->g_rob_elim : h->g_rob;
+  return run_call(h, g, stats, nullptr, nullptr, [&]() -> rpba_status {
+    PhaseTimer t(h, PH_ROBUST, stats ? 4 : 3);
+    launch_robust(h->d, (double*)(h->ws + h->map.rob_vals), (const int64_t*)(h->ws + h->map.rob_off),
+                  (int32_t*)(h->ws + h->map.rob_bad), (double*)(h->ws + h->map.rob_sigma), h->opt.t_v,
+                  h->opt.down_weight, eliminate, stats, h->stream);
+    return RPBA_OK;
+  });
+}
+
+rpba_status rpba_get_robust(rpba_problem* h, double* sigma_cam, double* obs_weight) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  const Plan& p = *h->plan;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (sigma_cam) {
+    std::vector<double> t(p.M);
+    HIP_TRY(hipMemcpy(t.data(), h->ws + h->map.rob_sigma, 8 * (size_t)p.M, hipMemcpyDeviceToHost));
+    for (int i = 0; i < p.M; ++i) sigma_cam[p.cam_orig[i]] = t[i];
+  }
+  if (obs_weight) {
+    std::vector<double> t(p.K);
+    HIP_TRY(hipMemcpy(t.data(), h->d.rw, 8 * (size_t)p.K, hipMemcpyDeviceToHost));
+    for (int k = 0; k < p.K; ++k) obs_weight[p.obs_orig[k]] = t[k];
+  }
+  return RPBA_OK;
 }
 
 int64_t rpba_num_copies(rpba_problem* h) { return h ? h->plan->NC : -1; }

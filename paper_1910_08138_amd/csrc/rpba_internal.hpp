@@ -126,6 +126,9 @@ void launch_zero(double* p, int64_t n, hipStream_t st);
 void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);
 void launch_bsr_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);
+int robust_lds_values();
+void launch_robust(const Dev& d, double* spill, const int64_t* spill_off, int32_t* bad, double* sigma_cam, double t_v,
+                   double down_weight, int eliminate, double* stats, hipStream_t st);
 size_t pcg_lds_bytes(int max_n);
 int mlp_num_params();
 int mlp_num_features();
