@@ -46,7 +46,8 @@ struct WsMap {
   size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
-      Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma;
+      Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
+      pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -117,6 +118,14 @@ WsMap layout_for(const Plan& P) {
   m.rob_off = L.add(i8 * P.M);
   m.rob_vals = L.add(f8 * robust_spill_values(P));
   m.rob_sigma = L.add(f8 * P.M);
+  m.pm_off = L.add(i4 * P.pm_off.size());
+  m.pm_k = L.add(i4 * P.pm_k.size());
+  m.pm_pos = L.add(i4 * P.pm_pos.size());
+  m.pm_cam = L.add(i4 * P.pm_cam.size());
+  m.iwg_cam_off = L.add(i4 * P.iwg_cam_off.size());
+  m.iwg_cams = L.add(i4 * std::max<size_t>(1, P.iwg_cams.size()));
+  m.pm_xy = L.add(f8 * 2 * P.K);
+  m.pm_w = L.add(f8 * (P.has_info ? 3 : 1) * P.K);
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -369,6 +378,12 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.obs_orig, p.obs_orig.data(), 4 * p.obs_orig.size()));
   HIP_TRY(up(m.cam_obs_off, p.cam_obs_off.data(), 4 * p.cam_obs_off.size()));
   HIP_TRY(up(m.cam_obs, p.cam_obs.data(), 4 * p.cam_obs.size()));
+  HIP_TRY(up(m.pm_off, p.pm_off.data(), 4 * p.pm_off.size()));
+  HIP_TRY(up(m.pm_k, p.pm_k.data(), 4 * p.pm_k.size()));
+  HIP_TRY(up(m.pm_pos, p.pm_pos.data(), 4 * p.pm_pos.size()));
+  HIP_TRY(up(m.pm_cam, p.pm_cam.data(), 4 * p.pm_cam.size()));
+  HIP_TRY(up(m.iwg_cam_off, p.iwg_cam_off.data(), 4 * p.iwg_cam_off.size()));
+  if (!p.iwg_cams.empty()) HIP_TRY(up(m.iwg_cams, p.iwg_cams.data(), 4 * p.iwg_cams.size()));
   HIP_TRY(up(m.copy_off, p.copy_off.data(), 4 * p.copy_off.size()));
   HIP_TRY(up(m.copy_pt, p.copy_pt.data(), 4 * p.copy_pt.size()));
   HIP_TRY(up(m.copy_blk, p.copy_blk.data(), 4 * p.copy_blk.size()));
@@ -505,6 +520,14 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.obs_copy = I(m.obs_copy);
   D.obs_orig = I(m.obs_orig);
   D.cam_obs_off = I(m.cam_obs_off);
+  D.pm_off = I(m.pm_off);
+  D.pm_k = I(m.pm_k);
+  D.pm_pos = I(m.pm_pos);
+  D.pm_cam = I(m.pm_cam);
+  D.iwg_cam_off = I(m.iwg_cam_off);
+  D.iwg_cams = I(m.iwg_cams);
+  D.pm_xy = F(m.pm_xy);
+  D.pm_w = F(m.pm_w);
   D.cam_obs = I(m.cam_obs);
   D.copy_off = I(m.copy_off);
   D.copy_pt = I(m.copy_pt);

@@ -74,110 +74,204 @@ __device__ __forceinline__ double* tile_ptr(const Dev& d, int l, int i, int j) {
   return d.S + d.rcs_off[l] + ((int64_t)i * (i + 1) / 2 + j) * (int64_t)T * T;
 }
 
-// Diagonal tile of step k: Cholesky factor and its inverse.  The 256 threads
-// form a 16 x 16 grid, each holding a B x B block (B = T / 16) of the tile in
-// registers; one column (resp. row) is broadcast through LDS per step.
+// ---- diagonal tile: factor and inverse, blocked by 16 inside the tile.
+// The tile sits in LDS (row-major, row stride T + 1).  For each 16-wide
+// column block kb one wave factors the whole panel below the diagonal
+// (lane = row, the step's column broadcast with readlane, so the serial chain
+// has no LDS round trip) and the trailing blocks are updated on the matrix
+// cores.  Afterwards each wave inverts one 16 x 16 diagonal factor block (lane
+// = column, forward substitution) and the inverse of the whole factor is
+// assembled block row by block row:
+//   Linv(i,i) = D_i^-1,  Linv(i,j) = -D_i^-1 sum_{k=j}^{i-1} L(i,k) Linv(k,j).
+template <int T>
+struct DiagLds {
+  static constexpr int LD = T + 1;
+  double A[T * LD];         // tile, then its factor (lower blocks)
+  double X[T * LD];         // inverse of the factor (lower blocks)
+  double Y[4][16 * 17];     // per-wave 16 x 16 staging
+  double ipv[T];            // 1 / L(c,c)
+  int fail;
+};
+
+__device__ __forceinline__ double bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1 / sqrt(d) for d > 0: hardware estimate and two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * (1.5 - 0.5 * d * y * y);
+  y = y * (1.5 - 0.5 * d * y * y);
+  return y;
+}
+
+// one wave: factor columns o .. o + 15 of rows o .. T - 1 (right-looking
+// inside the panel); lane q holds row o + q
+template <int T>
+__device__ __forceinline__ void factor_panel(DiagLds<T>& sm, int o) {
+  constexpr int LD = DiagLds<T>::LD;
+  const int lane = threadIdx.x & 63;
+  const bool live = o + lane < T;
+  const int row = live ? o + lane : T - 1;
+  double a[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = sm.A[row * LD + o + c];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    double dcc = bcast(a[c], c);
+    if (!(dcc > 0.0)) {  // uniform: no divergence
+      if (lane == 0) sm.fail = 1;
+      dcc = 1.0;
+    }
+    const double ip = rsqrt_nr(dcc);
+    if (lane == 0) sm.ipv[o + c] = ip;
+    const double colv = lane > c ? a[c] * ip : (lane == c ? dcc * ip : 0.0);
+    a[c] = colv;
+#pragma unroll
+    for (int s2 = c + 1; s2 < 16; ++s2) a[s2] -= colv * bcast(colv, s2);
+  }
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) sm.A[row * LD + o + c] = a[c];
+  }
+}
+
+// one wave: X(o.., o..) = inverse of the 16 x 16 factor block at (o, o);
+// lane s computes column s
+template <int T>
+__device__ __forceinline__ void invert16(DiagLds<T>& sm, int o) {
+  constexpr int LD = DiagLds<T>::LD;
+  const int lane = threadIdx.x & 63, s = lane & 15;
+  double x[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    double acc = (t == s) ? 1.0 : 0.0;
+#pragma unroll
+    for (int u = 0; u < t; ++u) acc -= sm.A[(o + t) * LD + o + u] * x[u];
+    x[t] = acc * sm.ipv[o + t];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) sm.X[(o + t) * LD + o + s] = x[t];
+  }
+}
+
+// acc += P Q^T for 16 x 16 blocks of LDS matrices (row stride LD), P at
+// (pr, pc), Q at (qr, qc); `neg` negates P
+template <int LD>
+__device__ __forceinline__ v4d mf16_nt(const double* P, int pr, int pc, const double* Q, int qr, int qc, v4d acc,
+                                       bool neg) {
+  const int lane = threadIdx.x & 63;
+  const int rr = lane & 15, kk0 = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    double a = P[(pr + rr) * LD + pc + 4 * kk + kk0];
+    const double b = Q[(qr + rr) * LD + qc + 4 * kk + kk0];
+    if (neg) a = -a;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// acc += P Q for 16 x 16 blocks (P row stride LDP, Q row stride LDQ)
+template <int LDP, int LDQ>
+__device__ __forceinline__ v4d mf16_nn(const double* P, int pr, int pc, const double* Q, int qr, int qc, v4d acc) {
+  const int lane = threadIdx.x & 63;
+  const int rr = lane & 15, kk0 = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const double a = P[(pr + rr) * LDP + pc + 4 * kk + kk0];
+    const double b = Q[(qr + 4 * kk + kk0) * LDQ + qc + rr];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int LD>
+__device__ __forceinline__ v4d ld16(const double* P, int pr, int pc) {
+  const int lane = threadIdx.x & 63;
+  v4d v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = P[(pr + (lane >> 4) + 4 * e) * LD + pc + (lane & 15)];
+  return v;
+}
+
+template <int LD>
+__device__ __forceinline__ void st16(double* P, int pr, int pc, v4d v, bool neg) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) P[(pr + (lane >> 4) + 4 * e) * LD + pc + (lane & 15)] = neg ? -v[e] : v[e];
+}
+
+// Factor sm.A (T x T, lower part used) and leave L^-1 in sm.X (lower blocks
+// valid, diagonal blocks lower triangular).  All threads of the workgroup.
+template <int T>
+__device__ void factor_inverse_tile(DiagLds<T>& sm) {
+  constexpr int LD = DiagLds<T>::LD, NBK = T / 16;
+  const int wv = threadIdx.x >> 6;
+  for (int kb = 0; kb < NBK; ++kb) {
+    const int o = 16 * kb;
+    if (wv == 0) factor_panel<T>(sm, o);
+    __syncthreads();
+    // trailing update A(ib,jb) -= L(ib,kb) L(jb,kb)^T, kb < jb <= ib
+    const int m = NBK - 1 - kb;
+    if (m > 0) {
+      for (int t = wv; t < m * (m + 1) / 2; t += 4) {
+        int ib = 0;
+        while ((ib + 1) * (ib + 2) / 2 <= t) ++ib;
+        const int jb = t - ib * (ib + 1) / 2;
+        const int I = 16 * (kb + 1 + ib), J = 16 * (kb + 1 + jb);
+        v4d acc = ld16<LD>(sm.A, I, J);
+        acc = mf16_nt<LD>(sm.A, I, o, sm.A, J, o, acc, true);
+        st16<LD>(sm.A, I, J, acc, false);
+      }
+      __syncthreads();
+    }
+  }
+  for (int kb = wv; kb < NBK; kb += 4) invert16<T>(sm, 16 * kb);
+  __syncthreads();
+  // inverse, block row by block row
+  for (int i = 1; i < NBK; ++i) {
+    for (int j = wv; j < i; j += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k = j; k < i; ++k) acc = mf16_nn<LD, LD>(sm.A, 16 * i, 16 * k, sm.X, 16 * k, 16 * j, acc);
+      st16<17>(sm.Y[wv], 0, 0, acc, false);
+      v4d y = {0.0, 0.0, 0.0, 0.0};
+      y = mf16_nn<LD, 17>(sm.X, 16 * i, 16 * i, sm.Y[wv], 0, 0, y);
+      st16<LD>(sm.X, 16 * i, 16 * j, y, true);
+    }
+    __syncthreads();
+  }
+}
+
+// Diagonal tile of step k: the inverse of its Cholesky factor (the factor
+// itself is not needed: the panel solves and the backward substitution use
+// the inverse).  One workgroup per sub-block.
 template <int T>
 __global__ __launch_bounds__(NT) void k_chol_potrf(Dev d, int k, const int32_t* __restrict__ items) {
-  constexpr int B = T / 16;
-  __shared__ double Lsh[T][T + 1];
-  __shared__ double rowx[T];
-  __shared__ double piv;
-  __shared__ int fail;
+  constexpr int LD = DiagLds<T>::LD;
+  __shared__ DiagLds<T> sm;
   const int l = items[blockIdx.x] >> 16;
   if (d.active && !d.active[l]) return;
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
   const double* A = tile_ptr<T>(d, l, k, k);
-  double a[B][B];
-#pragma unroll
-  for (int rr = 0; rr < B; ++rr)
-#pragma unroll
-    for (int ss = 0; ss < B; ++ss) a[rr][ss] = A[mf_idx(T, ti * B + rr, tj * B + ss)];
-  if (threadIdx.x == 0) fail = 0;
-  // right-looking factorisation; per column one pivot broadcast and one
-  // column broadcast through LDS, updates as predicated multiply-adds (no
-  // divergent branches: entries outside the active part are masked to zero
-  // or left untouched by selects)
-  for (int cb = 0; cb < 16; ++cb) {
-#pragma unroll
-    for (int cc = 0; cc < B; ++cc) {
-      const int c = cb * B + cc;
-      if (threadIdx.x == cb * 16 + cb) {
-        double dv = a[cc][cc];
-        if (!(dv > 0.0)) {
-          fail = 1;
-          dv = 1.0;
-        }
-        piv = sqrt(dv);
-      }
-      __syncthreads();
-      const double p = piv;
-      const double ip = 1.0 / p;
-      if (tj == cb) {
-#pragma unroll
-        for (int rr = 0; rr < B; ++rr) {
-          const int r = ti * B + rr;
-          const double v = a[rr][cc];
-          const double nv = r > c ? v * ip : (r == c ? p : v);
-          a[rr][cc] = nv;
-          Lsh[r][c] = nv;
-        }
-      }
-      __syncthreads();
-      double ls[B];
-#pragma unroll
-      for (int ss = 0; ss < B; ++ss) {
-        const int s = tj * B + ss;
-        ls[ss] = s > c ? Lsh[s][c] : 0.0;
-      }
-#pragma unroll
-      for (int rr = 0; rr < B; ++rr) {
-        const int r = ti * B + rr;
-        const double lr = r > c ? Lsh[r][c] : 0.0;
-#pragma unroll
-        for (int ss = 0; ss < B; ++ss) a[rr][ss] -= lr * ls[ss];
-      }
-    }
+  if (threadIdx.x == 0) sm.fail = 0;
+  for (int idx = threadIdx.x; idx < T * T; idx += NT) {
+    const int blk = idx >> 6, w = idx & 63;
+    const int r = (blk / (T / 4)) * 16 + (w & 15), c = (blk % (T / 4)) * 4 + (w >> 4);
+    sm.A[r * LD + c] = A[idx];
   }
   __syncthreads();
-  // inverse X = L^-1 by a right-looking forward substitution on X = I
-  double x[B][B];
-#pragma unroll
-  for (int rr = 0; rr < B; ++rr)
-#pragma unroll
-    for (int ss = 0; ss < B; ++ss) x[rr][ss] = (ti * B + rr == tj * B + ss) ? 1.0 : 0.0;
-  for (int cb = 0; cb < 16; ++cb) {
-#pragma unroll
-    for (int cc = 0; cc < B; ++cc) {
-      const int c = cb * B + cc;
-      if (ti == cb) {
-        const double inv = 1.0 / Lsh[c][c];
-#pragma unroll
-        for (int ss = 0; ss < B; ++ss) {
-          x[cc][ss] *= inv;
-          rowx[tj * B + ss] = x[cc][ss];
-        }
-      }
-      __syncthreads();
-      double xs[B];
-#pragma unroll
-      for (int ss = 0; ss < B; ++ss) xs[ss] = rowx[tj * B + ss];
-#pragma unroll
-      for (int rr = 0; rr < B; ++rr) {
-        const int r = ti * B + rr;
-        const double lr = r > c ? Lsh[r][c] : 0.0;
-#pragma unroll
-        for (int ss = 0; ss < B; ++ss) x[rr][ss] -= lr * xs[ss];
-      }
-      __syncthreads();
-    }
-  }
+  factor_inverse_tile<T>(sm);
   double* Li = d.Li + d.diag_off[l] + (int64_t)k * T * T;
-#pragma unroll
-  for (int rr = 0; rr < B; ++rr)
-#pragma unroll
-    for (int ss = 0; ss < B; ++ss) Li[mf_idx(T, ti * B + rr, tj * B + ss)] = x[rr][ss];
-  if (threadIdx.x == 0 && fail) d.blk_fail[l] = 1;
+  for (int idx = threadIdx.x; idx < T * T; idx += NT) {
+    const int blk = idx >> 6, w = idx & 63;
+    const int r = (blk / (T / 4)) * 16 + (w & 15), c = (blk % (T / 4)) * 4 + (w >> 4);
+    Li[idx] = r >= c ? sm.X[r * LD + c] : 0.0;
+  }
+  if (threadIdx.x == 0 && sm.fail) d.blk_fail[l] = 1;
 }
 
 // L(i,k) = A(i,k) L(k,k)^-T, in place (the right-hand-side row i = nt included)

@@ -48,6 +48,15 @@ struct Dev {
   const int32_t* obs_orig;
   const int32_t* cam_obs_off;
   const int32_t* cam_obs;
+  // intersection stream, point-major (see the plan)
+  const int32_t* pm_off;
+  const int32_t* pm_k;
+  const int32_t* pm_pos;
+  const int32_t* pm_cam;
+  const int32_t* iwg_cam_off;
+  const int32_t* iwg_cams;
+  double* pm_xy;          // [K][2]
+  double* pm_w;           // [K] r w0, or [K][3] r W (with obs_info)
 
   // copies (sub-block, point)
   const int32_t* copy_off;

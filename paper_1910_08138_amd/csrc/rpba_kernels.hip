@@ -5,6 +5,7 @@
 // exchange (Sec. 5).
 #include "rpba_device.hpp"
 #include "rpba_internal.hpp"
+#include "rpba_plan.hpp"
 
 namespace rpba {
 
@@ -98,16 +99,80 @@ __global__ void k_pad_identity(Dev d) {
   }
 }
 
+// point-major copies of the pixel coordinates and the weights (LM order ->
+// intersection stream)
+__global__ void k_gather_pm(Dev d) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= d.K) return;
+  const int64_t k = d.pm_k[i];
+  d.pm_xy[2 * i] = d.xy[2 * k];
+  d.pm_xy[2 * i + 1] = d.xy[2 * k + 1];
+  const double r = d.rw[k];
+  if (d.has_info) {
+    for (int q = 0; q < 3; ++q) d.pm_w[3 * i + q] = r * d.info[3 * k + q];
+  } else {
+    d.pm_w[i] = r * d.w0;
+  }
+}
+
 // ------------------------------------------------------------ intersection
-// One thread per point (internal order).  Gauss-Newton with cameras fixed
+// One thread per point (internal order); a workgroup's points are
+// consecutive, and the cameras they see are staged in LDS first.  The point's
+// observations are read from the point-major stream, the next one prefetched
+// while the current one is linearised.  Gauss-Newton with cameras fixed
 // (eq:bars); on convergence: covariance, refined weights Omega^l = H - H^(l)
 // of every copy (Sec. 5.1), copies reset to Xbar, residuals stored.
+struct PmObs {
+  double x, y, wa, wb, wc;
+  int cam;
+};
+
+template <bool INFO>
+__device__ __forceinline__ void pm_load(const Dev& d, int i, PmObs& o) {
+  o.x = d.pm_xy[2 * (int64_t)i];
+  o.y = d.pm_xy[2 * (int64_t)i + 1];
+  if (INFO) {
+    const double* w = d.pm_w + 3 * (int64_t)i;
+    o.wa = w[0];
+    o.wb = w[1];
+    o.wc = w[2];
+  } else {
+    o.wa = d.pm_w[i];
+    o.wb = 0.0;
+    o.wc = o.wa;
+  }
+  o.cam = d.pm_cam[i];
+}
+
+__device__ __forceinline__ void cam_load(const Dev& d, const double* cams, int slot, double (&cm)[12]) {
+  if (slot >= 0) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) cm[q] = cams[12 * slot + q];
+  } else {
+    const double* g = d.cam + (int64_t)CAM_STRIDE * (-1 - slot);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) cm[q] = g[q];
+  }
+}
+
+template <bool INFO>
 __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* status_out) {
+  static_assert(NT == INT_WG, "one intersection workgroup per plan workgroup");
+  __shared__ double cams[INT_CAM_CAP * 12];
   __shared__ double sh[4 * 8];
+  {
+    const int cb = d.iwg_cam_off[blockIdx.x], nc = d.iwg_cam_off[blockIdx.x + 1] - cb;
+    for (int t = threadIdx.x; t < nc * 12; t += NT) {
+      const int sl = t / 12, q = t - 12 * sl;
+      cams[t] = d.cam[(int64_t)CAM_STRIDE * d.iwg_cams[cb + sl] + q];
+    }
+  }
+  __syncthreads();
   int j = blockIdx.x * NT + threadIdx.x;
   double accv[4] = {0.0, 0.0, 0.0, 0.0};
   if (j < d.N && d.status[j] == 0) {
     const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
+    const int i0 = d.pm_off[j], i1 = d.pm_off[j + 1];
     double X[3] = {d.P0[j], d.P0[(int64_t)d.N + j], d.P0[2 * (int64_t)d.N + j]};
     int st = 1;  // not converged
     double h[6], g[3], lch[6];
@@ -115,15 +180,17 @@ __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* s
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       g[0] = g[1] = g[2] = 0.0;
       bool behind = false;
-      for (int cc = c0; cc < c1; ++cc) {
-        int c = d.pt_copies[cc];
-        for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
-          const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
-          Lin<double> L;
-          linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
-          if (!(L.z > 0.0)) behind = true;
-          add_point_normals<double>(L, obs_weight(d, k), L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1], h, g);
-        }
+      PmObs nx;
+      pm_load<INFO>(d, i0, nx);
+      for (int i = i0; i < i1; ++i) {
+        const PmObs cur = nx;
+        if (i + 1 < i1) pm_load<INFO>(d, i + 1, nx);
+        double cm[12];
+        cam_load(d, cams, cur.cam, cm);
+        Lin<double> L;
+        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+        if (!(L.z > 0.0)) behind = true;
+        add_point_normals<double>(L, W2<double>{cur.wa, cur.wb, cur.wc}, L.g0 - cur.x, L.g1 - cur.y, h, g);
       }
       if (behind) {
         st = 2;
@@ -139,32 +206,51 @@ __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* s
       X[1] += dX[1];
       X[2] += dX[2];
       double nd = sqrt(dX[0] * dX[0] + dX[1] * dX[1] + dX[2] * dX[2]);
-      double nx = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
-      if (nd <= d.int_tol * (1.0 + nx)) {
+      double nx2 = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+      if (nd <= d.int_tol * (1.0 + nx2)) {
         st = 0;
         break;
       }
     }
+    // final pass at the converged point: normals, residuals, cost, and the
+    // per-copy normals H^(l) (parked in Om until H is complete)
     double cost = 0.0, sq = 0.0, nobs = 0.0;
+    const bool tp = c1 - c0 > 1;
     if (st == 0) {
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
-      g[0] = g[1] = g[2] = 0.0;
       bool behind = false;
-      for (int cc = c0; cc < c1; ++cc) {
-        int c = d.pt_copies[cc];
-        for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
-          const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
-          Lin<double> L;
-          linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
-          if (!(L.z > 0.0)) behind = true;
-          double v0 = L.g0 - d.xy[2 * k], v1 = L.g1 - d.xy[2 * k + 1];
-          W2<double> W = obs_weight(d, k);
-          add_point_normals<double>(L, W, v0, v1, h, g);
-          d.res[2 * k] = v0;
-          d.res[2 * k + 1] = v1;
-          cost += wquad(W, v0, v1);
-          sq += v0 * v0 + v1 * v1;
-          nobs += 1.0;
+      int cc = c0, c = d.pt_copies[c0];
+      int iend = i0 + (d.copy_off[c + 1] - d.copy_off[c]);
+      double hl[6] = {0, 0, 0, 0, 0, 0}, gl[3] = {0, 0, 0};
+      PmObs nx;
+      pm_load<INFO>(d, i0, nx);
+      for (int i = i0; i < i1; ++i) {
+        const PmObs cur = nx;
+        if (i + 1 < i1) pm_load<INFO>(d, i + 1, nx);
+        double cm[12];
+        cam_load(d, cams, cur.cam, cm);
+        Lin<double> L;
+        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+        if (!(L.z > 0.0)) behind = true;
+        const double v0 = L.g0 - cur.x, v1 = L.g1 - cur.y;
+        const W2<double> W{cur.wa, cur.wb, cur.wc};
+        add_point_normals<double>(L, W, v0, v1, hl, gl);
+        const int64_t k = d.pm_k[i];
+        d.res[2 * k] = v0;
+        d.res[2 * k + 1] = v1;
+        cost += wquad(W, v0, v1);
+        sq += v0 * v0 + v1 * v1;
+        nobs += 1.0;
+        if (i + 1 == iend) {  // copy c complete
+          for (int q = 0; q < 6; ++q) {
+            h[q] += hl[q];
+            if (tp) d.Om[6 * (int64_t)c + q] = hl[q];
+            hl[q] = 0.0;
+          }
+          if (++cc < c1) {
+            c = d.pt_copies[cc];
+            iend += d.copy_off[c + 1] - d.copy_off[c];
+          }
         }
       }
       if (behind) st = 2;
@@ -181,16 +267,12 @@ __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* s
         d.P0[(int64_t)r * d.N + j] = X[r];
         d.u_pts[(int64_t)r * d.N + o] = X[r];
       }
+      // Omega^l = H - H^(l): information from the cameras outside sub-block l
+      // (zero for a point seen by one sub-block only)
       for (int cc = c0; cc < c1; ++cc) {
         int c = d.pt_copies[cc];
-        double hl[6] = {0, 0, 0, 0, 0, 0}, gl[3] = {0, 0, 0};
-        for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
-          const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
-          Lin<double> L;
-          linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
-          add_point_normals<double>(L, obs_weight(d, k), L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1], hl, gl);
-        }
-        for (int q = 0; q < 6; ++q) d.Om[6 * (int64_t)c + q] = h[q] - hl[q];
+        double* om = d.Om + 6 * (int64_t)c;
+        for (int q = 0; q < 6; ++q) om[q] = tp ? h[q] - om[q] : 0.0;
         for (int r = 0; r < 3; ++r) d.Xc[3 * (int64_t)c + r] = X[r];
       }
       accv[0] = cost;
@@ -500,6 +582,7 @@ void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
 
 void launch_gather(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_obs, dim3(grid_for(d.K)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_gather_pm, dim3(grid_for(d.K)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_gather_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_gather_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
 }
@@ -510,7 +593,10 @@ void launch_init_rcs(const Dev& d, hipStream_t st) {
 
 void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
   launch_zero(d.acc_int, 4, st);
-  hipLaunchKernelGGL(k_intersect, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
+  if (d.has_info)
+    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
+  else
+    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
   if (stats) hipLaunchKernelGGL(k_intersect_stats, dim3(1), dim3(64), 0, st, d, stats);
 }
 

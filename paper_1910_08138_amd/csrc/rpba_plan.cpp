@@ -75,17 +75,26 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
   for (int32_t l = 0; l < L; ++l) P.max_blk_cams = std::max(P.max_blk_cams, P.blk_cam_off[l + 1] - P.blk_cam_off[l]);
   if (6 * P.max_blk_cams > 255 * tile) return "sub-block too large for the Cholesky tiling";
 
-  // points ordered by their lowest sub-block
-  std::vector<int32_t> owner(N, L);
-  for (int32_t k = 0; k < K; ++k) owner[obs_pt[k]] = std::min(owner[obs_pt[k]], cam_block[obs_cam[k]]);
+  // points ordered by their lowest sub-block and, inside it, by their first
+  // camera (cameras of a sub-block are in the caller's order, which for image
+  // blocks follows the flight path): neighbouring points then share cameras,
+  // so a wave's gathers of camera data and copy records hit the same lines
+  std::vector<int32_t> owner(N, L), first(N, M);
+  for (int32_t k = 0; k < K; ++k) {
+    const int32_t j = obs_pt[k], l = cam_block[obs_cam[k]];
+    if (l < owner[j] || (l == owner[j] && cam_new[obs_cam[k]] < first[j])) {
+      owner[j] = l;
+      first[j] = cam_new[obs_cam[k]];
+    }
+  }
   P.pt_orig.resize(N);
   std::vector<int32_t> pt_new(N);
   {
-    std::vector<int32_t> cnt(L + 1, 0);
-    for (int32_t j = 0; j < N; ++j) cnt[owner[j] + 1]++;
-    for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
+    std::vector<int32_t> cnt(M + 1, 0);
+    for (int32_t j = 0; j < N; ++j) cnt[first[j] + 1]++;
+    for (int32_t i = 0; i < M; ++i) cnt[i + 1] += cnt[i];
     for (int32_t j = 0; j < N; ++j) {
-      int32_t n = cnt[owner[j]]++;
+      int32_t n = cnt[first[j]]++;
       P.pt_orig[n] = j;
       pt_new[j] = n;
     }
@@ -136,6 +145,50 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
   {
     std::vector<int32_t> fill(P.pt_copy_off.begin(), P.pt_copy_off.end() - 1);
     for (int64_t c = 0; c < P.NC; ++c) P.pt_copies[fill[P.copy_pt[c]]++] = (int32_t)c;
+  }
+
+  // point-major observation stream of the intersection and the cameras of
+  // each of its workgroups
+  P.pm_off.assign(N + 1, 0);
+  P.pm_k.resize(K);
+  P.pm_pos.resize(K);
+  P.pm_cam.resize(K);
+  {
+    int32_t i = 0;
+    for (int32_t j = 0; j < N; ++j) {
+      P.pm_off[j] = i;
+      for (int32_t cc = P.pt_copy_off[j]; cc < P.pt_copy_off[j + 1]; ++cc) {
+        const int32_t c = P.pt_copies[cc];
+        for (int32_t k = P.copy_off[c]; k < P.copy_off[c + 1]; ++k) {
+          P.pm_k[i] = k;
+          P.pm_pos[k] = i;
+          ++i;
+        }
+      }
+    }
+    P.pm_off[N] = i;
+    const int32_t nwg = (N + INT_WG - 1) / INT_WG;
+    P.iwg_cam_off.assign(nwg + 1, 0);
+    P.iwg_cams.clear();
+    std::vector<int32_t> stamp(M, -1), slot(M, 0);
+    for (int32_t w = 0; w < nwg; ++w) {
+      const int32_t j0 = w * INT_WG, j1 = std::min(N, j0 + INT_WG);
+      int32_t n = 0;
+      for (int32_t q = P.pm_off[j0]; q < P.pm_off[j1]; ++q) {
+        const int32_t cam = P.obs_cam[P.pm_k[q]];
+        if (stamp[cam] != w) {
+          stamp[cam] = w;
+          if (n < INT_CAM_CAP) {
+            slot[cam] = n++;
+            P.iwg_cams.push_back(cam);
+          } else {
+            slot[cam] = -1 - cam;
+          }
+        }
+        P.pm_cam[q] = slot[cam];
+      }
+      P.iwg_cam_off[w + 1] = (int32_t)P.iwg_cams.size();
+    }
   }
 
   // observations of each camera (ascending LM index)

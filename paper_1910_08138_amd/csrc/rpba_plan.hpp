@@ -17,6 +17,9 @@
 
 namespace rpba {
 
+constexpr int INT_WG = 256;        // points per intersection workgroup
+constexpr int INT_CAM_CAP = 384;   // cameras staged per intersection workgroup
+
 struct Plan {
   int32_t M = 0, N = 0, K = 0, L = 0;
   int64_t NC = 0;  // copies
@@ -35,6 +38,16 @@ struct Plan {
   std::vector<int64_t> blk_copy_off;   // [L+1]
   std::vector<int32_t> pt_copy_off;    // [N+1]
   std::vector<int32_t> pt_copies;      // [NC] copy indices grouped by point (ascending sub-block)
+  // intersection stream (point-major): the observations of point j at
+  // [pm_off[j], pm_off[j+1]), copy by copy in pt_copies order; each launch
+  // workgroup of INT_WG points stages the cameras it sees (at most
+  // INT_CAM_CAP) in LDS: pm_cam is the slot there, or -1 - camera
+  std::vector<int32_t> pm_off;         // [N+1]
+  std::vector<int32_t> pm_k;           // [K] LM index
+  std::vector<int32_t> pm_pos;         // [K] position of LM index k
+  std::vector<int32_t> pm_cam;         // [K]
+  std::vector<int32_t> iwg_cam_off;    // [ceil(N / INT_WG) + 1]
+  std::vector<int32_t> iwg_cams;       // internal camera indices
   std::vector<int32_t> cam_obs_off;    // [M+1]
   std::vector<int32_t> cam_obs;        // [K] LM-ordered observation indices per camera
   std::vector<int32_t> nb_off;         // [M+1] neighbour lists (cameras of the same

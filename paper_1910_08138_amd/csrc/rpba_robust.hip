@@ -147,6 +147,12 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
       }
     }
     d.rw[k] = w;
+    const int64_t pos = d.pm_pos[k];  // the intersection's copy of the weight
+    if (d.has_info) {
+      for (int q = 0; q < 3; ++q) d.pm_w[3 * pos + q] = w * d.info[3 * (int64_t)k + q];
+    } else {
+      d.pm_w[pos] = w * d.w0;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) nflag += __shfl_xor(nflag, o);
   if ((threadIdx.x & 63) == 0) sh_flag[threadIdx.x >> 6] = nflag;
