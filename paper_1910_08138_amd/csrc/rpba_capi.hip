@@ -47,7 +47,7 @@ struct WsMap {
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
-      pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w;
+      pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -126,6 +126,7 @@ WsMap layout_for(const Plan& P) {
   m.iwg_cams = L.add(i4 * std::max<size_t>(1, P.iwg_cams.size()));
   m.pm_xy = L.add(f8 * 2 * P.K);
   m.pm_w = L.add(f8 * (P.has_info ? 3 : 1) * P.K);
+  m.cam_obs_c = L.add(i4 * P.cam_obs_c.size());
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -137,7 +138,7 @@ WsMap layout_for(const Plan& P) {
   m.res = L.add(f8 * 2 * P.K);
   m.Xc = L.add(f8 * 3 * P.NC);
   m.Om = L.add(f8 * 6 * P.NC);
-  m.cpk = L.add(f8 * 12 * P.NC);
+  m.cpk = L.add(f8 * CPK * P.NC);
   m.S = L.add(f8 * P.rcs_total);
   m.Ld = L.add(f8 * P.diag_total);
   m.Li = L.add(f8 * P.diag_total);
@@ -378,6 +379,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.obs_orig, p.obs_orig.data(), 4 * p.obs_orig.size()));
   HIP_TRY(up(m.cam_obs_off, p.cam_obs_off.data(), 4 * p.cam_obs_off.size()));
   HIP_TRY(up(m.cam_obs, p.cam_obs.data(), 4 * p.cam_obs.size()));
+  HIP_TRY(up(m.cam_obs_c, p.cam_obs_c.data(), 4 * p.cam_obs_c.size()));
   HIP_TRY(up(m.pm_off, p.pm_off.data(), 4 * p.pm_off.size()));
   HIP_TRY(up(m.pm_k, p.pm_k.data(), 4 * p.pm_k.size()));
   HIP_TRY(up(m.pm_pos, p.pm_pos.data(), 4 * p.pm_pos.size()));
@@ -520,6 +522,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.obs_copy = I(m.obs_copy);
   D.obs_orig = I(m.obs_orig);
   D.cam_obs_off = I(m.cam_obs_off);
+  D.cam_obs_c = I(m.cam_obs_c);
   D.pm_off = I(m.pm_off);
   D.pm_k = I(m.pm_k);
   D.pm_pos = I(m.pm_pos);
@@ -570,7 +573,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_gather(D, st);
   launch_zero(D.Xc, 3 * D.NC, st);
   launch_zero(D.Om, 6 * D.NC, st);
-  launch_zero(D.cpk, 12 * D.NC, st);
+  launch_zero(D.cpk, CPK * D.NC, st);
   launch_zero(D.S, p.rcs_total, st);
   launch_zero(D.Ld, p.diag_total, st);
   launch_zero(D.Li, p.diag_total, st);
@@ -619,6 +622,19 @@ static rpba_status assemble(rpba_problem* h, const uint8_t* active) {
   return RPBA_OK;
 }
 
+// Forward factorisation of the dense reduced camera systems, step k = 0 ..
+// nt - 1, three launches per step over all sub-blocks: diagonal factor,
+// panel solves, trailing update.
+static rpba_status chol_forward(rpba_problem* h, const int32_t* pot, const int32_t* fwd, const int32_t* upd) {
+  hipStream_t st = h->stream;
+  for (int k = 0; k < h->nt_max_dense; ++k) {
+    launch_chol_potrf(h->d, k, pot + h->pot_off[k], h->pot_off[k + 1] - h->pot_off[k], st);
+    launch_chol_trsm(h->d, k, fwd + h->fwd_off[k], h->fwd_off[k + 1] - h->fwd_off[k], st);
+    launch_chol_update(h->d, k, upd + h->upd_off[k], h->upd_off[k + 1] - h->upd_off[k], st);
+  }
+  return RPBA_OK;
+}
+
 rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double* block_stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run before the first LM step");
@@ -633,10 +649,8 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
     if (h->any_dense) {
       {
         PhaseTimer t(h, PH_CHOL_FWD, 3 * h->nt_max_dense);
-        for (int k = 0; k < h->nt_max_dense; ++k)
-          launch_chol_step(h->d, k, pot + h->pot_off[k], h->pot_off[k + 1] - h->pot_off[k], fwd + h->fwd_off[k],
-                           h->fwd_off[k + 1] - h->fwd_off[k], upd + h->upd_off[k], h->upd_off[k + 1] - h->upd_off[k],
-                           h->stream);
+        rpba_status s2 = chol_forward(h, pot, fwd, upd);
+        if (s2 != RPBA_OK) return s2;
       }
       {
         PhaseTimer t(h, PH_CHOL_BWD, h->nt_max_dense + 1);
@@ -781,7 +795,7 @@ rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e)
   size_t need = (size_t)n6 * n6 + n6;
   double* stage = nullptr;
   if ((int64_t)need <= p.diag_total * 2) stage = h->d.Ld;  // Ld and Li are contiguous in the layout
-  else if ((int64_t)need <= 12 * p.NC) stage = h->d.cpk;
+  else if ((int64_t)need <= CPK * p.NC) stage = h->d.cpk;
   else return fail(RPBA_ERR_STATE, "no staging space for this sub-block");
   if (h->blk_pcg[l]) {
     launch_zero(stage, (int64_t)n6 * n6, h->stream);

@@ -48,25 +48,30 @@ __device__ __forceinline__ void acc_rc(int p, int q, int e, int& r, int& c) {
   c = (wv & 1) * (T / 2) + 16 * q + (lane & 15);
 }
 
-// acc += A B^T for T x T tiles stored in the matrix-core layout
-template <int T>
+// acc += A B^T for T x T tiles stored in the matrix-core layout.  Every
+// operand fragment of the wave is loaded before the first product, so the
+// tile costs one memory latency rather than one per k step.
+template <int T, bool NEG = false>
 __device__ __forceinline__ void gemm_nt_mf(const double* __restrict__ A, const double* __restrict__ B, Acc<T>& acc) {
-  constexpr int NB = T / 32;
+  constexpr int NB = T / 32, KG = T / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int rb0 = (wv >> 1) * NB, cb0 = (wv & 1) * NB;
-#pragma unroll 4
-  for (int kg = 0; kg < T / 4; ++kg) {
-    double a[NB], b[NB];
+  double a[KG][NB], b[KG][NB];
+#pragma unroll
+  for (int kg = 0; kg < KG; ++kg)
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      a[q] = A[((rb0 + q) * (T / 4) + kg) * 64 + lane];
-      b[q] = B[((cb0 + q) * (T / 4) + kg) * 64 + lane];
+      a[kg][q] = NEG ? -A[((rb0 + q) * (T / 4) + kg) * 64 + lane] : A[((rb0 + q) * (T / 4) + kg) * 64 + lane];
+      b[kg][q] = B[((cb0 + q) * (T / 4) + kg) * 64 + lane];
     }
+  __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the products
+#pragma unroll
+  for (int kg = 0; kg < KG; ++kg)
 #pragma unroll
     for (int p = 0; p < NB; ++p)
 #pragma unroll
-      for (int q = 0; q < NB; ++q) acc.v[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc.v[p][q], 0, 0, 0);
-  }
+      for (int q = 0; q < NB; ++q)
+        acc.v[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kg][p], b[kg][q], acc.v[p][q], 0, 0, 0);
 }
 
 template <int T>
@@ -308,9 +313,8 @@ __global__ __launch_bounds__(NT) void k_chol_update(Dev d, int k, const int32_t*
   const double* Aik = tile_ptr<T>(d, l, i, k);
   const double* Ajk = tile_ptr<T>(d, l, j, k);
   double* C = tile_ptr<T>(d, l, i, j);
+  // acc = C - L(i,k) L(j,k)^T, C read with the operands
   Acc<T> acc;
-  acc.zero();
-  gemm_nt_mf<T>(Aik, Ajk, acc);
 #pragma unroll
   for (int p = 0; p < Acc<T>::NB; ++p)
 #pragma unroll
@@ -319,7 +323,18 @@ __global__ __launch_bounds__(NT) void k_chol_update(Dev d, int k, const int32_t*
       for (int e = 0; e < 4; ++e) {
         int r, c;
         acc_rc<T>(p, q, e, r, c);
-        C[mf_idx(T, r, c)] -= acc.v[p][q][e];
+        acc.v[p][q][e] = C[mf_idx(T, r, c)];
+      }
+  gemm_nt_mf<T, true>(Aik, Ajk, acc);
+#pragma unroll
+  for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+    for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int r, c;
+        acc_rc<T>(p, q, e, r, c);
+        C[mf_idx(T, r, c)] = acc.v[p][q][e];
       }
 }
 
@@ -406,17 +421,22 @@ __global__ __launch_bounds__(NT) void k_selftest_gemm(const double* A, const dou
 
 }  // namespace
 
-void launch_chol_step(const Dev& d, int k, const int32_t* pot, int64_t npot, const int32_t* trsm, int64_t ntrsm,
-                      const int32_t* upd, int64_t nupd, hipStream_t st) {
-  if (d.T == 64) {
-    if (npot) hipLaunchKernelGGL(k_chol_potrf<64>, dim3((unsigned)npot), dim3(NT), 0, st, d, k, pot);
-    if (ntrsm) hipLaunchKernelGGL(k_chol_trsm<64>, dim3((unsigned)ntrsm), dim3(NT), 0, st, d, k, trsm);
-    if (nupd) hipLaunchKernelGGL(k_chol_update<64>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
-  } else {
-    if (npot) hipLaunchKernelGGL(k_chol_potrf<32>, dim3((unsigned)npot), dim3(NT), 0, st, d, k, pot);
-    if (ntrsm) hipLaunchKernelGGL(k_chol_trsm<32>, dim3((unsigned)ntrsm), dim3(NT), 0, st, d, k, trsm);
-    if (nupd) hipLaunchKernelGGL(k_chol_update<32>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
-  }
+void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st) {
+  if (npot <= 0) return;
+  if (d.T == 64) hipLaunchKernelGGL(k_chol_potrf<64>, dim3((unsigned)npot), dim3(NT), 0, st, d, k, pot);
+  else hipLaunchKernelGGL(k_chol_potrf<32>, dim3((unsigned)npot), dim3(NT), 0, st, d, k, pot);
+}
+
+void launch_chol_trsm(const Dev& d, int k, const int32_t* trsm, int64_t ntrsm, hipStream_t st) {
+  if (ntrsm <= 0) return;
+  if (d.T == 64) hipLaunchKernelGGL(k_chol_trsm<64>, dim3((unsigned)ntrsm), dim3(NT), 0, st, d, k, trsm);
+  else hipLaunchKernelGGL(k_chol_trsm<32>, dim3((unsigned)ntrsm), dim3(NT), 0, st, d, k, trsm);
+}
+
+void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, hipStream_t st) {
+  if (nupd <= 0) return;
+  if (d.T == 64) hipLaunchKernelGGL(k_chol_update<64>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
+  else hipLaunchKernelGGL(k_chol_update<32>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
 }
 
 void launch_rhs_extract(const Dev& d, hipStream_t st) {

@@ -25,6 +25,21 @@ struct Lin {
   T Ar[2][3];    // dg/d(rotation increment)
 };
 
+// 1 / x: in FP64 the hardware reciprocal estimate refined by two Newton
+// steps (within an ulp or two for the depths met here, cheaper than the
+// correctly rounded division); in FP32 the plain division
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ double recip<double>(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  y = y * (2.0 - x * y);
+  return y;
+}
+
 // linearisation from the offset d = X - C (formed by the caller, in FP64 when T
 // is float, so that large coordinates do not cancel in single precision)
 template <typename T>
@@ -33,7 +48,7 @@ __device__ __forceinline__ void linearise_d(const T* __restrict__ R, T d0, T d1,
   T p1 = R[3] * d0 + R[4] * d1 + R[5] * d2;
   T p2 = R[6] * d0 + R[7] * d1 + R[8] * d2;
   o.z = p2;
-  T iz = T(1) / p2;
+  T iz = recip(p2);
   T u = p0 * iz, w = p1 * iz;
   o.g0 = f * u + cx;
   o.g1 = f * w + cy;

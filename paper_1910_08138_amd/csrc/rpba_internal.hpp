@@ -42,12 +42,13 @@ struct Dev {
   double* xy;             // [K][2]
   double* info;           // [K][3] or null
   double* rw;             // [K] robust weight multiplier
-  double* res;            // [K][2] residuals of the last intersection
+  double* res;            // [K][2] residuals of the last intersection, point-major
   const int32_t* obs_cam;
   const int32_t* obs_copy;
   const int32_t* obs_orig;
   const int32_t* cam_obs_off;
   const int32_t* cam_obs;
+  const int32_t* cam_obs_c;  // copy of each cam_obs entry
   // intersection stream, point-major (see the plan)
   const int32_t* pm_off;
   const int32_t* pm_k;
@@ -65,7 +66,7 @@ struct Dev {
   const int64_t* blk_copy_off;
   double* Xc;             // [NC][3] X_j^l
   double* Om;             // [NC][6] refined tie-point weight
-  double* cpk;            // [NC][12] X, damped V^-1 (6), g_X (3) of the current step
+  double* cpk;            // [NC][CPK] X (3), valid (1 or 0), damped V^-1 (6), g_X (3), spare (3)
   const int32_t* nb_off;
   const int32_t* nb_cam;
   // pair blocks (see the plan) and the block-sparse matrix of iterative sub-blocks
@@ -103,6 +104,9 @@ struct Dev {
   double* acc_rob;        // [2]
 };
 
+// one 128-byte record per copy for the current LM step
+constexpr int CPK = 16;
+
 // In-tile layout of the RCS tiles, chosen for the FP64 matrix cores: element
 // (r, c) of a T x T tile lives at ((r / 16) (T / 4) + c / 4) 64 + r % 16 +
 // 16 (c % 4), so that the 16 x 4 operand fragment a 64-lane wave feeds to one
@@ -125,8 +129,9 @@ void launch_init_rcs(const Dev& d, hipStream_t st);
 void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st);
 void launch_copy_prep(const Dev& d, hipStream_t st);
 void launch_schur(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st);
-void launch_chol_step(const Dev& d, int k, const int32_t* pot, int64_t npot, const int32_t* trsm, int64_t ntrsm,
-                      const int32_t* upd, int64_t nupd, hipStream_t st);
+void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st);
+void launch_chol_trsm(const Dev& d, int k, const int32_t* trsm, int64_t ntrsm, hipStream_t st);
+void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, hipStream_t st);
 void launch_rhs_extract(const Dev& d, hipStream_t st);
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st);
 void launch_update(const Dev& d, double* block_stats, hipStream_t st);

@@ -156,7 +156,7 @@ __device__ __forceinline__ void cam_load(const Dev& d, const double* cams, int s
 }
 
 template <bool INFO>
-__global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* status_out) {
+__global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t* status_out) {
   static_assert(NT == INT_WG, "one intersection workgroup per plan workgroup");
   __shared__ double cams[INT_CAM_CAP * 12];
   __shared__ double sh[4 * 8];
@@ -180,17 +180,24 @@ __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* s
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       g[0] = g[1] = g[2] = 0.0;
       bool behind = false;
-      PmObs nx;
-      pm_load<INFO>(d, i0, nx);
-      for (int i = i0; i < i1; ++i) {
-        const PmObs cur = nx;
-        if (i + 1 < i1) pm_load<INFO>(d, i + 1, nx);
+      auto gn_obs = [&](const PmObs& o) {
         double cm[12];
-        cam_load(d, cams, cur.cam, cm);
+        cam_load(d, cams, o.cam, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0)) behind = true;
-        add_point_normals<double>(L, W2<double>{cur.wa, cur.wb, cur.wc}, L.g0 - cur.x, L.g1 - cur.y, h, g);
+        add_point_normals<double>(L, W2<double>{o.wa, o.wb, o.wc}, L.g0 - o.x, L.g1 - o.y, h, g);
+      };
+      // two buffers: observation i + 1 is in flight while i is linearised
+      PmObs oa, ob;
+      pm_load<INFO>(d, i0, oa);
+      for (int i = i0;;) {
+        if (i + 1 < i1) pm_load<INFO>(d, i + 1, ob);
+        gn_obs(oa);
+        if (++i >= i1) break;
+        if (i + 1 < i1) pm_load<INFO>(d, i + 1, oa);
+        gn_obs(ob);
+        if (++i >= i1) break;
       }
       if (behind) {
         st = 2;
@@ -213,15 +220,16 @@ __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* s
       }
     }
     // final pass at the converged point: normals, residuals, cost, and the
-    // per-copy normals H^(l) (parked in Om until H is complete)
+    // per-copy normals H^(l): those of the first and the last copy stay in
+    // registers, any in between are parked in Om until H is complete
     double cost = 0.0, sq = 0.0, nobs = 0.0;
-    const bool tp = c1 - c0 > 1;
+    double hl0[6] = {0, 0, 0, 0, 0, 0}, hl[6] = {0, 0, 0, 0, 0, 0};
     if (st == 0) {
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       bool behind = false;
       int cc = c0, c = d.pt_copies[c0];
       int iend = i0 + (d.copy_off[c + 1] - d.copy_off[c]);
-      double hl[6] = {0, 0, 0, 0, 0, 0}, gl[3] = {0, 0, 0};
+      double gl[3] = {0, 0, 0};
       PmObs nx;
       pm_load<INFO>(d, i0, nx);
       for (int i = i0; i < i1; ++i) {
@@ -235,19 +243,22 @@ __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* s
         const double v0 = L.g0 - cur.x, v1 = L.g1 - cur.y;
         const W2<double> W{cur.wa, cur.wb, cur.wc};
         add_point_normals<double>(L, W, v0, v1, hl, gl);
-        const int64_t k = d.pm_k[i];
-        d.res[2 * k] = v0;
-        d.res[2 * k + 1] = v1;
+        reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
         cost += wquad(W, v0, v1);
         sq += v0 * v0 + v1 * v1;
         nobs += 1.0;
         if (i + 1 == iend) {  // copy c complete
-          for (int q = 0; q < 6; ++q) {
-            h[q] += hl[q];
-            if (tp) d.Om[6 * (int64_t)c + q] = hl[q];
-            hl[q] = 0.0;
-          }
+          for (int q = 0; q < 6; ++q) h[q] += hl[q];
           if (++cc < c1) {
+            if (cc == c0 + 1) {
+              for (int q = 0; q < 6; ++q) hl0[q] = hl[q];
+            } else {
+              double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)c);
+              om[0] = make_double2(hl[0], hl[1]);
+              om[1] = make_double2(hl[2], hl[3]);
+              om[2] = make_double2(hl[4], hl[5]);
+            }
+            for (int q = 0; q < 6; ++q) hl[q] = 0.0;
             c = d.pt_copies[cc];
             iend += d.copy_off[c + 1] - d.copy_off[c];
           }
@@ -270,9 +281,27 @@ __global__ __launch_bounds__(NT) void k_intersect(Dev d, double* cov, int32_t* s
       // Omega^l = H - H^(l): information from the cameras outside sub-block l
       // (zero for a point seen by one sub-block only)
       for (int cc = c0; cc < c1; ++cc) {
-        int c = d.pt_copies[cc];
-        double* om = d.Om + 6 * (int64_t)c;
-        for (int q = 0; q < 6; ++q) om[q] = tp ? h[q] - om[q] : 0.0;
+        const int c = d.pt_copies[cc];
+        double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)c);
+        double o6[6];
+        if (c1 - c0 == 1) {
+          for (int q = 0; q < 6; ++q) o6[q] = 0.0;
+        } else if (cc == c0) {
+          for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl0[q];
+        } else if (cc == c1 - 1) {
+          for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl[q];
+        } else {
+          const double2 a = om[0], b = om[1], e = om[2];
+          o6[0] = h[0] - a.x;
+          o6[1] = h[1] - a.y;
+          o6[2] = h[2] - b.x;
+          o6[3] = h[3] - b.y;
+          o6[4] = h[4] - e.x;
+          o6[5] = h[5] - e.y;
+        }
+        om[0] = make_double2(o6[0], o6[1]);
+        om[1] = make_double2(o6[2], o6[3]);
+        om[2] = make_double2(o6[4], o6[5]);
         for (int r = 0; r < 3; ++r) d.Xc[3 * (int64_t)c + r] = X[r];
       }
       accv[0] = cost;
@@ -317,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
   if (c < d.NC) {
     int l = d.copy_blk[c];
     bool act = d.active == nullptr || d.active[l];
-    double* pk = d.cpk + 12 * c;
+    double* pk = d.cpk + CPK * c;
     if (act && d.status[d.copy_pt[c]] == 0) {
       double X[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
       const double* om = d.Om + 6 * c;
@@ -344,16 +373,20 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
       if (ok) chol3_inverse(lch, inv);
       else
         for (int q = 0; q < 6; ++q) inv[q] = 0.0;
-      pk[0] = X[0];
-      pk[1] = X[1];
-      pk[2] = X[2];
-      for (int q = 0; q < 6; ++q) pk[3 + q] = inv[q];
-      for (int q = 0; q < 3; ++q) pk[9 + q] = ok ? g[q] : 0.0;
+      double2* p2 = reinterpret_cast<double2*>(pk);
+      p2[0] = make_double2(X[0], X[1]);
+      p2[1] = make_double2(X[2], 1.0);
+      p2[2] = make_double2(inv[0], inv[1]);
+      p2[3] = make_double2(inv[2], inv[3]);
+      p2[4] = make_double2(inv[4], inv[5]);
+      p2[5] = make_double2(ok ? g[0] : 0.0, ok ? g[1] : 0.0);
+      p2[6] = make_double2(ok ? g[2] : 0.0, 0.0);
       int slot = l - l_first;
       if (slot >= 0 && slot < 8) atomicAdd(&sh[slot], cost);
       else atomicAdd(&d.acc_blk[4 * l + 0], cost);
     } else {
-      for (int q = 0; q < 12; ++q) pk[q] = 0.0;
+      double2* p2 = reinterpret_cast<double2*>(pk);
+      for (int q = 0; q < CPK / 2; ++q) p2[q] = make_double2(0.0, 0.0);
     }
   }
   __syncthreads();
@@ -399,9 +432,9 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
     int l = d.copy_blk[c];
     bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
     if (act && d.status[d.copy_pt[c]] == 0) {
-      const double* pk = d.cpk + 12 * c;
+      const double* pk = d.cpk + CPK * c;
       double X[3] = {pk[0], pk[1], pk[2]};
-      double rhs[3] = {-pk[9], -pk[10], -pk[11]};
+      double rhs[3] = {-pk[10], -pk[11], -pk[12]};
       const int base = d.blk_cam_off[l];
       const double* xs = d.x + d.vec_off[l];
       for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
@@ -420,7 +453,7 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
         for (int s = 0; s < 3; ++s) rhs[s] -= L.B[0][s] * wt0 + L.B[1][s] * wt1;
       }
       double dX[3];
-      sym3_mul(pk + 3, rhs, dX);
+      sym3_mul(pk + 4, rhs, dX);
       double Xn[3] = {X[0] + dX[0], X[1] + dX[1], X[2] + dX[2]};
       d.Xc[3 * c] = Xn[0];
       d.Xc[3 * c + 1] = Xn[1];

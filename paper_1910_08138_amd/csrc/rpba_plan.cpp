@@ -93,11 +93,15 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     std::vector<int32_t> cnt(M + 1, 0);
     for (int32_t j = 0; j < N; ++j) cnt[first[j] + 1]++;
     for (int32_t i = 0; i < M; ++i) cnt[i + 1] += cnt[i];
-    for (int32_t j = 0; j < N; ++j) {
-      int32_t n = cnt[first[j]]++;
-      P.pt_orig[n] = j;
-      pt_new[j] = n;
+    for (int32_t j = 0; j < N; ++j) P.pt_orig[cnt[first[j]]++] = j;
+    // inside each intersection workgroup, the points with more observations
+    // first: a wave's lanes then walk observation lists of similar length
+    for (int32_t b = 0; b < N; b += INT_WG) {
+      const int32_t e = std::min(N, b + INT_WG);
+      std::stable_sort(P.pt_orig.begin() + b, P.pt_orig.begin() + e,
+                       [&](int32_t x, int32_t y) { return pcount[x] > pcount[y]; });
     }
+    for (int32_t n = 0; n < N; ++n) pt_new[P.pt_orig[n]] = n;
   }
 
   // observations in (sub-block, point, camera) order
@@ -203,6 +207,8 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     std::vector<int32_t> fill(P.cam_obs_off.begin(), P.cam_obs_off.end() - 1);
     for (int32_t k = 0; k < K; ++k) P.cam_obs[fill[P.obs_cam[k]]++] = k;
   }
+  P.cam_obs_c.resize(K);
+  for (int32_t q = 0; q < K; ++q) P.cam_obs_c[q] = P.obs_copy[P.cam_obs[q]];
 
   // neighbour lists: cameras of the same sub-block sharing a point copy, local index <= own
   std::vector<std::vector<int32_t>> nb(M);
@@ -278,15 +284,16 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     }
     for (int64_t q = 0; q < NPB; ++q) cnt[q + 1] += cnt[q];
     P.pb_ent_off = cnt;
-    P.pb_ent.resize(2 * (size_t)cnt[NPB]);
+    P.pb_ent.resize(3 * (size_t)cnt[NPB]);
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
     for (int64_t c = 0; c < P.NC; ++c) {
       int32_t b = P.copy_off[c], e = P.copy_off[c + 1], base = P.blk_cam_off[P.copy_blk[c]];
       for (int32_t k1 = b; k1 < e; ++k1)
         for (int32_t k2 = b; k2 <= k1; ++k2) {
           int64_t at = fill[pb_of(P.obs_cam[k1], P.obs_cam[k2] - base)]++;
-          P.pb_ent[2 * at] = k1;
-          P.pb_ent[2 * at + 1] = k2;
+          P.pb_ent[3 * at] = (int32_t)c;
+          P.pb_ent[3 * at + 1] = k1;
+          P.pb_ent[3 * at + 2] = k2;
         }
     }
     P.od_pb.clear();

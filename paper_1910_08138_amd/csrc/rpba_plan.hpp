@@ -50,6 +50,7 @@ struct Plan {
   std::vector<int32_t> iwg_cams;       // internal camera indices
   std::vector<int32_t> cam_obs_off;    // [M+1]
   std::vector<int32_t> cam_obs;        // [K] LM-ordered observation indices per camera
+  std::vector<int32_t> cam_obs_c;      // [K] copy of each entry of cam_obs
   std::vector<int32_t> nb_off;         // [M+1] neighbour lists (cameras of the same
   std::vector<int32_t> nb_cam;         //        sub-block sharing a point, local index <= own)
   int32_t max_nb = 0, max_blk_cams = 0, max_cam_obs = 0;
@@ -58,7 +59,7 @@ struct Plan {
   // neighbour, same copy) that contribute to it
   std::vector<int32_t> pb_row;         // [NPB] internal camera i
   std::vector<int64_t> pb_ent_off;     // [NPB+1]
-  std::vector<int32_t> pb_ent;         // [2 * entries] (k1, k2)
+  std::vector<int32_t> pb_ent;         // [3 * entries] (copy, k1, k2)
   std::vector<int32_t> od_pb;          // off-diagonal pair blocks (i2 != i)
   std::vector<int32_t> pb_bsr;         // [NPB] position of block (i, i2) in the full block-sparse matrix
   std::vector<int32_t> pb_bsr_t;       // [NPB] position of block (i2, i)

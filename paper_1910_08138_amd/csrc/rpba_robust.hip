@@ -116,7 +116,8 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
     if (d.status[d.copy_pt[d.obs_copy[k]]] != 0) continue;
     const W2<double> W = base_weight(d, k);
     const double l11 = sqrt(W.a), l21 = W.b / l11, l22 = sqrt(W.c - l21 * l21);
-    const double v0 = d.res[2 * k], v1 = d.res[2 * k + 1];
+    const int64_t pos = d.pm_pos[k];  // residuals are stored point-major
+    const double v0 = d.res[2 * pos], v1 = d.res[2 * pos + 1];
     const int at = atomicAdd(&cnt, 2);
     vals[at] = l11 * v0 + l21 * v1;
     vals[at + 1] = l22 * v1;
@@ -138,7 +139,8 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
     const int pt = d.copy_pt[d.obs_copy[k]];
     double w = 1.0;
     if (d.status[pt] == 0) {
-      const double v0 = d.res[2 * k], v1 = d.res[2 * k + 1];
+      const int64_t pos = d.pm_pos[k];
+      const double v0 = d.res[2 * pos], v1 = d.res[2 * pos + 1];
       const double vb = sqrt(wquad(base_weight(d, k), v0, v1));
       if (s0 > 0.0 && vb > t_v * s0) {
         w = down_weight;

@@ -118,15 +118,14 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
 
   for (int idx = d.cam_obs_off[i] + lane; idx < d.cam_obs_off[i + 1]; idx += 64) {
     const int k = d.cam_obs[idx];
-    const int c = d.obs_copy[k];
-    if (d.status[d.copy_pt[c]] != 0) continue;
-    const double* pk = d.cpk + 12 * (int64_t)c;
-    const double X[3] = {pk[0], pk[1], pk[2]};
-    T Vi[6], gX[3];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) Vi[q] = (T)pk[3 + q];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) gX[q] = (T)pk[9 + q];
+    const int c = d.cam_obs_c[idx];
+    const double2* pk = reinterpret_cast<const double2*>(d.cpk + CPK * (int64_t)c);
+    const double2 p0 = pk[0], p1 = pk[1];
+    if (p1.y == 0.0) continue;  // point not valid (or sub-block inactive)
+    const double2 p2 = pk[2], p3 = pk[3], p4 = pk[4], p5 = pk[5], p6 = pk[6];
+    const double X[3] = {p0.x, p0.y, p1.x};
+    const T Vi[6] = {(T)p2.x, (T)p2.y, (T)p3.x, (T)p3.y, (T)p4.x, (T)p4.y};
+    const T gX[3] = {(T)p5.x, (T)p5.y, (T)p6.x};
     Lin<T> L;
     cm.lin(X, d, L);
     const W2<T> W = obs_weight_t<T>(d, k);
@@ -225,14 +224,13 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
 #pragma unroll
   for (int u = 0; u < 36; ++u) acc[u] = T(0);
   for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += 16) {
-    const int k1 = d.pb_ent[2 * e], k2 = d.pb_ent[2 * e + 1];
-    const int c = d.obs_copy[k1];
-    if (d.status[d.copy_pt[c]] != 0) continue;
-    const double* pk = d.cpk + 12 * (int64_t)c;
-    const double X[3] = {pk[0], pk[1], pk[2]};
-    T Vi[6];
-#pragma unroll
-    for (int u = 0; u < 6; ++u) Vi[u] = (T)pk[3 + u];
+    const int c = d.pb_ent[3 * e], k1 = d.pb_ent[3 * e + 1], k2 = d.pb_ent[3 * e + 2];
+    const double2* pk = reinterpret_cast<const double2*>(d.cpk + CPK * (int64_t)c);
+    const double2 p0 = pk[0], p1 = pk[1];
+    if (p1.y == 0.0) continue;  // point not valid
+    const double2 p2 = pk[2], p3 = pk[3], p4 = pk[4];
+    const double X[3] = {p0.x, p0.y, p1.x};
+    const T Vi[6] = {(T)p2.x, (T)p2.y, (T)p3.x, (T)p3.y, (T)p4.x, (T)p4.y};
     Lin<T> L1, L2;
     c1.lin(X, d, L1);
     c2.lin(X, d, L2);
