@@ -57,6 +57,10 @@ typedef enum {
 enum { RPBA_FP64 = 0, RPBA_MIXED = 1 };
 /* solver of the reduced camera system */
 enum { RPBA_SOLVER_CHOL = 0, RPBA_SOLVER_PCG_BJ = 1, RPBA_SOLVER_PCG_LEARNED = 2, RPBA_SOLVER_AUTO = 3 };
+/* schedule of the dense Cholesky factorisation: one persistent launch over
+ * a tile task list with per-tile ready flags (dataflow), or three launches
+ * per tile column (stepwise) */
+enum { RPBA_CHOL_DEFAULT = 0, RPBA_CHOL_STEPWISE = 1, RPBA_CHOL_DATAFLOW = 2 };
 /* per-point status written by rpba_intersect */
 enum {
   RPBA_PT_OK = 0,
@@ -96,7 +100,7 @@ typedef struct {
   double t_v;            /* robust threshold on the normalised residual (Sec. 5.3, parallel variant): 4 */
   double down_weight;    /* weight multiplier of flagged observations: 1e-4 */
   int32_t chol_tile;     /* Cholesky tile edge, 32 or 64 (0 = library choice) */
-  int32_t reserved;
+  int32_t chol_schedule; /* RPBA_CHOL_*; DEFAULT = dataflow */
 } rpba_options;
 
 /* Fill *opt with the defaults listed above.  HOST pointer. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "librpba.so")
 
 RPBA_FP64, RPBA_MIXED = 0, 1
 RPBA_SOLVER_CHOL, RPBA_SOLVER_PCG_BJ, RPBA_SOLVER_PCG_LEARNED, RPBA_SOLVER_AUTO = 0, 1, 2, 3
+RPBA_CHOL_DEFAULT, RPBA_CHOL_STEPWISE, RPBA_CHOL_DATAFLOW = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_WORKSPACE", 4: "ERR_NOT_SPD", 5: "ERR_STATE"}
 
 # every symbol include/rpba.h declares
@@ -53,7 +54,7 @@ class Options(ctypes.Structure):
         ("int_tol", ctypes.c_double), ("int_maxit", ctypes.c_int32), ("pcg_maxit", ctypes.c_int32),
         ("pcg_tol", ctypes.c_double), ("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
         ("pcg_min_cams", ctypes.c_int32), ("t_v", ctypes.c_double), ("down_weight", ctypes.c_double),
-        ("chol_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("chol_tile", ctypes.c_int32), ("chol_schedule", ctypes.c_int32),
     ]
 
 

@@ -47,7 +47,8 @@ struct WsMap {
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
-      pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c;
+      pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
+      df_ctl;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -127,6 +128,9 @@ WsMap layout_for(const Plan& P) {
   m.pm_xy = L.add(f8 * 2 * P.K);
   m.pm_w = L.add(f8 * (P.has_info ? 3 : 1) * P.K);
   m.cam_obs_c = L.add(i4 * P.cam_obs_c.size());
+  m.df_tasks = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
+  m.df_flags = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
+  m.df_ctl = L.add(i4 * 4);
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -191,6 +195,8 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
   if (o->precision != RPBA_FP64 && o->precision != RPBA_MIXED) return fail(RPBA_ERR_ARG, "unknown precision");
   if (!(o->lambda >= 0) || !(o->int_tol > 0) || o->int_maxit < 1) return fail(RPBA_ERR_ARG, "bad LM / intersection options");
   if (o->chol_tile != 0 && o->chol_tile != 32 && o->chol_tile != 64) return fail(RPBA_ERR_ARG, "chol_tile must be 0, 32 or 64");
+  if (o->chol_schedule < RPBA_CHOL_DEFAULT || o->chol_schedule > RPBA_CHOL_DATAFLOW)
+    return fail(RPBA_ERR_ARG, "chol_schedule must be RPBA_CHOL_DEFAULT, _STEPWISE or _DATAFLOW");
   return RPBA_OK;
 }
 
@@ -224,6 +230,9 @@ struct rpba_problem {
   std::vector<uint8_t> blk_pcg;
   // Cholesky work lists restricted to the sub-blocks solved densely
   std::vector<int64_t> pot_off, fwd_off, upd_off, bwd_off;
+  // dataflow factorisation: task count and resident workers
+  bool dataflow = true;
+  int32_t df_ntask = 0, df_workers = 0;
   int32_t nt_max_dense = 0;
   int32_t n_pcg = 0, max_pcg_n = 0, n_pcg_cams = 0;
   bool have_weights = false;
@@ -326,6 +335,7 @@ rpba_status rpba_default_options(rpba_options* o) {
   o->t_v = 4.0;
   o->down_weight = 1e-4;
   o->chol_tile = 0;
+  o->chol_schedule = RPBA_CHOL_DEFAULT;
   return RPBA_OK;
 }
 
@@ -478,6 +488,25 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
         h->any_dense = true;
         h->nt_max_dense = std::max(h->nt_max_dense, p.nt[l]);
       }
+    // dataflow task list: tile column by tile column, inside a column the
+    // sub-blocks with most tiles first, the diagonal tile before those below
+    std::vector<int32_t> dense;
+    for (int l = 0; l < p.L; ++l)
+      if (!h->blk_pcg[l]) dense.push_back(l);
+    std::stable_sort(dense.begin(), dense.end(), [&](int a, int b) { return p.nt[a] > p.nt[b]; });
+    tmp.clear();
+    for (int j = 0; j < h->nt_max_dense; ++j)
+      for (int l : dense) {
+        if (p.nt[l] <= j) continue;
+        for (int i = j; i <= p.nt[l]; ++i) tmp.push_back((l << 16) | (i << 8) | j);
+      }
+    h->df_ntask = (int32_t)tmp.size();
+    if (!tmp.empty()) HIP_TRY(up(m.df_tasks, tmp.data(), 4 * tmp.size()));
+    h->dataflow = o->chol_schedule != RPBA_CHOL_STEPWISE;
+    int dev = 0, ncu = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    h->df_workers = ncu * (p.T == 64 ? 2 : 4);
   }
 
   Dev& D = h->d;
@@ -581,6 +610,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero(D.ys, p.vec_total, st);
   launch_zero(D.x, p.vec_total, st);
   launch_zero_i32(D.blk_fail, D.L, st);
+  launch_zero_i32((int32_t*)(w + m.df_flags), p.rcs_total / ((int64_t)p.T * p.T), st);
+  launch_zero_i32((int32_t*)(w + m.df_ctl), 4, st);
   launch_zero_i32((int32_t*)(w + m.rob_bad), D.N, st);
   launch_zero((double*)(w + m.rob_sigma), D.M, st);
   launch_init_rcs(D, st);
@@ -627,6 +658,11 @@ static rpba_status assemble(rpba_problem* h, const uint8_t* active) {
 // panel solves, trailing update.
 static rpba_status chol_forward(rpba_problem* h, const int32_t* pot, const int32_t* fwd, const int32_t* upd) {
   hipStream_t st = h->stream;
+  if (h->dataflow) {
+    launch_chol_dataflow(h->d, (const int32_t*)(h->ws + h->map.df_tasks), h->df_ntask,
+                         (int*)(h->ws + h->map.df_flags), (int*)(h->ws + h->map.df_ctl), h->df_workers, st);
+    return RPBA_OK;
+  }
   for (int k = 0; k < h->nt_max_dense; ++k) {
     launch_chol_potrf(h->d, k, pot + h->pot_off[k], h->pot_off[k + 1] - h->pot_off[k], st);
     launch_chol_trsm(h->d, k, fwd + h->fwd_off[k], h->fwd_off[k + 1] - h->fwd_off[k], st);
@@ -648,7 +684,7 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
     const int32_t* bwd = (const int32_t*)(h->ws + h->map.bwd_items);
     if (h->any_dense) {
       {
-        PhaseTimer t(h, PH_CHOL_FWD, 3 * h->nt_max_dense);
+        PhaseTimer t(h, PH_CHOL_FWD, h->dataflow ? 3 : 3 * h->nt_max_dense);
         rpba_status s2 = chol_forward(h, pot, fwd, upd);
         if (s2 != RPBA_OK) return s2;
       }

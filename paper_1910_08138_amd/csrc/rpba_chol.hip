@@ -19,6 +19,8 @@
 // Backward launch k: x_k = L(k,k)^-T z_k, z_j -= L(k,j)^T x_k for j < k.
 #include "rpba_internal.hpp"
 
+#include <algorithm>
+
 namespace rpba {
 
 namespace {
@@ -72,6 +74,53 @@ __device__ __forceinline__ void gemm_nt_mf(const double* __restrict__ A, const d
 #pragma unroll
       for (int q = 0; q < NB; ++q)
         acc.v[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kg][p], b[kg][q], acc.v[p][q], 0, 0, 0);
+}
+
+// The same product with the k range in four groups, double-buffered: the
+// operands of group g + 1 are in flight while group g is multiplied (fewer
+// registers than loading everything up front).
+// device-coherent element access (relaxed atomics at agent scope): used for
+// the tiles that workgroups of one persistent launch hand to each other
+__device__ __forceinline__ double coh_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coh_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int T, bool NEG = false, bool COH_A = false, bool COH_B = false>
+__device__ __forceinline__ void gemm_nt_mf_pipe(const double* __restrict__ A, const double* __restrict__ B,
+                                                Acc<T>& acc) {
+  constexpr int NB = T / 32, KG = T / 4, G = 4, KGB = KG / G;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rb0 = (wv >> 1) * NB, cb0 = (wv & 1) * NB;
+  double a[2][KGB][NB], b[2][KGB][NB];
+  auto load = [&](int g, int buf) {
+#pragma unroll
+    for (int kk = 0; kk < KGB; ++kk)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int kg = g * KGB + kk;
+        const double* pa = A + ((rb0 + q) * (T / 4) + kg) * 64 + lane;
+        const double* pb = B + ((cb0 + q) * (T / 4) + kg) * 64 + lane;
+        const double av = COH_A ? coh_load(pa) : *pa;
+        a[buf][kk][q] = NEG ? -av : av;
+        b[buf][kk][q] = COH_B ? coh_load(pb) : *pb;
+      }
+  };
+  load(0, 0);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (g + 1 < G) load(g + 1, (g + 1) & 1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < KGB; ++kk)
+#pragma unroll
+      for (int p = 0; p < NB; ++p)
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          acc.v[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[g & 1][kk][p], b[g & 1][kk][q], acc.v[p][q], 0, 0, 0);
+  }
 }
 
 template <int T>
@@ -419,6 +468,159 @@ __global__ __launch_bounds__(NT) void k_selftest_gemm(const double* A, const dou
       }
 }
 
+
+// ---- one persistent launch for the whole forward factorisation ----------
+// Every tile (i, j), j <= i, j < nt, of every dense sub-block (the
+// right-hand-side row i = nt included) is one task.  Tasks are numbered
+// column by column (j ascending; inside a column the largest sub-blocks
+// first, the diagonal tile before the tiles below it), and a task only ever
+// waits for tasks with smaller numbers: the tiles (i,k), (j,k), k < j, and
+// for j < i the diagonal tile (j,j).  Workgroups take task numbers from a
+// ticket counter, so a task being waited for is always held by a running
+// workgroup and the launch cannot deadlock.  A finished tile publishes a
+// ready flag equal to the call's epoch; waits are bounded, and a wait that
+// runs out of its budget is counted as an error (the sub-blocks are then
+// reported as failed instead of hanging).
+//
+// Left-looking per tile: acc = A(i,j) - sum_k L(i,k) L(j,k)^T in registers,
+// then for i == j the diagonal factor and its inverse, for i > j the panel
+// solve L(i,j) = acc L(j,j)^-T.
+constexpr int DF_SPIN_LIMIT = 1 << 20;
+
+__device__ __forceinline__ int df_flag_load(const int* f) {
+  return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// thread 0 waits for the flags; the workgroup then reads the tiles with
+// device-coherent loads
+__device__ __forceinline__ void df_wait(const int* f1, const int* f2, int epoch, int* err) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    // an exhausted wait anywhere ends all later waits at once, so a broken
+    // dependency costs one wait budget, not one per task
+    while ((df_flag_load(f1) != epoch || (f2 && df_flag_load(f2) != epoch)) && df_flag_load(err) == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > DF_SPIN_LIMIT) {
+        atomicAdd(err, 1);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// the tile was written with device-coherent stores: every wave waits until
+// its stores are complete, then thread 0 sets the flag
+__device__ __forceinline__ void df_publish(int* f, int epoch) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_df_begin(int* ctl) {
+  if (threadIdx.x == 0) {
+    ctl[0] = 0;           // ticket
+    ctl[1] = ctl[1] + 1;  // epoch of this call
+    ctl[2] = 0;           // exhausted waits
+  }
+}
+
+__global__ void k_df_end(Dev d, const int* ctl) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < d.L && ctl[2] != 0) d.blk_fail[l] = 1;
+}
+
+template <int T>
+__global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* __restrict__ tasks, int ntask, int* flags,
+                                                      int* ctl) {
+  constexpr int LD = DiagLds<T>::LD;
+  __shared__ DiagLds<T> sm;
+  __shared__ int s_task;
+  const int epoch = ctl[1];
+  int* err = ctl + 2;
+  for (;;) {
+    __syncthreads();  // the previous task is done with s_task and LDS
+    if (threadIdx.x == 0) s_task = atomicAdd(ctl, 1);
+    __syncthreads();
+    const int t = s_task;
+    if (t >= ntask) break;
+    const int it = tasks[t];
+    const int l = it >> 16, i = (it >> 8) & 255, j = it & 255;
+    if (d.active && !d.active[l]) continue;
+    const int64_t tile0 = d.rcs_off[l] / (T * T);
+    auto fl = [&](int r, int c) { return flags + tile0 + (int64_t)r * (r + 1) / 2 + c; };
+    double* C = tile_ptr<T>(d, l, i, j);
+    Acc<T> acc;
+#pragma unroll
+    for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+      for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int r, c;
+          acc_rc<T>(p, q, e, r, c);
+          acc.v[p][q][e] = C[mf_idx(T, r, c)];
+        }
+    for (int k = 0; k < j; ++k) {
+      df_wait(fl(i, k), i == j ? nullptr : fl(j, k), epoch, err);
+      gemm_nt_mf_pipe<T, true, true, true>(tile_ptr<T>(d, l, i, k), tile_ptr<T>(d, l, j, k), acc);
+    }
+    if (i == j) {
+      // diagonal: factor and inverse through LDS
+      if (threadIdx.x == 0) sm.fail = 0;
+#pragma unroll
+      for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+        for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            int r, c;
+            acc_rc<T>(p, q, e, r, c);
+            sm.A[r * LD + c] = acc.v[p][q][e];
+          }
+      __syncthreads();
+      factor_inverse_tile<T>(sm);
+      double* Li = d.Li + d.diag_off[l] + (int64_t)j * T * T;
+      for (int idx = threadIdx.x; idx < T * T; idx += NT) {
+        const int blk = idx >> 6, w = idx & 63;
+        const int r = (blk / (T / 4)) * 16 + (w & 15), c = (blk % (T / 4)) * 4 + (w >> 4);
+        coh_store(Li + idx, r >= c ? sm.X[r * LD + c] : 0.0);
+      }
+      if (threadIdx.x == 0 && sm.fail) d.blk_fail[l] = 1;
+      df_publish(fl(j, j), epoch);
+    } else {
+      // panel solve: L(i,j) = acc Li(j,j)^T with acc staged in LDS in the
+      // matrix-core layout
+#pragma unroll
+      for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+        for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            int r, c;
+            acc_rc<T>(p, q, e, r, c);
+            sm.A[mf_idx(T, r, c)] = acc.v[p][q][e];
+          }
+      df_wait(fl(j, j), nullptr, epoch, err);  // also orders the LDS stores
+      const double* Li = d.Li + d.diag_off[l] + (int64_t)j * T * T;
+      Acc<T> out;
+      out.zero();
+      gemm_nt_mf_pipe<T, false, false, true>(sm.A, Li, out);
+#pragma unroll
+      for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+        for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            int r, c;
+            acc_rc<T>(p, q, e, r, c);
+            coh_store(C + mf_idx(T, r, c), out.v[p][q][e]);
+          }
+      df_publish(fl(i, j), epoch);
+    }
+  }
+}
+
 }  // namespace
 
 void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st) {
@@ -437,6 +639,19 @@ void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, h
   if (nupd <= 0) return;
   if (d.T == 64) hipLaunchKernelGGL(k_chol_update<64>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
   else hipLaunchKernelGGL(k_chol_update<32>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
+}
+
+void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_df_begin, dim3(1), dim3(64), 0, st, ctl);
+  if (ntask > 0) {
+    const unsigned g = (unsigned)std::max(1, std::min(ntask, nworkers));
+    if (d.T == 64)
+      hipLaunchKernelGGL(k_chol_dataflow<64>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, ctl);
+    else
+      hipLaunchKernelGGL(k_chol_dataflow<32>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, ctl);
+  }
+  hipLaunchKernelGGL(k_df_end, dim3((d.L + 255) / 256), dim3(256), 0, st, d, (const int*)ctl);
 }
 
 void launch_rhs_extract(const Dev& d, hipStream_t st) {

@@ -132,6 +132,10 @@ void launch_schur(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStr
 void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st);
 void launch_chol_trsm(const Dev& d, int k, const int32_t* trsm, int64_t ntrsm, hipStream_t st);
 void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, hipStream_t st);
+// the whole forward factorisation of all dense sub-blocks as one persistent
+// launch over a task list (see rpba_chol.hip); ctl = [ticket, epoch, errors]
+void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
+                          hipStream_t st);
 void launch_rhs_extract(const Dev& d, hipStream_t st);
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st);
 void launch_update(const Dev& d, double* block_stats, hipStream_t st);

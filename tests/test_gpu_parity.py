@@ -193,3 +193,24 @@ def test_single_camera_and_single_subblock_edges(rp):
     gp, gh, op, oh = _run_both(s2, 2, 2)
     for g, o in zip(gh, oh):
         assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0)
+
+
+@pytest.mark.parametrize("schedule", ["stepwise", "dataflow"])
+@pytest.mark.parametrize("tile", [32, 64])
+def test_cholesky_schedules(rp, schedule, tile):
+    """Both factorisation schedules (three launches per tile column, or one
+    persistent launch over a tile task list) at both tile edges, over a fixed
+    schedule, vs the oracle; graph replay on."""
+    from paper_1910_08138_amd import binding
+    sched = binding.RPBA_CHOL_STEPWISE if schedule == "stepwise" else binding.RPBA_CHOL_DATAFLOW
+    s = _scene("oblique-small", 8)
+    gp, gh = binding.run_schedule(s, T=3, I=2, graph=True, chol_tile=tile, chol_schedule=sched)
+    op, oh = oracle.run_schedule(s, T=3, I=2)
+    for g, o in zip(gh, oh):
+        assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0), (g["t"], g["int_stats"], o["int_stats"])
+        for bg, (bo, fails) in zip(g.get("steps", []), o.get("steps", [])):
+            assert fails == 0
+            assert np.allclose(bg[:, 1], bo[:, 1], rtol=TOL, atol=0)
+    gR, gC = gp.cameras()
+    oR, oC = op.cameras()
+    assert np.abs(gC - oC).max() <= TOL * _extent(s)

@@ -98,3 +98,5 @@ def test_validation_rejects_empty_subblock_and_bad_tile():
     s = scenes.config_scene(1, 0)
     rc, _, msg = _size(s, chol_tile=48)
     assert rc == 1 and "chol_tile" in msg
+    rc, _, msg = _size(s, chol_schedule=7)
+    assert rc == 1 and "chol_schedule" in msg
