@@ -306,3 +306,50 @@ def run_schedule(scene, T=6, I=4, robust=False, t_r=2, t_v=4.0, down_weight=1e-4
     final = op.intersect()
     hist.append(dict(t=T, int_stats=final))
     return op, hist
+
+
+def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, **kw):
+    """Schedule driven by the paper's improvement test (Sec. 5.4): a loop goes
+    on while the best cost so far divided by the current one reaches `ratio`;
+    the first step that falls short is tolerated once, the second one ends the
+    loop.  Inner loop per sub-block on its cost (a sub-block that stops is
+    left out of later steps of this outer iteration); outer loop on the
+    reprojection RMS of the intersections.  Returns the problem and per outer
+    iteration the number of steps each sub-block took."""
+    op = OracleProblem(scene, **kw)
+    L = scene.L
+    hist = []
+    best_out, grace_out = np.inf, False
+    for t in range(T_max):
+        st = op.intersect()
+        rms = st[2]
+        if t > 0:
+            rho = best_out / rms
+            if rho < ratio:
+                if grace_out:
+                    break
+                grace_out = True
+        best_out = min(best_out, rms)
+        active = np.ones(L, dtype=np.uint8)
+        steps = np.zeros(L, dtype=np.int64)
+        best = None
+        grace = np.zeros(L, dtype=bool)
+        for s in range(I_max):
+            bs, fails = op.lm_step(active)
+            on = active.astype(bool)
+            steps[on] += 1
+            if best is None:
+                best = bs[:, 0].copy()
+            cost = bs[:, 1]
+            slow = on & (best / np.where(on, cost, 1.0) < ratio)
+            stop = slow & grace
+            grace |= slow
+            best = np.where(on, np.minimum(best, cost), best)
+            active[stop] = 0
+            if not active.any():
+                break
+        op.consensus()
+        hist.append(dict(t=t, int_stats=st, steps=steps))
+    final = op.intersect()
+    hist.append(dict(t=len(hist), int_stats=final))
+    return op, hist

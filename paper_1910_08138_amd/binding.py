@@ -31,7 +31,7 @@ EXPORTS = [
     "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
 ]
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
-          "robust", "iterative_solve"]
+          "robust", "iterative_solve", "schur_pairs"]
 
 
 class RpbaError(RuntimeError):
@@ -366,4 +366,57 @@ def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, graph=Fals
         p.rpba_robust_reweight(True)
     final = _host(p, p.rpba_intersect())
     hist.append(dict(t=T, int_stats=final))
+    return p, hist
+
+
+def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, graph=False, **opts):
+    """Schedule driven by the improvement test of the method (Sec. 5.4): a
+    loop continues while best-cost-so-far / current-cost reaches `ratio`; the
+    first step that falls short is tolerated once, the second ends the loop.
+    The inner loop runs per sub-block on its cost, a stopped sub-block being
+    masked out of the later steps of the outer iteration (the `active` mask
+    of rpba_subblock_lm_step); the outer loop runs on the reprojection RMS of
+    the intersections.  Returns the problem and per outer iteration the
+    number of LM steps each sub-block took."""
+    import torch
+    p = Problem(scene, **opts)
+    if graph:
+        p.set_graph(True)
+    L = scene.L
+    hist = []
+    best_out, grace_out = np.inf, False
+    act_dev = torch.ones(L, dtype=torch.uint8, device=p.dev)
+    for t in range(T_max):
+        st = _host(p, p.rpba_intersect())
+        rms = st[2]
+        if t > 0:
+            if best_out / rms < ratio:
+                if grace_out:
+                    break
+                grace_out = True
+        best_out = min(best_out, rms)
+        active = np.ones(L, dtype=np.uint8)
+        steps = np.zeros(L, dtype=np.int64)
+        best = None
+        grace = np.zeros(L, dtype=bool)
+        for s in range(I_max):
+            act_dev.copy_(torch.as_tensor(active))
+            bs = _host(p, p.rpba_subblock_lm_step(act_dev))
+            on = active.astype(bool)
+            steps[on] += 1
+            if best is None:
+                best = bs[:, 0].copy()
+            cost = bs[:, 1]
+            with np.errstate(divide="ignore", invalid="ignore"):
+                slow = on & (best / np.where(on, cost, 1.0) < ratio)
+            stop = slow & grace
+            grace |= slow
+            best = np.where(on, np.minimum(best, cost), best)
+            active[stop] = 0
+            if not active.any():
+                break
+        p.rpba_consensus()
+        hist.append(dict(t=t, int_stats=st, steps=steps))
+    final = _host(p, p.rpba_intersect())
+    hist.append(dict(t=len(hist), int_stats=final))
     return p, hist

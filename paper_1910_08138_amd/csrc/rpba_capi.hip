@@ -217,7 +217,7 @@ struct CallGraph {
 };
 
 enum Phase { PH_INTERSECT = 0, PH_COPY_PREP, PH_SCHUR, PH_CHOL_FWD, PH_CHOL_BWD, PH_UPDATE, PH_CONSENSUS, PH_ROBUST,
-             PH_SOLVE_IT, NPHASE };
+             PH_SOLVE_IT, PH_SCHUR_OD, NPHASE };
 
 struct rpba_problem {
   std::shared_ptr<Plan> plan;
@@ -646,8 +646,14 @@ static rpba_status assemble(rpba_problem* h, const uint8_t* active) {
   }
   {
     const bool fp32 = h->opt.precision == RPBA_MIXED;
-    PhaseTimer t(h, PH_SCHUR, (h->d.n_od ? 2 : 1) + (h->any_dense ? 2 : 0));
-    launch_schur(h->d, fp32, h->any_dense, h->plan->rcs_total, h->stream);
+    {
+      PhaseTimer t(h, PH_SCHUR, 1 + (h->any_dense ? 2 : 0));
+      launch_schur_diag(h->d, fp32, h->any_dense, h->plan->rcs_total, h->stream);
+    }
+    if (h->d.n_od) {
+      PhaseTimer t(h, PH_SCHUR_OD, 1);
+      launch_schur_offdiag(h->d, fp32, h->stream);
+    }
   }
   HIP_TRY(hipGetLastError());
   return RPBA_OK;

@@ -517,6 +517,23 @@ __device__ __forceinline__ void df_publish(int* f, int epoch) {
   if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// wave 0 checks the flags of columns k .. min(j, k + 64) - 1 of tile rows
+// r1 and r2 (r2 < 0: r1 only) at once; returns (to every thread) the first
+// column that is not ready yet, or j
+__device__ __forceinline__ int df_poll(const int* row1, const int* row2, int k, int j, int epoch, int* sh) {
+  if (threadIdx.x < 64) {
+    const int kk = k + threadIdx.x;
+    bool ready = true;
+    if (kk < j) ready = df_flag_load(row1 + kk) == epoch && (row2 == nullptr || df_flag_load(row2 + kk) == epoch);
+    const unsigned long long not_ready = __ballot(!ready);
+    if (threadIdx.x == 0) *sh = not_ready ? k + __ffsll((long long)not_ready) - 1 : min(j, k + 64);
+  }
+  __syncthreads();
+  const int r = *sh;
+  __syncthreads();
+  return r;
+}
+
 __global__ void k_df_begin(int* ctl) {
   if (threadIdx.x == 0) {
     ctl[0] = 0;           // ticket
@@ -535,7 +552,7 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
                                                       int* ctl) {
   constexpr int LD = DiagLds<T>::LD;
   __shared__ DiagLds<T> sm;
-  __shared__ int s_task;
+  __shared__ int s_task, s_poll;
   const int epoch = ctl[1];
   int* err = ctl + 2;
   for (;;) {
@@ -561,8 +578,16 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
           acc_rc<T>(p, q, e, r, c);
           acc.v[p][q][e] = C[mf_idx(T, r, c)];
         }
+    // tiles (i,k) and (j,k) of the row: flags of row r start at fl(r, 0)
+    int kready = 0;  // every k < kready is known to be ready
     for (int k = 0; k < j; ++k) {
-      df_wait(fl(i, k), i == j ? nullptr : fl(j, k), epoch, err);
+      if (k >= kready) {
+        kready = df_poll(fl(i, 0), i == j ? nullptr : fl(j, 0), k, j, epoch, &s_poll);
+        if (kready == k) {
+          df_wait(fl(i, k), i == j ? nullptr : fl(j, k), epoch, err);
+          kready = k + 1;
+        }
+      }
       gemm_nt_mf_pipe<T, true, true, true>(tile_ptr<T>(d, l, i, k), tile_ptr<T>(d, l, j, k), acc);
     }
     if (i == j) {

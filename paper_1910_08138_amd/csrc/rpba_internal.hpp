@@ -128,7 +128,8 @@ void launch_gather(const Dev& d, hipStream_t st);
 void launch_init_rcs(const Dev& d, hipStream_t st);
 void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st);
 void launch_copy_prep(const Dev& d, hipStream_t st);
-void launch_schur(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st);
+void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st);
+void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st);
 void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st);
 void launch_chol_trsm(const Dev& d, int k, const int32_t* trsm, int64_t ntrsm, hipStream_t st);
 void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, hipStream_t st);

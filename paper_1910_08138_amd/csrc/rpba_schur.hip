@@ -262,7 +262,7 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
 
 }  // namespace
 
-void launch_schur(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st) {
+void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st) {
   if (dense) {
     // every lower element not covered by a pair block is zero; the padded
     // identity of the last diagonal tile is restored as well
@@ -270,14 +270,15 @@ void launch_schur(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStr
     launch_init_rcs(d, st);
   }
   const unsigned gd = (unsigned)((d.M + 3) / 4);
+  if (fp32) hipLaunchKernelGGL(k_schur_diag<float>, dim3(gd), dim3(NT), 0, st, d);
+  else hipLaunchKernelGGL(k_schur_diag<double>, dim3(gd), dim3(NT), 0, st, d);
+}
+
+void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st) {
   const unsigned go = (unsigned)((d.n_od + 15) / 16);
-  if (fp32) {
-    hipLaunchKernelGGL(k_schur_diag<float>, dim3(gd), dim3(NT), 0, st, d);
-    if (go) hipLaunchKernelGGL(k_schur_offdiag<float>, dim3(go), dim3(NT), 0, st, d);
-  } else {
-    hipLaunchKernelGGL(k_schur_diag<double>, dim3(gd), dim3(NT), 0, st, d);
-    if (go) hipLaunchKernelGGL(k_schur_offdiag<double>, dim3(go), dim3(NT), 0, st, d);
-  }
+  if (!go) return;
+  if (fp32) hipLaunchKernelGGL(k_schur_offdiag<float>, dim3(go), dim3(NT), 0, st, d);
+  else hipLaunchKernelGGL(k_schur_offdiag<double>, dim3(go), dim3(NT), 0, st, d);
 }
 
 }  // namespace rpba

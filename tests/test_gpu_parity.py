@@ -214,3 +214,23 @@ def test_cholesky_schedules(rp, schedule, tile):
     gR, gC = gp.cameras()
     oR, oC = op.cameras()
     assert np.abs(gC - oC).max() <= TOL * _extent(s)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_ratio_rule_schedule(rp, graph):
+    """Schedule driven by the improvement test (inner loop per sub-block via
+    the active mask, outer loop on the RMS): the GPU takes the same decisions
+    as the oracle and ends at the same state."""
+    from paper_1910_08138_amd import binding
+    s = _scene("aerial-small", 3)
+    gp, gh = binding.run_ratio_rule(s, T_max=6, I_max=10, graph=graph)
+    op, oh = oracle.run_ratio_rule(s, T_max=6, I_max=10)
+    assert len(gh) == len(oh)
+    for g, o in zip(gh, oh):
+        assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0), (g["t"], g["int_stats"], o["int_stats"])
+        if g.get("steps") is not None:
+            assert np.array_equal(g["steps"], o["steps"]), (g["t"], g["steps"], o["steps"])
+    assert any((g["steps"] < 10).any() for g in gh[:-1])   # the rule did stop sub-blocks early
+    gR, gC = gp.cameras()
+    oR, oC = op.cameras()
+    assert np.abs(gC - oC).max() <= TOL * _extent(s)

@@ -395,3 +395,17 @@ def test_robust_mad_recovers_sigma_and_flags_outliers():
     n2, _ = op.robust_reweight(4.0, 1e-4, eliminate=True)
     _, _, st = op.intersection()
     assert (st == oracle.ST_ELIMINATED).sum() > 0.8 * np.unique(s.obs_pt[out]).size
+
+
+def test_ratio_rule_stops_on_small_improvements():
+    """The improvement test ends an inner loop at the second step whose
+    best-so-far / current cost is below 1.01, and the outer loop likewise on
+    the RMS; with noisy data the RMS sequence then stops near sigma."""
+    s = scenes.config_scene(1, 4)
+    op, hist = oracle.run_ratio_rule(s, T_max=12, I_max=10)
+    steps = [h["steps"] for h in hist[:-1]]
+    assert all((st >= 1).all() and (st <= 10).all() for st in steps)
+    assert any((st < 10).all() for st in steps)
+    rms = [h["int_stats"][2] for h in hist]
+    assert len(hist) - 1 < 12                       # the outer loop stopped by itself
+    assert rms[-1] < 0.6 and rms[-1] > 0.4          # noise sigma = 0.5 px
