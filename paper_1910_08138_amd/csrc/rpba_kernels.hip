@@ -432,9 +432,16 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
     int l = d.copy_blk[c];
     bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
     if (act && d.status[d.copy_pt[c]] == 0) {
-      const double* pk = d.cpk + CPK * c;
-      double X[3] = {pk[0], pk[1], pk[2]};
-      double rhs[3] = {-pk[10], -pk[11], -pk[12]};
+      // the point block V* and g_X are rebuilt from the same linearisation
+      // that forms Y^T dC (as in the point-block pass: no stored inverse is
+      // read back), then V* dX = -g_X - sum_k Y_k^T dC_i(k)
+      double X[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
+      const int p = d.copy_pt[c];
+      const double* om = d.Om + 6 * c;
+      double dx0[3] = {X[0] - d.Xbar[p], X[1] - d.Xbar[(int64_t)d.N + p], X[2] - d.Xbar[2 * (int64_t)d.N + p]};
+      double h[6], g[3], bt[3] = {0.0, 0.0, 0.0};
+      for (int q = 0; q < 6; ++q) h[q] = om[q];
+      sym3_mul(om, dx0, g);
       const int base = d.blk_cam_off[l];
       const double* xs = d.x + d.vec_off[l];
       for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
@@ -442,23 +449,29 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
         const double* cm = d.cam + (int64_t)CAM_STRIDE * i;
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+        const W2<double> W = obs_weight(d, k);
+        add_point_normals<double>(L, W, L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1], h, g);
         const double* dC = xs + 6 * (i - base);
         // t = A dC = Ar w - B dc ; Y^T dC = B^T W t
         double t0 = L.Ar[0][0] * dC[0] + L.Ar[0][1] * dC[1] + L.Ar[0][2] * dC[2] -
                     (L.B[0][0] * dC[3] + L.B[0][1] * dC[4] + L.B[0][2] * dC[5]);
         double t1 = L.Ar[1][0] * dC[0] + L.Ar[1][1] * dC[1] + L.Ar[1][2] * dC[2] -
                     (L.B[1][0] * dC[3] + L.B[1][1] * dC[4] + L.B[1][2] * dC[5]);
-        W2<double> W = obs_weight(d, k);
         double wt0 = W.a * t0 + W.b * t1, wt1 = W.b * t0 + W.c * t1;
-        for (int s = 0; s < 3; ++s) rhs[s] -= L.B[0][s] * wt0 + L.B[1][s] * wt1;
+        for (int s = 0; s < 3; ++s) bt[s] += L.B[0][s] * wt0 + L.B[1][s] * wt1;
       }
-      double dX[3];
-      sym3_mul(pk + 4, rhs, dX);
+      h[0] *= 1.0 + d.lambda;
+      h[3] *= 1.0 + d.lambda;
+      h[5] *= 1.0 + d.lambda;
+      double lch[6], dX[3] = {0.0, 0.0, 0.0};
+      if (chol3(h, lch)) {
+        double rhs[3] = {-g[0] - bt[0], -g[1] - bt[1], -g[2] - bt[2]};
+        chol3_solve(lch, rhs, dX);
+      }
       double Xn[3] = {X[0] + dX[0], X[1] + dX[1], X[2] + dX[2]};
       d.Xc[3 * c] = Xn[0];
       d.Xc[3 * c + 1] = Xn[1];
       d.Xc[3 * c + 2] = Xn[2];
-      int p = d.copy_pt[c];
       double dx[3] = {Xn[0] - d.Xbar[p], Xn[1] - d.Xbar[(int64_t)d.N + p], Xn[2] - d.Xbar[2 * (int64_t)d.N + p]};
       double og[3];
       sym3_mul(d.Om + 6 * c, dx, og);

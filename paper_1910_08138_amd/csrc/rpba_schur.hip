@@ -99,6 +99,45 @@ __device__ __forceinline__ T group16_sum(T v) {
   return v;
 }
 
+// Inputs of one observation k of copy c to the Schur pass, loaded ahead of
+// use: the copy's point (FP64) and damped inverse, g_X (diagonal pass only),
+// the pixel and the weight, converted to T.
+template <typename T>
+struct ObsIn {
+  double X[3];
+  T Vi[6], gX[3], x, y;
+  W2<T> W;
+  bool valid;
+};
+
+template <typename T, bool DIAG>
+__device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_range, ObsIn<T>& o) {
+  o.valid = false;
+  if (!in_range) return;
+  const double2* pk = reinterpret_cast<const double2*>(d.cpk + CPK * (int64_t)c);
+  const double2 p0 = pk[0], p1 = pk[1], p2 = pk[2], p3 = pk[3], p4 = pk[4];
+  o.valid = p1.y != 0.0;  // point not valid (or sub-block inactive): zero record
+  o.X[0] = p0.x;
+  o.X[1] = p0.y;
+  o.X[2] = p1.x;
+  o.Vi[0] = (T)p2.x;
+  o.Vi[1] = (T)p2.y;
+  o.Vi[2] = (T)p3.x;
+  o.Vi[3] = (T)p3.y;
+  o.Vi[4] = (T)p4.x;
+  o.Vi[5] = (T)p4.y;
+  if (DIAG) {
+    const double2 p5 = pk[5], p6 = pk[6];
+    o.gX[0] = (T)p5.x;
+    o.gX[1] = (T)p5.y;
+    o.gX[2] = (T)p6.x;
+    const double2 xy = reinterpret_cast<const double2*>(d.xy)[k];
+    o.x = (T)xy.x;
+    o.y = (T)xy.y;
+  }
+  o.W = obs_weight_t<T>(d, k);
+}
+
 // One wave per camera: diagonal block S_(i,i) = U*_i - sum_k Y_k V*^-1 Y_k^T
 // and e_i.
 template <typename T>
@@ -116,20 +155,11 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
 #pragma unroll
   for (int q = 0; q < 6; ++q) gC[q] = ep[q] = T(0);
 
-  for (int idx = d.cam_obs_off[i] + lane; idx < d.cam_obs_off[i + 1]; idx += 64) {
-    const int k = d.cam_obs[idx];
-    const int c = d.cam_obs_c[idx];
-    const double2* pk = reinterpret_cast<const double2*>(d.cpk + CPK * (int64_t)c);
-    const double2 p0 = pk[0], p1 = pk[1];
-    if (p1.y == 0.0) continue;  // point not valid (or sub-block inactive)
-    const double2 p2 = pk[2], p3 = pk[3], p4 = pk[4], p5 = pk[5], p6 = pk[6];
-    const double X[3] = {p0.x, p0.y, p1.x};
-    const T Vi[6] = {(T)p2.x, (T)p2.y, (T)p3.x, (T)p3.y, (T)p4.x, (T)p4.y};
-    const T gX[3] = {(T)p5.x, (T)p5.y, (T)p6.x};
+  auto process = [&](const ObsIn<T>& o) {
     Lin<T> L;
-    cm.lin(X, d, L);
-    const W2<T> W = obs_weight_t<T>(d, k);
-    const T v0 = L.g0 - (T)d.xy[2 * k], v1 = L.g1 - (T)d.xy[2 * k + 1];
+    cm.lin(o.X, d, L);
+    const W2<T> W = o.W;
+    const T v0 = L.g0 - o.x, v1 = L.g1 - o.y;
     T A[2][6], WA[2][6];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -152,12 +182,52 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
     }
     T Y[6][3], Z[6][3];
     y_block<T>(L, W, Y);
-    z_block<T>(Y, Vi, Z);
+    z_block<T>(Y, o.Vi, Z);
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
-      ep[r] += Z[r][0] * gX[0] + Z[r][1] * gX[1] + Z[r][2] * gX[2];
+      ep[r] += Z[r][0] * o.gX[0] + Z[r][1] * o.gX[1] + Z[r][2] * o.gX[2];
 #pragma unroll
       for (int s = r; s < 6; ++s) acc[up6(r, s)] -= Z[r][0] * Y[s][0] + Z[r][1] * Y[s][1] + Z[r][2] * Y[s][2];
+    }
+  };
+  const int o0 = d.cam_obs_off[i], o1 = d.cam_obs_off[i + 1];
+  if constexpr (sizeof(T) == 4) {
+    // FP32: a two-stage software pipeline over the camera's observations
+    // (indices two rounds ahead, the copy record, pixel and weight one round
+    // ahead); in FP64 the extra registers would cost occupancy
+    int t = o0 + lane;
+    int kB = 0, cB = 0;
+    ObsIn<T> cur;
+    {
+      int kA = 0, cA = 0;
+      if (t < o1) {
+        kA = d.cam_obs[t];
+        cA = d.cam_obs_c[t];
+      }
+      if (t + 64 < o1) {
+        kB = d.cam_obs[t + 64];
+        cB = d.cam_obs_c[t + 64];
+      }
+      obs_in_load<T, true>(d, kA, cA, t < o1, cur);
+    }
+    for (; t < o1; t += 64) {
+      int kC = 0, cC = 0;
+      if (t + 128 < o1) {
+        kC = d.cam_obs[t + 128];
+        cC = d.cam_obs_c[t + 128];
+      }
+      ObsIn<T> nxt;
+      obs_in_load<T, true>(d, kB, cB, t + 64 < o1, nxt);
+      if (cur.valid) process(cur);
+      cur = nxt;
+      kB = kC;
+      cB = cC;
+    }
+  } else {
+    for (int t = o0 + lane; t < o1; t += 64) {
+      ObsIn<T> cur;
+      obs_in_load<T, true>(d, d.cam_obs[t], d.cam_obs_c[t], true, cur);
+      if (cur.valid) process(cur);
     }
   }
 #pragma unroll
@@ -225,19 +295,16 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
   for (int u = 0; u < 36; ++u) acc[u] = T(0);
   for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += 16) {
     const int c = d.pb_ent[3 * e], k1 = d.pb_ent[3 * e + 1], k2 = d.pb_ent[3 * e + 2];
-    const double2* pk = reinterpret_cast<const double2*>(d.cpk + CPK * (int64_t)c);
-    const double2 p0 = pk[0], p1 = pk[1];
-    if (p1.y == 0.0) continue;  // point not valid
-    const double2 p2 = pk[2], p3 = pk[3], p4 = pk[4];
-    const double X[3] = {p0.x, p0.y, p1.x};
-    const T Vi[6] = {(T)p2.x, (T)p2.y, (T)p3.x, (T)p3.y, (T)p4.x, (T)p4.y};
+    ObsIn<T> o;
+    obs_in_load<T, false>(d, k1, c, true, o);
+    if (!o.valid) continue;
     Lin<T> L1, L2;
-    c1.lin(X, d, L1);
-    c2.lin(X, d, L2);
+    c1.lin(o.X, d, L1);
+    c2.lin(o.X, d, L2);
     T Y1[6][3], Y2[6][3], Z1[6][3];
-    y_block<T>(L1, obs_weight_t<T>(d, k1), Y1);
+    y_block<T>(L1, o.W, Y1);
     y_block<T>(L2, obs_weight_t<T>(d, k2), Y2);
-    z_block<T>(Y1, Vi, Z1);
+    z_block<T>(Y1, o.Vi, Z1);
 #pragma unroll
     for (int r = 0; r < 6; ++r)
 #pragma unroll
