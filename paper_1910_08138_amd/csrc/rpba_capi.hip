@@ -519,6 +519,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.T = p.T;
   D.int_maxit = o->int_maxit;
   D.has_info = p.has_info ? 1 : 0;
+  D.cpk_f32 = o->precision == RPBA_MIXED ? 1 : 0;
   D.f = d->f;
   D.cx = d->cx;
   D.cy = d->cy;

@@ -66,7 +66,10 @@ struct Dev {
   const int64_t* blk_copy_off;
   double* Xc;             // [NC][3] X_j^l
   double* Om;             // [NC][6] refined tie-point weight
-  double* cpk;            // [NC][CPK] X (3), valid (1 or 0), damped V^-1 (6), g_X (3), spare (3)
+  double* cpk;            // [NC][CPK] X (3), valid (1 or 0), damped V^-1 (6), g_X (3), spare (3);
+                          // on the mixed path [NC][CPK32]: X (3 doubles), then
+                          // as floats V^-1 (6), g_X (3), valid
+  int32_t cpk_f32;        // 1: compact FP32 copy records
   const int32_t* nb_off;
   const int32_t* nb_cam;
   // pair blocks (see the plan) and the block-sparse matrix of iterative sub-blocks
@@ -104,8 +107,10 @@ struct Dev {
   double* acc_rob;        // [2]
 };
 
-// one 128-byte record per copy for the current LM step
+// one 128-byte record per copy for the current LM step (64 bytes, CPK32
+// doubles, on the mixed path)
 constexpr int CPK = 16;
+constexpr int CPK32 = 8;
 
 // In-tile layout of the RCS tiles, chosen for the FP64 matrix cores: element
 // (r, c) of a T x T tile lives at ((r / 16) (T / 4) + c / 4) 64 + r % 16 +

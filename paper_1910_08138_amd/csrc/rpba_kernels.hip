@@ -373,20 +373,40 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
       if (ok) chol3_inverse(lch, inv);
       else
         for (int q = 0; q < 6; ++q) inv[q] = 0.0;
-      double2* p2 = reinterpret_cast<double2*>(pk);
-      p2[0] = make_double2(X[0], X[1]);
-      p2[1] = make_double2(X[2], 1.0);
-      p2[2] = make_double2(inv[0], inv[1]);
-      p2[3] = make_double2(inv[2], inv[3]);
-      p2[4] = make_double2(inv[4], inv[5]);
-      p2[5] = make_double2(ok ? g[0] : 0.0, ok ? g[1] : 0.0);
-      p2[6] = make_double2(ok ? g[2] : 0.0, 0.0);
+      if (d.cpk_f32) {
+        // compact record: X in FP64, V*^-1 and g_X rounded to FP32 (the
+        // precision the mixed Schur pass computes in), valid flag
+        uint32_t w[16];
+        __builtin_memcpy(w, X, 24);
+        float f[10];
+        for (int q = 0; q < 6; ++q) f[q] = (float)inv[q];
+        for (int q = 0; q < 3; ++q) f[6 + q] = ok ? (float)g[q] : 0.f;
+        f[9] = 1.f;
+        __builtin_memcpy(w + 6, f, 40);
+        uint4* p4 = reinterpret_cast<uint4*>(d.cpk + CPK32 * c);
+        for (int q = 0; q < 4; ++q) p4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      } else {
+        double2* p2 = reinterpret_cast<double2*>(pk);
+        p2[0] = make_double2(X[0], X[1]);
+        p2[1] = make_double2(X[2], 1.0);
+        p2[2] = make_double2(inv[0], inv[1]);
+        p2[3] = make_double2(inv[2], inv[3]);
+        p2[4] = make_double2(inv[4], inv[5]);
+        p2[5] = make_double2(ok ? g[0] : 0.0, ok ? g[1] : 0.0);
+        p2[6] = make_double2(ok ? g[2] : 0.0, 0.0);
+      }
       int slot = l - l_first;
       if (slot >= 0 && slot < 8) atomicAdd(&sh[slot], cost);
       else atomicAdd(&d.acc_blk[4 * l + 0], cost);
     } else {
-      double2* p2 = reinterpret_cast<double2*>(pk);
-      for (int q = 0; q < CPK / 2; ++q) p2[q] = make_double2(0.0, 0.0);
+      // zero record: the Schur pass skips the copy
+      if (d.cpk_f32) {
+        uint4* p4 = reinterpret_cast<uint4*>(d.cpk + CPK32 * c);
+        for (int q = 0; q < 4; ++q) p4[q] = make_uint4(0u, 0u, 0u, 0u);
+      } else {
+        double2* p2 = reinterpret_cast<double2*>(pk);
+        for (int q = 0; q < CPK / 2; ++q) p2[q] = make_double2(0.0, 0.0);
+      }
     }
   }
   __syncthreads();

@@ -114,23 +114,51 @@ template <typename T, bool DIAG>
 __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_range, ObsIn<T>& o) {
   o.valid = false;
   if (!in_range) return;
-  const double2* pk = reinterpret_cast<const double2*>(d.cpk + CPK * (int64_t)c);
-  const double2 p0 = pk[0], p1 = pk[1], p2 = pk[2], p3 = pk[3], p4 = pk[4];
-  o.valid = p1.y != 0.0;  // point not valid (or sub-block inactive): zero record
-  o.X[0] = p0.x;
-  o.X[1] = p0.y;
-  o.X[2] = p1.x;
-  o.Vi[0] = (T)p2.x;
-  o.Vi[1] = (T)p2.y;
-  o.Vi[2] = (T)p3.x;
-  o.Vi[3] = (T)p3.y;
-  o.Vi[4] = (T)p4.x;
-  o.Vi[5] = (T)p4.y;
+  if constexpr (sizeof(T) == 4) {
+    // compact record of the mixed path: X (3 doubles), V*^-1 (6 floats),
+    // g_X (3 floats), valid (float)
+    const uint4* p4 = reinterpret_cast<const uint4*>(d.cpk + CPK32 * (int64_t)c);
+    uint32_t w[16];
+    const uint4 a = p4[0], b = p4[1], e = p4[2];
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+    w[8] = e.x; w[9] = e.y; w[10] = e.z; w[11] = e.w;
+    if (DIAG) {
+      const uint4 f4 = p4[3];
+      w[12] = f4.x; w[13] = f4.y; w[14] = f4.z; w[15] = f4.w;
+    } else {
+      const uint4 f4 = p4[3];
+      w[15] = f4.w;
+      w[12] = w[13] = w[14] = 0u;
+    }
+    __builtin_memcpy(o.X, w, 24);
+    float f[10];
+    __builtin_memcpy(f, w + 6, 40);
+    o.valid = f[9] != 0.f;
+    for (int q = 0; q < 6; ++q) o.Vi[q] = (T)f[q];
+    if (DIAG)
+      for (int q = 0; q < 3; ++q) o.gX[q] = (T)f[6 + q];
+  } else {
+    const double2* pk = reinterpret_cast<const double2*>(d.cpk + CPK * (int64_t)c);
+    const double2 p0 = pk[0], p1 = pk[1], p2 = pk[2], p3 = pk[3], p4 = pk[4];
+    o.valid = p1.y != 0.0;  // point not valid (or sub-block inactive): zero record
+    o.X[0] = p0.x;
+    o.X[1] = p0.y;
+    o.X[2] = p1.x;
+    o.Vi[0] = (T)p2.x;
+    o.Vi[1] = (T)p2.y;
+    o.Vi[2] = (T)p3.x;
+    o.Vi[3] = (T)p3.y;
+    o.Vi[4] = (T)p4.x;
+    o.Vi[5] = (T)p4.y;
+    if (DIAG) {
+      const double2 p5 = pk[5], p6 = pk[6];
+      o.gX[0] = (T)p5.x;
+      o.gX[1] = (T)p5.y;
+      o.gX[2] = (T)p6.x;
+    }
+  }
   if (DIAG) {
-    const double2 p5 = pk[5], p6 = pk[6];
-    o.gX[0] = (T)p5.x;
-    o.gX[1] = (T)p5.y;
-    o.gX[2] = (T)p6.x;
     const double2 xy = reinterpret_cast<const double2*>(d.xy)[k];
     o.x = (T)xy.x;
     o.y = (T)xy.y;
