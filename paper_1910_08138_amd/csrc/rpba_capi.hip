@@ -48,7 +48,7 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl;
+      df_ctl, blk_fresh;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -131,6 +131,7 @@ WsMap layout_for(const Plan& P) {
   m.df_tasks = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
   m.df_flags = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
   m.df_ctl = L.add(i4 * 4);
+  m.blk_fresh = L.add(i4 * P.L);
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -567,6 +568,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.copy_blk = I(m.copy_blk);
   D.blk_copy_off = (const int64_t*)(w + m.blk_copy_off);
   D.Xc = F(m.Xc);
+  D.blk_fresh = I(m.blk_fresh);
   D.Om = F(m.Om);
   D.cpk = F(m.cpk);
   D.nb_off = I(m.nb_off);
@@ -613,6 +615,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero_i32(D.blk_fail, D.L, st);
   launch_zero_i32((int32_t*)(w + m.df_flags), p.rcs_total / ((int64_t)p.T * p.T), st);
   launch_zero_i32((int32_t*)(w + m.df_ctl), 4, st);
+  launch_zero_i32(D.blk_fresh, D.L, st);
   launch_zero_i32((int32_t*)(w + m.rob_bad), D.N, st);
   launch_zero((double*)(w + m.rob_sigma), D.M, st);
   launch_init_rcs(D, st);
@@ -817,7 +820,17 @@ rpba_status rpba_get_copies(rpba_problem* h, int32_t* blk, int32_t* pt, double* 
   if (blk) std::memcpy(blk, p.copy_blk.data(), 4 * p.NC);
   if (pt)
     for (int64_t c = 0; c < p.NC; ++c) pt[c] = p.pt_orig[p.copy_pt[c]];
-  if (X) HIP_TRY(hipMemcpy(X, h->d.Xc, 8 * 3 * p.NC, hipMemcpyDeviceToHost));
+  if (X) {
+    // copies of a sub-block not updated since the last intersection are at Xbar
+    HIP_TRY(hipMemcpy(X, h->d.Xc, 8 * 3 * p.NC, hipMemcpyDeviceToHost));
+    std::vector<int32_t> fresh(p.L);
+    HIP_TRY(hipMemcpy(fresh.data(), h->d.blk_fresh, 4 * (size_t)p.L, hipMemcpyDeviceToHost));
+    std::vector<double> xb(3 * (size_t)p.N);
+    HIP_TRY(hipMemcpy(xb.data(), h->d.Xbar, 8 * 3 * (size_t)p.N, hipMemcpyDeviceToHost));
+    for (int64_t c = 0; c < p.NC; ++c)
+      if (fresh[p.copy_blk[c]])
+        for (int r = 0; r < 3; ++r) X[3 * c + r] = xb[(size_t)r * p.N + p.copy_pt[c]];
+  }
   if (omega) HIP_TRY(hipMemcpy(omega, h->d.Om, 8 * 6 * p.NC, hipMemcpyDeviceToHost));
   return RPBA_OK;
 }

@@ -64,7 +64,9 @@ struct Dev {
   const int32_t* copy_pt;
   const int32_t* copy_blk;
   const int64_t* blk_copy_off;
-  double* Xc;             // [NC][3] X_j^l
+  double* Xc;             // [NC][3] X_j^l (valid when the sub-block is not fresh)
+  int32_t* blk_fresh;     // [L] 1: every copy of the sub-block is still at Xbar (set by the
+                          // intersection, cleared by the sub-block's next update)
   double* Om;             // [NC][6] refined tie-point weight
   double* cpk;            // [NC][CPK] X (3), valid (1 or 0), damped V^-1 (6), g_X (3), spare (3);
                           // on the mixed path [NC][CPK32]: X (3 doubles), then

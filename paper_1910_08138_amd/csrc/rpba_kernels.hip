@@ -160,6 +160,8 @@ __global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t
   static_assert(NT == INT_WG, "one intersection workgroup per plan workgroup");
   __shared__ double cams[INT_CAM_CAP * 12];
   __shared__ double sh[4 * 8];
+  if (blockIdx.x == 0)
+    for (int l = threadIdx.x; l < d.L; l += NT) d.blk_fresh[l] = 1;
   {
     const int cb = d.iwg_cam_off[blockIdx.x], nc = d.iwg_cam_off[blockIdx.x + 1] - cb;
     for (int t = threadIdx.x; t < nc * 12; t += NT) {
@@ -279,7 +281,8 @@ __global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t
         d.u_pts[(int64_t)r * d.N + o] = X[r];
       }
       // Omega^l = H - H^(l): information from the cameras outside sub-block l
-      // (zero for a point seen by one sub-block only)
+      // (zero for a point seen by one sub-block only).  The copies themselves
+      // are reset to Xbar through the sub-blocks' fresh flags.
       for (int cc = c0; cc < c1; ++cc) {
         const int c = d.pt_copies[cc];
         double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)c);
@@ -302,7 +305,6 @@ __global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t
         om[0] = make_double2(o6[0], o6[1]);
         om[1] = make_double2(o6[2], o6[3]);
         om[2] = make_double2(o6[4], o6[5]);
-        for (int r = 0; r < 3; ++r) d.Xc[3 * (int64_t)c + r] = X[r];
       }
       accv[0] = cost;
       accv[1] = sq;
@@ -348,10 +350,13 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
     bool act = d.active == nullptr || d.active[l];
     double* pk = d.cpk + CPK * c;
     if (act && d.status[d.copy_pt[c]] == 0) {
-      double X[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
+      const int p = d.copy_pt[c];
+      const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
+      double X[3] = {xb[0], xb[1], xb[2]};
+      if (!d.blk_fresh[l])
+        for (int r = 0; r < 3; ++r) X[r] = d.Xc[3 * c + r];
       const double* om = d.Om + 6 * c;
-      int p = d.copy_pt[c];
-      double dx[3] = {X[0] - d.Xbar[p], X[1] - d.Xbar[(int64_t)d.N + p], X[2] - d.Xbar[2 * (int64_t)d.N + p]};
+      double dx[3] = {X[0] - xb[0], X[1] - xb[1], X[2] - xb[2]};
       double h[6], g[3];
       for (int q = 0; q < 6; ++q) h[q] = om[q];
       sym3_mul(om, dx, g);
@@ -455,10 +460,13 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       // the point block V* and g_X are rebuilt from the same linearisation
       // that forms Y^T dC (as in the point-block pass: no stored inverse is
       // read back), then V* dX = -g_X - sum_k Y_k^T dC_i(k)
-      double X[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
       const int p = d.copy_pt[c];
+      const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
+      double X[3] = {xb[0], xb[1], xb[2]};
+      if (!d.blk_fresh[l])
+        for (int r = 0; r < 3; ++r) X[r] = d.Xc[3 * c + r];
       const double* om = d.Om + 6 * c;
-      double dx0[3] = {X[0] - d.Xbar[p], X[1] - d.Xbar[(int64_t)d.N + p], X[2] - d.Xbar[2 * (int64_t)d.N + p]};
+      double dx0[3] = {X[0] - xb[0], X[1] - xb[1], X[2] - xb[2]};
       double h[6], g[3], bt[3] = {0.0, 0.0, 0.0};
       for (int q = 0; q < 6; ++q) h[q] = om[q];
       sym3_mul(om, dx0, g);
@@ -492,7 +500,7 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       d.Xc[3 * c] = Xn[0];
       d.Xc[3 * c + 1] = Xn[1];
       d.Xc[3 * c + 2] = Xn[2];
-      double dx[3] = {Xn[0] - d.Xbar[p], Xn[1] - d.Xbar[(int64_t)d.N + p], Xn[2] - d.Xbar[2 * (int64_t)d.N + p]};
+      double dx[3] = {Xn[0] - xb[0], Xn[1] - xb[1], Xn[2] - xb[2]};
       double og[3];
       sym3_mul(d.Om + 6 * c, dx, og);
       double cost = dx[0] * og[0] + dx[1] * og[1] + dx[2] * og[2];
@@ -531,6 +539,7 @@ __global__ void k_block_stats(Dev d, double* bs) {
   if (l >= d.L) return;
   bool act = d.active == nullptr || d.active[l];
   const double* a = d.acc_blk + 4 * l;
+  if (act && d.blk_fail[l] == 0) d.blk_fresh[l] = 0;  // its copies were written by the update
   if (bs) {
     bs[4 * l + 0] = act ? a[0] : 0.0;
     bs[4 * l + 1] = act ? (d.blk_fail[l] ? a[0] : a[1]) : 0.0;
@@ -548,9 +557,23 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
     int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
     if (c1 - c0 > 1) ntp = 1.0;
     if (d.status[j] == 0) {
+      // copy positions: a fresh sub-block's copies are still at Xbar
+      const double xb[3] = {d.Xbar[j], d.Xbar[(int64_t)d.N + j], d.Xbar[2 * (int64_t)d.N + j]};
+      auto copy_x = [&](int c, double (&x)[3]) {
+        if (d.blk_fresh[d.copy_blk[c]]) {
+          x[0] = xb[0];
+          x[1] = xb[1];
+          x[2] = xb[2];
+        } else {
+          x[0] = d.Xc[3 * (int64_t)c];
+          x[1] = d.Xc[3 * (int64_t)c + 1];
+          x[2] = d.Xc[3 * (int64_t)c + 2];
+        }
+      };
       double m[3] = {0, 0, 0};
       for (int cc = c0; cc < c1; ++cc) {
-        const double* x = d.Xc + 3 * (int64_t)d.pt_copies[cc];
+        double x[3];
+        copy_x(d.pt_copies[cc], x);
         m[0] += x[0];
         m[1] += x[1];
         m[2] += x[2];
@@ -558,7 +581,8 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
       double inv = 1.0 / (double)(c1 - c0);
       for (int r = 0; r < 3; ++r) m[r] *= inv;
       for (int cc = c0; cc < c1; ++cc) {
-        const double* x = d.Xc + 3 * (int64_t)d.pt_copies[cc];
+        double x[3];
+        copy_x(d.pt_copies[cc], x);
         double e0 = x[0] - m[0], e1 = x[1] - m[1], e2 = x[2] - m[2];
         dmax = fmax(dmax, sqrt(e0 * e0 + e1 * e1 + e2 * e2));
       }
