@@ -48,7 +48,7 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl, blk_fresh;
+      df_ctl, blk_fresh, dfb_tasks, dfb_flags;
   size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -132,6 +132,8 @@ WsMap layout_for(const Plan& P) {
   m.df_flags = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
   m.df_ctl = L.add(i4 * 4);
   m.blk_fresh = L.add(i4 * P.L);
+  m.dfb_tasks = L.add(i4 * (P.vec_total / P.T));
+  m.dfb_flags = L.add(i4 * (P.vec_total / P.T));
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
@@ -233,7 +235,7 @@ struct rpba_problem {
   std::vector<int64_t> pot_off, fwd_off, upd_off, bwd_off;
   // dataflow factorisation: task count and resident workers
   bool dataflow = true;
-  int32_t df_ntask = 0, df_workers = 0;
+  int32_t df_ntask = 0, df_workers = 0, dfb_ntask = 0;
   int32_t nt_max_dense = 0;
   int32_t n_pcg = 0, max_pcg_n = 0, n_pcg_cams = 0;
   bool have_weights = false;
@@ -503,6 +505,13 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
       }
     h->df_ntask = (int32_t)tmp.size();
     if (!tmp.empty()) HIP_TRY(up(m.df_tasks, tmp.data(), 4 * tmp.size()));
+    // backward tasks: tile rows from the last one down
+    tmp.clear();
+    for (int k = h->nt_max_dense - 1; k >= 0; --k)
+      for (int l : dense)
+        if (p.nt[l] > k) tmp.push_back((l << 16) | (k << 8));
+    h->dfb_ntask = (int32_t)tmp.size();
+    if (!tmp.empty()) HIP_TRY(up(m.dfb_tasks, tmp.data(), 4 * tmp.size()));
     h->dataflow = o->chol_schedule != RPBA_CHOL_STEPWISE;
     int dev = 0, ncu = 256;
     HIP_TRY(hipGetDevice(&dev));
@@ -616,6 +625,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero_i32((int32_t*)(w + m.df_flags), p.rcs_total / ((int64_t)p.T * p.T), st);
   launch_zero_i32((int32_t*)(w + m.df_ctl), 4, st);
   launch_zero_i32(D.blk_fresh, D.L, st);
+  launch_zero_i32((int32_t*)(w + m.dfb_flags), p.vec_total / p.T, st);
   launch_zero_i32((int32_t*)(w + m.rob_bad), D.N, st);
   launch_zero((double*)(w + m.rob_sigma), D.M, st);
   launch_init_rcs(D, st);
@@ -699,10 +709,15 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
         if (s2 != RPBA_OK) return s2;
       }
       {
-        PhaseTimer t(h, PH_CHOL_BWD, h->nt_max_dense + 1);
+        PhaseTimer t(h, PH_CHOL_BWD, h->dataflow ? 4 : h->nt_max_dense + 1);
         launch_rhs_extract(h->d, h->stream);
-        for (int s2 = 0; s2 < p.nt_max; ++s2)
-          launch_chol_backward(h->d, bwd + h->bwd_off[s2], h->bwd_off[s2 + 1] - h->bwd_off[s2], h->stream);
+        if (h->dataflow)
+          launch_chol_backward_dataflow(h->d, (const int32_t*)(h->ws + h->map.dfb_tasks), h->dfb_ntask,
+                                        (int*)(h->ws + h->map.dfb_flags), (int*)(h->ws + h->map.df_ctl),
+                                        h->df_workers, h->stream);
+        else
+          for (int s2 = 0; s2 < p.nt_max; ++s2)
+            launch_chol_backward(h->d, bwd + h->bwd_off[s2], h->bwd_off[s2 + 1] - h->bwd_off[s2], h->stream);
       }
     }
     if (h->n_pcg) {

@@ -646,6 +646,76 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
   }
 }
 
+
+// ---- one persistent launch for the backward substitution ------------------
+// Task (l, k) produces x_k = L(k,k)^-T z_k with z_k = y_k - sum_{m > k}
+// L(m,k)^T x_m (y = L^-1 e from the forward factorisation).  Tasks are
+// numbered by k descending, so a task only waits for tasks with smaller
+// numbers; x segments are handed over with device-coherent stores and a ready
+// flag per segment (same epoch and error word as the forward launch).
+__global__ void k_dfb_begin(int* ctl) {
+  if (threadIdx.x == 0) ctl[3] = 0;  // ticket of the backward launch
+}
+
+template <int T>
+__global__ __launch_bounds__(NT) void k_chol_backward_df(Dev d, const int32_t* __restrict__ tasks, int ntask,
+                                                         int* xflags, int* ctl) {
+  constexpr int P = NT / T;
+  __shared__ double z[T], xm[T];
+  __shared__ int s_task;
+  const int epoch = ctl[1];
+  int* err = ctl + 2;
+  const int r = threadIdx.x / P, part = threadIdx.x % P;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_task = atomicAdd(ctl + 3, 1);
+    __syncthreads();
+    const int t = s_task;
+    if (t >= ntask) break;
+    const int it = tasks[t];
+    const int l = it >> 16, k = (it >> 8) & 255;
+    if (d.active && !d.active[l]) continue;
+    const int nt = d.nt[l];
+    const int64_t vb = d.vec_off[l];
+    int* xf = xflags + vb / T;
+    for (int q = threadIdx.x; q < T; q += NT) z[q] = d.ys[vb + (int64_t)k * T + q];
+    __syncthreads();
+    // this thread's columns of L(k,k)^-T, loaded before any wait
+    const double* Li = d.Li + d.diag_off[l] + (int64_t)k * T * T;
+    double li[T / P];
+#pragma unroll
+    for (int q = 0; q < T / P; ++q) {
+      const int m = q * P + part;
+      li[q] = m >= r ? Li[mf_idx(T, m, r)] : 0.0;
+    }
+    double zr = 0.0;  // this thread's share of the update of z[r]
+    for (int m = nt - 1; m > k; --m) {
+      // the tile L(m,k) does not depend on x_m: load it before waiting
+      const double* Lmk = tile_ptr<T>(d, l, m, k);
+      double lv[T / P];
+#pragma unroll
+      for (int q = 0; q < T / P; ++q) lv[q] = Lmk[mf_idx(T, q * P + part, r)];
+      df_wait(xf + m, nullptr, epoch, err);
+      for (int q = threadIdx.x; q < T; q += NT) xm[q] = coh_load(d.x + vb + (int64_t)m * T + q);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < T / P; ++q) zr += lv[q] * xm[q * P + part];
+      __syncthreads();  // xm is reloaded next round
+    }
+#pragma unroll
+    for (int o = 1; o < P; o <<= 1) zr += __shfl_xor(zr, o);
+    if (part == 0) z[r] -= zr;
+    __syncthreads();
+    double sx = 0.0;
+#pragma unroll
+    for (int q = 0; q < T / P; ++q) sx += li[q] * z[q * P + part];
+#pragma unroll
+    for (int o = 1; o < P; o <<= 1) sx += __shfl_xor(sx, o);
+    if (part == 0) coh_store(d.x + vb + (int64_t)k * T + r, sx);
+    df_publish(xf + k, epoch);
+  }
+}
+
 }  // namespace
 
 void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st) {
@@ -675,6 +745,19 @@ void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* fl
       hipLaunchKernelGGL(k_chol_dataflow<64>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, ctl);
     else
       hipLaunchKernelGGL(k_chol_dataflow<32>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, ctl);
+  }
+  hipLaunchKernelGGL(k_df_end, dim3((d.L + 255) / 256), dim3(256), 0, st, d, (const int*)ctl);
+}
+
+void launch_chol_backward_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* xflags, int* ctl,
+                                   int nworkers, hipStream_t st) {
+  hipLaunchKernelGGL(k_dfb_begin, dim3(1), dim3(64), 0, st, ctl);
+  if (ntask > 0) {
+    const unsigned g = (unsigned)std::max(1, std::min(ntask, nworkers));
+    if (d.T == 64)
+      hipLaunchKernelGGL(k_chol_backward_df<64>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, xflags, ctl);
+    else
+      hipLaunchKernelGGL(k_chol_backward_df<32>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, xflags, ctl);
   }
   hipLaunchKernelGGL(k_df_end, dim3((d.L + 255) / 256), dim3(256), 0, st, d, (const int*)ctl);
 }

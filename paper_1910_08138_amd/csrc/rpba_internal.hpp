@@ -144,6 +144,9 @@ void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, h
 // launch over a task list (see rpba_chol.hip); ctl = [ticket, epoch, errors]
 void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
                           hipStream_t st);
+// the backward substitution as one persistent launch (ctl[3] = its ticket)
+void launch_chol_backward_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* xflags, int* ctl,
+                                   int nworkers, hipStream_t st);
 void launch_rhs_extract(const Dev& d, hipStream_t st);
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st);
 void launch_update(const Dev& d, double* block_stats, hipStream_t st);
