@@ -3,6 +3,8 @@
 // sequences.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -491,18 +493,23 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
         h->any_dense = true;
         h->nt_max_dense = std::max(h->nt_max_dense, p.nt[l]);
       }
-    // dataflow task list: tile column by tile column, inside a column the
-    // sub-blocks with most tiles first, the diagonal tile before those below
+    // dataflow task list, ordered by the length of the chain of diagonal
+    // tiles still ahead (nt - j, longest first), then by column, sub-block
+    // and row: the largest sub-blocks' critical tiles are taken first, and
+    // inside a sub-block every dependency of tile (i, j) (tiles (i,k), (j,k),
+    // k < j, and (j,j)) still comes earlier
     std::vector<int32_t> dense;
     for (int l = 0; l < p.L; ++l)
       if (!h->blk_pcg[l]) dense.push_back(l);
     std::stable_sort(dense.begin(), dense.end(), [&](int a, int b) { return p.nt[a] > p.nt[b]; });
+    std::vector<std::pair<std::array<int32_t, 4>, int32_t>> keyed;
+    for (int l : dense)
+      for (int j = 0; j < p.nt[l]; ++j)
+        for (int i = j; i <= p.nt[l]; ++i)
+          keyed.push_back({{-(p.nt[l] - j), j, l, i}, (l << 16) | (i << 8) | j});
+    std::sort(keyed.begin(), keyed.end());
     tmp.clear();
-    for (int j = 0; j < h->nt_max_dense; ++j)
-      for (int l : dense) {
-        if (p.nt[l] <= j) continue;
-        for (int i = j; i <= p.nt[l]; ++i) tmp.push_back((l << 16) | (i << 8) | j);
-      }
+    for (auto& kv : keyed) tmp.push_back(kv.second);
     h->df_ntask = (int32_t)tmp.size();
     if (!tmp.empty()) HIP_TRY(up(m.df_tasks, tmp.data(), 4 * tmp.size()));
     // backward tasks: tile rows from the last one down
