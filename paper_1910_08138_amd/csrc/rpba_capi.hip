@@ -128,7 +128,7 @@ WsMap layout_for(const Plan& P) {
   m.iwg_cam_off = L.add(i4 * P.iwg_cam_off.size());
   m.iwg_cams = L.add(i4 * std::max<size_t>(1, P.iwg_cams.size()));
   m.pm_xy = L.add(f8 * 2 * P.K);
-  m.pm_w = L.add(f8 * (P.has_info ? 3 : 1) * P.K);
+  m.pm_w = L.add(P.has_info ? f8 * 3 * P.K : 0);
   m.cam_obs_c = L.add(i4 * P.cam_obs_c.size());
   m.df_tasks = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
   m.df_flags = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
@@ -536,6 +536,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.T = p.T;
   D.int_maxit = o->int_maxit;
   D.has_info = p.has_info ? 1 : 0;
+  D.down_weight = o->down_weight;
   D.cpk_f32 = o->precision == RPBA_MIXED ? 1 : 0;
   D.f = d->f;
   D.cx = d->cx;
@@ -573,7 +574,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.pm_off = I(m.pm_off);
   D.pm_k = I(m.pm_k);
   D.pm_pos = I(m.pm_pos);
-  D.pm_cam = I(m.pm_cam);
+  D.pm_code = I(m.pm_cam);
   D.iwg_cam_off = I(m.iwg_cam_off);
   D.iwg_cams = I(m.iwg_cams);
   D.pm_xy = F(m.pm_xy);

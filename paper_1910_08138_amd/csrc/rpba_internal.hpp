@@ -53,11 +53,12 @@ struct Dev {
   const int32_t* pm_off;
   const int32_t* pm_k;
   const int32_t* pm_pos;
-  const int32_t* pm_cam;
+  int32_t* pm_code;       // [K] camera slot / PM_GLOBAL | camera, PM_DOWN (see the plan)
   const int32_t* iwg_cam_off;
   const int32_t* iwg_cams;
   double* pm_xy;          // [K][2]
-  double* pm_w;           // [K] r w0, or [K][3] r W (with obs_info)
+  double* pm_w;           // [K][3] r W (with obs_info only)
+  double down_weight;     // weight multiplier of robustly flagged observations
 
   // copies (sub-block, point)
   const int32_t* copy_off;

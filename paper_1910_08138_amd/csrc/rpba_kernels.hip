@@ -111,66 +111,84 @@ __global__ void k_gather_pm(Dev d) {
   if (d.has_info) {
     for (int q = 0; q < 3; ++q) d.pm_w[3 * i + q] = r * d.info[3 * k + q];
   } else {
-    d.pm_w[i] = r * d.w0;
+    d.pm_code[i] = (d.pm_code[i] & ~PM_DOWN) | (r != 1.0 ? PM_DOWN : 0);
   }
 }
 
 // ------------------------------------------------------------ intersection
-// One thread per point (internal order); a workgroup's points are
-// consecutive, and the cameras they see are staged in LDS first.  The point's
-// observations are read from the point-major stream, the next one prefetched
-// while the current one is linearised.  Gauss-Newton with cameras fixed
-// (eq:bars); on convergence: covariance, refined weights Omega^l = H - H^(l)
-// of every copy (Sec. 5.1), copies reset to Xbar, residuals stored.
-struct PmObs {
-  double x, y, wa, wb, wc;
-  int cam;
+// One thread per point (internal order).  A workgroup's INT_WG consecutive
+// points read their observations (point-major, copy by copy) and the cameras
+// they see from LDS, where the workgroup stages them once: every
+// Gauss-Newton pass then costs LDS traffic only (observations or cameras
+// beyond the staging caps are read from memory).  Gauss-Newton with cameras
+// fixed (eq:bars); on convergence: covariance, refined weights
+// Omega^l = H - H^(l) of every copy (Sec. 5.1), residuals stored.
+constexpr int IT = INT_WG;  // threads per intersection workgroup
+
+struct Stage {
+  double cams[INT_CAM_CAP * 12];  // component-major: component q of slot s at q * INT_CAM_CAP + s
+  double2 xy[INT_OBS_CAP];
+  int32_t code[INT_OBS_CAP];
 };
 
+// observation i of the stream: pixel, weight and camera
 template <bool INFO>
-__device__ __forceinline__ void pm_load(const Dev& d, int i, PmObs& o) {
-  o.x = d.pm_xy[2 * (int64_t)i];
-  o.y = d.pm_xy[2 * (int64_t)i + 1];
+__device__ __forceinline__ void obs_get(const Dev& d, const Stage& sg, int b0, int nst, int i, double& x, double& y,
+                                        W2<double>& W, double (&cm)[12]) {
+  const int t = i - b0;
+  int32_t code;
+  if (t < nst) {
+    const double2 v = sg.xy[t];
+    x = v.x;
+    y = v.y;
+    code = sg.code[t];
+  } else {
+    const double2 v = reinterpret_cast<const double2*>(d.pm_xy)[i];
+    x = v.x;
+    y = v.y;
+    code = d.pm_code[i];
+  }
   if (INFO) {
     const double* w = d.pm_w + 3 * (int64_t)i;
-    o.wa = w[0];
-    o.wb = w[1];
-    o.wc = w[2];
+    W = {w[0], w[1], w[2]};
   } else {
-    o.wa = d.pm_w[i];
-    o.wb = 0.0;
-    o.wc = o.wa;
+    const double w = (code & PM_DOWN) ? d.down_weight * d.w0 : d.w0;
+    W = {w, 0.0, w};
   }
-  o.cam = d.pm_cam[i];
-}
-
-__device__ __forceinline__ void cam_load(const Dev& d, const double* cams, int slot, double (&cm)[12]) {
-  if (slot >= 0) {
-#pragma unroll
-    for (int q = 0; q < 12; ++q) cm[q] = cams[12 * slot + q];
-  } else {
-    const double* g = d.cam + (int64_t)CAM_STRIDE * (-1 - slot);
+  const int f = code & PM_FIELD;
+  if (code & PM_GLOBAL) {
+    const double* g = d.cam + (int64_t)CAM_STRIDE * f;
 #pragma unroll
     for (int q = 0; q < 12; ++q) cm[q] = g[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) cm[q] = sg.cams[q * INT_CAM_CAP + f];
   }
 }
 
 template <bool INFO>
-__global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t* status_out) {
-  static_assert(NT == INT_WG, "one intersection workgroup per plan workgroup");
-  __shared__ double cams[INT_CAM_CAP * 12];
-  __shared__ double sh[4 * 8];
+__global__ __launch_bounds__(IT) void k_intersect(Dev d, double* cov, int32_t* status_out) {
+  __shared__ Stage sg;
+  __shared__ double sh[4 * (IT / 64)];
   if (blockIdx.x == 0)
-    for (int l = threadIdx.x; l < d.L; l += NT) d.blk_fresh[l] = 1;
+    for (int l = threadIdx.x; l < d.L; l += IT) d.blk_fresh[l] = 1;
+  const int j0 = blockIdx.x * IT;
+  const int b0 = d.pm_off[j0];
+  const int nst = min(d.pm_off[min(j0 + IT, d.N)] - b0, INT_OBS_CAP);
   {
     const int cb = d.iwg_cam_off[blockIdx.x], nc = d.iwg_cam_off[blockIdx.x + 1] - cb;
-    for (int t = threadIdx.x; t < nc * 12; t += NT) {
+    for (int t = threadIdx.x; t < nc * 12; t += IT) {
       const int sl = t / 12, q = t - 12 * sl;
-      cams[t] = d.cam[(int64_t)CAM_STRIDE * d.iwg_cams[cb + sl] + q];
+      sg.cams[q * INT_CAM_CAP + sl] = d.cam[(int64_t)CAM_STRIDE * d.iwg_cams[cb + sl] + q];
+    }
+    const double2* gxy = reinterpret_cast<const double2*>(d.pm_xy) + b0;
+    for (int t = threadIdx.x; t < nst; t += IT) {
+      sg.xy[t] = gxy[t];
+      sg.code[t] = d.pm_code[b0 + t];
     }
   }
   __syncthreads();
-  int j = blockIdx.x * NT + threadIdx.x;
+  const int j = j0 + threadIdx.x;
   double accv[4] = {0.0, 0.0, 0.0, 0.0};
   if (j < d.N && d.status[j] == 0) {
     const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
@@ -182,25 +200,33 @@ __global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       g[0] = g[1] = g[2] = 0.0;
       bool behind = false;
-      auto gn_obs = [&](const PmObs& o) {
-        double cm[12];
-        cam_load(d, cams, o.cam, cm);
+      // two observations per trip into independent sums (two independent
+      // dependency chains for the scheduler), added at the end of the pass
+      double h2[6] = {0, 0, 0, 0, 0, 0}, g2[3] = {0, 0, 0};
+      int i = i0;
+      for (; i + 1 < i1; i += 2) {
+        double xa, ya, cma[12], xb, yb, cmb[12];
+        W2<double> Wa, Wb;
+        obs_get<INFO>(d, sg, b0, nst, i, xa, ya, Wa, cma);
+        obs_get<INFO>(d, sg, b0, nst, i + 1, xb, yb, Wb, cmb);
+        Lin<double> La, Lb;
+        linearise<double>(cma, cma + 9, X, d.f, d.cx, d.cy, La);
+        linearise<double>(cmb, cmb + 9, X, d.f, d.cx, d.cy, Lb);
+        if (!(La.z > 0.0) || !(Lb.z > 0.0)) behind = true;
+        add_point_normals<double>(La, Wa, La.g0 - xa, La.g1 - ya, h, g);
+        add_point_normals<double>(Lb, Wb, Lb.g0 - xb, Lb.g1 - yb, h2, g2);
+      }
+      if (i < i1) {
+        double x, y, cm[12];
+        W2<double> W;
+        obs_get<INFO>(d, sg, b0, nst, i, x, y, W, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0)) behind = true;
-        add_point_normals<double>(L, W2<double>{o.wa, o.wb, o.wc}, L.g0 - o.x, L.g1 - o.y, h, g);
-      };
-      // two buffers: observation i + 1 is in flight while i is linearised
-      PmObs oa, ob;
-      pm_load<INFO>(d, i0, oa);
-      for (int i = i0;;) {
-        if (i + 1 < i1) pm_load<INFO>(d, i + 1, ob);
-        gn_obs(oa);
-        if (++i >= i1) break;
-        if (i + 1 < i1) pm_load<INFO>(d, i + 1, oa);
-        gn_obs(ob);
-        if (++i >= i1) break;
+        add_point_normals<double>(L, W, L.g0 - x, L.g1 - y, h, g);
       }
+      for (int q = 0; q < 6; ++q) h[q] += h2[q];
+      for (int q = 0; q < 3; ++q) g[q] += g2[q];
       if (behind) {
         st = 2;
         break;
@@ -232,18 +258,14 @@ __global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t
       int cc = c0, c = d.pt_copies[c0];
       int iend = i0 + (d.copy_off[c + 1] - d.copy_off[c]);
       double gl[3] = {0, 0, 0};
-      PmObs nx;
-      pm_load<INFO>(d, i0, nx);
       for (int i = i0; i < i1; ++i) {
-        const PmObs cur = nx;
-        if (i + 1 < i1) pm_load<INFO>(d, i + 1, nx);
-        double cm[12];
-        cam_load(d, cams, cur.cam, cm);
+        double x, y, cm[12];
+        W2<double> W;
+        obs_get<INFO>(d, sg, b0, nst, i, x, y, W, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0)) behind = true;
-        const double v0 = L.g0 - cur.x, v1 = L.g1 - cur.y;
-        const W2<double> W{cur.wa, cur.wb, cur.wc};
+        const double v0 = L.g0 - x, v1 = L.g1 - y;
         add_point_normals<double>(L, W, v0, v1, hl, gl);
         reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
         cost += wquad(W, v0, v1);
@@ -316,9 +338,19 @@ __global__ __launch_bounds__(NT, 4) void k_intersect(Dev d, double* cov, int32_t
   } else if (j < d.N && status_out) {
     status_out[d.pt_orig[j]] = d.status[j];
   }
-  block_sum<4>(accv, sh);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < 4; ++q) atomicAdd(&d.acc_int[q], accv[q]);
+  // workgroup sum of the statistics, one atomic per value
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) accv[q] += __shfl_xor(accv[q], o);
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 4; ++q) sh[q * (IT / 64) + (threadIdx.x >> 6)] = accv[q];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    for (int w = 0; w < IT / 64; ++w) v += sh[threadIdx.x * (IT / 64) + w];
+    atomicAdd(&d.acc_int[threadIdx.x], v);
+  }
 }
 
 // stats = (cost, sigma0, RMS, N_valid) from the accumulated sums
@@ -684,9 +716,9 @@ void launch_init_rcs(const Dev& d, hipStream_t st) {
 void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
   launch_zero(d.acc_int, 4, st);
   if (d.has_info)
-    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
+    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov, status_out);
   else
-    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
+    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov, status_out);
   if (stats) hipLaunchKernelGGL(k_intersect_stats, dim3(1), dim3(64), 0, st, d, stats);
 }
 

@@ -186,7 +186,7 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
             slot[cam] = n++;
             P.iwg_cams.push_back(cam);
           } else {
-            slot[cam] = -1 - cam;
+            slot[cam] = PM_GLOBAL | cam;
           }
         }
         P.pm_cam[q] = slot[cam];

@@ -17,8 +17,14 @@
 
 namespace rpba {
 
-constexpr int INT_WG = 256;        // points per intersection workgroup
-constexpr int INT_CAM_CAP = 384;   // cameras staged per intersection workgroup
+constexpr int INT_WG = 128;        // points per intersection workgroup
+constexpr int INT_CAM_CAP = 192;   // cameras staged in LDS per intersection workgroup
+constexpr int INT_OBS_CAP = 768;   // observations staged in LDS per intersection workgroup
+// intersection observation code: camera slot in the workgroup's LDS list, or
+// with PM_GLOBAL the camera index itself; PM_DOWN = robust down-weighting
+constexpr int32_t PM_GLOBAL = 1 << 29;
+constexpr int32_t PM_DOWN = 1 << 30;
+constexpr int32_t PM_FIELD = PM_GLOBAL - 1;
 
 struct Plan {
   int32_t M = 0, N = 0, K = 0, L = 0;
@@ -40,8 +46,9 @@ struct Plan {
   std::vector<int32_t> pt_copies;      // [NC] copy indices grouped by point (ascending sub-block)
   // intersection stream (point-major): the observations of point j at
   // [pm_off[j], pm_off[j+1]), copy by copy in pt_copies order; each launch
-  // workgroup of INT_WG points stages the cameras it sees (at most
-  // INT_CAM_CAP) in LDS: pm_cam is the slot there, or -1 - camera
+  // workgroup of INT_WG points stages its observations (at most INT_OBS_CAP)
+  // and the cameras they see (at most INT_CAM_CAP) in LDS: pm_cam is the
+  // camera's slot there, or PM_GLOBAL | camera
   std::vector<int32_t> pm_off;         // [N+1]
   std::vector<int32_t> pm_k;           // [K] LM index
   std::vector<int32_t> pm_pos;         // [K] position of LM index k

@@ -11,6 +11,7 @@
 // observations).  Median of an even count = mean of the two middle values.
 #include "rpba_device.hpp"
 #include "rpba_internal.hpp"
+#include "rpba_plan.hpp"
 
 namespace rpba {
 
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
     if (d.has_info) {
       for (int q = 0; q < 3; ++q) d.pm_w[3 * pos + q] = w * d.info[3 * (int64_t)k + q];
     } else {
-      d.pm_w[pos] = w * d.w0;
+      d.pm_code[pos] = (d.pm_code[pos] & ~PM_DOWN) | (w != 1.0 ? PM_DOWN : 0);
     }
   }
   for (int o = 32; o > 0; o >>= 1) nflag += __shfl_xor(nflag, o);
