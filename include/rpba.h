@@ -169,7 +169,9 @@ rpba_status rpba_subblock_lm_step(rpba_problem *h, const uint8_t *active, double
  *         (or NULL) */
 rpba_status rpba_consensus(rpba_problem *h, double *stats);
 
-/* Release the handle (host memory only; caller buffers are untouched). */
+/* Wait for the work queued on the handle's stream, then release the handle
+ * (host memory only; caller buffers are untouched and may be freed once this
+ * returns). */
 rpba_status rpba_destroy(rpba_problem *h);
 
 /* Thread-local message of the last non-OK status. */

@@ -248,6 +248,13 @@ class Problem:
         # copy) must land before the library's kernels read it
         self.stream.wait_stream(self.torch.cuda.current_stream(self.dev))
 
+    def _hold(self, t):
+        # a caller tensor read by work queued on the handle's stream: its
+        # memory must not be handed out again (by torch's caching allocator,
+        # on the caller's stream) before that work has run
+        if t is not None:
+            t.record_stream(self.stream)
+
     def rpba_intersect(self, cov=True, status=True):
         self._order()
         _check(self.L_.rpba_intersect(self.h, _ptr(self.cov) if cov else None, _ptr(self.status) if status else None,
@@ -270,6 +277,7 @@ class Problem:
     def rpba_subblock_lm_step(self, active=None):
         self._order()
         _check(self.L_.rpba_subblock_lm_step(self.h, _ptr(active), _ptr(self.block_stats)), "rpba_subblock_lm_step")
+        self._hold(active)
         return self.block_stats
 
     def rpba_consensus(self):
@@ -308,6 +316,7 @@ class Problem:
         """W: FP32 device tensor of rpba_precond_num_params() parameters."""
         self._order()
         _check(self.L_.rpba_set_precond_weights(self.h, _ptr(W)), "rpba_set_precond_weights")
+        self._hold(W)
 
     def precond_harvest(self, z):
         """Training samples of the systems at the current state; z: FP32 device
@@ -318,6 +327,9 @@ class Problem:
         out = self.torch.empty((ns, stride), dtype=self.torch.float32, device=self.dev)
         self._order()
         _check(self.L_.rpba_precond_harvest(self.h, _ptr(z), nz, _ptr(out)), "rpba_precond_harvest")
+        self._hold(z)
+        # the samples are read on the caller's stream: order it after the harvest
+        self.torch.cuda.current_stream(self.dev).wait_stream(self.stream)
         return out
 
     def block_solver(self, l):

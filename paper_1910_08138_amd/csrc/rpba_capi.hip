@@ -45,13 +45,13 @@ struct Layout {
 
 // byte offsets of every workspace array
 struct WsMap {
-  size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
+  size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_new, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
       df_ctl, blk_fresh, dfb_tasks, dfb_flags;
-  size_t cam, camN, P0, Xbar, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
+  size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
 };
@@ -79,6 +79,7 @@ WsMap layout_for(const Plan& P) {
   m.blk_cam_off = L.add(i4 * (P.L + 1));
   m.cam_orig = L.add(i4 * P.M);
   m.pt_orig = L.add(i4 * P.N);
+  m.pt_new = L.add(i4 * P.N);
   m.pt_copy_off = L.add(i4 * (P.N + 1));
   m.pt_copies = L.add(i4 * P.NC);
   m.obs_cam = L.add(i4 * P.K);
@@ -140,6 +141,8 @@ WsMap layout_for(const Plan& P) {
   m.camN = L.add(f8 * 12 * P.M);
   m.P0 = L.add(f8 * 3 * P.N);
   m.Xbar = L.add(f8 * 3 * P.N);
+  m.pxs = L.add(f8 * 4 * P.N);
+  m.covi = L.add(f8 * 6 * P.N);
   m.status = L.add(i4 * P.N);
   m.xy = L.add(f8 * 2 * P.K);
   m.info = L.add(P.has_info ? f8 * 3 * P.K : 0);
@@ -251,6 +254,8 @@ struct rpba_problem {
   int64_t launches[NPHASE] = {};
   int64_t calls[NPHASE] = {};
   ~rpba_problem() {
+    // queued work may still read the workspace and the caller's arrays
+    (void)hipStreamSynchronize(stream);
     g_int.reset();
     g_step.reset();
     g_cons.reset();
@@ -387,6 +392,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.blk_cam_off, p.blk_cam_off.data(), 4 * p.blk_cam_off.size()));
   HIP_TRY(up(m.cam_orig, p.cam_orig.data(), 4 * p.cam_orig.size()));
   HIP_TRY(up(m.pt_orig, p.pt_orig.data(), 4 * p.pt_orig.size()));
+  HIP_TRY(up(m.pt_new, p.pt_new.data(), 4 * p.pt_new.size()));
   HIP_TRY(up(m.pt_copy_off, p.pt_copy_off.data(), 4 * p.pt_copy_off.size()));
   HIP_TRY(up(m.pt_copies, p.pt_copies.data(), 4 * p.pt_copies.size()));
   HIP_TRY(up(m.obs_cam, p.obs_cam.data(), 4 * p.obs_cam.size()));
@@ -558,8 +564,11 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.cam_orig = I(m.cam_orig);
   D.P0 = F(m.P0);
   D.Xbar = F(m.Xbar);
+  D.pxs = F(m.pxs);
+  D.covi = F(m.covi);
   D.status = I(m.status);
   D.pt_orig = I(m.pt_orig);
+  D.pt_new = I(m.pt_new);
   D.pt_copy_off = I(m.pt_copy_off);
   D.pt_copies = I(m.pt_copies);
   D.xy = F(m.xy);
@@ -651,7 +660,7 @@ rpba_status rpba_destroy(rpba_problem* h) {
 rpba_status rpba_intersect(rpba_problem* h, double* cov, int32_t* status, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   rpba_status s = run_call(h, h->g_int, cov, status, stats, [&]() -> rpba_status {
-    PhaseTimer t(h, PH_INTERSECT, stats ? 3 : 2);
+    PhaseTimer t(h, PH_INTERSECT, stats ? 4 : 3);
     launch_intersect(h->d, cov, status, stats, h->stream);
     return RPBA_OK;
   });
@@ -751,7 +760,7 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
 rpba_status rpba_consensus(rpba_problem* h, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   return run_call(h, h->g_cons, stats, nullptr, nullptr, [&]() -> rpba_status {
-    PhaseTimer t(h, PH_CONSENSUS, stats ? 4 : 3);
+    PhaseTimer t(h, PH_CONSENSUS, stats ? 5 : 4);
     launch_consensus(h->d, stats, h->stream);
     return RPBA_OK;
   });

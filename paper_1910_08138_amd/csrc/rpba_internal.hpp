@@ -35,6 +35,9 @@ struct Dev {
   double* Xbar;           // [3][N] last intersection
   int32_t* status;        // [N]
   const int32_t* pt_orig;
+  const int32_t* pt_new;  // [N] internal index of caller point o
+  double* pxs;            // [N][4] X (3), status: latest point per internal index, exported to u_pts
+  double* covi;           // [N][6] covariance of the last intersection, internal order
   const int32_t* pt_copy_off;
   const int32_t* pt_copies;
 

@@ -166,8 +166,17 @@ __device__ __forceinline__ void obs_get(const Dev& d, const Stage& sg, int b0, i
   }
 }
 
+// latest point of internal index j and its status, written whole so that
+// the record lines fill completely (exported to the caller's order by
+// k_export_pts)
+__device__ __forceinline__ void put_pxs(const Dev& d, int j, const double (&X)[3], int st) {
+  double2* p = reinterpret_cast<double2*>(d.pxs + 4 * (int64_t)j);
+  p[0] = make_double2(X[0], X[1]);
+  p[1] = make_double2(X[2], (double)st);
+}
+
 template <bool INFO>
-__global__ __launch_bounds__(IT) void k_intersect(Dev d, double* cov, int32_t* status_out) {
+__global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   __shared__ Stage sg;
   __shared__ double sh[4 * (IT / 64)];
   if (blockIdx.x == 0)
@@ -291,16 +300,12 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, double* cov, int32_t* s
       if (behind) st = 2;
       else if (!chol3(h, lch)) st = 3;
     }
+    double inv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (st == 0) {
-      double inv[6];
       chol3_inverse(lch, inv);
-      int o = d.pt_orig[j];
-      if (cov)
-        for (int q = 0; q < 6; ++q) cov[(int64_t)q * d.N + o] = inv[q];
       for (int r = 0; r < 3; ++r) {
         d.Xbar[(int64_t)r * d.N + j] = X[r];
         d.P0[(int64_t)r * d.N + j] = X[r];
-        d.u_pts[(int64_t)r * d.N + o] = X[r];
       }
       // Omega^l = H - H^(l): information from the cameras outside sub-block l
       // (zero for a point seen by one sub-block only).  The copies themselves
@@ -334,9 +339,16 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, double* cov, int32_t* s
       accv[3] = 1.0;
     }
     d.status[j] = st;
-    if (status_out) status_out[d.pt_orig[j]] = st;
-  } else if (j < d.N && status_out) {
-    status_out[d.pt_orig[j]] = d.status[j];
+    put_pxs(d, j, X, st);
+    if (want_cov) {
+      double2* cv = reinterpret_cast<double2*>(d.covi + 6 * (int64_t)j);
+      cv[0] = make_double2(inv[0], inv[1]);
+      cv[1] = make_double2(inv[2], inv[3]);
+      cv[2] = make_double2(inv[4], inv[5]);
+    }
+  } else if (j < d.N) {
+    const double z[3] = {0.0, 0.0, 0.0};
+    put_pxs(d, j, z, d.status[j]);
   }
   // workgroup sum of the statistics, one atomic per value
 #pragma unroll
@@ -350,6 +362,33 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, double* cov, int32_t* s
     double v = 0.0;
     for (int w = 0; w < IT / 64; ++w) v += sh[threadIdx.x * (IT / 64) + w];
     atomicAdd(&d.acc_int[threadIdx.x], v);
+  }
+}
+
+// Caller-order export: one thread per caller point o gathers the internal
+// record of its point, so that the caller's arrays are written line by line
+// (points and covariances of invalid points are left as they were)
+__global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* status_out) {
+  const int o = blockIdx.x * NT + threadIdx.x;
+  if (o >= d.N) return;
+  const int j = d.pt_new[o];
+  const double2* p = reinterpret_cast<const double2*>(d.pxs + 4 * (int64_t)j);
+  const double2 a = p[0], b = p[1];
+  const int st = (int)b.y;
+  if (status_out) status_out[o] = st;
+  if (st != 0) return;
+  d.u_pts[o] = a.x;
+  d.u_pts[(int64_t)d.N + o] = a.y;
+  d.u_pts[2 * (int64_t)d.N + o] = b.x;
+  if (cov) {
+    const double2* c = reinterpret_cast<const double2*>(d.covi + 6 * (int64_t)j);
+    const double2 c0 = c[0], c1 = c[1], c2 = c[2];
+    cov[o] = c0.x;
+    cov[(int64_t)d.N + o] = c0.y;
+    cov[2 * (int64_t)d.N + o] = c1.x;
+    cov[3 * (int64_t)d.N + o] = c1.y;
+    cov[4 * (int64_t)d.N + o] = c2.x;
+    cov[5 * (int64_t)d.N + o] = c2.y;
   }
 }
 
@@ -618,11 +657,11 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
         double e0 = x[0] - m[0], e1 = x[1] - m[1], e2 = x[2] - m[2];
         dmax = fmax(dmax, sqrt(e0 * e0 + e1 * e1 + e2 * e2));
       }
-      int o = d.pt_orig[j];
-      for (int r = 0; r < 3; ++r) {
-        d.P0[(int64_t)r * d.N + j] = m[r];
-        d.u_pts[(int64_t)r * d.N + o] = m[r];
-      }
+      for (int r = 0; r < 3; ++r) d.P0[(int64_t)r * d.N + j] = m[r];
+      put_pxs(d, j, m, 0);
+    } else {
+      const double z[3] = {0.0, 0.0, 0.0};
+      put_pxs(d, j, z, d.status[j]);
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -716,9 +755,10 @@ void launch_init_rcs(const Dev& d, hipStream_t st) {
 void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
   launch_zero(d.acc_int, 4, st);
   if (d.has_info)
-    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov, status_out);
+    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov != nullptr);
   else
-    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov, status_out);
+    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov != nullptr);
+  hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
   if (stats) hipLaunchKernelGGL(k_intersect_stats, dim3(1), dim3(64), 0, st, d, stats);
 }
 
@@ -738,6 +778,7 @@ void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
 void launch_consensus(const Dev& d, double* stats, hipStream_t st) {
   launch_zero(d.acc_cons, 2, st);
   hipLaunchKernelGGL(k_consensus_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, (double*)nullptr, (int32_t*)nullptr);
   hipLaunchKernelGGL(k_consensus_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
   if (stats) hipLaunchKernelGGL(k_copy2, dim3(1), dim3(64), 0, st, (const double*)d.acc_cons, stats, 2);
 }

@@ -88,7 +88,8 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     }
   }
   P.pt_orig.resize(N);
-  std::vector<int32_t> pt_new(N);
+  std::vector<int32_t>& pt_new = P.pt_new;
+  pt_new.assign(N, 0);
   {
     std::vector<int32_t> cnt(M + 1, 0);
     for (int32_t j = 0; j < N; ++j) cnt[first[j] + 1]++;

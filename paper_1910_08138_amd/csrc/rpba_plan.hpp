@@ -34,6 +34,7 @@ struct Plan {
 
   // permutations (new -> original)
   std::vector<int32_t> cam_orig, pt_orig, obs_orig;
+  std::vector<int32_t> pt_new;         // [N] internal index of caller point o
   std::vector<int32_t> cam_blk;        // [M] sub-block of internal camera
   std::vector<int32_t> blk_cam_off;    // [L+1]
   std::vector<int32_t> obs_cam;        // [K] internal camera of LM-ordered observation

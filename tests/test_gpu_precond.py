@@ -81,10 +81,13 @@ def test_trained_network_gain_over_block_jacobi(rp):
     W, losses = precond.train(data, nz=4, epochs=40, batch=512, lr=3e-3, seed=0)
     assert losses[-1] < losses[0]
     held = scenes.config_scene(5, 12, small=True)
-    # an inner cap high enough that both refinements reach their tolerance
-    # (the learned blocks need several times more CG iterations)
-    it_bj, ms_bj, st_bj = precond.evaluate(held, None, T=2, I=2, pcg_maxit=1000)
-    it_le, ms_le, st_le = precond.evaluate(held, W, T=2, I=2, pcg_maxit=1000)
+    # both solves refined to a relative residual of 1e-13 (the FP64 residual
+    # of the stored system reaches it): at the default 1e-10 the solutions of
+    # the two preconditioners may still differ by the condition number of
+    # the damped system times that residual, which moves the final RMS by
+    # about 1e-6; the learned blocks need several times more CG iterations
+    it_bj, ms_bj, st_bj = precond.evaluate(held, None, T=2, I=2, pcg_maxit=1000, ir_tol=1e-13, ir_maxit=30)
+    it_le, ms_le, st_le = precond.evaluate(held, W, T=2, I=2, pcg_maxit=1000, ir_tol=1e-13, ir_maxit=30)
     print(f"loss {losses[0]:.5f} -> {losses[-1]:.5f}; CG iterations block-Jacobi {it_bj:.0f}, learned {it_le:.0f} "
           f"(ratio {it_le / it_bj:.3f}); solve ms {ms_bj:.2f} vs {ms_le:.2f}")
     assert abs(st_le[2] - st_bj[2]) <= 1e-6 * st_bj[2]
