@@ -112,44 +112,54 @@ __device__ __forceinline__ void rotate_left(const double w[3], const double* Rin
     for (int c = 0; c < 3; ++c) Rout[3 * r + c] = E[3 * r] * Rin[c] + E[3 * r + 1] * Rin[3 + c] + E[3 * r + 2] * Rin[6 + c];
 }
 
+// 1 / sqrt(x) in FP64: the hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
 // Symmetric 3x3 stored as (xx, xy, xz, yy, yz, zz).
 // Cholesky with the pivot test pivot > 1e-12 * max diagonal; on success
-// writes the lower factor l = (l00, l10, l20, l11, l21, l22).
+// writes the lower factor with its diagonal held as reciprocals,
+// l = (1/l00, l10, l20, 1/l11, l21, 1/l22), so that the solves and the
+// inverse below multiply instead of divide.
 __device__ __forceinline__ bool chol3(const double h[6], double l[6]) {
   double dmax = fmax(h[0], fmax(h[3], h[5]));
   if (!(dmax > 0.0)) return false;
   double thr = 1e-12 * dmax;
   double p0 = h[0];
   if (!(p0 > thr)) return false;
-  l[0] = sqrt(p0);
-  l[1] = h[1] / l[0];
-  l[2] = h[2] / l[0];
+  l[0] = rsqrt_nr(p0);
+  l[1] = h[1] * l[0];
+  l[2] = h[2] * l[0];
   double p1 = h[3] - l[1] * l[1];
   if (!(p1 > thr)) return false;
-  l[3] = sqrt(p1);
-  l[4] = (h[4] - l[2] * l[1]) / l[3];
+  l[3] = rsqrt_nr(p1);
+  l[4] = (h[4] - l[2] * l[1]) * l[3];
   double p2 = h[5] - l[2] * l[2] - l[4] * l[4];
   if (!(p2 > thr)) return false;
-  l[5] = sqrt(p2);
+  l[5] = rsqrt_nr(p2);
   return true;
 }
 
 // x = (L L^T)^-1 b
 __device__ __forceinline__ void chol3_solve(const double l[6], const double b[3], double x[3]) {
-  double y0 = b[0] / l[0];
-  double y1 = (b[1] - l[1] * y0) / l[3];
-  double y2 = (b[2] - l[2] * y0 - l[4] * y1) / l[5];
-  x[2] = y2 / l[5];
-  x[1] = (y1 - l[4] * x[2]) / l[3];
-  x[0] = (y0 - l[1] * x[1] - l[2] * x[2]) / l[0];
+  double y0 = b[0] * l[0];
+  double y1 = (b[1] - l[1] * y0) * l[3];
+  double y2 = (b[2] - l[2] * y0 - l[4] * y1) * l[5];
+  x[2] = y2 * l[5];
+  x[1] = (y1 - l[4] * x[2]) * l[3];
+  x[0] = (y0 - l[1] * x[1] - l[2] * x[2]) * l[0];
 }
 
 // inverse (sym6 layout) from the Cholesky factor: Inv = L^-T L^-1
 __device__ __forceinline__ void chol3_inverse(const double l[6], double inv[6]) {
   // M = L^-1 (lower)
-  double m00 = 1.0 / l[0];
-  double m11 = 1.0 / l[3];
-  double m22 = 1.0 / l[5];
+  double m00 = l[0];
+  double m11 = l[3];
+  double m22 = l[5];
   double m10 = -l[1] * m00 * m11;
   double m21 = -l[4] * m11 * m22;
   double m20 = -(l[2] * m00 + l[4] * m10) * m22;

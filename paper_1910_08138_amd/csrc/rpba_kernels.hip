@@ -131,17 +131,20 @@ struct Stage {
   int32_t code[INT_OBS_CAP];
 };
 
-// observation i of the stream: pixel, weight and camera
-template <bool INFO>
-__device__ __forceinline__ void obs_get(const Dev& d, const Stage& sg, int b0, int nst, int i, double& x, double& y,
+// observation i of the stream: pixel, weight and camera.  OLDS: the
+// workgroup's observations are all staged (a workgroup-uniform choice, so
+// the common path carries no per-lane test of where they live).  The camera
+// is read from its LDS slot unconditionally; the rare camera beyond the
+// staging cap is then replaced from memory in a branch of its own.
+template <bool INFO, bool OLDS>
+__device__ __forceinline__ void obs_get(const Dev& d, const Stage& sg, int b0, int i, double& x, double& y,
                                         W2<double>& W, double (&cm)[12]) {
-  const int t = i - b0;
   int32_t code;
-  if (t < nst) {
-    const double2 v = sg.xy[t];
+  if (OLDS) {
+    const double2 v = sg.xy[i - b0];
     x = v.x;
     y = v.y;
-    code = sg.code[t];
+    code = sg.code[i - b0];
   } else {
     const double2 v = reinterpret_cast<const double2*>(d.pm_xy)[i];
     x = v.x;
@@ -156,13 +159,18 @@ __device__ __forceinline__ void obs_get(const Dev& d, const Stage& sg, int b0, i
     W = {w, 0.0, w};
   }
   const int f = code & PM_FIELD;
-  if (code & PM_GLOBAL) {
-    const double* g = d.cam + (int64_t)CAM_STRIDE * f;
+  const bool glb = (code & PM_GLOBAL) != 0;
+  const int sl = glb ? 0 : f;
 #pragma unroll
-    for (int q = 0; q < 12; ++q) cm[q] = g[q];
-  } else {
+  for (int q = 0; q < 12; ++q) cm[q] = sg.cams[q * INT_CAM_CAP + sl];
+  if (__builtin_expect(glb, 0)) {
+    const double2* g = reinterpret_cast<const double2*>(d.cam + (int64_t)CAM_STRIDE * f);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) cm[q] = sg.cams[q * INT_CAM_CAP + f];
+    for (int q = 0; q < 6; ++q) {
+      const double2 v = g[q];
+      cm[2 * q] = v.x;
+      cm[2 * q + 1] = v.y;
+    }
   }
 }
 
@@ -175,30 +183,12 @@ __device__ __forceinline__ void put_pxs(const Dev& d, int j, const double (&X)[3
   p[1] = make_double2(X[2], (double)st);
 }
 
-template <bool INFO>
-__global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
-  __shared__ Stage sg;
-  __shared__ double sh[4 * (IT / 64)];
-  if (blockIdx.x == 0)
-    for (int l = threadIdx.x; l < d.L; l += IT) d.blk_fresh[l] = 1;
-  const int j0 = blockIdx.x * IT;
-  const int b0 = d.pm_off[j0];
-  const int nst = min(d.pm_off[min(j0 + IT, d.N)] - b0, INT_OBS_CAP);
-  {
-    const int cb = d.iwg_cam_off[blockIdx.x], nc = d.iwg_cam_off[blockIdx.x + 1] - cb;
-    for (int t = threadIdx.x; t < nc * 12; t += IT) {
-      const int sl = t / 12, q = t - 12 * sl;
-      sg.cams[q * INT_CAM_CAP + sl] = d.cam[(int64_t)CAM_STRIDE * d.iwg_cams[cb + sl] + q];
-    }
-    const double2* gxy = reinterpret_cast<const double2*>(d.pm_xy) + b0;
-    for (int t = threadIdx.x; t < nst; t += IT) {
-      sg.xy[t] = gxy[t];
-      sg.code[t] = d.pm_code[b0 + t];
-    }
-  }
-  __syncthreads();
-  const int j = j0 + threadIdx.x;
-  double accv[4] = {0.0, 0.0, 0.0, 0.0};
+// one point: Gauss-Newton to convergence, then the final pass (covariance,
+// residuals, refined weights of the copies); accv gets the point's share of
+// the statistics
+template <bool INFO, bool OLDS>
+__device__ __forceinline__ void intersect_point(const Dev& d, const Stage& sg, int b0, int j, int want_cov,
+                                                double (&accv)[4]) {
   if (j < d.N && d.status[j] == 0) {
     const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
     const int i0 = d.pm_off[j], i1 = d.pm_off[j + 1];
@@ -216,8 +206,8 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       for (; i + 1 < i1; i += 2) {
         double xa, ya, cma[12], xb, yb, cmb[12];
         W2<double> Wa, Wb;
-        obs_get<INFO>(d, sg, b0, nst, i, xa, ya, Wa, cma);
-        obs_get<INFO>(d, sg, b0, nst, i + 1, xb, yb, Wb, cmb);
+        obs_get<INFO, OLDS>(d, sg, b0, i, xa, ya, Wa, cma);
+        obs_get<INFO, OLDS>(d, sg, b0, i + 1, xb, yb, Wb, cmb);
         Lin<double> La, Lb;
         linearise<double>(cma, cma + 9, X, d.f, d.cx, d.cy, La);
         linearise<double>(cmb, cmb + 9, X, d.f, d.cx, d.cy, Lb);
@@ -228,7 +218,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       if (i < i1) {
         double x, y, cm[12];
         W2<double> W;
-        obs_get<INFO>(d, sg, b0, nst, i, x, y, W, cm);
+        obs_get<INFO, OLDS>(d, sg, b0, i, x, y, W, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0)) behind = true;
@@ -270,7 +260,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       for (int i = i0; i < i1; ++i) {
         double x, y, cm[12];
         W2<double> W;
-        obs_get<INFO>(d, sg, b0, nst, i, x, y, W, cm);
+        obs_get<INFO, OLDS>(d, sg, b0, i, x, y, W, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0)) behind = true;
@@ -350,6 +340,74 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
     const double z[3] = {0.0, 0.0, 0.0};
     put_pxs(d, j, z, d.status[j]);
   }
+}
+
+template <bool INFO>
+__global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
+  __shared__ Stage sg;
+  __shared__ double sh[4 * (IT / 64)];
+  if (blockIdx.x == 0)
+    for (int l = threadIdx.x; l < d.L; l += IT) d.blk_fresh[l] = 1;
+  const int j0 = blockIdx.x * IT;
+  const int b0 = d.pm_off[j0];
+  const int nobs = d.pm_off[min(j0 + IT, d.N)] - b0;
+  const int nst = min(nobs, INT_OBS_CAP);
+  {
+    // every load of the staging is issued before the first LDS write (one
+    // round of memory latency for the indices, one for the data): each
+    // thread owns whole camera slots and a fixed set of observations
+    constexpr int CS = (INT_CAM_CAP + IT - 1) / IT, OS = (INT_OBS_CAP + IT - 1) / IT;
+    const int cb = d.iwg_cam_off[blockIdx.x], nc = d.iwg_cam_off[blockIdx.x + 1] - cb;
+    int ci[CS];
+#pragma unroll
+    for (int u = 0; u < CS; ++u) {
+      const int sl = threadIdx.x + u * IT;
+      ci[u] = sl < nc ? d.iwg_cams[cb + sl] : -1;
+    }
+    const double2* gxy = reinterpret_cast<const double2*>(d.pm_xy) + b0;
+    double2 ov[OS];
+    int32_t oc[OS];
+    if (nst > 0) {
+      // unconditional loads at a clamped index (in range), stores guarded
+#pragma unroll
+      for (int u = 0; u < OS; ++u) {
+        const int t = min((int)threadIdx.x + u * IT, nst - 1);
+        ov[u] = gxy[t];
+        oc[u] = d.pm_code[b0 + t];
+      }
+    }
+    double2 cv[CS][6];
+#pragma unroll
+    for (int u = 0; u < CS; ++u)
+      if (ci[u] >= 0) {
+        const double2* g = reinterpret_cast<const double2*>(d.cam + (int64_t)CAM_STRIDE * ci[u]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) cv[u][q] = g[q];
+      }
+#pragma unroll
+    for (int u = 0; u < OS; ++u) {
+      const int t = threadIdx.x + u * IT;
+      if (t < nst) {
+        sg.xy[t] = ov[u];
+        sg.code[t] = oc[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CS; ++u)
+      if (ci[u] >= 0) {
+        const int sl = threadIdx.x + u * IT;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          sg.cams[(2 * q) * INT_CAM_CAP + sl] = cv[u][q].x;
+          sg.cams[(2 * q + 1) * INT_CAM_CAP + sl] = cv[u][q].y;
+        }
+      }
+  }
+  __syncthreads();
+  const int j = j0 + threadIdx.x;
+  double accv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (nobs <= INT_OBS_CAP) intersect_point<INFO, true>(d, sg, b0, j, want_cov, accv);
+  else intersect_point<INFO, false>(d, sg, b0, j, want_cov, accv);
   // workgroup sum of the statistics, one atomic per value
 #pragma unroll
   for (int q = 0; q < 4; ++q)
