@@ -686,8 +686,33 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
     int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
     if (c1 - c0 > 1) ntp = 1.0;
     if (d.status[j] == 0) {
-      // copy positions: a fresh sub-block's copies are still at Xbar
+      // copy positions: a fresh sub-block's copies are still at Xbar.  The
+      // first CU copies are gathered into registers with their loads issued
+      // together (indices clamped into the point's range); further copies,
+      // rare, are read in a loop.
       const double xb[3] = {d.Xbar[j], d.Xbar[(int64_t)d.N + j], d.Xbar[2 * (int64_t)d.N + j]};
+      constexpr int CU = 4;
+      const int n = c1 - c0;
+      double xu[CU][3];
+      if (n > 0) {
+        int cu[CU], fr[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) cu[u] = d.pt_copies[c0 + min(u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+          fr[u] = d.blk_fresh[d.copy_blk[cu[u]]];
+          xu[u][0] = d.Xc[3 * (int64_t)cu[u]];
+          xu[u][1] = d.Xc[3 * (int64_t)cu[u] + 1];
+          xu[u][2] = d.Xc[3 * (int64_t)cu[u] + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+          if (fr[u]) {
+            xu[u][0] = xb[0];
+            xu[u][1] = xb[1];
+            xu[u][2] = xb[2];
+          }
+      }
       auto copy_x = [&](int c, double (&x)[3]) {
         if (d.blk_fresh[d.copy_blk[c]]) {
           x[0] = xb[0];
@@ -700,16 +725,33 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
         }
       };
       double m[3] = {0, 0, 0};
-      for (int cc = c0; cc < c1; ++cc) {
+#pragma unroll
+      for (int u = 0; u < CU; ++u)
+        if (u < n) {
+          m[0] += xu[u][0];
+          m[1] += xu[u][1];
+          m[2] += xu[u][2];
+        }
+      for (int cc = c0 + CU; cc < c1; ++cc) {
         double x[3];
         copy_x(d.pt_copies[cc], x);
         m[0] += x[0];
         m[1] += x[1];
         m[2] += x[2];
       }
-      double inv = 1.0 / (double)(c1 - c0);
-      for (int r = 0; r < 3; ++r) m[r] *= inv;
-      for (int cc = c0; cc < c1; ++cc) {
+      if (n > 0) {
+        double inv = 1.0 / (double)n;
+        for (int r = 0; r < 3; ++r) m[r] *= inv;
+      } else {  // no copy: the consensus is the intersection itself
+        for (int r = 0; r < 3; ++r) m[r] = xb[r];
+      }
+#pragma unroll
+      for (int u = 0; u < CU; ++u)
+        if (u < n) {
+          double e0 = xu[u][0] - m[0], e1 = xu[u][1] - m[1], e2 = xu[u][2] - m[2];
+          dmax = fmax(dmax, sqrt(e0 * e0 + e1 * e1 + e2 * e2));
+        }
+      for (int cc = c0 + CU; cc < c1; ++cc) {
         double x[3];
         copy_x(d.pt_copies[cc], x);
         double e0 = x[0] - m[0], e1 = x[1] - m[1], e2 = x[2] - m[2];
