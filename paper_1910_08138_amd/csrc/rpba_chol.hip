@@ -131,9 +131,9 @@ __device__ __forceinline__ double* tile_ptr(const Dev& d, int l, int i, int j) {
 // ---- diagonal tile: factor and inverse, blocked by 16 inside the tile.
 // The tile sits in LDS (row-major, row stride T + 1).  For each 16-wide
 // column block kb one wave factors the whole panel below the diagonal
-// (lane = row, the step's column broadcast with readlane, so the serial chain
-// has no LDS round trip) and the trailing blocks are updated on the matrix
-// cores.  Afterwards each wave inverts one 16 x 16 diagonal factor block (lane
+// (lane = row; the pivot is broadcast with readlane, the rest of the step's
+// column through one LDS store and broadcast reads, which keeps the scalar
+// registers free) and the trailing blocks are updated on the matrix cores.  Afterwards each wave inverts one 16 x 16 diagonal factor block (lane
 // = column, forward substitution) and the inverse of the whole factor is
 // assembled block row by block row:
 //   Linv(i,i) = D_i^-1,  Linv(i,j) = -D_i^-1 sum_{k=j}^{i-1} L(i,k) Linv(k,j).
@@ -173,6 +173,9 @@ __device__ __forceinline__ void factor_panel(DiagLds<T>& sm, int o) {
   double a[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) a[c] = sm.A[row * LD + o + c];
+  // the step's column goes to the other rows through LDS (the wave's own
+  // stores are seen by its later loads), one broadcast read per element
+  double* colb = sm.Y[0];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     double dcc = bcast(a[c], c);
@@ -184,8 +187,11 @@ __device__ __forceinline__ void factor_panel(DiagLds<T>& sm, int o) {
     if (lane == 0) sm.ipv[o + c] = ip;
     const double colv = lane > c ? a[c] * ip : (lane == c ? dcc * ip : 0.0);
     a[c] = colv;
+    if (c < 15) {
+      colb[lane] = colv;
 #pragma unroll
-    for (int s2 = c + 1; s2 < 16; ++s2) a[s2] -= colv * bcast(colv, s2);
+      for (int s2 = c + 1; s2 < 16; ++s2) a[s2] -= colv * colb[s2];
+    }
   }
   if (live) {
 #pragma unroll
