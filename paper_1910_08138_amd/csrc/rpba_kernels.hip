@@ -137,8 +137,8 @@ struct Stage {
 // is read from its LDS slot unconditionally; the rare camera beyond the
 // staging cap is then replaced from memory in a branch of its own.
 template <bool INFO, bool OLDS>
-__device__ __forceinline__ void obs_get(const Dev& d, const Stage& sg, int b0, int i, double& x, double& y,
-                                        W2<double>& W, double (&cm)[12]) {
+__device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0, int i, double& x, double& y,
+                                           W2<double>& W, double (&cm)[12]) {
   int32_t code;
   if (OLDS) {
     const double2 v = sg.xy[i - b0];
@@ -172,6 +172,7 @@ __device__ __forceinline__ void obs_get(const Dev& d, const Stage& sg, int b0, i
       cm[2 * q + 1] = v.y;
     }
   }
+  return code;
 }
 
 // latest point of internal index j and its status, written whole so that
@@ -190,9 +191,17 @@ template <bool INFO, bool OLDS>
 __device__ __forceinline__ void intersect_point(const Dev& d, const Stage& sg, int b0, int j, int want_cov,
                                                 double (&accv)[4]) {
   if (j < d.N && d.status[j] == 0) {
-    const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1];
+    const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1], n = c1 - c0;
     const int i0 = d.pm_off[j], i1 = d.pm_off[j + 1];
     double X[3] = {d.P0[j], d.P0[(int64_t)d.N + j], d.P0[2 * (int64_t)d.N + j]};
+    // the point's first copies, loaded now and used after Gauss-Newton
+    constexpr int CU = 4;
+    int cpy[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) cpy[u] = n > 0 ? d.pt_copies[c0 + min(u, n - 1)] : 0;
+    auto copy_at = [&](int u) {
+      return u == 0 ? cpy[0] : u == 1 ? cpy[1] : u == 2 ? cpy[2] : u == 3 ? cpy[3] : d.pt_copies[c0 + u];
+    };
     int st = 1;  // not converged
     double h[6], g[3], lch[6];
     for (int it = 0; it < d.int_maxit; ++it) {
@@ -254,13 +263,12 @@ __device__ __forceinline__ void intersect_point(const Dev& d, const Stage& sg, i
     if (st == 0) {
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       bool behind = false;
-      int cc = c0, c = d.pt_copies[c0];
-      int iend = i0 + (d.copy_off[c + 1] - d.copy_off[c]);
+      int u = 0;  // copy being summed
       double gl[3] = {0, 0, 0};
       for (int i = i0; i < i1; ++i) {
         double x, y, cm[12];
         W2<double> W;
-        obs_get<INFO, OLDS>(d, sg, b0, i, x, y, W, cm);
+        const int32_t code = obs_get<INFO, OLDS>(d, sg, b0, i, x, y, W, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0)) behind = true;
@@ -270,21 +278,20 @@ __device__ __forceinline__ void intersect_point(const Dev& d, const Stage& sg, i
         cost += wquad(W, v0, v1);
         sq += v0 * v0 + v1 * v1;
         nobs += 1.0;
-        if (i + 1 == iend) {  // copy c complete
+        if (code & PM_LAST) {  // copy u complete
           for (int q = 0; q < 6; ++q) h[q] += hl[q];
-          if (++cc < c1) {
-            if (cc == c0 + 1) {
+          if (u + 1 < n) {
+            if (u == 0) {
               for (int q = 0; q < 6; ++q) hl0[q] = hl[q];
             } else {
-              double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)c);
+              double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)copy_at(u));
               om[0] = make_double2(hl[0], hl[1]);
               om[1] = make_double2(hl[2], hl[3]);
               om[2] = make_double2(hl[4], hl[5]);
             }
             for (int q = 0; q < 6; ++q) hl[q] = 0.0;
-            c = d.pt_copies[cc];
-            iend += d.copy_off[c + 1] - d.copy_off[c];
           }
+          ++u;
         }
       }
       if (behind) st = 2;
@@ -300,15 +307,14 @@ __device__ __forceinline__ void intersect_point(const Dev& d, const Stage& sg, i
       // Omega^l = H - H^(l): information from the cameras outside sub-block l
       // (zero for a point seen by one sub-block only).  The copies themselves
       // are reset to Xbar through the sub-blocks' fresh flags.
-      for (int cc = c0; cc < c1; ++cc) {
-        const int c = d.pt_copies[cc];
-        double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)c);
+      for (int u2 = 0; u2 < n; ++u2) {
+        double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)copy_at(u2));
         double o6[6];
-        if (c1 - c0 == 1) {
+        if (n == 1) {
           for (int q = 0; q < 6; ++q) o6[q] = 0.0;
-        } else if (cc == c0) {
+        } else if (u2 == 0) {
           for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl0[q];
-        } else if (cc == c1 - 1) {
+        } else if (u2 == n - 1) {
           for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl[q];
         } else {
           const double2 a = om[0], b = om[1], e = om[2];

@@ -167,6 +167,7 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
         for (int32_t k = P.copy_off[c]; k < P.copy_off[c + 1]; ++k) {
           P.pm_k[i] = k;
           P.pm_pos[k] = i;
+          P.pm_cam[i] = k + 1 == P.copy_off[c + 1] ? PM_LAST : 0;
           ++i;
         }
       }
@@ -190,7 +191,7 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
             slot[cam] = PM_GLOBAL | cam;
           }
         }
-        P.pm_cam[q] = slot[cam];
+        P.pm_cam[q] |= slot[cam];
       }
       P.iwg_cam_off[w + 1] = (int32_t)P.iwg_cams.size();
     }

@@ -21,10 +21,13 @@ constexpr int INT_WG = 128;        // points per intersection workgroup
 constexpr int INT_CAM_CAP = 192;   // cameras staged in LDS per intersection workgroup
 constexpr int INT_OBS_CAP = 768;   // observations staged in LDS per intersection workgroup
 // intersection observation code: camera slot in the workgroup's LDS list, or
-// with PM_GLOBAL the camera index itself; PM_DOWN = robust down-weighting
+// with PM_GLOBAL the camera index itself; PM_DOWN = robust down-weighting;
+// PM_LAST = last observation of its copy (the copies of a point follow each
+// other in the stream)
+constexpr int32_t PM_LAST = 1 << 28;
 constexpr int32_t PM_GLOBAL = 1 << 29;
 constexpr int32_t PM_DOWN = 1 << 30;
-constexpr int32_t PM_FIELD = PM_GLOBAL - 1;
+constexpr int32_t PM_FIELD = PM_LAST - 1;
 
 struct Plan {
   int32_t M = 0, N = 0, K = 0, L = 0;
