@@ -24,6 +24,40 @@ __device__ __forceinline__ W2<double> obs_weight(const Dev& d, int64_t k) {
   return {r * d.w0, 0.0, r * d.w0};
 }
 
+// one observation of a copy (LM order): camera index, pixel, weight and the
+// camera itself from `cams` (the cameras of the step or the updated ones)
+struct CopyObs {
+  int cam;
+  double x, y;
+  W2<double> W;
+  double cm[12];
+};
+__device__ __forceinline__ void copy_obs(const Dev& d, const double* cams, int64_t k, CopyObs& o) {
+  o.cam = d.obs_cam[k];
+  const double2 v = reinterpret_cast<const double2*>(d.xy)[k];
+  o.x = v.x;
+  o.y = v.y;
+  o.W = obs_weight(d, k);
+  const double2* g = reinterpret_cast<const double2*>(cams + (int64_t)CAM_STRIDE * o.cam);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double2 w = g[q];
+    o.cm[2 * q] = w.x;
+    o.cm[2 * q + 1] = w.y;
+  }
+}
+
+// f(observation) over the observations [k0, k1) of a copy, in order (one at
+// a time: a second one in flight costs more occupancy than it hides)
+template <typename F>
+__device__ __forceinline__ void for_copy_obs(const Dev& d, const double* cams, int k0, int k1, F&& f) {
+  for (int k = k0; k < k1; ++k) {
+    CopyObs a;
+    copy_obs(d, cams, k, a);
+    f(a);
+  }
+}
+
 // sum over a workgroup of 256 threads of `n` doubles; result valid in thread 0
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][8] */) {
@@ -481,22 +515,27 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
   }
   __syncthreads();
   if (c < d.NC) {
-    int l = d.copy_blk[c];
-    bool act = d.active == nullptr || d.active[l];
+    // the copy's indices, flags and point are loaded together, ahead of the
+    // tests that use them (the copy's own data stays behind them: holding it
+    // across the tests costs more occupancy than it saves here)
+    const int l = d.copy_blk[c], p = d.copy_pt[c];
+    const int k0 = d.copy_off[c], k1 = d.copy_off[c + 1];
+    const bool act = d.active == nullptr || d.active[l];
+    const int stp = d.status[p], fresh = d.blk_fresh[l];
+    const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
     double* pk = d.cpk + CPK * c;
-    if (act && d.status[d.copy_pt[c]] == 0) {
-      const int p = d.copy_pt[c];
-      const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
+    if (act && stp == 0) {
       double X[3] = {xb[0], xb[1], xb[2]};
-      if (!d.blk_fresh[l])
+      if (!fresh)
         for (int r = 0; r < 3; ++r) X[r] = d.Xc[3 * c + r];
-      const double* om = d.Om + 6 * c;
+      double om[6];
+      for (int q = 0; q < 6; ++q) om[q] = d.Om[6 * c + q];
       double dx[3] = {X[0] - xb[0], X[1] - xb[1], X[2] - xb[2]};
       double h[6], g[3];
       for (int q = 0; q < 6; ++q) h[q] = om[q];
       sym3_mul(om, dx, g);
       double cost = dx[0] * g[0] + dx[1] * g[1] + dx[2] * g[2];
-      for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
+      for (int k = k0; k < k1; ++k) {
         const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
@@ -589,32 +628,34 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
   }
   __syncthreads();
   if (c < d.NC) {
-    int l = d.copy_blk[c];
-    bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
-    if (act && d.status[d.copy_pt[c]] == 0) {
+    // the copy's inputs are loaded together, ahead of the tests that use them
+    const int l = d.copy_blk[c], p = d.copy_pt[c];
+    const int k0 = d.copy_off[c], k1 = d.copy_off[c + 1];
+    const bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
+    const int stp = d.status[p], fresh = d.blk_fresh[l];
+    const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
+    const double xc[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
+    double om[6];
+    for (int q = 0; q < 6; ++q) om[q] = d.Om[6 * c + q];
+    if (act && stp == 0) {
       // the point block V* and g_X are rebuilt from the same linearisation
       // that forms Y^T dC (as in the point-block pass: no stored inverse is
       // read back), then V* dX = -g_X - sum_k Y_k^T dC_i(k)
-      const int p = d.copy_pt[c];
-      const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
       double X[3] = {xb[0], xb[1], xb[2]};
-      if (!d.blk_fresh[l])
-        for (int r = 0; r < 3; ++r) X[r] = d.Xc[3 * c + r];
-      const double* om = d.Om + 6 * c;
+      if (!fresh)
+        for (int r = 0; r < 3; ++r) X[r] = xc[r];
       double dx0[3] = {X[0] - xb[0], X[1] - xb[1], X[2] - xb[2]};
       double h[6], g[3], bt[3] = {0.0, 0.0, 0.0};
       for (int q = 0; q < 6; ++q) h[q] = om[q];
       sym3_mul(om, dx0, g);
       const int base = d.blk_cam_off[l];
       const double* xs = d.x + d.vec_off[l];
-      for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
-        int i = d.obs_cam[k];
-        const double* cm = d.cam + (int64_t)CAM_STRIDE * i;
+      for_copy_obs(d, d.cam, k0, k1, [&](const CopyObs& o) {
         Lin<double> L;
-        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
-        const W2<double> W = obs_weight(d, k);
-        add_point_normals<double>(L, W, L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1], h, g);
-        const double* dC = xs + 6 * (i - base);
+        linearise<double>(o.cm, o.cm + 9, X, d.f, d.cx, d.cy, L);
+        const W2<double> W = o.W;
+        add_point_normals<double>(L, W, L.g0 - o.x, L.g1 - o.y, h, g);
+        const double* dC = xs + 6 * (o.cam - base);
         // t = A dC = Ar w - B dc ; Y^T dC = B^T W t
         double t0 = L.Ar[0][0] * dC[0] + L.Ar[0][1] * dC[1] + L.Ar[0][2] * dC[2] -
                     (L.B[0][0] * dC[3] + L.B[0][1] * dC[4] + L.B[0][2] * dC[5]);
@@ -622,7 +663,7 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
                     (L.B[1][0] * dC[3] + L.B[1][1] * dC[4] + L.B[1][2] * dC[5]);
         double wt0 = W.a * t0 + W.b * t1, wt1 = W.b * t0 + W.c * t1;
         for (int s = 0; s < 3; ++s) bt[s] += L.B[0][s] * wt0 + L.B[1][s] * wt1;
-      }
+      });
       h[0] *= 1.0 + d.lambda;
       h[3] *= 1.0 + d.lambda;
       h[5] *= 1.0 + d.lambda;
@@ -637,14 +678,13 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       d.Xc[3 * c + 2] = Xn[2];
       double dx[3] = {Xn[0] - xb[0], Xn[1] - xb[1], Xn[2] - xb[2]};
       double og[3];
-      sym3_mul(d.Om + 6 * c, dx, og);
+      sym3_mul(om, dx, og);
       double cost = dx[0] * og[0] + dx[1] * og[1] + dx[2] * og[2];
-      for (int k = d.copy_off[c]; k < d.copy_off[c + 1]; ++k) {
-        const double* cm = d.camN + (int64_t)CAM_STRIDE * d.obs_cam[k];
+      for_copy_obs(d, d.camN, k0, k1, [&](const CopyObs& o) {
         Lin<double> L;
-        linearise<double>(cm, cm + 9, Xn, d.f, d.cx, d.cy, L);
-        cost += wquad(obs_weight(d, k), L.g0 - d.xy[2 * k], L.g1 - d.xy[2 * k + 1]);
-      }
+        linearise<double>(o.cm, o.cm + 9, Xn, d.f, d.cx, d.cy, L);
+        cost += wquad(o.W, L.g0 - o.x, L.g1 - o.y);
+      });
       double s2 = dX[0] * dX[0] + dX[1] * dX[1] + dX[2] * dX[2];
       int slot = l - l_first;
       if (slot >= 0 && slot < 8) {
