@@ -75,16 +75,19 @@ def algorithmic(scene, counts, dense_blocks):
     import numpy as np
     nc, nc_tp, pairs = counts
     K, N = scene.K, scene.N
-    # intersection: observations (x, y, camera, weight) in, residuals out;
-    # start point and status in; point, covariance and status out; refined
-    # weight of every tie-point copy and the reset copies out
-    b_int = K * (16 + 4 + 8 + 16) + N * (24 + 4 + 24 + 48 + 4) + nc_tp * 48 + nc * 24
+    # intersection kernel: per observation the pixel and its code in (weights
+    # too with an information matrix per observation), the residual out; per
+    # point the start value, status and stream offsets in, the point (twice),
+    # status and the export records (point + status, covariance) out; per copy
+    # its index in and its refined weight out; every camera once
+    info = getattr(scene, "obs_info", None) is not None
+    b_int = K * (16 + 4 + 16 + (24 if info else 0)) + N * (24 + 4 + 8 + 8 + 48 + 4 + 32 + 48) + nc * (4 + 48) + scene.M * 96
     n6 = 6.0 * np.bincount(scene.cam_block, minlength=scene.L)[dense_blocks]
     f_chol = float((n6 ** 3 / 3.0 + n6 ** 2).sum())
     # camera-pair Schur blocks: per observation pair its entry (copy, k1, k2),
     # the copy's point and damped inverse, two weights; one 6x6 block out per pair
     b_pairs = pairs * (12 + 72 + 16)
-    return {"intersect": ("hbm", b_int, f"K*44 + N*104 + NC_tp*48 + NC*24 bytes (K={K}, N={N}, NC={nc}, NC_tp={nc_tp})"),
+    return {"intersect": ("hbm", b_int, f"K*{36 + (24 if info else 0)} + N*176 + NC*52 + M*96 bytes (K={K}, N={N}, NC={nc}, M={scene.M})"),
             "chol_forward": ("mfma", f_chol, "sum over dense sub-blocks of (6n)^3/3 + (6n)^2 FLOP"),
             "schur_pairs": ("hbm", b_pairs, f"pairs*100 bytes (pairs={pairs})")}
 
@@ -186,12 +189,16 @@ def write_traffic(fetch_csv, write_csv, command):
     fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
     write = per_dispatch(write_csv, "WRITE_SIZE")
 
-    def med(tab, needle):
-        v = [x for (name, _), x in tab.items() if needle in name]
+    def base(name):  # "void ns::(anonymous namespace)::k_name<64>(args)" -> "k_name"
+        n = name.replace("(anonymous namespace)::", "").split("(")[0].split("<")[0]
+        return n.split("::")[-1].replace("void ", "").strip()
+
+    def med(tab, kname):
+        v = [x for (name, _), x in tab.items() if base(name) == kname]
         return statistics.median(v) if v else None
 
-    def copy_of(tab):  # the 1 GiB calibration copy: the largest copy dispatch of the run
-        v = [x for (name, _), x in tab.items() if "copy" in name.lower()]
+    def copy_of(tab):  # the 1 GiB calibration copy: the runtime's device-to-device copy kernel
+        v = [x for (name, _), x in tab.items() if "copyBuffer" in name]
         return max(v) if v else None
 
     cf, cw = copy_of(fetch), copy_of(write)
