@@ -52,6 +52,10 @@ struct Dev {
   const int32_t* cam_obs_off;
   const int32_t* cam_obs;
   const int32_t* cam_obs_c;  // copy of each cam_obs entry
+  // camera-major copies (cam_obs order) for the diagonal Schur pass
+  double* cm_xy;          // [K][2] pixel
+  double* cm_rw;          // [K] robust weight multiplier (kept with rw)
+  double* cm_info;        // [K][3] or null
   // intersection stream, point-major (see the plan)
   const int32_t* pm_off;
   const int32_t* pm_k;

@@ -92,6 +92,18 @@ __global__ void k_gather_obs(Dev d) {
   d.res[2 * k + 1] = 0.0;
 }
 
+// camera-major copies of the pixels and weights (after k_gather_obs)
+__global__ void k_gather_cm(Dev d) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= d.K) return;
+  const int64_t k = d.cam_obs[t];
+  d.cm_xy[2 * t] = d.xy[2 * k];
+  d.cm_xy[2 * t + 1] = d.xy[2 * k + 1];
+  d.cm_rw[t] = d.rw[k];
+  if (d.has_info)
+    for (int q = 0; q < 3; ++q) d.cm_info[3 * t + q] = d.info[3 * k + q];
+}
+
 __global__ void k_gather_cams(Dev d) {
   int i = blockIdx.x * NT + threadIdx.x;
   if (i >= d.M) return;
@@ -890,6 +902,7 @@ void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
 void launch_gather(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_obs, dim3(grid_for(d.K)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_gather_pm, dim3(grid_for(d.K)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_gather_cm, dim3(grid_for(d.K)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_gather_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_gather_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
 }

@@ -150,6 +150,7 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
       }
     }
     d.rw[k] = w;
+    d.cm_rw[t] = w;  // the diagonal Schur pass's camera-major copy
     const int64_t pos = d.pm_pos[k];  // the intersection's copy of the weight
     if (d.has_info) {
       for (int q = 0; q < 3; ++q) d.pm_w[3 * pos + q] = w * d.info[3 * (int64_t)k + q];

@@ -110,6 +110,8 @@ struct ObsIn {
   bool valid;
 };
 
+// inputs of one observation of copy c: k is its position in the camera's
+// observation list for the diagonal pass (DIAG), its LM index for the pair pass
 template <typename T, bool DIAG>
 __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_range, ObsIn<T>& o) {
   o.valid = false;
@@ -159,11 +161,21 @@ __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_
     }
   }
   if (DIAG) {
-    const double2 xy = reinterpret_cast<const double2*>(d.xy)[k];
+    // k is the observation's position in its camera's list: pixel and weight
+    // come from the camera-major copies, read in order by the camera's wave
+    const double2 xy = reinterpret_cast<const double2*>(d.cm_xy)[k];
     o.x = (T)xy.x;
     o.y = (T)xy.y;
+    const double r = d.cm_rw[k];
+    if (d.has_info) {
+      const double* w = d.cm_info + 3 * (int64_t)k;
+      o.W = {(T)(r * w[0]), (T)(r * w[1]), (T)(r * w[2])};
+    } else {
+      o.W = {(T)(r * d.w0), T(0), (T)(r * d.w0)};
+    }
+  } else {
+    o.W = obs_weight_t<T>(d, k);
   }
-  o.W = obs_weight_t<T>(d, k);
 }
 
 // One wave per camera: diagonal block S_(i,i) = U*_i - sum_k Y_k V*^-1 Y_k^T
@@ -229,11 +241,11 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
     {
       int kA = 0, cA = 0;
       if (t < o1) {
-        kA = d.cam_obs[t];
+        kA = t;
         cA = d.cam_obs_c[t];
       }
       if (t + 64 < o1) {
-        kB = d.cam_obs[t + 64];
+        kB = t + 64;
         cB = d.cam_obs_c[t + 64];
       }
       obs_in_load<T, true>(d, kA, cA, t < o1, cur);
@@ -241,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
     for (; t < o1; t += 64) {
       int kC = 0, cC = 0;
       if (t + 128 < o1) {
-        kC = d.cam_obs[t + 128];
+        kC = t + 128;
         cC = d.cam_obs_c[t + 128];
       }
       ObsIn<T> nxt;
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
   } else {
     for (int t = o0 + lane; t < o1; t += 64) {
       ObsIn<T> cur;
-      obs_in_load<T, true>(d, d.cam_obs[t], d.cam_obs_c[t], true, cur);
+      obs_in_load<T, true>(d, t, d.cam_obs_c[t], true, cur);
       if (cur.valid) process(cur);
     }
   }
