@@ -287,6 +287,10 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     for (int64_t q = 0; q < NPB; ++q) cnt[q + 1] += cnt[q];
     P.pb_ent_off = cnt;
     P.pb_ent.resize(3 * (size_t)cnt[NPB]);
+    // observations are referred to by their position in their camera's list,
+    // where the pair pass reads their weights (in order within a pair block)
+    std::vector<int32_t> pos_in_cam(K);
+    for (int32_t q = 0; q < K; ++q) pos_in_cam[P.cam_obs[q]] = q;
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
     for (int64_t c = 0; c < P.NC; ++c) {
       int32_t b = P.copy_off[c], e = P.copy_off[c + 1], base = P.blk_cam_off[P.copy_blk[c]];
@@ -294,8 +298,8 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
         for (int32_t k2 = b; k2 <= k1; ++k2) {
           int64_t at = fill[pb_of(P.obs_cam[k1], P.obs_cam[k2] - base)]++;
           P.pb_ent[3 * at] = (int32_t)c;
-          P.pb_ent[3 * at + 1] = k1;
-          P.pb_ent[3 * at + 2] = k2;
+          P.pb_ent[3 * at + 1] = pos_in_cam[k1];
+          P.pb_ent[3 * at + 2] = pos_in_cam[k2];
         }
     }
     P.od_pb.clear();

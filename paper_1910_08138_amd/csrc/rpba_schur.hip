@@ -25,11 +25,13 @@ namespace {
 
 constexpr int NT = 256;
 
+// weight of the observation at position t of its camera's list (camera-major
+// copies of the robust multiplier and of the information matrix)
 template <typename T>
-__device__ __forceinline__ W2<T> obs_weight_t(const Dev& d, int64_t k) {
-  double r = d.rw[k];
+__device__ __forceinline__ W2<T> cm_weight_t(const Dev& d, int64_t t) {
+  const double r = d.cm_rw[t];
   if (d.has_info) {
-    const double* w = d.info + 3 * k;
+    const double* w = d.cm_info + 3 * t;
     return {(T)(r * w[0]), (T)(r * w[1]), (T)(r * w[2])};
   }
   return {(T)(r * d.w0), T(0), (T)(r * d.w0)};
@@ -110,8 +112,9 @@ struct ObsIn {
   bool valid;
 };
 
-// inputs of one observation of copy c: k is its position in the camera's
-// observation list for the diagonal pass (DIAG), its LM index for the pair pass
+// inputs of one observation of copy c; k is the observation's position in
+// its camera's list: pixel (diagonal pass only) and weight come from the
+// camera-major copies, read in order by the camera's wave or pair group
 template <typename T, bool DIAG>
 __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_range, ObsIn<T>& o) {
   o.valid = false;
@@ -161,21 +164,11 @@ __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_
     }
   }
   if (DIAG) {
-    // k is the observation's position in its camera's list: pixel and weight
-    // come from the camera-major copies, read in order by the camera's wave
     const double2 xy = reinterpret_cast<const double2*>(d.cm_xy)[k];
     o.x = (T)xy.x;
     o.y = (T)xy.y;
-    const double r = d.cm_rw[k];
-    if (d.has_info) {
-      const double* w = d.cm_info + 3 * (int64_t)k;
-      o.W = {(T)(r * w[0]), (T)(r * w[1]), (T)(r * w[2])};
-    } else {
-      o.W = {(T)(r * d.w0), T(0), (T)(r * d.w0)};
-    }
-  } else {
-    o.W = obs_weight_t<T>(d, k);
   }
+  o.W = cm_weight_t<T>(d, k);
 }
 
 // One wave per camera: diagonal block S_(i,i) = U*_i - sum_k Y_k V*^-1 Y_k^T
@@ -334,16 +327,16 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
 #pragma unroll
   for (int u = 0; u < 36; ++u) acc[u] = T(0);
   for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += 16) {
-    const int c = d.pb_ent[3 * e], k1 = d.pb_ent[3 * e + 1], k2 = d.pb_ent[3 * e + 2];
+    const int c = d.pb_ent[3 * e], t1 = d.pb_ent[3 * e + 1], t2 = d.pb_ent[3 * e + 2];
     ObsIn<T> o;
-    obs_in_load<T, false>(d, k1, c, true, o);
+    obs_in_load<T, false>(d, t1, c, true, o);
     if (!o.valid) continue;
     Lin<T> L1, L2;
     c1.lin(o.X, d, L1);
     c2.lin(o.X, d, L2);
     T Y1[6][3], Y2[6][3], Z1[6][3];
     y_block<T>(L1, o.W, Y1);
-    y_block<T>(L2, obs_weight_t<T>(d, k2), Y2);
+    y_block<T>(L2, cm_weight_t<T>(d, t2), Y2);
     z_block<T>(Y1, o.Vi, Z1);
 #pragma unroll
     for (int r = 0; r < 6; ++r)
