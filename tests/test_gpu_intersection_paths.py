@@ -1,0 +1,146 @@
+"""Intersection paths (paper eq:bars, Sec. 5.1) that the benchmark workload
+barely exercises, on the GPU against the FP64 oracle:
+
+* workgroups whose observations do not fit the LDS staging (they are read
+  from memory),
+* workgroups that see more cameras than the LDS camera list holds (the rest
+  are read from memory),
+* both at once,
+* the caller-order export: an invalid point keeps its previous position and
+  covariance in the caller's arrays, its status is reported.
+
+The scenes are asserted to exceed the staging caps, from the point order the
+library uses (points by their first camera, cameras by sub-block; within each
+group of 128 points the points with more views first)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_08138_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+WG = 128          # points per intersection workgroup
+OBS_CAP = 768     # observations a workgroup stages in LDS
+CAM_CAP = 192     # cameras a workgroup stages in LDS
+
+CASES = {
+    "obs-over-cap": dict(seed=7, n_cams=40, n_pts=3000, views=(10, 14)),
+    "cams-over-cap": dict(seed=8, n_cams=600, n_pts=6000, views=(3, 6)),
+    "both": dict(seed=8, n_cams=1000, n_pts=6000, views=(4, 8)),
+}
+
+
+@pytest.fixture(scope="module")
+def rp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_08138_amd import binding
+    binding.load_library()
+    return binding
+
+
+def _workgroup_extent(s):
+    """Largest number of cameras and of observations of one workgroup."""
+    M, N = s.M, s.N
+    cam_new = np.empty(M, np.int64)
+    cam_new[np.lexsort((np.arange(M), s.cam_block))] = np.arange(M)
+    cn = cam_new[s.obs_cam]
+    first = np.full(N, M)
+    np.minimum.at(first, s.obs_pt, cn)
+    views = np.bincount(s.obs_pt, minlength=N)
+    order = np.argsort(first, kind="stable")
+    for b in range(0, N, WG):
+        seg = order[b:b + WG]
+        order[b:b + WG] = seg[np.argsort(-views[seg], kind="stable")]
+    pt_new = np.empty(N, np.int64)
+    pt_new[order] = np.arange(N)
+    wg = pt_new[s.obs_pt] // WG
+    nwg = (N + WG - 1) // WG
+    cams = max(len(np.unique(cn[wg == w])) for w in range(nwg))
+    return cams, int(np.bincount(wg, minlength=nwg).max())
+
+
+def _compare(gp, op, s):
+    gX, gcov, gstat = gp.intersection()
+    oX, ocov, ostat = op.intersection()
+    assert np.array_equal(gstat, ostat)
+    ok = ostat == 0
+    assert ok.sum() > 0.9 * s.N
+    assert np.abs(gX[:, ok] - oX[:, ok]).max() <= TOL * (np.abs(oX).max() + 1)
+    rel = np.linalg.norm(gcov[:, ok] - ocov[:, ok], axis=0) / np.linalg.norm(ocov[:, ok], axis=0)
+    assert rel.max() <= 1e-8, rel.max()
+    # refined weights Omega = H - H^(l) of every copy
+    gb, gpt, _, gom = gp.copies()
+    ob, opt_, _, oom = op.copies()
+    o1, o2 = np.lexsort((gpt, gb)), np.lexsort((opt_, ob))
+    assert np.array_equal(gb[o1], ob[o2]) and np.array_equal(gpt[o1], opt_[o2])
+    assert np.abs(gom[o1] - oom[o2]).max() <= TOL * np.abs(oom).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_intersection_beyond_staging_caps(rp, name):
+    s = scenes.ring_scene(**CASES[name])
+    cams, obs = _workgroup_extent(s)
+    if name != "cams-over-cap":
+        assert obs > OBS_CAP, obs
+    if name != "obs-over-cap":
+        assert cams > CAM_CAP, cams
+    gp = rp.Problem(s)
+    op = oracle.OracleProblem(s)
+    gst = rp._host(gp, gp.rpba_intersect())
+    ost = op.intersect()
+    assert np.allclose(gst, ost, rtol=TOL, atol=0), (gst, ost)
+    _compare(gp, op, s)
+    # a second intersection from the same points (every point already
+    # converged: one Gauss-Newton step) and after one LM step + consensus
+    gp.rpba_subblock_lm_step()
+    op.lm_step()
+    assert np.allclose(rp._host(gp, gp.rpba_consensus()), op.consensus(), rtol=TOL, atol=TOL)
+    gst = rp._host(gp, gp.rpba_intersect())
+    ost = op.intersect()
+    assert np.allclose(gst, ost, rtol=TOL, atol=0), (gst, ost)
+    _compare(gp, op, s)
+
+
+def test_export_leaves_invalid_points_untouched(rp):
+    """Camera 3 is turned half a revolution about its y axis: its points lie
+    behind it and the intersection rejects them.  Caller arrays prefilled with
+    sentinels: valid points get the oracle's point, covariance and status,
+    invalid ones keep their previous point and the sentinel covariance."""
+    import ctypes
+
+    import torch
+    s = scenes.ring_scene(5, n_cams=12, n_pts=600)
+    R = s.cam_R[3].reshape(3, 3)
+    s.cam_R[3] = (np.diag([-1.0, 1.0, -1.0]) @ R).ravel()
+    gp = rp.Problem(s)
+    pts0 = gp.points().copy()
+    cov = torch.full((6, s.N), 7.0, dtype=torch.float64, device="cuda")
+    status = torch.full((s.N,), -5, dtype=torch.int32, device="cuda")
+    gp._order()
+    rc = gp.L_.rpba_intersect(gp.h, ctypes.c_void_p(cov.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                              ctypes.c_void_p(gp.int_stats.data_ptr()))
+    assert rc == 0
+    gp.sync()
+    op = oracle.OracleProblem(s)
+    op.intersect()
+    oX, ocov, ostat = op.intersection()
+    st = status.cpu().numpy()
+    assert np.array_equal(st, ostat)
+    bad = ostat != 0
+    assert bad.sum() > 0 and (~bad).sum() > 0
+    pts = gp.points()
+    c = cov.cpu().numpy()
+    assert np.array_equal(pts[:, bad], pts0[:, bad])
+    assert np.all(c[:, bad] == 7.0)
+    assert np.abs(pts[:, ~bad] - oX[:, ~bad]).max() <= TOL * (np.abs(oX).max() + 1)
+    rel = np.linalg.norm(c[:, ~bad] - ocov[:, ~bad], axis=0) / np.linalg.norm(ocov[:, ~bad], axis=0)
+    assert rel.max() <= 1e-8
+    # the consensus export leaves the invalid points as they were too
+    gp.rpba_subblock_lm_step()
+    gp.rpba_consensus()
+    pts2 = gp.points()
+    assert np.array_equal(pts2[:, bad], pts0[:, bad])
