@@ -45,7 +45,7 @@ struct Dev {
   double* xy;             // [K][2]
   double* info;           // [K][3] or null
   double* rw;             // [K] robust weight multiplier
-  double* res;            // [K][2] residuals of the last intersection, point-major
+  double* res;            // [K][2] residuals of the last intersection, point-major (valid points only)
   const int32_t* obs_cam;
   const int32_t* obs_copy;
   const int32_t* obs_orig;

@@ -234,7 +234,7 @@ __device__ __forceinline__ void put_pxs(const Dev& d, int j, const double (&X)[3
 // residuals, refined weights of the copies); accv gets the point's share of
 // the statistics
 template <bool INFO, bool OLDS>
-__device__ __forceinline__ void intersect_point(const Dev& d, const Stage& sg, int b0, int j, int want_cov,
+__device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0, int j, int want_cov,
                                                 double (&accv)[4]) {
   if (j < d.N && d.status[j] == 0) {
     const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1], n = c1 - c0;
@@ -320,7 +320,10 @@ __device__ __forceinline__ void intersect_point(const Dev& d, const Stage& sg, i
         if (!(L.z > 0.0)) behind = true;
         const double v0 = L.g0 - x, v1 = L.g1 - y;
         add_point_normals<double>(L, W, v0, v1, hl, gl);
-        reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
+        // the residual takes the place of the pixel in LDS (this pass reads
+        // it last), and the workgroup copies them out coalesced
+        if (OLDS) sg.xy[i - b0] = make_double2(v0, v1);
+        else reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
         cost += wquad(W, v0, v1);
         sq += v0 * v0 + v1 * v1;
         nobs += 1.0;
@@ -458,8 +461,17 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   __syncthreads();
   const int j = j0 + threadIdx.x;
   double accv[4] = {0.0, 0.0, 0.0, 0.0};
-  if (nobs <= INT_OBS_CAP) intersect_point<INFO, true>(d, sg, b0, j, want_cov, accv);
-  else intersect_point<INFO, false>(d, sg, b0, j, want_cov, accv);
+  if (nobs <= INT_OBS_CAP) {
+    intersect_point<INFO, true>(d, sg, b0, j, want_cov, accv);
+    // residuals of the workgroup's stream, one coalesced copy (the slots of
+    // points left invalid hold their pixels: residuals are only read for
+    // valid points)
+    __syncthreads();
+    double2* res = reinterpret_cast<double2*>(d.res) + b0;
+    for (int t = threadIdx.x; t < nobs; t += IT) res[t] = sg.xy[t];
+  } else {
+    intersect_point<INFO, false>(d, sg, b0, j, want_cov, accv);
+  }
   // workgroup sum of the statistics, one atomic per value
 #pragma unroll
   for (int q = 0; q < 4; ++q)
