@@ -71,7 +71,7 @@ struct Plan {
   std::vector<int32_t> pb_row;         // [NPB] internal camera i
   std::vector<int64_t> pb_ent_off;     // [NPB+1]
   std::vector<int32_t> pb_ent;         // [3 * entries] (copy, t1, t2): t = the observation's position in cam_obs
-  std::vector<int32_t> od_pb;          // off-diagonal pair blocks (i2 != i), most entries first
+  std::vector<int32_t> od_pb;          // off-diagonal pair blocks (i2 != i), most 16-lane rounds first
   std::vector<int32_t> pb_bsr;         // [NPB] position of block (i, i2) in the full block-sparse matrix
   std::vector<int32_t> pb_bsr_t;       // [NPB] position of block (i2, i)
 
