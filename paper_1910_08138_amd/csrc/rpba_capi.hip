@@ -602,6 +602,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.Xc = F(m.Xc);
   D.blk_fresh = I(m.blk_fresh);
   D.Om = F(m.Om);
+  D.Omf = reinterpret_cast<float*>(D.Om);
+  D.om_f32 = o->precision == RPBA_MIXED;
   D.cpk = F(m.cpk);
   D.nb_off = I(m.nb_off);
   D.nb_cam = I(m.nb_cam);
@@ -869,7 +871,15 @@ rpba_status rpba_get_copies(rpba_problem* h, int32_t* blk, int32_t* pt, double* 
       if (fresh[p.copy_blk[c]])
         for (int r = 0; r < 3; ++r) X[3 * c + r] = xb[(size_t)r * p.N + p.copy_pt[c]];
   }
-  if (omega) HIP_TRY(hipMemcpy(omega, h->d.Om, 8 * 6 * p.NC, hipMemcpyDeviceToHost));
+  if (omega) {
+    if (h->d.om_f32) {
+      std::vector<float> om((size_t)6 * p.NC);
+      HIP_TRY(hipMemcpy(om.data(), h->d.Omf, 4 * om.size(), hipMemcpyDeviceToHost));
+      for (size_t q = 0; q < om.size(); ++q) omega[q] = om[q];
+    } else {
+      HIP_TRY(hipMemcpy(omega, h->d.Om, 8 * 6 * p.NC, hipMemcpyDeviceToHost));
+    }
+  }
   return RPBA_OK;
 }
 

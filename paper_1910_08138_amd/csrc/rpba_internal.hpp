@@ -75,7 +75,9 @@ struct Dev {
   double* Xc;             // [NC][3] X_j^l (valid when the sub-block is not fresh)
   int32_t* blk_fresh;     // [L] 1: every copy of the sub-block is still at Xbar (set by the
                           // intersection, cleared by the sub-block's next update)
-  double* Om;             // [NC][6] refined tie-point weight
+  double* Om;             // [NC][6] refined tie-point weight (FP64 path)
+  float* Omf;             // the same region as [NC][6] floats on the mixed path (om_f32)
+  int32_t om_f32;         // 1: the refined weights are stored in FP32
   double* cpk;            // [NC][CPK] X (3), valid (1 or 0), damped V^-1 (6), g_X (3), spare (3);
                           // on the mixed path [NC][CPK32]: X (3 doubles), then
                           // as floats V^-1 (6), g_X (3), valid

@@ -221,6 +221,31 @@ __device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0
   return code;
 }
 
+// where the intersection parks the normals H^(l) of a point's middle copies
+// until H is complete: in the copy's refined-weight slot on the FP64 path; on
+// the mixed path (FP32 refined weights) in the copy's record of the last LM
+// step, free until the next point-block pass rewrites it, so that the
+// difference H - H^(l) is still formed in FP64
+__device__ __forceinline__ double2* om_park(const Dev& d, int64_t c) {
+  return reinterpret_cast<double2*>(d.om_f32 ? d.cpk + CPK32 * c : d.Om + 6 * c);
+}
+
+// refined weight Omega of copy c (FP32 storage on the mixed path)
+__device__ __forceinline__ void om_load(const Dev& d, int64_t c, double (&om)[6]) {
+  if (d.om_f32) {
+    const float2* f = reinterpret_cast<const float2*>(d.Omf + 6 * c);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float2 v = f[q];
+      om[2 * q] = v.x;
+      om[2 * q + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) om[q] = d.Om[6 * c + q];
+  }
+}
+
 // latest point of internal index j and its status, written whole so that
 // the record lines fill completely (exported to the caller's order by
 // k_export_pts)
@@ -333,7 +358,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
             if (u == 0) {
               for (int q = 0; q < 6; ++q) hl0[q] = hl[q];
             } else {
-              double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)copy_at(u));
+              double2* om = om_park(d, copy_at(u));
               om[0] = make_double2(hl[0], hl[1]);
               om[1] = make_double2(hl[2], hl[3]);
               om[2] = make_double2(hl[4], hl[5]);
@@ -357,7 +382,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
       // (zero for a point seen by one sub-block only).  The copies themselves
       // are reset to Xbar through the sub-blocks' fresh flags.
       for (int u2 = 0; u2 < n; ++u2) {
-        double2* om = reinterpret_cast<double2*>(d.Om + 6 * (int64_t)copy_at(u2));
+        const int64_t c = copy_at(u2);
         double o6[6];
         if (n == 1) {
           for (int q = 0; q < 6; ++q) o6[q] = 0.0;
@@ -366,6 +391,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
         } else if (u2 == n - 1) {
           for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl[q];
         } else {
+          const double2* om = om_park(d, c);
           const double2 a = om[0], b = om[1], e = om[2];
           o6[0] = h[0] - a.x;
           o6[1] = h[1] - a.y;
@@ -374,9 +400,17 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
           o6[4] = h[4] - e.x;
           o6[5] = h[5] - e.y;
         }
-        om[0] = make_double2(o6[0], o6[1]);
-        om[1] = make_double2(o6[2], o6[3]);
-        om[2] = make_double2(o6[4], o6[5]);
+        if (d.om_f32) {
+          float2* om = reinterpret_cast<float2*>(d.Omf + 6 * c);
+          om[0] = make_float2((float)o6[0], (float)o6[1]);
+          om[1] = make_float2((float)o6[2], (float)o6[3]);
+          om[2] = make_float2((float)o6[4], (float)o6[5]);
+        } else {
+          double2* om = reinterpret_cast<double2*>(d.Om + 6 * c);
+          om[0] = make_double2(o6[0], o6[1]);
+          om[1] = make_double2(o6[2], o6[3]);
+          om[2] = make_double2(o6[4], o6[5]);
+        }
       }
       accv[0] = cost;
       accv[1] = sq;
@@ -553,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
       if (!fresh)
         for (int r = 0; r < 3; ++r) X[r] = d.Xc[3 * c + r];
       double om[6];
-      for (int q = 0; q < 6; ++q) om[q] = d.Om[6 * c + q];
+      om_load(d, c, om);
       double dx[3] = {X[0] - xb[0], X[1] - xb[1], X[2] - xb[2]};
       double h[6], g[3];
       for (int q = 0; q < 6; ++q) h[q] = om[q];
@@ -660,7 +694,7 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
     const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
     const double xc[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
     double om[6];
-    for (int q = 0; q < 6; ++q) om[q] = d.Om[6 * c + q];
+    om_load(d, c, om);
     if (act && stp == 0) {
       // the point block V* and g_X are rebuilt from the same linearisation
       // that forms Y^T dC (as in the point-block pass: no stored inverse is
