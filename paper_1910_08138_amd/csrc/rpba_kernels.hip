@@ -177,33 +177,43 @@ struct Stage {
   int32_t code[INT_OBS_CAP];
 };
 
-// observation i of the stream: pixel, weight and camera.  OLDS: the
-// workgroup's observations are all staged (a workgroup-uniform choice, so
-// the common path carries no per-lane test of where they live).  The camera
-// is read from its LDS slot unconditionally; the rare camera beyond the
-// staging cap is then replaced from memory in a branch of its own.
-template <bool INFO, bool OLDS>
-__device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0, int i, double& x, double& y,
-                                           W2<double>& W, double (&cm)[12]) {
+// observation i of the stream, in two parts: its head (pixel, weight and
+// code) and the camera the code names.  OLDS: the workgroup's observations
+// are all staged (a workgroup-uniform choice, so the common path carries no
+// per-lane test of where they live).  The camera is read from its LDS slot
+// unconditionally; the rare camera beyond the staging cap is then replaced
+// from memory in a branch of its own.
+struct ObsHead {
+  double x, y;
+  W2<double> W;
   int32_t code;
+};
+
+template <bool INFO, bool OLDS>
+__device__ __forceinline__ ObsHead obs_head(const Dev& d, const Stage& sg, int b0, int i) {
+  ObsHead o;
   if (OLDS) {
     const double2 v = sg.xy[i - b0];
-    x = v.x;
-    y = v.y;
-    code = sg.code[i - b0];
+    o.x = v.x;
+    o.y = v.y;
+    o.code = sg.code[i - b0];
   } else {
     const double2 v = reinterpret_cast<const double2*>(d.pm_xy)[i];
-    x = v.x;
-    y = v.y;
-    code = d.pm_code[i];
+    o.x = v.x;
+    o.y = v.y;
+    o.code = d.pm_code[i];
   }
   if (INFO) {
     const double* w = d.pm_w + 3 * (int64_t)i;
-    W = {w[0], w[1], w[2]};
+    o.W = {w[0], w[1], w[2]};
   } else {
-    const double w = (code & PM_DOWN) ? d.down_weight * d.w0 : d.w0;
-    W = {w, 0.0, w};
+    const double w = (o.code & PM_DOWN) ? d.down_weight * d.w0 : d.w0;
+    o.W = {w, 0.0, w};
   }
+  return o;
+}
+
+__device__ __forceinline__ void obs_cam(const Dev& d, const Stage& sg, int32_t code, double (&cm)[12]) {
   const int f = code & PM_FIELD;
   const bool glb = (code & PM_GLOBAL) != 0;
   const int sl = glb ? 0 : f;
@@ -218,7 +228,17 @@ __device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0
       cm[2 * q + 1] = v.y;
     }
   }
-  return code;
+}
+
+template <bool INFO, bool OLDS>
+__device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0, int i, double& x, double& y,
+                                           W2<double>& W, double (&cm)[12]) {
+  const ObsHead o = obs_head<INFO, OLDS>(d, sg, b0, i);
+  x = o.x;
+  y = o.y;
+  W = o.W;
+  obs_cam(d, sg, o.code, cm);
+  return o.code;
 }
 
 // where the intersection parks the normals H^(l) of a point's middle copies
@@ -283,26 +303,35 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
       // dependency chains for the scheduler), added at the end of the pass
       double h2[6] = {0, 0, 0, 0, 0, 0}, g2[3] = {0, 0, 0};
       int i = i0;
+      // the heads of the next pair are read while this pair is computed
+      // (indices clamped into the point's own range)
+      ObsHead ha, hb;
+      if (i0 < i1) {
+        ha = obs_head<INFO, OLDS>(d, sg, b0, i0);
+        hb = obs_head<INFO, OLDS>(d, sg, b0, min(i0 + 1, i1 - 1));
+      }
       for (; i + 1 < i1; i += 2) {
-        double xa, ya, cma[12], xb, yb, cmb[12];
-        W2<double> Wa, Wb;
-        obs_get<INFO, OLDS>(d, sg, b0, i, xa, ya, Wa, cma);
-        obs_get<INFO, OLDS>(d, sg, b0, i + 1, xb, yb, Wb, cmb);
+        double cma[12], cmb[12];
+        obs_cam(d, sg, ha.code, cma);
+        obs_cam(d, sg, hb.code, cmb);
+        const ObsHead na = obs_head<INFO, OLDS>(d, sg, b0, min(i + 2, i1 - 1));
+        const ObsHead nb = obs_head<INFO, OLDS>(d, sg, b0, min(i + 3, i1 - 1));
         Lin<double> La, Lb;
         linearise<double>(cma, cma + 9, X, d.f, d.cx, d.cy, La);
         linearise<double>(cmb, cmb + 9, X, d.f, d.cx, d.cy, Lb);
         if (!(La.z > 0.0) || !(Lb.z > 0.0)) behind = true;
-        add_point_normals<double>(La, Wa, La.g0 - xa, La.g1 - ya, h, g);
-        add_point_normals<double>(Lb, Wb, Lb.g0 - xb, Lb.g1 - yb, h2, g2);
+        add_point_normals<double>(La, ha.W, La.g0 - ha.x, La.g1 - ha.y, h, g);
+        add_point_normals<double>(Lb, hb.W, Lb.g0 - hb.x, Lb.g1 - hb.y, h2, g2);
+        ha = na;
+        hb = nb;
       }
-      if (i < i1) {
-        double x, y, cm[12];
-        W2<double> W;
-        obs_get<INFO, OLDS>(d, sg, b0, i, x, y, W, cm);
+      if (i < i1) {  // ha holds the head of observation i
+        double cm[12];
+        obs_cam(d, sg, ha.code, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0)) behind = true;
-        add_point_normals<double>(L, W, L.g0 - x, L.g1 - y, h, g);
+        add_point_normals<double>(L, ha.W, L.g0 - ha.x, L.g1 - ha.y, h, g);
       }
       for (int q = 0; q < 6; ++q) h[q] += h2[q];
       for (int q = 0; q < 3; ++q) g[q] += g2[q];
