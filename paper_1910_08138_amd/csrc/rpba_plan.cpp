@@ -307,11 +307,12 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
       int32_t i = P.pb_row[q];
       if (P.nb_cam[q] != i - P.blk_cam_off[P.cam_blk[i]]) P.od_pb.push_back((int32_t)q);
     }
-    // by the number of rounds a 16-lane group needs, most first: the four
-    // pair blocks of a wave take the same number of rounds (a wave lasts as
-    // long as its longest) and the long ones start early; inside a class the
-    // blocks keep their order (neighbouring cameras, shared copy records)
-    auto rounds = [&](int32_t q) { return (P.pb_ent_off[q + 1] - P.pb_ent_off[q] + 15) / 16; };
+    // by the number of rounds a lane group of the pair pass needs, most
+    // first: the pair blocks of a wave take the same number of rounds (a wave
+    // lasts as long as its longest) and the long ones start early; inside a
+    // class the blocks keep their order (neighbouring cameras, shared copy
+    // records)
+    auto rounds = [&](int32_t q) { return (P.pb_ent_off[q + 1] - P.pb_ent_off[q] + PB_LANES - 1) / PB_LANES; };
     std::stable_sort(P.od_pb.begin(), P.od_pb.end(), [&](int32_t a, int32_t b) { return rounds(a) > rounds(b); });
     P.pb_bsr.resize(NPB);
     P.pb_bsr_t.resize(NPB);

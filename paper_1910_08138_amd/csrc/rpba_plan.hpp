@@ -20,6 +20,7 @@ namespace rpba {
 constexpr int INT_WG = 128;        // points per intersection workgroup
 constexpr int INT_CAM_CAP = 192;   // cameras staged in LDS per intersection workgroup
 constexpr int INT_OBS_CAP = 768;   // observations staged in LDS per intersection workgroup
+constexpr int PB_LANES = 8;        // lanes per off-diagonal pair block in the pair Schur pass
 // intersection observation code: camera slot in the workgroup's LDS list, or
 // with PM_GLOBAL the camera index itself; PM_DOWN = robust down-weighting;
 // PM_LAST = last observation of its copy (the copies of a point follow each
@@ -71,7 +72,7 @@ struct Plan {
   std::vector<int32_t> pb_row;         // [NPB] internal camera i
   std::vector<int64_t> pb_ent_off;     // [NPB+1]
   std::vector<int32_t> pb_ent;         // [3 * entries] (copy, t1, t2): t = the observation's position in cam_obs
-  std::vector<int32_t> od_pb;          // off-diagonal pair blocks (i2 != i), most 16-lane rounds first
+  std::vector<int32_t> od_pb;          // off-diagonal pair blocks (i2 != i), most lane-group rounds first
   std::vector<int32_t> pb_bsr;         // [NPB] position of block (i, i2) in the full block-sparse matrix
   std::vector<int32_t> pb_bsr_t;       // [NPB] position of block (i2, i)
 

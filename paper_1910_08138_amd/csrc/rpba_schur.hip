@@ -18,6 +18,7 @@
 // solved iteratively.
 #include "rpba_device.hpp"
 #include "rpba_internal.hpp"
+#include "rpba_plan.hpp"
 
 namespace rpba {
 
@@ -94,10 +95,10 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-template <typename T>
-__device__ __forceinline__ T group16_sum(T v) {
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
   return v;
 }
 
@@ -307,12 +308,12 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
   }
 }
 
-// One 16-lane group per off-diagonal pair block (i, i2), i2 < i in the sub-block.
+// One PB_LANES-lane group per off-diagonal pair block (i, i2), i2 < i in the sub-block.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
-  const int gl = threadIdx.x & 15;
-  const int64_t t = (int64_t)blockIdx.x * (NT / 16) + (threadIdx.x >> 4);
-  if (t >= d.n_od) return;  // uniform over the 16-lane group
+  const int gl = threadIdx.x & (PB_LANES - 1);
+  const int64_t t = (int64_t)blockIdx.x * (NT / PB_LANES) + (threadIdx.x / PB_LANES);
+  if (t >= d.n_od) return;  // uniform over the lane group
   const int q = d.od_pb[t];
   const int i1 = d.pb_row[q];
   const int l = d.cam_blk[i1];
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
   T acc[36];
 #pragma unroll
   for (int u = 0; u < 36; ++u) acc[u] = T(0);
-  for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += 16) {
+  for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += PB_LANES) {
     const int c = d.pb_ent[3 * e], t1 = d.pb_ent[3 * e + 1], t2 = d.pb_ent[3 * e + 2];
     ObsIn<T> o;
     obs_in_load<T, false>(d, t1, c, true, o);
@@ -344,12 +345,12 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
       for (int s = 0; s < 6; ++s) acc[6 * r + s] -= Z1[r][0] * Y2[s][0] + Z1[r][1] * Y2[s][1] + Z1[r][2] * Y2[s][2];
   }
 #pragma unroll
-  for (int u = 0; u < 36; ++u) acc[u] = group16_sum(acc[u]);
+  for (int u = 0; u < 36; ++u) acc[u] = group_sum<PB_LANES>(acc[u]);
   const int a1 = i1 - base;
   const bool sparse = d.blk_pcg && d.blk_pcg[l];
 #pragma unroll
   for (int u = 0; u < 36; ++u) {
-    if ((u & 15) != gl) continue;
+    if ((u & (PB_LANES - 1)) != gl) continue;
     const int r = u / 6, s = u % 6;
     if (sparse) {
       d.bsr[(int64_t)d.pb_bsr[q] * 36 + u] = (float)acc[u];
@@ -375,7 +376,7 @@ void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, h
 }
 
 void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st) {
-  const unsigned go = (unsigned)((d.n_od + 15) / 16);
+  const unsigned go = (unsigned)((d.n_od + NT / PB_LANES - 1) / (NT / PB_LANES));
   if (!go) return;
   if (fp32) hipLaunchKernelGGL(k_schur_offdiag<float>, dim3(go), dim3(NT), 0, st, d);
   else hipLaunchKernelGGL(k_schur_offdiag<double>, dim3(go), dim3(NT), 0, st, d);
