@@ -504,9 +504,12 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
       }
     // dataflow task list, ordered by the length of the chain of diagonal
     // tiles still ahead (nt - j, longest first), then by column, sub-block
-    // and row: the largest sub-blocks' critical tiles are taken first, and
-    // inside a sub-block every dependency of tile (i, j) (tiles (i,k), (j,k),
-    // k < j, and (j,j)) still comes earlier
+    // and row: the largest sub-blocks' critical tiles are taken first.  The
+    // diagonal tile (c, c), c > 0, is listed in column c - 1 right after the
+    // tile (c, c - 1) it waits for last, so it is taken early enough to sum
+    // its c products while column c - 1 is still being factored.  Inside a
+    // sub-block every dependency of tile (i, j) (tiles (i,k), (j,k), k < j,
+    // and (j,j)) still comes earlier.
     std::vector<int32_t> dense;
     for (int l = 0; l < p.L; ++l)
       if (!h->blk_pcg[l]) dense.push_back(l);
@@ -515,7 +518,10 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
     for (int l : dense)
       for (int j = 0; j < p.nt[l]; ++j)
         for (int i = j; i <= p.nt[l]; ++i)
-          keyed.push_back({{-(p.nt[l] - j), j, l, i}, (l << 16) | (i << 8) | j});
+          if (i == j && j > 0)
+            keyed.push_back({{-(p.nt[l] - j + 1), j - 1, l, 2 * i + 1}, (l << 16) | (i << 8) | j});
+          else
+            keyed.push_back({{-(p.nt[l] - j), j, l, 2 * i}, (l << 16) | (i << 8) | j});
     std::sort(keyed.begin(), keyed.end());
     tmp.clear();
     for (auto& kv : keyed) tmp.push_back(kv.second);
