@@ -502,29 +502,12 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
         h->any_dense = true;
         h->nt_max_dense = std::max(h->nt_max_dense, p.nt[l]);
       }
-    // dataflow task list, ordered by the length of the chain of diagonal
-    // tiles still ahead (nt - j, longest first), then by column, sub-block
-    // and row: the largest sub-blocks' critical tiles are taken first.  The
-    // diagonal tile (c, c), c > 0, is listed in column c - 1 right after the
-    // tile (c, c - 1) it waits for last, so it is taken early enough to sum
-    // its c products while column c - 1 is still being factored.  Inside a
-    // sub-block every dependency of tile (i, j) (tiles (i,k), (j,k), k < j,
-    // and (j,j)) still comes earlier.
+    // dataflow task list (see dataflow_order)
     std::vector<int32_t> dense;
     for (int l = 0; l < p.L; ++l)
       if (!h->blk_pcg[l]) dense.push_back(l);
-    std::stable_sort(dense.begin(), dense.end(), [&](int a, int b) { return p.nt[a] > p.nt[b]; });
-    std::vector<std::pair<std::array<int32_t, 4>, int32_t>> keyed;
-    for (int l : dense)
-      for (int j = 0; j < p.nt[l]; ++j)
-        for (int i = j; i <= p.nt[l]; ++i)
-          if (i == j && j > 0)
-            keyed.push_back({{-(p.nt[l] - j + 1), j - 1, l, 2 * i + 1}, (l << 16) | (i << 8) | j});
-          else
-            keyed.push_back({{-(p.nt[l] - j), j, l, 2 * i}, (l << 16) | (i << 8) | j});
-    std::sort(keyed.begin(), keyed.end());
-    tmp.clear();
-    for (auto& kv : keyed) tmp.push_back(kv.second);
+    tmp = dataflow_order(p.nt, dense);
+    if (tmp.empty() && !dense.empty()) return fail(RPBA_ERR_ARG, "internal: the dataflow task order is not topological");
     h->df_ntask = (int32_t)tmp.size();
     if (!tmp.empty()) HIP_TRY(up(m.df_tasks, tmp.data(), 4 * tmp.size()));
     // backward tasks: tile rows from the last one down

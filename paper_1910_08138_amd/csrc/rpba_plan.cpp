@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <queue>
+#include <tuple>
 
 namespace rpba {
 
@@ -389,6 +391,79 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
   P.blk_pcg.assign(L, 0);
   P.key = topology_key(M, N, K, L, obs_cam, obs_pt, cam_block, tile);
   return "";
+}
+
+// Workgroups take the tasks in list order, and a task holds its workgroup
+// from the moment it is taken: it sums its j tile products as their inputs
+// appear, then factors the diagonal tile or, below the diagonal, waits for
+// the diagonal tile and solves.  The tiles on the chain diagonal (j) ->
+// panel (j + 1, j) -> diagonal (j + 1) set the length of the launch, and each
+// of them sums j products before its last input arrives, so a good order
+// takes every task at about the latest time that still lets it finish when
+// the chain needs it: finish time = depth on the chain (diagonal (j) at 2j,
+// tiles below it at 2j + 1, the chains of all sub-blocks ending together)
+// times the half-column time, start = finish - own work.  Tasks are released
+// in that order, each only after its dependencies (Kahn's algorithm), so a
+// task never waits for a task further down the list and the launch cannot
+// deadlock.  The costs are measured per-task times of the 64-wide tiles, in
+// microseconds; only their ratios matter.
+std::vector<int32_t> dataflow_order(const std::vector<int32_t>& nt, const std::vector<int32_t>& blocks) {
+  constexpr double kHalfColumn = 14.0, kProduct = 3.0, kFactor = 17.0, kSolve = 5.0;
+  struct Task {
+    int32_t l, i, j;
+  };
+  std::vector<Task> tasks;
+  std::vector<int64_t> base(blocks.size() + 1, 0);
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    const int64_t n = nt[blocks[b]];
+    base[b + 1] = base[b] + n * (n + 1) / 2 + n;  // lower triangle + right-hand-side row
+  }
+  // index of tile (i, j) of the b-th listed sub-block: rows 0 .. n, row i
+  // holding columns 0 .. min(i, n - 1)
+  auto id = [&](size_t b, int32_t i, int32_t j) { return base[b] + (int64_t)i * (i + 1) / 2 + j; };
+  const int64_t ntask = base.back();
+  tasks.resize(ntask);
+  std::vector<double> prio(ntask);
+  std::vector<int32_t> indeg(ntask, 0);
+  std::vector<std::vector<int64_t>> users(ntask);
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    const int32_t l = blocks[b], n = nt[l];
+    for (int32_t j = 0; j < n; ++j)
+      for (int32_t i = j; i <= n; ++i) {
+        const int64_t t = id(b, i, j);
+        tasks[t] = {l, i, j};
+        const int depth = i == j ? 2 * j : 2 * j + 1;
+        prio[t] = (depth - (2 * n - 1)) * kHalfColumn - (j * kProduct + (i == j ? kFactor : kSolve));
+        for (int32_t k = 0; k < j; ++k) {
+          users[id(b, i, k)].push_back(t);
+          if (i != j) users[id(b, j, k)].push_back(t);
+        }
+        if (i != j) users[id(b, j, j)].push_back(t);
+        indeg[t] = i == j ? j : 2 * j + 1;
+      }
+  }
+  using Key = std::tuple<double, int32_t, int32_t, int32_t, int64_t>;
+  std::priority_queue<Key, std::vector<Key>, std::greater<Key>> ready;
+  for (int64_t t = 0; t < ntask; ++t)
+    if (indeg[t] == 0) ready.push({prio[t], tasks[t].l, tasks[t].j, tasks[t].i, t});
+  std::vector<int32_t> out;
+  out.reserve(ntask);
+  std::vector<int64_t> pos(ntask, -1);
+  while (!ready.empty()) {
+    const int64_t t = std::get<4>(ready.top());
+    ready.pop();
+    pos[t] = (int64_t)out.size();
+    out.push_back((tasks[t].l << 16) | (tasks[t].i << 8) | tasks[t].j);
+    for (int64_t u : users[t])
+      if (--indeg[u] == 0) ready.push({prio[u], tasks[u].l, tasks[u].j, tasks[u].i, u});
+  }
+  // every dependency strictly earlier
+  bool ok = (int64_t)out.size() == ntask;
+  for (int64_t t = 0; ok && t < ntask; ++t)
+    for (int64_t u : users[t])
+      if (pos[t] < 0 || pos[t] >= pos[u]) ok = false;
+  if (!ok) out.clear();
+  return out;
 }
 
 }  // namespace rpba

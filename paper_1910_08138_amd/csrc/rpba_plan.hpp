@@ -112,4 +112,12 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
 uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
                       const int32_t* cam_block, int32_t tile);
 
+// Task list of the persistent forward factorisation: every tile (i, j),
+// j <= i <= nt, j < nt, of the listed sub-blocks, packed (l << 16) | (i << 8)
+// | j.  Tile (i, j) waits for the tiles (i, k) and (j, k), k < j, and for
+// i > j for the diagonal tile (j, j); the list is a topological order of
+// these dependencies (checked before it is returned: an empty list means a
+// broken order).
+std::vector<int32_t> dataflow_order(const std::vector<int32_t>& nt, const std::vector<int32_t>& blocks);
+
 }  // namespace rpba
