@@ -133,8 +133,9 @@ __device__ __forceinline__ double* tile_ptr(const Dev& d, int l, int i, int j) {
 // column block kb one wave factors the whole panel below the diagonal
 // (lane = row; the pivot is broadcast with readlane, the rest of the step's
 // column through one LDS store and broadcast reads, which keeps the scalar
-// registers free) and the trailing blocks are updated on the matrix cores.  Afterwards each wave inverts one 16 x 16 diagonal factor block (lane
-// = column, forward substitution) and the inverse of the whole factor is
+// registers free and the round trip off the chain of pivots) and the trailing blocks are updated on the matrix cores.  The
+// 16 x 16 diagonal factor blocks are inverted by one wave each (lane =
+// column, forward substitution) and the inverse of the whole factor is
 // assembled block row by block row:
 //   Linv(i,i) = D_i^-1,  Linv(i,j) = -D_i^-1 sum_{k=j}^{i-1} L(i,k) Linv(k,j).
 template <int T>
@@ -174,11 +175,15 @@ __device__ __forceinline__ void factor_panel(DiagLds<T>& sm, int o) {
 #pragma unroll
   for (int c = 0; c < 16; ++c) a[c] = sm.A[row * LD + o + c];
   // the step's column goes to the other rows through LDS (the wave's own
-  // stores are seen by its later loads), one broadcast read per element
+  // stores are seen by its later loads), one broadcast read per element.
+  // The next pivot does not wait for that round trip: lane c + 1 updates its
+  // own diagonal entry with its own column value, and the pivot is read from
+  // there while the broadcast reads are in flight.
   double* colb = sm.Y[0];
+  double piv = bcast(a[0], 0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    double dcc = bcast(a[c], c);
+    double dcc = piv;
     if (!(dcc > 0.0)) {  // uniform: no divergence
       if (lane == 0) sm.fail = 1;
       dcc = 1.0;
@@ -188,6 +193,7 @@ __device__ __forceinline__ void factor_panel(DiagLds<T>& sm, int o) {
     const double colv = lane > c ? a[c] * ip : (lane == c ? dcc * ip : 0.0);
     a[c] = colv;
     if (c < 15) {
+      piv = bcast(a[c + 1] - colv * colv, c + 1);
       colb[lane] = colv;
 #pragma unroll
       for (int s2 = c + 1; s2 < 16; ++s2) a[s2] -= colv * colb[s2];
@@ -266,15 +272,41 @@ __device__ __forceinline__ void st16(double* P, int pr, int pc, v4d v, bool neg)
   for (int e = 0; e < 4; ++e) P[(pr + (lane >> 4) + 4 * e) * LD + pc + (lane & 15)] = neg ? -v[e] : v[e];
 }
 
+// block (r, j), j < r, of the inverse of the factor, from the blocks of the
+// rows above it and the inverse diagonal block of row r:
+//   Linv(r,j) = -D_r^-1 sum_{k=j}^{r-1} L(r,k) Linv(k,j)   (one wave)
+template <int T>
+__device__ __forceinline__ void inverse_block(DiagLds<T>& sm, int r, int j) {
+  constexpr int LD = DiagLds<T>::LD;
+  const int wv = threadIdx.x >> 6;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k = j; k < r; ++k) acc = mf16_nn<LD, LD>(sm.A, 16 * r, 16 * k, sm.X, 16 * k, 16 * j, acc);
+  st16<17>(sm.Y[wv], 0, 0, acc, false);
+  v4d y = {0.0, 0.0, 0.0, 0.0};
+  y = mf16_nn<LD, 17>(sm.X, 16 * r, 16 * r, sm.Y[wv], 0, 0, y);
+  st16<LD>(sm.X, 16 * r, 16 * j, y, true);
+}
+
 // Factor sm.A (T x T, lower part used) and leave L^-1 in sm.X (lower blocks
 // valid, diagonal blocks lower triangular).  All threads of the workgroup.
+// Wave 0 factors the 16-wide panels one after the other; while it does, the
+// other waves build the inverse of what is already factored: wave 1 inverts
+// the diagonal block of the previous panel, waves 2 and 3 the block row two
+// panels back (it needs that row's inverted diagonal block).  What is left at
+// the end is the last diagonal block and the last two block rows.
 template <int T>
 __device__ void factor_inverse_tile(DiagLds<T>& sm) {
   constexpr int LD = DiagLds<T>::LD, NBK = T / 16;
   const int wv = threadIdx.x >> 6;
   for (int kb = 0; kb < NBK; ++kb) {
     const int o = 16 * kb;
-    if (wv == 0) factor_panel<T>(sm, o);
+    if (wv == 0) {
+      factor_panel<T>(sm, o);
+    } else if (wv == 1) {
+      if (kb >= 1) invert16<T>(sm, o - 16);
+    } else {
+      for (int j = wv - 2; j < kb - 2; j += 2) inverse_block<T>(sm, kb - 2, j);
+    }
     __syncthreads();
     // trailing update A(ib,jb) -= L(ib,kb) L(jb,kb)^T, kb < jb <= ib
     const int m = NBK - 1 - kb;
@@ -291,20 +323,14 @@ __device__ void factor_inverse_tile(DiagLds<T>& sm) {
       __syncthreads();
     }
   }
-  for (int kb = wv; kb < NBK; kb += 4) invert16<T>(sm, 16 * kb);
-  __syncthreads();
-  // inverse, block row by block row
-  for (int i = 1; i < NBK; ++i) {
-    for (int j = wv; j < i; j += 4) {
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-      for (int k = j; k < i; ++k) acc = mf16_nn<LD, LD>(sm.A, 16 * i, 16 * k, sm.X, 16 * k, 16 * j, acc);
-      st16<17>(sm.Y[wv], 0, 0, acc, false);
-      v4d y = {0.0, 0.0, 0.0, 0.0};
-      y = mf16_nn<LD, 17>(sm.X, 16 * i, 16 * i, sm.Y[wv], 0, 0, y);
-      st16<LD>(sm.X, 16 * i, 16 * j, y, true);
-    }
-    __syncthreads();
+  if (wv == 0) {
+    invert16<T>(sm, 16 * (NBK - 1));
+  } else {
+    for (int j = wv - 1; j < NBK - 2; j += 3) inverse_block<T>(sm, NBK - 2, j);
   }
+  __syncthreads();
+  for (int j = wv; j < NBK - 1; j += 4) inverse_block<T>(sm, NBK - 1, j);
+  __syncthreads();
 }
 
 // Diagonal tile of step k: the inverse of its Cholesky factor (the factor
