@@ -179,26 +179,37 @@ __device__ __forceinline__ void factor_panel(DiagLds<T>& sm, int o) {
   // The next pivot does not wait for that round trip: lane c + 1 updates its
   // own diagonal entry with its own column value, and the pivot is read from
   // there while the broadcast reads are in flight.
+  // The sixteen steps have no branches (a failed pivot and the reciprocal
+  // pivots are recorded with selects and stored afterwards), and each step
+  // computes the next pivot while its column broadcast is in flight.
   double* colb = sm.Y[0];
   double piv = bcast(a[0], 0);
+  bool bad = !(piv > 0.0);
+  double dcc = bad ? 1.0 : piv;
+  double ip = rsqrt_nr(dcc);
+  double myip = 0.0;  // lane c: 1 / L(o + c, o + c)
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    double dcc = piv;
-    if (!(dcc > 0.0)) {  // uniform: no divergence
-      if (lane == 0) sm.fail = 1;
-      dcc = 1.0;
-    }
-    const double ip = rsqrt_nr(dcc);
-    if (lane == 0) sm.ipv[o + c] = ip;
+    myip = lane == c ? ip : myip;
     const double colv = lane > c ? a[c] * ip : (lane == c ? dcc * ip : 0.0);
     a[c] = colv;
     if (c < 15) {
-      piv = bcast(a[c + 1] - colv * colv, c + 1);
+      const double dn = a[c + 1] - colv * colv;
       colb[lane] = colv;
+      double cb[16];
 #pragma unroll
-      for (int s2 = c + 1; s2 < 16; ++s2) a[s2] -= colv * colb[s2];
+      for (int s2 = c + 1; s2 < 16; ++s2) cb[s2] = colb[s2];
+      piv = bcast(dn, c + 1);
+      const bool nonpos = !(piv > 0.0);  // uniform
+      bad = bad || nonpos;
+      dcc = nonpos ? 1.0 : piv;
+      ip = rsqrt_nr(dcc);
+#pragma unroll
+      for (int s2 = c + 1; s2 < 16; ++s2) a[s2] -= colv * cb[s2];
     }
   }
+  if (lane < 16) sm.ipv[o + lane] = myip;
+  if (bad && lane == 0) sm.fail = 1;
   if (live) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) sm.A[row * LD + o + c] = a[c];
