@@ -184,9 +184,11 @@ const char *rpba_last_error(void);
  *   index, X^l [n][3] and Omega [n][6]; any pointer may be NULL.
  * rpba_get_block_rcs: assembles the reduced camera system of every sub-block at
  *   the current state (as an LM step would, without solving) and copies S of
- *   sub-block l (n6 x n6 row-major; the lower triangle for Cholesky
- *   sub-blocks, both triangles of the stored FP32 blocks for iterative ones)
- *   and e; n6 = 6 cameras of l, cameras in ascending original index.
+ *   sub-block l (n6 x n6 row-major, both triangles: the mirrored lower
+ *   triangle for Cholesky sub-blocks, the stored FP32 blocks for iterative
+ *   ones) and e; n6 = 6 cameras of l, cameras in ascending original index
+ *   (the library orders the cameras of a sub-block by its own rule and
+ *   reorders the copy).
  * rpba_block_cameras: number of cameras of sub-block l. */
 int64_t rpba_num_copies(rpba_problem *h);
 rpba_status rpba_get_copies(rpba_problem *h, int32_t *blk, int32_t *pt, double *X, double *omega);
@@ -194,7 +196,8 @@ rpba_status rpba_set_debug(rpba_problem *h, int32_t on);
 rpba_status rpba_get_block_rcs(rpba_problem *h, int32_t l, double *S, double *e);
 int32_t rpba_block_cameras(rpba_problem *h, int32_t l);
 /* rpba_get_block_solution: the camera step (n6 values) of sub-block l from the
- * last rpba_subblock_lm_step.  rpba_block_solver: 0 = Cholesky, 1 = iterative. */
+ * last rpba_subblock_lm_step, cameras in ascending original index.
+ * rpba_block_solver: 0 = Cholesky, 1 = iterative. */
 rpba_status rpba_get_block_solution(rpba_problem *h, int32_t l, double *x);
 int32_t rpba_block_solver(rpba_problem *h, int32_t l);
 

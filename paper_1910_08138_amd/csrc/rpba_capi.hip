@@ -45,7 +45,7 @@ struct Layout {
 
 // byte offsets of every workspace array
 struct WsMap {
-  size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_new, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
+  size_t cam_blk, blk_cam_off, cam_orig, pt_orig, pt_new, tile_nz, pt_copy_off, pt_copies, obs_cam, obs_copy, obs_orig, cam_obs_off,
       cam_obs, copy_off, copy_pt, copy_blk, blk_copy_off, nb_off, nb_cam, nt, rcs_off, diag_off, vec_off, fwd_items,
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
@@ -95,6 +95,7 @@ WsMap layout_for(const Plan& P) {
   m.nb_cam = L.add(i4 * P.nb_cam.size());
   m.nt = L.add(i4 * P.L);
   m.rcs_off = L.add(i8 * P.L);
+  m.tile_nz = L.add(P.tile_nz.size());
   m.diag_off = L.add(i8 * P.L);
   m.vec_off = L.add(i8 * P.L);
   m.fwd_items = L.add(i4 * P.fwd_items.size());
@@ -418,6 +419,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.nb_cam, p.nb_cam.data(), 4 * p.nb_cam.size()));
   HIP_TRY(up(m.nt, p.nt.data(), 4 * p.nt.size()));
   HIP_TRY(up(m.rcs_off, p.rcs_off.data(), 8 * p.rcs_off.size()));
+  HIP_TRY(up(m.tile_nz, p.tile_nz.data(), p.tile_nz.size()));
   HIP_TRY(up(m.diag_off, p.diag_off.data(), 8 * p.diag_off.size()));
   HIP_TRY(up(m.vec_off, p.vec_off.data(), 8 * p.vec_off.size()));
   HIP_TRY(up(m.pb_row, p.pb_row.data(), 4 * p.pb_row.size()));
@@ -506,7 +508,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
     std::vector<int32_t> dense;
     for (int l = 0; l < p.L; ++l)
       if (!h->blk_pcg[l]) dense.push_back(l);
-    tmp = dataflow_order(p.nt, dense);
+    tmp = dataflow_order(p, dense);
     if (tmp.empty() && !dense.empty()) return fail(RPBA_ERR_ARG, "internal: the dataflow task order is not topological");
     h->df_ntask = (int32_t)tmp.size();
     if (!tmp.empty()) HIP_TRY(up(m.df_tasks, tmp.data(), 4 * tmp.size()));
@@ -616,6 +618,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.x = F(m.x);
   D.nt = I(m.nt);
   D.rcs_off = (const int64_t*)(w + m.rcs_off);
+  D.tile_nz = (const uint8_t*)(w + m.tile_nz);
   D.diag_off = (const int64_t*)(w + m.diag_off);
   D.vec_off = (const int64_t*)(w + m.vec_off);
   D.blk_fail = I(m.blk_fail);
@@ -872,9 +875,20 @@ rpba_status rpba_get_copies(rpba_problem* h, int32_t* blk, int32_t* pt, double* 
   return RPBA_OK;
 }
 
-// S of sub-block l assembled at the current state (cameras of l in ascending
-// original index = internal order within the sub-block).  Runs the assembly
-// kernels of an LM step without solving.
+// caller rank (position in ascending original index) of each internal camera
+// position of sub-block l
+static std::vector<int32_t> block_caller_rank(const Plan& p, int32_t l) {
+  const int32_t b = p.blk_cam_off[l], n = p.blk_cam_off[l + 1] - b;
+  std::vector<int32_t> q(n), rank(n);
+  for (int32_t a = 0; a < n; ++a) q[a] = a;
+  std::sort(q.begin(), q.end(), [&](int32_t x, int32_t y) { return p.cam_orig[b + x] < p.cam_orig[b + y]; });
+  for (int32_t r = 0; r < n; ++r) rank[q[r]] = r;
+  return rank;
+}
+
+// S of sub-block l assembled at the current state, rows and columns in the
+// caller's camera order (the library keeps its own order inside a
+// sub-block).  Runs the assembly kernels of an LM step without solving.
 rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   const Plan& p = *h->plan;
@@ -898,8 +912,21 @@ rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e)
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(h->stream));
-  if (S) HIP_TRY(hipMemcpy(S, stage, 8 * (size_t)n6 * n6, hipMemcpyDeviceToHost));
-  if (e) HIP_TRY(hipMemcpy(e, stage + (size_t)n6 * n6, 8 * (size_t)n6, hipMemcpyDeviceToHost));
+  std::vector<double> Si((size_t)n6 * n6), ei(n6);
+  HIP_TRY(hipMemcpy(Si.data(), stage, 8 * (size_t)n6 * n6, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ei.data(), stage + (size_t)n6 * n6, 8 * (size_t)n6, hipMemcpyDeviceToHost));
+  // a Cholesky sub-block stores its lower triangle only: mirror it before
+  // the reordering moves entries across the diagonal
+  if (!h->blk_pcg[l])
+    for (int r = 0; r < n6; ++r)
+      for (int c = r + 1; c < n6; ++c) Si[(size_t)r * n6 + c] = Si[(size_t)c * n6 + r];
+  const std::vector<int32_t> rank = block_caller_rank(p, l);
+  auto to = [&](int r) { return 6 * rank[r / 6] + r % 6; };
+  if (S)
+    for (int r = 0; r < n6; ++r)
+      for (int c = 0; c < n6; ++c) S[(size_t)to(r) * n6 + to(c)] = Si[(size_t)r * n6 + c];
+  if (e)
+    for (int r = 0; r < n6; ++r) e[to(r)] = ei[r];
   return RPBA_OK;
 }
 
@@ -909,7 +936,10 @@ rpba_status rpba_get_block_solution(rpba_problem* h, int32_t l, double* x) {
   if (l < 0 || l >= p.L) return fail(RPBA_ERR_ARG, "sub-block out of range");
   int n6 = 6 * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
   HIP_TRY(hipStreamSynchronize(h->stream));
-  HIP_TRY(hipMemcpy(x, h->d.x + p.vec_off[l], 8 * (size_t)n6, hipMemcpyDeviceToHost));
+  std::vector<double> xi(n6);
+  HIP_TRY(hipMemcpy(xi.data(), h->d.x + p.vec_off[l], 8 * (size_t)n6, hipMemcpyDeviceToHost));
+  const std::vector<int32_t> rank = block_caller_rank(p, l);
+  for (int r = 0; r < n6; ++r) x[6 * rank[r / 6] + r % 6] = xi[r];
   return RPBA_OK;
 }
 

@@ -562,12 +562,15 @@ __device__ __forceinline__ void df_publish(int* f, int epoch) {
 
 // wave 0 checks the flags of columns k .. min(j, k + 64) - 1 of tile rows
 // r1 and r2 (r2 < 0: r1 only) at once; returns (to every thread) the first
-// column that is not ready yet, or j
-__device__ __forceinline__ int df_poll(const int* row1, const int* row2, int k, int j, int epoch, int* sh) {
+// column that is not ready yet, or j.  A column whose product has a tile
+// that stays zero (nz1, nz2: the rows' nonzero-tile flags) counts as ready.
+__device__ __forceinline__ int df_poll(const int* row1, const int* row2, const uint8_t* nz1, const uint8_t* nz2, int k,
+                                       int j, int epoch, int* sh) {
   if (threadIdx.x < 64) {
     const int kk = k + threadIdx.x;
     bool ready = true;
-    if (kk < j) ready = df_flag_load(row1 + kk) == epoch && (row2 == nullptr || df_flag_load(row2 + kk) == epoch);
+    if (kk < j && nz1[kk] && nz2[kk])
+      ready = df_flag_load(row1 + kk) == epoch && (row2 == nullptr || df_flag_load(row2 + kk) == epoch);
     const unsigned long long not_ready = __ballot(!ready);
     if (threadIdx.x == 0) *sh = not_ready ? k + __ffsll((long long)not_ready) - 1 : min(j, k + 64);
   }
@@ -621,11 +624,15 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
           acc_rc<T>(p, q, e, r, c);
           acc.v[p][q][e] = C[mf_idx(T, r, c)];
         }
-    // tiles (i,k) and (j,k) of the row: flags of row r start at fl(r, 0)
+    // tiles (i,k) and (j,k) of the row: flags of row r start at fl(r, 0);
+    // products with a tile that stays zero are left out
+    const uint8_t* nzi = d.tile_nz + tile0 + (int64_t)i * (i + 1) / 2;
+    const uint8_t* nzj = d.tile_nz + tile0 + (int64_t)j * (j + 1) / 2;
     int kready = 0;  // every k < kready is known to be ready
     for (int k = 0; k < j; ++k) {
+      if (!nzi[k] || !nzj[k]) continue;
       if (k >= kready) {
-        kready = df_poll(fl(i, 0), i == j ? nullptr : fl(j, 0), k, j, epoch, &s_poll);
+        kready = df_poll(fl(i, 0), i == j ? nullptr : fl(j, 0), nzi, nzj, k, j, epoch, &s_poll);
         if (kready == k) {
           df_wait(fl(i, k), i == j ? nullptr : fl(j, k), epoch, err);
           kready = k + 1;
@@ -732,7 +739,9 @@ __global__ __launch_bounds__(NT) void k_chol_backward_df(Dev d, const int32_t* _
       li[q] = m >= r ? Li[mf_idx(T, m, r)] : 0.0;
     }
     double zr = 0.0;  // this thread's share of the update of z[r]
+    const uint8_t* nz = d.tile_nz + d.rcs_off[l] / (T * T);
     for (int m = nt - 1; m > k; --m) {
+      if (!nz[(int64_t)m * (m + 1) / 2 + k]) continue;  // L(m,k) stays zero
       // the tile L(m,k) does not depend on x_m: load it before waiting
       const double* Lmk = tile_ptr<T>(d, l, m, k);
       double lv[T / P];

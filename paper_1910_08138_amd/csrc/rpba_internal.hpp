@@ -107,6 +107,7 @@ struct Dev {
   double* x;              // solution (camera steps)
   const int32_t* nt;
   const int64_t* rcs_off;
+  const uint8_t* tile_nz;  // [rcs_total / T^2] tile of the factor may be nonzero (plan's numbering)
   const int64_t* diag_off;
   const int64_t* vec_off;
   int32_t* blk_fail;      // [L]

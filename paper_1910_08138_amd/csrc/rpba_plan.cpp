@@ -9,6 +9,82 @@
 
 namespace rpba {
 
+namespace {
+
+// Position of every camera inside its sub-block: reverse Cuthill-McKee order
+// of the sub-block's co-visibility graph (two cameras are adjacent if they
+// observe a common point).  Neighbouring cameras get neighbouring positions,
+// so the reduced camera system of the sub-block has its nonzero 6 x 6 blocks
+// in a band and its Cholesky factor stays zero outside that band.  Each
+// connected part starts at an unvisited camera of least degree; neighbours
+// are taken by ascending degree, then by caller order.
+std::vector<int32_t> covisibility_rcm(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam,
+                                      const int32_t* obs_pt, const int32_t* cam_block, const std::vector<int32_t>& loc,
+                                      const std::vector<int32_t>& blk_cam_off) {
+  // adjacency bit matrices, one per sub-block, indexed by loc
+  std::vector<int64_t> mat_off(L + 1, 0);
+  for (int32_t l = 0; l < L; ++l) {
+    const int64_t n = blk_cam_off[l + 1] - blk_cam_off[l];
+    mat_off[l + 1] = mat_off[l] + n * ((n + 63) / 64);
+  }
+  std::vector<uint64_t> adj(mat_off[L], 0);
+  auto words = [&](int32_t l) { return (int64_t)(blk_cam_off[l + 1] - blk_cam_off[l] + 63) / 64; };
+  {
+    std::vector<int32_t> off(N + 1, 0), cams(K);
+    for (int32_t k = 0; k < K; ++k) off[obs_pt[k] + 1]++;
+    for (int32_t j = 0; j < N; ++j) off[j + 1] += off[j];
+    std::vector<int32_t> at(off.begin(), off.end() - 1);
+    for (int32_t k = 0; k < K; ++k) cams[at[obs_pt[k]]++] = obs_cam[k];
+    for (int32_t j = 0; j < N; ++j)
+      for (int32_t a = off[j]; a < off[j + 1]; ++a)
+        for (int32_t b = off[j]; b < off[j + 1]; ++b) {
+          const int32_t ca = cams[a], cb = cams[b];
+          if (a == b || cam_block[ca] != cam_block[cb]) continue;
+          const int32_t l = cam_block[ca];
+          adj[mat_off[l] + loc[ca] * words(l) + loc[cb] / 64] |= 1ull << (loc[cb] % 64);
+        }
+  }
+  std::vector<int32_t> pos(M);
+  std::vector<int32_t> blk_cam(M);  // caller index by (sub-block, loc)
+  for (int32_t i = 0; i < M; ++i) blk_cam[blk_cam_off[cam_block[i]] + loc[i]] = i;
+  for (int32_t l = 0; l < L; ++l) {
+    const int32_t n = blk_cam_off[l + 1] - blk_cam_off[l];
+    const int64_t W = words(l);
+    const uint64_t* A = adj.data() + mat_off[l];
+    std::vector<int32_t> deg(n, 0), order, nb;
+    for (int32_t u = 0; u < n; ++u)
+      for (int64_t w = 0; w < W; ++w) deg[u] += __builtin_popcountll(A[u * W + w]);
+    std::vector<char> seen(n, 0);
+    order.reserve(n);
+    while ((int32_t)order.size() < n) {
+      int32_t s0 = -1;
+      for (int32_t u = 0; u < n; ++u)
+        if (!seen[u] && (s0 < 0 || deg[u] < deg[s0])) s0 = u;
+      seen[s0] = 1;
+      size_t head = order.size();
+      order.push_back(s0);
+      while (head < order.size()) {
+        const int32_t u = order[head++];
+        nb.clear();
+        for (int64_t w = 0; w < W; ++w)
+          for (uint64_t bits = A[u * W + w]; bits; bits &= bits - 1) {
+            const int32_t v = (int32_t)(w * 64 + __builtin_ctzll(bits));
+            if (!seen[v]) nb.push_back(v);
+          }
+        std::sort(nb.begin(), nb.end(), [&](int32_t x, int32_t y) { return deg[x] != deg[y] ? deg[x] < deg[y] : x < y; });
+        for (int32_t v : nb) {
+          seen[v] = 1;
+          order.push_back(v);
+        }
+      }
+    }
+    for (int32_t q = 0; q < n; ++q) pos[blk_cam[blk_cam_off[l] + order[n - 1 - q]]] = q;
+  }
+  return pos;
+}
+
+}  // namespace
+
 uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
                       const int32_t* cam_block, int32_t tile) {
   // FNV-1a over sizes and the three index arrays
@@ -66,9 +142,12 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
   P.cam_blk.resize(M);
   std::vector<int32_t> cam_new(M);
   {
-    std::vector<int32_t> fill(P.blk_cam_off.begin(), P.blk_cam_off.end() - 1);
+    // loc: rank of a camera among the cameras of its sub-block, caller order
+    std::vector<int32_t> loc(M), fill(L, 0);
+    for (int32_t i = 0; i < M; ++i) loc[i] = fill[cam_block[i]]++;
+    const std::vector<int32_t> rcm = covisibility_rcm(M, N, K, L, obs_cam, obs_pt, cam_block, loc, P.blk_cam_off);
     for (int32_t i = 0; i < M; ++i) {
-      int32_t n = fill[cam_block[i]]++;
+      const int32_t n = P.blk_cam_off[cam_block[i]] + rcm[i];
       P.cam_orig[n] = i;
       cam_new[i] = n;
       P.cam_blk[n] = cam_block[i];
@@ -350,6 +429,34 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     P.vec_off[l] = P.vec_total;
     P.vec_total += (int64_t)nt * tile;
   }
+  // tiles of each factor that can be nonzero: the tiles touched by a 6 x 6
+  // block of S (a camera's six rows may straddle two tiles), the diagonal
+  // tiles, then the fill of a Cholesky factorisation by tiles; the
+  // right-hand-side tile row is full
+  P.tile_nz.assign(P.rcs_total / T2, 0);
+  for (int32_t l = 0; l < L; ++l) {
+    const int32_t nt = P.nt[l];
+    uint8_t* z = P.tile_nz.data() + P.rcs_off[l] / T2;
+    auto at = [&](int32_t i, int32_t j) -> uint8_t& { return i >= j ? z[i * (i + 1) / 2 + j] : z[j * (j + 1) / 2 + i]; };
+    for (int32_t i = 0; i < nt; ++i) at(i, i) = 1;
+    for (int32_t j = 0; j < nt; ++j) at(nt, j) = 1;
+    for (int32_t c = P.blk_cam_off[l]; c < P.blk_cam_off[l + 1]; ++c) {
+      const int32_t a = c - P.blk_cam_off[l];
+      for (int32_t q = P.nb_off[c]; q < P.nb_off[c + 1]; ++q) {
+        const int32_t b = P.nb_cam[q];
+        for (int32_t ra : {6 * a / tile, (6 * a + 5) / tile})
+          for (int32_t rb : {6 * b / tile, (6 * b + 5) / tile}) at(ra, rb) = 1;
+      }
+    }
+    std::vector<int32_t> rows;
+    for (int32_t k = 0; k < nt; ++k) {
+      rows.clear();
+      for (int32_t i = k + 1; i < nt; ++i)
+        if (at(i, k)) rows.push_back(i);
+      for (size_t x = 0; x < rows.size(); ++x)
+        for (size_t y = 0; y <= x; ++y) at(rows[x], rows[y]) = 1;
+    }
+  }
   // larger sub-blocks first: their tiles carry the longest dependency chains
   std::vector<int32_t> order(L);
   for (int32_t l = 0; l < L; ++l) order[l] = l;
@@ -394,11 +501,12 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
 }
 
 // Workgroups take the tasks in list order, and a task holds its workgroup
-// from the moment it is taken: it sums its j tile products as their inputs
-// appear, then factors the diagonal tile or, below the diagonal, waits for
-// the diagonal tile and solves.  The tiles on the chain diagonal (j) ->
-// panel (j + 1, j) -> diagonal (j + 1) set the length of the launch, and each
-// of them sums j products before its last input arrives, so a good order
+// from the moment it is taken: it sums its tile products (k < j with both
+// tiles nonzero) as their inputs appear, then factors the diagonal tile or,
+// below the diagonal, waits for the diagonal tile and solves.  The tiles on
+// the chain diagonal (j) -> panel (j + 1, j) -> diagonal (j + 1) set the
+// length of the launch, and each of them sums its products before its last
+// input arrives, so a good order
 // takes every task at about the latest time that still lets it finish when
 // the chain needs it: finish time = depth on the chain (diagonal (j) at 2j,
 // tiles below it at 2j + 1, the chains of all sub-blocks ending together)
@@ -407,48 +515,59 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
 // task never waits for a task further down the list and the launch cannot
 // deadlock.  The costs are measured per-task times of the 64-wide tiles, in
 // microseconds; only their ratios matter.
-std::vector<int32_t> dataflow_order(const std::vector<int32_t>& nt, const std::vector<int32_t>& blocks) {
+std::vector<int32_t> dataflow_order(const Plan& P, const std::vector<int32_t>& blocks) {
   constexpr double kHalfColumn = 14.0, kProduct = 3.0, kFactor = 17.0, kSolve = 5.0;
+  const int64_t T2 = (int64_t)P.T * P.T;
   struct Task {
     int32_t l, i, j;
   };
-  std::vector<Task> tasks;
+  // task ids: the tiles of the listed sub-blocks in storage order
   std::vector<int64_t> base(blocks.size() + 1, 0);
   for (size_t b = 0; b < blocks.size(); ++b) {
-    const int64_t n = nt[blocks[b]];
-    base[b + 1] = base[b] + n * (n + 1) / 2 + n;  // lower triangle + right-hand-side row
+    const int64_t n = P.nt[blocks[b]];
+    base[b + 1] = base[b] + n * (n + 1) / 2 + n;
   }
-  // index of tile (i, j) of the b-th listed sub-block: rows 0 .. n, row i
-  // holding columns 0 .. min(i, n - 1)
   auto id = [&](size_t b, int32_t i, int32_t j) { return base[b] + (int64_t)i * (i + 1) / 2 + j; };
-  const int64_t ntask = base.back();
-  tasks.resize(ntask);
-  std::vector<double> prio(ntask);
-  std::vector<int32_t> indeg(ntask, 0);
-  std::vector<std::vector<int64_t>> users(ntask);
+  const int64_t ntile = base.back();
+  std::vector<Task> tasks(ntile);
+  std::vector<char> live(ntile, 0);
+  std::vector<double> prio(ntile);
+  std::vector<int32_t> indeg(ntile, 0);
+  std::vector<std::vector<int64_t>> users(ntile);
   for (size_t b = 0; b < blocks.size(); ++b) {
-    const int32_t l = blocks[b], n = nt[l];
+    const int32_t l = blocks[b], n = P.nt[l];
+    const uint8_t* z = P.tile_nz.data() + P.rcs_off[l] / T2;
+    auto nz = [&](int32_t i, int32_t j) { return z[i * (i + 1) / 2 + j] != 0; };
     for (int32_t j = 0; j < n; ++j)
       for (int32_t i = j; i <= n; ++i) {
+        if (!nz(i, j)) continue;
         const int64_t t = id(b, i, j);
         tasks[t] = {l, i, j};
-        const int depth = i == j ? 2 * j : 2 * j + 1;
-        prio[t] = (depth - (2 * n - 1)) * kHalfColumn - (j * kProduct + (i == j ? kFactor : kSolve));
+        live[t] = 1;
+        int32_t nprod = 0;
         for (int32_t k = 0; k < j; ++k) {
+          if (!nz(i, k) || !nz(j, k)) continue;
+          ++nprod;
           users[id(b, i, k)].push_back(t);
           if (i != j) users[id(b, j, k)].push_back(t);
         }
         if (i != j) users[id(b, j, j)].push_back(t);
-        indeg[t] = i == j ? j : 2 * j + 1;
+        indeg[t] = i == j ? nprod : 2 * nprod + 1;
+        const int depth = i == j ? 2 * j : 2 * j + 1;
+        prio[t] = (depth - (2 * n - 1)) * kHalfColumn - (nprod * kProduct + (i == j ? kFactor : kSolve));
       }
   }
   using Key = std::tuple<double, int32_t, int32_t, int32_t, int64_t>;
   std::priority_queue<Key, std::vector<Key>, std::greater<Key>> ready;
-  for (int64_t t = 0; t < ntask; ++t)
-    if (indeg[t] == 0) ready.push({prio[t], tasks[t].l, tasks[t].j, tasks[t].i, t});
+  int64_t nlive = 0;
+  for (int64_t t = 0; t < ntile; ++t)
+    if (live[t]) {
+      ++nlive;
+      if (indeg[t] == 0) ready.push({prio[t], tasks[t].l, tasks[t].j, tasks[t].i, t});
+    }
   std::vector<int32_t> out;
-  out.reserve(ntask);
-  std::vector<int64_t> pos(ntask, -1);
+  out.reserve(nlive);
+  std::vector<int64_t> pos(ntile, -1);
   while (!ready.empty()) {
     const int64_t t = std::get<4>(ready.top());
     ready.pop();
@@ -458,10 +577,10 @@ std::vector<int32_t> dataflow_order(const std::vector<int32_t>& nt, const std::v
       if (--indeg[u] == 0) ready.push({prio[u], tasks[u].l, tasks[u].j, tasks[u].i, u});
   }
   // every dependency strictly earlier
-  bool ok = (int64_t)out.size() == ntask;
-  for (int64_t t = 0; ok && t < ntask; ++t)
+  bool ok = (int64_t)out.size() == nlive;
+  for (int64_t t = 0; ok && t < ntile; ++t)
     for (int64_t u : users[t])
-      if (pos[t] < 0 || pos[t] >= pos[u]) ok = false;
+      if (!live[t] || pos[t] < 0 || pos[t] >= pos[u]) ok = false;
   if (!ok) out.clear();
   return out;
 }

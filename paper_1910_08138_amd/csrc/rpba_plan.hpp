@@ -83,6 +83,10 @@ struct Plan {
   std::vector<int64_t> vec_off;        // [L] offset of the padded vectors
   int64_t rcs_total = 0, diag_total = 0, vec_total = 0;
   int32_t nt_max = 0;
+  // [rcs_total / T^2] 1 = the tile may be nonzero in the Cholesky factor
+  // (tiles numbered like the storage: sub-block l's tile (i, j) is tile
+  // rcs_off[l] / T^2 + i (i + 1) / 2 + j); a zero tile keeps the zeros of S
+  std::vector<uint8_t> tile_nz;
   // Cholesky work lists: item = (l << 16) | (i << 8) | j.  Tile row nt of a
   // sub-block holds the right-hand side (row 0 = e^T), so that the forward
   // substitution is part of the factorisation.
@@ -118,6 +122,8 @@ uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t*
 // i > j for the diagonal tile (j, j); the list is a topological order of
 // these dependencies (checked before it is returned: an empty list means a
 // broken order).
-std::vector<int32_t> dataflow_order(const std::vector<int32_t>& nt, const std::vector<int32_t>& blocks);
+// Tiles that stay zero in the factor (tile_nz) get no task, and products with
+// a zero tile are left out of the sums and of the dependencies.
+std::vector<int32_t> dataflow_order(const Plan& P, const std::vector<int32_t>& blocks);
 
 }  // namespace rpba
