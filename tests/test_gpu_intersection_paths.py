@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+import plan_order
 from paper_1910_08138_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -43,58 +44,10 @@ def rp():
     return binding
 
 
-def _camera_order(s):
-    """Internal camera index: cameras grouped by sub-block, inside a sub-block
-    in reverse Cuthill-McKee order of the co-visibility graph (start at an
-    unvisited camera of least degree, neighbours by degree, then by caller
-    order), as the library's plan orders them."""
-    M = s.M
-    L = int(s.cam_block.max()) + 1
-    off = np.zeros(L + 1, np.int64)
-    np.add.at(off, s.cam_block + 1, 1)
-    off = np.cumsum(off)
-    members = [np.flatnonzero(s.cam_block == l) for l in range(L)]
-    loc = np.empty(M, np.int64)
-    for l in range(L):
-        loc[members[l]] = np.arange(len(members[l]))
-    adj = [dict() for _ in range(L)]
-    o = np.argsort(s.obs_pt, kind="stable")
-    pts, cams = s.obs_pt[o], s.obs_cam[o]
-    starts = np.flatnonzero(np.r_[True, pts[1:] != pts[:-1]])
-    for a, b in zip(starts, np.r_[starts[1:], len(pts)]):
-        cs = cams[a:b]
-        for ca in cs:
-            for cb in cs:
-                if ca != cb and s.cam_block[ca] == s.cam_block[cb]:
-                    adj[s.cam_block[ca]].setdefault(loc[ca], set()).add(loc[cb])
-    cam_new = np.empty(M, np.int64)
-    for l in range(L):
-        n = len(members[l])
-        nbr = [sorted(adj[l].get(u, ())) for u in range(n)]
-        deg = [len(x) for x in nbr]
-        seen = [False] * n
-        order = []
-        while len(order) < n:
-            s0 = min((u for u in range(n) if not seen[u]), key=lambda u: (deg[u], u))
-            seen[s0] = True
-            order.append(s0)
-            head = len(order) - 1
-            while head < len(order):
-                u = order[head]
-                head += 1
-                nxt = sorted((v for v in nbr[u] if not seen[v]), key=lambda v: (deg[v], v))
-                for v in nxt:
-                    seen[v] = True
-                    order.append(v)
-        for q in range(n):
-            cam_new[members[l][order[n - 1 - q]]] = off[l] + q
-    return cam_new
-
-
 def _workgroup_extent(s):
     """Largest number of cameras and of observations of one workgroup."""
     M, N = s.M, s.N
-    cam_new = _camera_order(s)
+    cam_new = plan_order.camera_order(s)
     cn = cam_new[s.obs_cam]
     first = np.full(N, M)
     np.minimum.at(first, s.obs_pt, cn)

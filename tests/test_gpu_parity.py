@@ -234,3 +234,27 @@ def test_ratio_rule_schedule(rp, graph):
     gR, gC = gp.cameras()
     oR, oC = op.cameras()
     assert np.abs(gC - oC).max() <= TOL * _extent(s)
+
+
+def test_banded_factor_skips_zero_tiles(rp):
+    """An oblique strip block whose sub-blocks (up to 330 cameras) get a
+    banded reduced camera system in the library's camera order: about a fifth
+    of the factor tiles stay zero and the persistent factorisation leaves them
+    and their products out.  A fixed schedule against the oracle."""
+    import plan_order
+    s = scenes.oblique_scene(1, n_strips=6, n_stations=40, n_pts=120_000, n_blocks=4, size_range=(150, 330))
+    tiles = plan_order.factor_tiles(s, 64)
+    nz = sum(int(z.sum()) for z in tiles)
+    dense = sum(z.shape[0] * (z.shape[0] + 1) // 2 for z in tiles)
+    assert nz <= 0.9 * dense, (nz, dense)
+    gp, gh, op, oh = _run_both(s, 2, 2, graph=True)
+    for g, o in zip(gh, oh):
+        assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0), (g["t"], g["int_stats"], o["int_stats"])
+        for bg, (bo, fails) in zip(g.get("steps", []), o.get("steps", [])):
+            assert fails == 0
+            assert np.allclose(bg[:, 0], bo[:, 0], rtol=TOL, atol=0)
+            assert np.allclose(bg[:, 1], bo[:, 1], rtol=TOL, atol=0)
+    gR, gC = gp.cameras()
+    oR, oC = op.cameras()
+    assert np.abs(gC - oC).max() <= TOL * _extent(s)
+    assert _rot_angle(gR, oR) <= TOL
