@@ -244,7 +244,7 @@ struct rpba_problem {
   std::vector<int64_t> pot_off, fwd_off, upd_off, bwd_off;
   // dataflow factorisation: task count and resident workers
   bool dataflow = true;
-  int32_t df_ntask = 0, df_workers = 0, dfb_ntask = 0;
+  int32_t df_ntask = 0, df_workers = 0, df_fwd_workers = 0, dfb_ntask = 0;
   int32_t nt_max_dense = 0;
   int32_t n_pcg = 0, max_pcg_n = 0, n_pcg_cams = 0;
   bool have_weights = false;
@@ -524,6 +524,11 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     h->df_workers = ncu * (p.T == 64 ? 2 : 4);
+    // the forward launch gets exactly the workgroups that can be resident
+    // at once (a persistent grid; more would only start after the work is
+    // done)
+    h->df_fwd_workers = ncu * chol_dataflow_resident_per_cu(p.T);
+    if (h->df_fwd_workers <= 0) return fail(RPBA_ERR_HIP, "dataflow Cholesky occupancy query failed");
   }
 
   Dev& D = h->d;
@@ -697,7 +702,7 @@ static rpba_status chol_forward(rpba_problem* h, const int32_t* pot, const int32
   hipStream_t st = h->stream;
   if (h->dataflow) {
     launch_chol_dataflow(h->d, (const int32_t*)(h->ws + h->map.df_tasks), h->df_ntask,
-                         (int*)(h->ws + h->map.df_flags), (int*)(h->ws + h->map.df_ctl), h->df_workers, st);
+                         (int*)(h->ws + h->map.df_flags), (int*)(h->ws + h->map.df_ctl), h->df_fwd_workers, st);
     return RPBA_OK;
   }
   for (int k = 0; k < h->nt_max_dense; ++k) {

@@ -788,6 +788,13 @@ void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, h
   else hipLaunchKernelGGL(k_chol_update<32>, dim3((unsigned)nupd), dim3(NT), 0, st, d, k, upd);
 }
 
+int chol_dataflow_resident_per_cu(int T) {
+  int n = 0;
+  const hipError_t e = T == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_chol_dataflow<64>, NT, 0)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_chol_dataflow<32>, NT, 0);
+  return e == hipSuccess ? n : 0;
+}
+
 void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_df_begin, dim3(1), dim3(64), 0, st, ctl);

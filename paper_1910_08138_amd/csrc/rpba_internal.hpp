@@ -152,7 +152,10 @@ void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hi
 void launch_chol_trsm(const Dev& d, int k, const int32_t* trsm, int64_t ntrsm, hipStream_t st);
 void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, hipStream_t st);
 // the whole forward factorisation of all dense sub-blocks as one persistent
-// launch over a task list (see rpba_chol.hip); ctl = [ticket, epoch, errors]
+// launch over a task list (see rpba_chol.hip); ctl = [ticket, epoch, errors].
+// chol_dataflow_resident_per_cu: its workgroups that fit on one CU at once
+// (0 if the query fails)
+int chol_dataflow_resident_per_cu(int T);
 void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
                           hipStream_t st);
 // the backward substitution as one persistent launch (ctl[3] = its ticket)
