@@ -246,7 +246,8 @@ rpba_status rpba_precond_train_step(const float *samples, int32_t nsamp, int32_t
  *   launches and calls for phases 0..n-1: intersection, point blocks, Schur
  *   diagonal blocks and right-hand side, Cholesky forward, Cholesky
  *   backward, update, consensus, robust, iterative solver, Schur
- *   off-diagonal (camera pair) blocks; returns the number of phases. */
+ *   off-diagonal (camera pair) blocks, caller-order export of the
+ *   intersection; returns the number of phases. */
 rpba_status rpba_set_graph(rpba_problem *h, int32_t on);
 rpba_status rpba_set_timing(rpba_problem *h, int32_t on);
 int32_t rpba_get_timing(rpba_problem *h, double *ms, int64_t *launches, int64_t *calls, int32_t n);

@@ -31,7 +31,7 @@ EXPORTS = [
     "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
 ]
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
-          "robust", "iterative_solve", "schur_pairs"]
+          "robust", "iterative_solve", "schur_pairs", "intersect_export"]
 
 
 class RpbaError(RuntimeError):

@@ -229,7 +229,7 @@ struct CallGraph {
 };
 
 enum Phase { PH_INTERSECT = 0, PH_COPY_PREP, PH_SCHUR, PH_CHOL_FWD, PH_CHOL_BWD, PH_UPDATE, PH_CONSENSUS, PH_ROBUST,
-             PH_SOLVE_IT, PH_SCHUR_OD, NPHASE };
+             PH_SOLVE_IT, PH_SCHUR_OD, PH_INT_EXPORT, NPHASE };
 
 struct rpba_problem {
   std::shared_ptr<Plan> plan;
@@ -646,6 +646,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero_i32(D.blk_fail, D.L, st);
   launch_zero_i32((int32_t*)(w + m.df_flags), p.rcs_total / ((int64_t)p.T * p.T), st);
   launch_zero_i32((int32_t*)(w + m.df_ctl), 4, st);
+  launch_df_reset((int32_t*)(w + m.df_ctl), st);
   launch_zero_i32(D.blk_fresh, D.L, st);
   launch_zero_i32((int32_t*)(w + m.dfb_flags), p.vec_total / p.T, st);
   launch_zero_i32((int32_t*)(w + m.rob_bad), D.N, st);
@@ -665,8 +666,12 @@ rpba_status rpba_destroy(rpba_problem* h) {
 rpba_status rpba_intersect(rpba_problem* h, double* cov, int32_t* status, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   rpba_status s = run_call(h, h->g_int, cov, status, stats, [&]() -> rpba_status {
-    PhaseTimer t(h, PH_INTERSECT, stats ? 4 : 3);
-    launch_intersect(h->d, cov, status, stats, h->stream);
+    {
+      PhaseTimer t(h, PH_INTERSECT, 2);
+      launch_intersect(h->d, cov != nullptr, h->stream);
+    }
+    PhaseTimer t(h, PH_INT_EXPORT, stats ? 2 : 1);
+    launch_intersect_export(h->d, cov, status, stats, h->stream);
     return RPBA_OK;
   });
   if (s != RPBA_OK) return s;
@@ -726,13 +731,13 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
     const int32_t* bwd = (const int32_t*)(h->ws + h->map.bwd_items);
     if (h->any_dense) {
       {
-        PhaseTimer t(h, PH_CHOL_FWD, h->dataflow ? 3 : 3 * h->nt_max_dense);
+        PhaseTimer t(h, PH_CHOL_FWD, h->dataflow ? 1 : 3 * h->nt_max_dense);
         rpba_status s2 = chol_forward(h, pot, fwd, upd);
         if (s2 != RPBA_OK) return s2;
       }
       {
-        PhaseTimer t(h, PH_CHOL_BWD, h->dataflow ? 4 : h->nt_max_dense + 1);
-        launch_rhs_extract(h->d, h->stream);
+        PhaseTimer t(h, PH_CHOL_BWD, h->dataflow ? 3 : h->nt_max_dense + 1);
+        launch_rhs_extract(h->d, (const int*)(h->ws + h->map.df_ctl), h->stream);
         if (h->dataflow)
           launch_chol_backward_dataflow(h->d, (const int32_t*)(h->ws + h->map.dfb_tasks), h->dfb_ntask,
                                         (int*)(h->ws + h->map.dfb_flags), (int*)(h->ws + h->map.df_ctl),

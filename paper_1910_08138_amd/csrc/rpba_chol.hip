@@ -430,10 +430,13 @@ __global__ __launch_bounds__(NT) void k_chol_update(Dev d, int k, const int32_t*
       }
 }
 
-// ys = L^-1 e: row 0 of the factored right-hand-side tile row
+// ys = L^-1 e: row 0 of the factored right-hand-side tile row.  A wait of
+// the persistent forward launch that ran out of budget (ctl[2], never set by
+// the stepwise launches) marks every sub-block failed.
 template <int T>
-__global__ void k_rhs_extract(Dev d) {
+__global__ void k_rhs_extract(Dev d, const int* ctl) {
   const int l = blockIdx.x;
+  if (threadIdx.x == 0 && ctl[2] != 0) d.blk_fail[l] = 1;
   if (d.active && !d.active[l]) return;
   const int nt = d.nt[l];
   const int64_t vb = d.vec_off[l];
@@ -580,17 +583,32 @@ __device__ __forceinline__ int df_poll(const int* row1, const int* row2, const u
   return r;
 }
 
-__global__ void k_df_begin(int* ctl) {
+// ctl = [forward ticket, epoch, exhausted waits, backward ticket].  The
+// launches of one LM step share an epoch; the step's last kernel
+// (k_df_finish) marks every sub-block failed if a wait ran out, then readies
+// ctl for the next step (tickets 0, next epoch, no errors).  k_df_reset
+// readies it once after the workspace is zeroed.
+__global__ void k_df_reset(int* ctl) {
   if (threadIdx.x == 0) {
-    ctl[0] = 0;           // ticket
-    ctl[1] = ctl[1] + 1;  // epoch of this call
-    ctl[2] = 0;           // exhausted waits
+    ctl[0] = 0;
+    ctl[1] = ctl[1] + 1;
+    ctl[2] = 0;
+    ctl[3] = 0;
   }
 }
 
-__global__ void k_df_end(Dev d, const int* ctl) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < d.L && ctl[2] != 0) d.blk_fail[l] = 1;
+// one workgroup
+__global__ void k_df_finish(Dev d, int* ctl) {
+  const bool err = ctl[2] != 0;
+  for (int l = threadIdx.x; l < d.L; l += blockDim.x)
+    if (err) d.blk_fail[l] = 1;
+  __syncthreads();  // every thread has read the error word
+  if (threadIdx.x == 0) {
+    ctl[0] = 0;
+    ctl[1] = ctl[1] + 1;
+    ctl[2] = 0;
+    ctl[3] = 0;
+  }
 }
 
 template <int T>
@@ -703,10 +721,6 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
 // numbered by k descending, so a task only waits for tasks with smaller
 // numbers; x segments are handed over with device-coherent stores and a ready
 // flag per segment (same epoch and error word as the forward launch).
-__global__ void k_dfb_begin(int* ctl) {
-  if (threadIdx.x == 0) ctl[3] = 0;  // ticket of the backward launch
-}
-
 template <int T>
 __global__ __launch_bounds__(NT) void k_chol_backward_df(Dev d, const int32_t* __restrict__ tasks, int ntask,
                                                          int* xflags, int* ctl) {
@@ -797,7 +811,6 @@ int chol_dataflow_resident_per_cu(int T) {
 
 void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_df_begin, dim3(1), dim3(64), 0, st, ctl);
   if (ntask > 0) {
     const unsigned g = (unsigned)std::max(1, std::min(ntask, nworkers));
     if (d.T == 64)
@@ -805,12 +818,12 @@ void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* fl
     else
       hipLaunchKernelGGL(k_chol_dataflow<32>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, ctl);
   }
-  hipLaunchKernelGGL(k_df_end, dim3((d.L + 255) / 256), dim3(256), 0, st, d, (const int*)ctl);
 }
+
+void launch_df_reset(int* ctl, hipStream_t st) { hipLaunchKernelGGL(k_df_reset, dim3(1), dim3(64), 0, st, ctl); }
 
 void launch_chol_backward_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* xflags, int* ctl,
                                    int nworkers, hipStream_t st) {
-  hipLaunchKernelGGL(k_dfb_begin, dim3(1), dim3(64), 0, st, ctl);
   if (ntask > 0) {
     const unsigned g = (unsigned)std::max(1, std::min(ntask, nworkers));
     if (d.T == 64)
@@ -818,12 +831,12 @@ void launch_chol_backward_dataflow(const Dev& d, const int32_t* tasks, int ntask
     else
       hipLaunchKernelGGL(k_chol_backward_df<32>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, xflags, ctl);
   }
-  hipLaunchKernelGGL(k_df_end, dim3((d.L + 255) / 256), dim3(256), 0, st, d, (const int*)ctl);
+  hipLaunchKernelGGL(k_df_finish, dim3(1), dim3(256), 0, st, d, ctl);
 }
 
-void launch_rhs_extract(const Dev& d, hipStream_t st) {
-  if (d.T == 64) hipLaunchKernelGGL(k_rhs_extract<64>, dim3(d.L), dim3(NT), 0, st, d);
-  else hipLaunchKernelGGL(k_rhs_extract<32>, dim3(d.L), dim3(NT), 0, st, d);
+void launch_rhs_extract(const Dev& d, const int* ctl, hipStream_t st) {
+  if (d.T == 64) hipLaunchKernelGGL(k_rhs_extract<64>, dim3(d.L), dim3(NT), 0, st, d, ctl);
+  else hipLaunchKernelGGL(k_rhs_extract<32>, dim3(d.L), dim3(NT), 0, st, d, ctl);
 }
 
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st) {

@@ -144,7 +144,10 @@ __host__ __device__ __forceinline__ int64_t rcs_elem(const Dev& d, int l, int ro
 // kernel launchers (all asynchronous on `st`)
 void launch_gather(const Dev& d, hipStream_t st);
 void launch_init_rcs(const Dev& d, hipStream_t st);
-void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st);
+// the intersection itself (point records, and covariances if want_cov), then
+// the caller-order export of points, covariances, statuses and the statistics
+void launch_intersect(const Dev& d, bool want_cov, hipStream_t st);
+void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st);
 void launch_copy_prep(const Dev& d, hipStream_t st);
 void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st);
 void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st);
@@ -161,7 +164,11 @@ void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* fl
 // the backward substitution as one persistent launch (ctl[3] = its ticket)
 void launch_chol_backward_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* xflags, int* ctl,
                                    int nworkers, hipStream_t st);
-void launch_rhs_extract(const Dev& d, hipStream_t st);
+// ctl: the persistent launches' control words (its error word marks every
+// sub-block failed)
+void launch_rhs_extract(const Dev& d, const int* ctl, hipStream_t st);
+// readies the control words after the workspace is zeroed (next epoch)
+void launch_df_reset(int* ctl, hipStream_t st);
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st);
 void launch_update(const Dev& d, double* block_stats, hipStream_t st);
 void launch_consensus(const Dev& d, double* stats, hipStream_t st);

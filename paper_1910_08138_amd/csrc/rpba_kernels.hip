@@ -986,12 +986,15 @@ void launch_init_rcs(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_pad_identity, dim3(d.L), dim3(NT), 0, st, d);
 }
 
-void launch_intersect(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
+void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
   launch_zero(d.acc_int, 4, st);
   if (d.has_info)
-    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov != nullptr);
+    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
   else
-    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, cov != nullptr);
+    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
+}
+
+void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
   if (stats) hipLaunchKernelGGL(k_intersect_stats, dim3(1), dim3(64), 0, st, d, stats);
 }
