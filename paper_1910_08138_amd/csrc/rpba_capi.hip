@@ -670,7 +670,7 @@ rpba_status rpba_intersect(rpba_problem* h, double* cov, int32_t* status, double
       PhaseTimer t(h, PH_INTERSECT, 2);
       launch_intersect(h->d, cov != nullptr, h->stream);
     }
-    PhaseTimer t(h, PH_INT_EXPORT, stats ? 2 : 1);
+    PhaseTimer t(h, PH_INT_EXPORT, 1);
     launch_intersect_export(h->d, cov, status, stats, h->stream);
     return RPBA_OK;
   });
@@ -758,7 +758,7 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
                  h->opt.pcg_tol, h->opt.ir_tol, h->opt.ir_maxit, h->stream);
     }
     {
-      PhaseTimer t(h, PH_UPDATE, 4);
+      PhaseTimer t(h, PH_UPDATE, 3);
       launch_update(h->d, block_stats, h->stream);
     }
     return RPBA_OK;
@@ -770,7 +770,7 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
 rpba_status rpba_consensus(rpba_problem* h, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   return run_call(h, h->g_cons, stats, nullptr, nullptr, [&]() -> rpba_status {
-    PhaseTimer t(h, PH_CONSENSUS, stats ? 5 : 4);
+    PhaseTimer t(h, PH_CONSENSUS, 4);
     launch_consensus(h->d, stats, h->stream);
     return RPBA_OK;
   });

@@ -550,11 +550,23 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   }
 }
 
+// statistics of an intersection from its sums: cost, sigma0 (redundancy
+// 2 K_valid - 6 M - 3 N_valid), RMS reprojection error, valid points
+__device__ void intersect_stats(const Dev& d, double* stats) {
+  double cost = d.acc_int[0], sq = d.acc_int[1], kv = d.acc_int[2], nv = d.acc_int[3];
+  double red = 2.0 * kv - 6.0 * d.M - 3.0 * nv;
+  stats[0] = cost;
+  stats[1] = red > 0 ? sqrt(sq / red) : 0.0;
+  stats[2] = kv > 0 ? sqrt(sq / (2.0 * kv)) : 0.0;
+  stats[3] = nv;
+}
+
 // Caller-order export: one thread per caller point o gathers the internal
 // record of its point, so that the caller's arrays are written line by line
 // (points and covariances of invalid points are left as they were)
-__global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* status_out) {
+__global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* status_out, double* stats) {
   const int o = blockIdx.x * NT + threadIdx.x;
+  if (stats && o == 0) intersect_stats(d, stats);  // the intersection's sums are complete
   if (o >= d.N) return;
   const int j = d.pt_new[o];
   const double2* p = reinterpret_cast<const double2*>(d.pxs + 4 * (int64_t)j);
@@ -578,16 +590,6 @@ __global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* 
 }
 
 // stats = (cost, sigma0, RMS, N_valid) from the accumulated sums
-__global__ void k_intersect_stats(Dev d, double* stats) {
-  if (threadIdx.x != 0) return;
-  double cost = d.acc_int[0], sq = d.acc_int[1], kv = d.acc_int[2], nv = d.acc_int[3];
-  double red = 2.0 * kv - 6.0 * d.M - 3.0 * nv;
-  stats[0] = cost;
-  stats[1] = red > 0 ? sqrt(sq / red) : 0.0;
-  stats[2] = kv > 0 ? sqrt(sq / (2.0 * kv)) : 0.0;
-  stats[3] = nv;
-}
-
 // ------------------------------------------------ sub-block normal equations
 // One thread per copy: damped point block V* = (sum B^T W B + Omega)(1 + lambda
 // on the diagonal), its FP64 inverse, g_X = sum B^T W v + Omega (X - Xbar),
@@ -790,15 +792,13 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
   }
 }
 
-__global__ void k_cam_commit(Dev d) {
-  int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (t >= (int64_t)CAM_STRIDE * d.M) return;
-  d.cam[t] = d.camN[t];
-}
-
-__global__ void k_block_stats(Dev d, double* bs) {
-  int l = blockIdx.x * NT + threadIdx.x;
-  if (l >= d.L) return;
+// after the update: the new cameras become the current ones, and the
+// per-sub-block statistics of the step are written out
+__global__ void k_update_finish(Dev d, double* bs) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t < (int64_t)CAM_STRIDE * d.M) d.cam[t] = d.camN[t];
+  if (t >= d.L) return;
+  const int l = (int)t;
   bool act = d.active == nullptr || d.active[l];
   const double* a = d.acc_blk + 4 * l;
   if (act && d.blk_fail[l] == 0) d.blk_fresh[l] = 0;  // its copies were written by the update
@@ -913,18 +913,17 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
   }
 }
 
-__global__ void k_consensus_cams(Dev d) {
+__global__ void k_consensus_cams(Dev d, double* stats) {
   int i = blockIdx.x * NT + threadIdx.x;
+  if (stats && i == 0) {  // the point pass's sums are complete
+    stats[0] = d.acc_cons[0];
+    stats[1] = d.acc_cons[1];
+  }
   if (i >= d.M) return;
   int o = d.cam_orig[i];
   const double* c = d.cam + (int64_t)CAM_STRIDE * i;
   for (int q = 0; q < 9; ++q) d.u_camR[9 * (int64_t)o + q] = c[q];
   for (int r = 0; r < 3; ++r) d.u_camC[(int64_t)r * d.M + o] = c[9 + r];
-}
-
-__global__ void k_copy2(const double* src, double* dst, int n) {
-  if (threadIdx.x == 0)
-    for (int q = 0; q < n; ++q) dst[q] = src[q];
 }
 
 // dense copy-out of one sub-block's RCS (row-major n6 x n6 lower) and rhs
@@ -995,8 +994,7 @@ void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
 }
 
 void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
-  hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out);
-  if (stats) hipLaunchKernelGGL(k_intersect_stats, dim3(1), dim3(64), 0, st, d, stats);
+  hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out, stats);
 }
 
 void launch_copy_prep(const Dev& d, hipStream_t st) {
@@ -1008,16 +1006,16 @@ void launch_copy_prep(const Dev& d, hipStream_t st) {
 void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
   hipLaunchKernelGGL(k_cam_update, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_back_update, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
-  hipLaunchKernelGGL(k_cam_commit, dim3(grid_for((int64_t)CAM_STRIDE * d.M)), dim3(NT), 0, st, d);
-  hipLaunchKernelGGL(k_block_stats, dim3(grid_for(d.L)), dim3(NT), 0, st, d, block_stats);
+  hipLaunchKernelGGL(k_update_finish, dim3(grid_for(std::max<int64_t>((int64_t)CAM_STRIDE * d.M, d.L))), dim3(NT), 0,
+                     st, d, block_stats);
 }
 
 void launch_consensus(const Dev& d, double* stats, hipStream_t st) {
   launch_zero(d.acc_cons, 2, st);
   hipLaunchKernelGGL(k_consensus_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
-  hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, (double*)nullptr, (int32_t*)nullptr);
-  hipLaunchKernelGGL(k_consensus_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
-  if (stats) hipLaunchKernelGGL(k_copy2, dim3(1), dim3(64), 0, st, (const double*)d.acc_cons, stats, 2);
+  hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, (double*)nullptr, (int32_t*)nullptr,
+                     (double*)nullptr);
+  hipLaunchKernelGGL(k_consensus_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d, stats);
 }
 
 void launch_bsr_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st) {
