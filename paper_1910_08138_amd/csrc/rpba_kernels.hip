@@ -685,24 +685,34 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
 // ------------------------------------------------------- update of the step
 // One thread per camera: new pose R <- Exp([w]x) R, C <- C + dc into camN.
 __global__ void k_cam_update(Dev d) {
-  int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= d.M) return;
-  int l = d.cam_blk[i];
-  const double* c = d.cam + (int64_t)CAM_STRIDE * i;
-  double* n = d.camN + (int64_t)CAM_STRIDE * i;
-  bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
-  if (!act) {
-    for (int q = 0; q < 12; ++q) n[q] = c[q];
-    return;
+  const int i = blockIdx.x * NT + threadIdx.x;
+  int l = -1;
+  double s2 = 0.0;
+  if (i < d.M) {
+    l = d.cam_blk[i];
+    const double* c = d.cam + (int64_t)CAM_STRIDE * i;
+    double* n = d.camN + (int64_t)CAM_STRIDE * i;
+    const bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
+    if (!act) {
+      for (int q = 0; q < 12; ++q) n[q] = c[q];
+    } else {
+      const int a = i - d.blk_cam_off[l];
+      const double* dx = d.x + d.vec_off[l] + 6 * a;
+      double w[3] = {dx[0], dx[1], dx[2]};
+      rotate_left(w, c, n);
+      for (int r = 0; r < 3; ++r) n[9 + r] = c[9 + r] + dx[3 + r];
+      for (int q = 0; q < 6; ++q) s2 += dx[q] * dx[q];
+    }
   }
-  int a = i - d.blk_cam_off[l];
-  const double* dx = d.x + d.vec_off[l] + 6 * a;
-  double w[3] = {dx[0], dx[1], dx[2]};
-  rotate_left(w, c, n);
-  for (int r = 0; r < 3; ++r) n[9 + r] = c[9 + r] + dx[3 + r];
-  double s2 = 0;
-  for (int q = 0; q < 6; ++q) s2 += dx[q] * dx[q];
-  atomicAdd(&d.acc_blk[4 * l + 2], s2);
+  // the cameras of a sub-block are consecutive: a wave inside one sub-block
+  // sums its squares first and adds them with one atomic
+  const int l0 = __shfl(l, 0);
+  if (__all(l == l0)) {
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+    if ((threadIdx.x & 63) == 0 && l0 >= 0 && s2 != 0.0) atomicAdd(&d.acc_blk[4 * l0 + 2], s2);
+  } else if (l >= 0 && s2 != 0.0) {
+    atomicAdd(&d.acc_blk[4 * l + 2], s2);
+  }
 }
 
 // One thread per copy: dX = V*^-1 (-g_X - sum_k Y_k^T dC_i(k)) with Y_k at the
