@@ -516,21 +516,21 @@ __global__ __launch_bounds__(NT) void k_selftest_gemm(const double* A, const dou
 
 
 // ---- one persistent launch for the whole forward factorisation ----------
-// Every tile (i, j), j <= i, j < nt, of every dense sub-block (the
-// right-hand-side row i = nt included) is one task.  Tasks are numbered
-// column by column (j ascending; inside a column the largest sub-blocks
-// first, the diagonal tile before the tiles below it), and a task only ever
-// waits for tasks with smaller numbers: the tiles (i,k), (j,k), k < j, and
-// for j < i the diagonal tile (j,j).  Workgroups take task numbers from a
-// ticket counter, so a task being waited for is always held by a running
-// workgroup and the launch cannot deadlock.  A finished tile publishes a
-// ready flag equal to the call's epoch; waits are bounded, and a wait that
-// runs out of its budget is counted as an error (the sub-blocks are then
-// reported as failed instead of hanging).
+// Every tile (i, j), j <= i, j < nt, of every dense sub-block that can be
+// nonzero in the factor (the right-hand-side row i = nt included) is one
+// task.  The plan lists the tasks (dataflow_order: by latest start along
+// the chain of diagonal tiles, in a topological order), so a task only ever
+// waits for tasks listed before it: the tiles (i,k), (j,k), k < j, that are
+// both nonzero, and for j < i the diagonal tile (j,j).  Workgroups take
+// list positions from a ticket counter, so a task being waited for is always
+// held by a running workgroup and the launch cannot deadlock.  A finished
+// tile publishes a ready flag equal to the call's epoch; waits are bounded,
+// and a wait that runs out of its budget is counted as an error (the
+// sub-blocks are then reported as failed instead of hanging).
 //
-// Left-looking per tile: acc = A(i,j) - sum_k L(i,k) L(j,k)^T in registers,
-// then for i == j the diagonal factor and its inverse, for i > j the panel
-// solve L(i,j) = acc L(j,j)^-T.
+// Left-looking per tile: acc = A(i,j) - sum_k L(i,k) L(j,k)^T in registers
+// (tiles that stay zero left out), then for i == j the diagonal factor and
+// its inverse, for i > j the panel solve L(i,j) = acc L(j,j)^-T.
 constexpr int DF_SPIN_LIMIT = 1 << 20;
 
 __device__ __forceinline__ int df_flag_load(const int* f) {
