@@ -482,26 +482,25 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       const int sl = threadIdx.x + u * IT;
       ci[u] = sl < nc ? d.iwg_cams[cb + sl] : -1;
     }
+    // unconditional loads at clamped indices (in range: every workgroup has
+    // observations, since every point has at least two), stores guarded; no
+    // array is filled under a condition, so all of them stay in registers
     const double2* gxy = reinterpret_cast<const double2*>(d.pm_xy) + b0;
     double2 ov[OS];
     int32_t oc[OS];
-    if (nst > 0) {
-      // unconditional loads at a clamped index (in range), stores guarded
 #pragma unroll
-      for (int u = 0; u < OS; ++u) {
-        const int t = min((int)threadIdx.x + u * IT, nst - 1);
-        ov[u] = gxy[t];
-        oc[u] = d.pm_code[b0 + t];
-      }
+    for (int u = 0; u < OS; ++u) {
+      const int t = max(0, min((int)threadIdx.x + u * IT, nst - 1));
+      ov[u] = gxy[t];
+      oc[u] = d.pm_code[b0 + t];
     }
     double2 cv[CS][6];
 #pragma unroll
-    for (int u = 0; u < CS; ++u)
-      if (ci[u] >= 0) {
-        const double2* g = reinterpret_cast<const double2*>(d.cam + (int64_t)CAM_STRIDE * ci[u]);
+    for (int u = 0; u < CS; ++u) {
+      const double2* g = reinterpret_cast<const double2*>(d.cam + (int64_t)CAM_STRIDE * max(ci[u], 0));
 #pragma unroll
-        for (int q = 0; q < 6; ++q) cv[u][q] = g[q];
-      }
+      for (int q = 0; q < 6; ++q) cv[u][q] = g[q];
+    }
 #pragma unroll
     for (int u = 0; u < OS; ++u) {
       const int t = threadIdx.x + u * IT;
