@@ -835,31 +835,33 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
       const double xb[3] = {d.Xbar[j], d.Xbar[(int64_t)d.N + j], d.Xbar[2 * (int64_t)d.N + j]};
       constexpr int CU = 4;
       const int n = c1 - c0;
+      // unconditional gathers (indices clamped into the copy array, so no
+      // array is filled under a condition and all stay in registers)
       double xu[CU][3];
-      if (n > 0) {
-        int cu[CU], fr[CU];
+      int cu[CU], fr[CU];
 #pragma unroll
-        for (int u = 0; u < CU; ++u) cu[u] = d.pt_copies[c0 + min(u, n - 1)];
+      for (int u = 0; u < CU; ++u) cu[u] = d.pt_copies[min(c0 + max(0, min(u, n - 1)), (int)d.NC - 1)];
 #pragma unroll
-        for (int u = 0; u < CU; ++u) {
-          fr[u] = d.blk_fresh[d.copy_blk[cu[u]]];
-          xu[u][0] = d.Xc[3 * (int64_t)cu[u]];
-          xu[u][1] = d.Xc[3 * (int64_t)cu[u] + 1];
-          xu[u][2] = d.Xc[3 * (int64_t)cu[u] + 2];
-        }
-#pragma unroll
-        for (int u = 0; u < CU; ++u)
-          if (fr[u]) {
-            xu[u][0] = xb[0];
-            xu[u][1] = xb[1];
-            xu[u][2] = xb[2];
-          }
+      for (int u = 0; u < CU; ++u) {
+        fr[u] = d.blk_fresh[d.copy_blk[cu[u]]];
+        xu[u][0] = d.Xc[3 * (int64_t)cu[u]];
+        xu[u][1] = d.Xc[3 * (int64_t)cu[u] + 1];
+        xu[u][2] = d.Xc[3 * (int64_t)cu[u] + 2];
       }
-      auto copy_x = [&](int c, double (&x)[3]) {
+#pragma unroll
+      for (int u = 0; u < CU; ++u)
+        if (fr[u]) {
+          xu[u][0] = xb[0];
+          xu[u][1] = xb[1];
+          xu[u][2] = xb[2];
+        }
+      // (xb copied into the closure: an array captured by reference would be
+      // kept in scratch memory)
+      auto copy_x = [&d, b0 = xb[0], b1 = xb[1], b2 = xb[2]](int c, double (&x)[3]) {
         if (d.blk_fresh[d.copy_blk[c]]) {
-          x[0] = xb[0];
-          x[1] = xb[1];
-          x[2] = xb[2];
+          x[0] = b0;
+          x[1] = b1;
+          x[2] = b2;
         } else {
           x[0] = d.Xc[3 * (int64_t)c];
           x[1] = d.Xc[3 * (int64_t)c + 1];
