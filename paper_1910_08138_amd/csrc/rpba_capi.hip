@@ -50,7 +50,7 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, cm_info;
+      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info;
   size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -140,6 +140,7 @@ WsMap layout_for(const Plan& P) {
   m.dfb_flags = L.add(i4 * (P.vec_total / P.T));
   m.cm_xy = L.add(f8 * 2 * P.K);
   m.cm_rw = L.add(f8 * P.K);
+  m.rw_unit = L.add(4);
   m.cm_info = L.add(P.has_info ? f8 * 3 * P.K : 0);
   m.cam = L.add(f8 * 12 * P.M);
   m.camN = L.add(f8 * 12 * P.M);
@@ -566,6 +567,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.pxs = F(m.pxs);
   D.cm_xy = F(m.cm_xy);
   D.cm_rw = F(m.cm_rw);
+  D.rw_unit = I(m.rw_unit);
   D.cm_info = p.has_info ? F(m.cm_info) : nullptr;
   D.covi = F(m.covi);
   D.status = I(m.status);

@@ -55,6 +55,7 @@ struct Dev {
   // camera-major copies (cam_obs order) for the diagonal Schur pass
   double* cm_xy;          // [K][2] pixel
   double* cm_rw;          // [K] robust weight multiplier (kept with rw)
+  int* rw_unit;           // [1] 1 while every robust weight is 1 (the Schur passes then skip reading them)
   double* cm_info;        // [K][3] or null
   // intersection stream, point-major (see the plan)
   const int32_t* pm_off;

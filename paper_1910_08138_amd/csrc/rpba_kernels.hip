@@ -97,6 +97,7 @@ __global__ void k_gather_cm(Dev d) {
   const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (t >= d.K) return;
   const int64_t k = d.cam_obs[t];
+  if (t == 0) *d.rw_unit = 1;  // k_gather_obs set every robust weight to 1
   d.cm_xy[2 * t] = d.xy[2 * k];
   d.cm_xy[2 * t + 1] = d.xy[2 * k + 1];
   d.cm_rw[t] = d.rw[k];

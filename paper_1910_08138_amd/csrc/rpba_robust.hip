@@ -151,6 +151,7 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
     }
     d.rw[k] = w;
     d.cm_rw[t] = w;  // the diagonal Schur pass's camera-major copy
+    if (w != 1.0) *d.rw_unit = 0;  // from now on the Schur passes read the weights
     const int64_t pos = d.pm_pos[k];  // the intersection's copy of the weight
     if (d.has_info) {
       for (int q = 0; q < 3; ++q) d.pm_w[3 * pos + q] = w * d.info[3 * (int64_t)k + q];

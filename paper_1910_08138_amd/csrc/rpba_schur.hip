@@ -27,10 +27,11 @@ namespace {
 constexpr int NT = 256;
 
 // weight of the observation at position t of its camera's list (camera-major
-// copies of the robust multiplier and of the information matrix)
+// copies of the robust multiplier and of the information matrix); unit:
+// every robust multiplier is 1 and is not read
 template <typename T>
-__device__ __forceinline__ W2<T> cm_weight_t(const Dev& d, int64_t t) {
-  const double r = d.cm_rw[t];
+__device__ __forceinline__ W2<T> cm_weight_t(const Dev& d, int64_t t, bool unit) {
+  const double r = unit ? 1.0 : d.cm_rw[t];
   if (d.has_info) {
     const double* w = d.cm_info + 3 * t;
     return {(T)(r * w[0]), (T)(r * w[1]), (T)(r * w[2])};
@@ -117,7 +118,7 @@ struct ObsIn {
 // its camera's list: pixel (diagonal pass only) and weight come from the
 // camera-major copies, read in order by the camera's wave or pair group
 template <typename T, bool DIAG>
-__device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_range, ObsIn<T>& o) {
+__device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_range, bool unit, ObsIn<T>& o) {
   o.valid = false;
   if (!in_range) return;
   if constexpr (sizeof(T) == 4) {
@@ -169,7 +170,7 @@ __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_
     o.x = (T)xy.x;
     o.y = (T)xy.y;
   }
-  o.W = cm_weight_t<T>(d, k);
+  o.W = cm_weight_t<T>(d, k, unit);
 }
 
 // One wave per camera: diagonal block S_(i,i) = U*_i - sum_k Y_k V*^-1 Y_k^T
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
   if (i >= d.M) return;
   const int l = d.cam_blk[i];
   if (d.active && !d.active[l]) return;
+  const bool unit = *d.rw_unit != 0;
   CamReg<T> cm;
   cm.load(d, i);
   T acc[21], U[21], gC[6], ep[6];
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
         kB = t + 64;
         cB = d.cam_obs_c[t + 64];
       }
-      obs_in_load<T, true>(d, kA, cA, t < o1, cur);
+      obs_in_load<T, true>(d, kA, cA, t < o1, unit, cur);
     }
     for (; t < o1; t += 64) {
       int kC = 0, cC = 0;
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
         cC = d.cam_obs_c[t + 128];
       }
       ObsIn<T> nxt;
-      obs_in_load<T, true>(d, kB, cB, t + 64 < o1, nxt);
+      obs_in_load<T, true>(d, kB, cB, t + 64 < o1, unit, nxt);
       if (cur.valid) process(cur);
       cur = nxt;
       kB = kC;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
   } else {
     for (int t = o0 + lane; t < o1; t += 64) {
       ObsIn<T> cur;
-      obs_in_load<T, true>(d, t, d.cam_obs_c[t], true, cur);
+      obs_in_load<T, true>(d, t, d.cam_obs_c[t], true, unit, cur);
       if (cur.valid) process(cur);
     }
   }
@@ -321,6 +323,7 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
   const int base = d.blk_cam_off[l];
   const int a2 = d.nb_cam[q];
   const int i2 = base + a2;
+  const bool unit = *d.rw_unit != 0;
   CamReg<T> c1, c2;
   c1.load(d, i1);
   c2.load(d, i2);
@@ -330,14 +333,14 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
   for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += PB_LANES) {
     const int c = d.pb_ent[3 * e], t1 = d.pb_ent[3 * e + 1], t2 = d.pb_ent[3 * e + 2];
     ObsIn<T> o;
-    obs_in_load<T, false>(d, t1, c, true, o);
+    obs_in_load<T, false>(d, t1, c, true, unit, o);
     if (!o.valid) continue;
     Lin<T> L1, L2;
     c1.lin(o.X, d, L1);
     c2.lin(o.X, d, L2);
     T Y1[6][3], Y2[6][3], Z1[6][3];
     y_block<T>(L1, o.W, Y1);
-    y_block<T>(L2, cm_weight_t<T>(d, t2), Y2);
+    y_block<T>(L2, cm_weight_t<T>(d, t2, unit), Y2);
     z_block<T>(Y1, o.Vi, Z1);
 #pragma unroll
     for (int r = 0; r < 6; ++r)
