@@ -15,8 +15,10 @@ constexpr int NT = 256;  // threads per workgroup of the streaming kernels
 
 inline unsigned grid_for(int64_t n, int per = NT) { return (unsigned)((n + per - 1) / per); }
 
-__device__ __forceinline__ W2<double> obs_weight(const Dev& d, int64_t k) {
-  double r = d.rw[k];
+// weight of LM-order observation k; unit: every robust multiplier is 1 and
+// is not read
+__device__ __forceinline__ W2<double> obs_weight(const Dev& d, int64_t k, bool unit) {
+  const double r = unit ? 1.0 : d.rw[k];
   if (d.has_info) {
     const double* w = d.info + 3 * k;
     return {r * w[0], r * w[1], r * w[2]};
@@ -32,12 +34,12 @@ struct CopyObs {
   W2<double> W;
   double cm[12];
 };
-__device__ __forceinline__ void copy_obs(const Dev& d, const double* cams, int64_t k, CopyObs& o) {
+__device__ __forceinline__ void copy_obs(const Dev& d, const double* cams, int64_t k, bool unit, CopyObs& o) {
   o.cam = d.obs_cam[k];
   const double2 v = reinterpret_cast<const double2*>(d.xy)[k];
   o.x = v.x;
   o.y = v.y;
-  o.W = obs_weight(d, k);
+  o.W = obs_weight(d, k, unit);
   const double2* g = reinterpret_cast<const double2*>(cams + (int64_t)CAM_STRIDE * o.cam);
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
@@ -50,10 +52,10 @@ __device__ __forceinline__ void copy_obs(const Dev& d, const double* cams, int64
 // f(observation) over the observations [k0, k1) of a copy, in order (one at
 // a time: a second one in flight costs more occupancy than it hides)
 template <typename F>
-__device__ __forceinline__ void for_copy_obs(const Dev& d, const double* cams, int k0, int k1, F&& f) {
+__device__ __forceinline__ void for_copy_obs(const Dev& d, const double* cams, int k0, int k1, bool unit, F&& f) {
   for (int k = k0; k < k1; ++k) {
     CopyObs a;
-    copy_obs(d, cams, k, a);
+    copy_obs(d, cams, k, unit, a);
     f(a);
   }
 }
@@ -597,6 +599,7 @@ __global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* 
 __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
   __shared__ double sh[8];
   __shared__ int l_first;
+  const bool unit = *d.rw_unit != 0;
   int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (threadIdx.x == 0) {
     l_first = d.copy_blk[blockIdx.x * (int64_t)NT];
@@ -629,7 +632,7 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
         double v0 = L.g0 - d.xy[2 * k], v1 = L.g1 - d.xy[2 * k + 1];
-        W2<double> W = obs_weight(d, k);
+        W2<double> W = obs_weight(d, k, unit);
         add_point_normals<double>(L, W, v0, v1, h, g);
         cost += wquad(W, v0, v1);
       }
@@ -720,6 +723,7 @@ __global__ void k_cam_update(Dev d) {
 __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
   __shared__ double sh[16];
   __shared__ int l_first;
+  const bool unit = *d.rw_unit != 0;
   int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (threadIdx.x == 0) {
     l_first = d.copy_blk[blockIdx.x * (int64_t)NT];
@@ -749,7 +753,7 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       sym3_mul(om, dx0, g);
       const int base = d.blk_cam_off[l];
       const double* xs = d.x + d.vec_off[l];
-      for_copy_obs(d, d.cam, k0, k1, [&](const CopyObs& o) {
+      for_copy_obs(d, d.cam, k0, k1, unit, [&](const CopyObs& o) {
         Lin<double> L;
         linearise<double>(o.cm, o.cm + 9, X, d.f, d.cx, d.cy, L);
         const W2<double> W = o.W;
@@ -779,7 +783,7 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       double og[3];
       sym3_mul(om, dx, og);
       double cost = dx[0] * og[0] + dx[1] * og[1] + dx[2] * og[2];
-      for_copy_obs(d, d.camN, k0, k1, [&](const CopyObs& o) {
+      for_copy_obs(d, d.camN, k0, k1, unit, [&](const CopyObs& o) {
         Lin<double> L;
         linearise<double>(o.cm, o.cm + 9, Xn, d.f, d.cx, d.cy, L);
         cost += wquad(o.W, L.g0 - o.x, L.g1 - o.y);
