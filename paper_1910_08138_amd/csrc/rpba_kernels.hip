@@ -530,10 +530,15 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
     intersect_point<INFO, true>(d, sg, b0, j, want_cov, accv);
     // residuals of the workgroup's stream, one coalesced copy (the slots of
     // points left invalid hold their pixels: residuals are only read for
-    // valid points)
+    // valid points), as streaming stores: only a robust re-weighting reads
+    // them, long after
     __syncthreads();
     double2* res = reinterpret_cast<double2*>(d.res) + b0;
-    for (int t = threadIdx.x; t < nobs; t += IT) res[t] = sg.xy[t];
+    for (int t = threadIdx.x; t < nobs; t += IT) {
+      const double2 v = sg.xy[t];
+      __builtin_nontemporal_store(v.x, &res[t].x);
+      __builtin_nontemporal_store(v.y, &res[t].y);
+    }
   } else {
     intersect_point<INFO, false>(d, sg, b0, j, want_cov, accv);
   }
