@@ -576,27 +576,33 @@ __global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* 
   if (stats && o == 0) intersect_stats(d, stats);  // the intersection's sums are complete
   if (o >= d.N) return;
   const int j = d.pt_new[o];
+  // both gathers issued together; the caller's arrays are written with
+  // streaming stores (nothing in the library reads them back)
   const double2* p = reinterpret_cast<const double2*>(d.pxs + 4 * (int64_t)j);
   const double2 a = p[0], b = p[1];
-  const int st = (int)b.y;
-  if (status_out) status_out[o] = st;
-  if (st != 0) return;
-  d.u_pts[o] = a.x;
-  d.u_pts[(int64_t)d.N + o] = a.y;
-  d.u_pts[2 * (int64_t)d.N + o] = b.x;
+  double2 c0, c1, c2;
   if (cov) {
     const double2* c = reinterpret_cast<const double2*>(d.covi + 6 * (int64_t)j);
-    const double2 c0 = c[0], c1 = c[1], c2 = c[2];
-    cov[o] = c0.x;
-    cov[(int64_t)d.N + o] = c0.y;
-    cov[2 * (int64_t)d.N + o] = c1.x;
-    cov[3 * (int64_t)d.N + o] = c1.y;
-    cov[4 * (int64_t)d.N + o] = c2.x;
-    cov[5 * (int64_t)d.N + o] = c2.y;
+    c0 = c[0];
+    c1 = c[1];
+    c2 = c[2];
+  }
+  const int st = (int)b.y;
+  if (status_out) __builtin_nontemporal_store(st, status_out + o);
+  if (st != 0) return;
+  __builtin_nontemporal_store(a.x, d.u_pts + o);
+  __builtin_nontemporal_store(a.y, d.u_pts + (int64_t)d.N + o);
+  __builtin_nontemporal_store(b.x, d.u_pts + 2 * (int64_t)d.N + o);
+  if (cov) {
+    __builtin_nontemporal_store(c0.x, cov + o);
+    __builtin_nontemporal_store(c0.y, cov + (int64_t)d.N + o);
+    __builtin_nontemporal_store(c1.x, cov + 2 * (int64_t)d.N + o);
+    __builtin_nontemporal_store(c1.y, cov + 3 * (int64_t)d.N + o);
+    __builtin_nontemporal_store(c2.x, cov + 4 * (int64_t)d.N + o);
+    __builtin_nontemporal_store(c2.y, cov + 5 * (int64_t)d.N + o);
   }
 }
 
-// stats = (cost, sigma0, RMS, N_valid) from the accumulated sums
 // ------------------------------------------------ sub-block normal equations
 // One thread per copy: damped point block V* = (sum B^T W B + Omega)(1 + lambda
 // on the diagonal), its FP64 inverse, g_X = sum B^T W v + Omega (X - Xbar),
