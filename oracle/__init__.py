@@ -18,15 +18,20 @@ LIB = os.path.join(HERE, "liboracle.so")
 ST_OK, ST_NOT_CONVERGED, ST_BEHIND, ST_ILL, ST_ELIMINATED = 0, 1, 2, 3, 4
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (-O2, OpenMP)."""
+def build(force: bool = True, native: bool = False, path: str | None = None) -> str:
+    """Compile the oracle with g++ (-O3, OpenMP).  native=True adds
+    -march=native (for timing it on the host that runs it; the default build
+    stays portable because it travels with the tree)."""
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs
+    out = path or LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cmd = ["g++", "-std=c++17", "-O3", "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs
+        if native:
+            cmd.insert(2, "-march=native")
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -37,9 +42,24 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build(force=True)
-        _lib = ctypes.CDLL(LIB)
-        _declare(_lib)
+        load(LIB)
     return _lib
+
+
+def load(path):
+    """Use the oracle library at `path` (e.g. a native build) from now on."""
+    global _lib
+    _lib = ctypes.CDLL(path)
+    _declare(_lib)
+    return _lib
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +86,8 @@ def _declare(L):
     L.orc_num_copies.argtypes = [ctypes.c_void_p]
     L.orc_get_copies.argtypes = [ctypes.c_void_p, _ip, _ip, _dp, _dp]
     L.orc_get_weights.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_set_copies.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_set_residuals.argtypes = [ctypes.c_void_p, _dp]
     L.orc_get_residuals.argtypes = [ctypes.c_void_p, _dp]
     L.orc_block_rcs.restype = ctypes.c_int
     L.orc_block_rcs.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
@@ -76,6 +98,7 @@ def _declare(L):
     L.orc_cholesky.restype = ctypes.c_int
     L.orc_cholesky.argtypes = [ctypes.c_int, _dp]
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_num_threads.argtypes = [ctypes.c_int]
     _declare_solvers(L)
 
 
@@ -177,6 +200,18 @@ class OracleProblem:
         om = np.zeros((n, 6))
         self._lib.orc_get_copies(self.h, _p(blk, _ip), _p(pt, _ip), _p(X), _p(om))
         return blk, pt, X, om
+
+    def set_copies(self, X):
+        """Test hook: X [n_copies][3] in the order of copies()."""
+        X = f64(X)
+        assert X.shape == (self._lib.orc_num_copies(self.h), 3)
+        self._lib.orc_set_copies(self.h, _p(X))
+
+    def set_residuals(self, res):
+        """Test hook: residuals [2][K] of the last intersection (pixels)."""
+        res = f64(res)
+        assert res.shape == (2, self.K)
+        self._lib.orc_set_residuals(self.h, _p(res))
 
     def weights(self):
         w = np.zeros(self.K)
@@ -308,44 +343,57 @@ def run_schedule(scene, T=6, I=4, robust=False, t_r=2, t_v=4.0, down_weight=1e-4
     return op, hist
 
 
+class RatioRule:
+    """Improvement test that ends a loop (Sec. 5.4): the best cost reached
+    so far is compared with the current one; a ratio below `ratio` (1.01)
+    is tolerated once, the second such step ends the loop.  `first` is the
+    cost before the first step.  step(cost) returns False when the loop
+    ends with this step."""
+
+    def __init__(self, first, ratio=1.01):
+        self.best = float(first)
+        self.ratio = float(ratio)
+        self.grace = False
+
+    def step(self, cost):
+        slow = self.best / cost < self.ratio
+        self.best = min(self.best, cost)
+        if slow:
+            if self.grace:
+                return False
+            self.grace = True
+        return True
+
+
 def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, **kw):
-    """Schedule driven by the paper's improvement test (Sec. 5.4): a loop goes
-    on while the best cost so far divided by the current one reaches `ratio`;
-    the first step that falls short is tolerated once, the second one ends the
-    loop.  Inner loop per sub-block on its cost (a sub-block that stops is
-    left out of later steps of this outer iteration); outer loop on the
-    reprojection RMS of the intersections.  Returns the problem and per outer
-    iteration the number of steps each sub-block took."""
+    """Schedule driven by the improvement test (RatioRule): inner loop per
+    sub-block on its cost (a sub-block that stops is left out of the later
+    steps of this outer iteration), outer loop on the reprojection RMS of the
+    intersections.  Returns the problem and per outer iteration the number of
+    steps each sub-block took."""
     op = OracleProblem(scene, **kw)
     L = scene.L
     hist = []
-    best_out, grace_out = np.inf, False
+    outer = None
     for t in range(T_max):
         st = op.intersect()
         rms = st[2]
-        if t > 0:
-            rho = best_out / rms
-            if rho < ratio:
-                if grace_out:
-                    break
-                grace_out = True
-        best_out = min(best_out, rms)
+        if outer is None:
+            outer = RatioRule(rms, ratio)
+        elif not outer.step(rms):
+            break
         active = np.ones(L, dtype=np.uint8)
         steps = np.zeros(L, dtype=np.int64)
-        best = None
-        grace = np.zeros(L, dtype=bool)
+        rules = None
         for s in range(I_max):
             bs, fails = op.lm_step(active)
-            on = active.astype(bool)
-            steps[on] += 1
-            if best is None:
-                best = bs[:, 0].copy()
-            cost = bs[:, 1]
-            slow = on & (best / np.where(on, cost, 1.0) < ratio)
-            stop = slow & grace
-            grace |= slow
-            best = np.where(on, np.minimum(best, cost), best)
-            active[stop] = 0
+            if rules is None:
+                rules = [RatioRule(bs[l, 0], ratio) for l in range(L)]
+            for l in range(L):
+                if active[l]:
+                    steps[l] += 1
+                    if not rules[l].step(bs[l, 1]):
+                        active[l] = 0
             if not active.any():
                 break
         op.consensus()

@@ -813,6 +813,24 @@ void orc_get_copies(orc_problem* h, int32_t* blk, int32_t* pt, double* X, double
   }
 }
 
+// Test hook: place every copy X_j^l by hand (copies in (sub-block, point)
+// order, [n][3]), e.g. to pin the consensus mean against hand-computed values.
+void orc_set_copies(orc_problem* h, const double* X) {
+  Problem& P = h->P;
+  for (size_t c = 0; c < P.copies.size(); ++c)
+    for (int r = 0; r < 3; ++r) P.copies[c].X[r] = X[3 * c + r];
+}
+
+// Test hook: replace the residuals of the last intersection ([2][K], pixels),
+// e.g. to pin the robust scale against a hand-computed MAD.
+void orc_set_residuals(orc_problem* h, const double* res) {
+  Problem& P = h->P;
+  for (int k = 0; k < P.K; ++k) {
+    P.last_res[2 * k] = res[k];
+    P.last_res[2 * k + 1] = res[(size_t)P.K + k];
+  }
+}
+
 void orc_get_weights(orc_problem* h, double* w) {
   std::memcpy(w, h->P.rw.data(), sizeof(double) * h->P.K);
 }
@@ -885,6 +903,14 @@ int orc_cholesky(int n, double* A) {
   for (int i = 0; i < n; ++i)
     for (int j = 0; j <= i; ++j) A[(size_t)i * n + j] = S[(size_t)i * n + j];
   return 0;
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 int orc_num_threads(void) {
