@@ -19,7 +19,12 @@ autotuner (measured on the box, before the timed region).
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (its per-launch time taken live with HIP events on the handle's stream in an
-eager pass), and the CPU oracle's throughput on a bounded sample.
+eager pass; for the factorisation the FLOPs of the tiles it executes), a
+second roofline entry for the Schur pass (the algorithmic bytes of the
+point-block, camera-block and camera-pair kernels over their summed time),
+the FP64 oracle's final RMS on the same schedule, and the CPU oracle's
+throughput on a bounded sample (built -O3 -march=native on the host that
+runs the bench, timed at one thread and at all threads).
 """
 from __future__ import annotations
 
@@ -42,6 +47,10 @@ KERNEL_OF_PHASE = {
     "chol_forward": ("k_chol_dataflow", ["rpba_chol.hip", "rpba_internal.hpp"]),
     "schur_pairs": ("k_schur_offdiag", ["rpba_schur.hip", "rpba_device.hpp", "rpba_internal.hpp", "rpba_plan.cpp"]),
 }
+# the kernels of the Schur pass (point blocks, camera blocks and right-hand side, camera pairs)
+SCHUR_KERNELS = [("k_copy_prep", ["rpba_kernels.hip", "rpba_device.hpp", "rpba_internal.hpp", "rpba_plan.cpp"]),
+                 ("k_schur_diag", ["rpba_schur.hip", "rpba_device.hpp", "rpba_internal.hpp", "rpba_plan.cpp"]),
+                 ("k_schur_offdiag", ["rpba_schur.hip", "rpba_device.hpp", "rpba_internal.hpp", "rpba_plan.cpp"])]
 
 
 def log(msg):
@@ -70,9 +79,8 @@ def problem_counts(scene):
     return nc, nc_tp, pairs
 
 
-def algorithmic(scene, counts, dense_blocks):
+def algorithmic(scene, counts, flops):
     """Per-launch algorithmic bytes or FLOPs of the single-kernel phases."""
-    import numpy as np
     nc, nc_tp, pairs = counts
     K, N = scene.K, scene.N
     # intersection kernel: per observation the pixel and its code in (weights
@@ -82,14 +90,29 @@ def algorithmic(scene, counts, dense_blocks):
     # its index in and its refined weight out; every camera once
     info = getattr(scene, "obs_info", None) is not None
     b_int = K * (16 + 4 + 16 + (24 if info else 0)) + N * (24 + 4 + 8 + 8 + 48 + 4 + 32 + 48) + nc * (4 + 48) + scene.M * 96
-    n6 = 6.0 * np.bincount(scene.cam_block, minlength=scene.L)[dense_blocks]
-    f_chol = float((n6 ** 3 / 3.0 + n6 ** 2).sum())
     # camera-pair Schur blocks: per observation pair its entry (copy, k1, k2),
     # the copy's point and damped inverse, two weights; one 6x6 block out per pair
     b_pairs = pairs * (12 + 72 + 16)
     return {"intersect": ("hbm", b_int, f"K*{36 + (24 if info else 0)} + N*176 + NC*52 + M*96 bytes (K={K}, N={N}, NC={nc}, M={scene.M})"),
-            "chol_forward": ("mfma", f_chol, "sum over dense sub-blocks of (6n)^3/3 + (6n)^2 FLOP"),
+            "chol_forward": ("mfma", flops["executed"],
+                             "FP64 operations of the tiles the factor can hold (zero tiles skipped): T^3/3 per "
+                             "diagonal factor, T^3 per panel solve, 2T^3 per product (T^3 onto a diagonal tile), "
+                             "forward substitution in the right-hand-side row"),
             "schur_pairs": ("hbm", b_pairs, f"pairs*100 bytes (pairs={pairs})")}
+
+
+def schur_bytes(scene, counts, dense_sizes, s):
+    """Algorithmic HBM bytes of the Schur pass (point blocks, camera blocks
+    and right-hand side, camera pairs) with bulk data of s bytes:
+    K(2s+2) + NC(3s+4) + NC_TP 9s + the dense RCS lower triangles in FP64 +
+    NC(48 + 3s) + 6 M s."""
+    import numpy as np
+    nc, nc_tp, _ = counts
+    n6 = 6.0 * np.asarray(dense_sizes, dtype=np.float64)
+    rcs = 8.0 * float((n6 * (n6 + 1) / 2).sum())
+    parts = {"observations": scene.K * (2 * s + 2), "copies": nc * (3 * s + 4), "tie_point_weights": nc_tp * 9 * s,
+             "dense_rcs": rcs, "point_block_records": nc * (48 + 3 * s), "cameras": 6 * scene.M * s}
+    return float(sum(parts.values())), parts
 
 
 def run_path(scene, opts, steps, warmup):
@@ -131,7 +154,8 @@ def run_path(scene, opts, steps, warmup):
     ph = prob.timing()
     prob.set_timing(False)
     dense = [l for l in range(scene.L) if prob.block_solver(l) == binding.RPBA_SOLVER_CHOL]
-    res = dict(ms_per_step=ms, event_ms_per_step=ev_ms, value=scene.K / (wall / steps), phases=ph, dense=dense)
+    res = dict(ms_per_step=ms, event_ms_per_step=ev_ms, value=scene.K / (wall / steps), phases=ph, dense=dense,
+               flops=prob.factor_flops())
     del prob
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -144,6 +168,7 @@ def schedule_rms(scene, opts, T, I):
     t0 = time.time()
     p, hist = binding.run_schedule(scene, T=T, I=I, graph=True, **opts)
     rms = float(hist[-1]["int_stats"][2])
+    p.close()
     del p
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -206,7 +231,9 @@ def write_traffic(fetch_csv, write_csv, command):
     ws = COPY_BYTES / 1024.0 / cw if cw else None
     out = {"calibration": {"copy_bytes": COPY_BYTES, "copy_fetch_kib": cf, "copy_write_kib": cw,
                            "fetch_scale": fs, "write_scale": ws, "command": command}}
-    for phase, (kname, files) in KERNEL_OF_PHASE.items():
+    kernels = dict(KERNEL_OF_PHASE.values())
+    kernels.update(dict(SCHUR_KERNELS))
+    for kname, files in kernels.items():
         f, w = med(fetch, kname), med(write, kname)
         if f is None or w is None or fs is None or ws is None:
             continue
@@ -230,6 +257,7 @@ def main():
     ap.add_argument("--path", default="mixed", choices=["mixed", "fp64"], help="headline path")
     ap.add_argument("--no-compare", action="store_true", help="skip the other path and the RMS comparison")
     ap.add_argument("--schedule", type=int, nargs=2, default=[6, 4], metavar=("T", "I"))
+    ap.add_argument("--no-oracle-rms", action="store_true", help="skip the FP64 oracle's run of the fixed schedule")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference for the HBM traffic counters)")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -298,7 +326,7 @@ def main():
                                       "update", "iterative_solve"))
 
     # ---- roofline of the dominant single-kernel phase
-    alg = algorithmic(scene, counts, head["dense"])
+    alg = algorithmic(scene, counts, head["flops"])
     cand = [k for k in KERNEL_OF_PHASE
             if head["phases"][k]["calls"] > 0 and
             (k != "chol_forward" or head["opts"].get("chol_schedule") == binding.RPBA_CHOL_DATAFLOW or args.no_tune)]
@@ -310,6 +338,13 @@ def main():
         ach = amount / per_launch_s / 1e12
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / FP64_PEAK_TFLOPS, 4)}
+        fl = head["flops"]
+        roof.update(gflop_per_launch=round(amount / 1e9, 3),
+                    dense_equivalent={"gflop": round(fl["dense"] / 1e9, 3),
+                                      "tflops": round(fl["dense"] / per_launch_s / 1e12, 3),
+                                      "frac": round(fl["dense"] / per_launch_s / 1e12 / FP64_PEAK_TFLOPS, 4)},
+                    mfma_issued={"gflop": round(fl["mfma_issued"] / 1e9, 3),
+                                 "tflops": round(fl["mfma_issued"] / per_launch_s / 1e12, 3)})
     else:
         ach = amount / per_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -318,25 +353,90 @@ def main():
                 algorithmic=how, source_sha=source_hash(files))
     log(f"dominant kernel {kname}: {per_launch_s * 1e3:.3f} ms per launch, {roof['achieved']} {roof['unit']}")
 
-    # ---- CPU oracle on a bounded sample: one LM step of all sub-blocks
+    # ---- the Schur pass as a whole (point blocks, camera blocks, camera pairs)
+    sb = 4 if args.path == "mixed" else 8
+    dense_sizes = np.bincount(scene.cam_block, minlength=scene.L)[head["dense"]]
+    sch_bytes, sch_parts = schur_bytes(scene, counts, dense_sizes, sb)
+    sch_ms = per_step["point_blocks"] + per_step["schur_rows"] + per_step["schur_pairs"]
+    sch_traffic = [traffic_for(k, f) for k, f in SCHUR_KERNELS]
+    roof_schur = {"bound": "hbm", "achieved": round(sch_bytes / (sch_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(sch_bytes / (sch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "traffic": (sum(sch_traffic) if all(t is not None for t in sch_traffic) else None),
+                  "kernels": [k for k, _ in SCHUR_KERNELS], "ms_per_step": round(sch_ms, 4),
+                  "bytes": sch_bytes, "bytes_parts": sch_parts,
+                  "algorithmic": f"K(2s+2) + NC(3s+4) + NC_TP 9s + dense RCS (FP64 lower triangles) + NC(48+3s) + 6Ms, "
+                                 f"s={sb} (K={scene.K}, NC={counts[0]}, NC_TP={counts[1]}, M={scene.M})",
+                  "target_frac": 0.6}
+    log(f"Schur pass: {sch_bytes / 1e9:.3f} GB in {sch_ms:.3f} ms -> {roof_schur['achieved']} GB/s")
+
+    # ---- the FP64 oracle on the same fixed schedule (final RMS), and the CPU
+    # baseline: the oracle built -O3 -march=native here, one LM step of all
+    # sub-blocks at all threads and of a bounded subset at one thread
+    import oracle
+    try:
+        native = oracle.build(force=True, native=True, path=os.path.join("/tmp", f"liboracle_native_{os.getpid()}.so"))
+        oracle.load(native)
+        build_kind = "g++ -O3 -march=native -fopenmp (built on this host)"
+    except Exception as e:  # noqa: BLE001 - fall back to the portable build
+        log(f"native oracle build failed ({e}); using the portable -O3 build")
+        oracle.lib()
+        build_kind = "g++ -O3 -fopenmp (portable build)"
+    cores = oracle.num_threads()
+    oracle_rms = None
+    if not args.no_oracle_rms and not args.no_compare:
+        t0 = time.time()
+        T, I = args.schedule
+        op, oh = oracle.run_schedule(scene, T=T, I=I, callback=lambda o, r: log(
+            f"  oracle outer iteration {r['t']}: RMS {r['int_stats'][2]:.9f}"))
+        rms_o = float(oh[-1]["int_stats"][2])
+        del op
+        oracle_rms = {"oracle_fp64": rms_o, "seconds": round(time.time() - t0, 1),
+                      "rel_diff": {p: abs(out_paths[p]["schedule_rms"] - rms_o) / rms_o for p in out_paths},
+                      "bound": 1e-6}
+        log(f"oracle fixed schedule final RMS {rms_o:.9f} px ({time.time() - t0:.1f} s); rel diff " +
+            ", ".join(f"{p} {v:.2e}" for p, v in oracle_rms["rel_diff"].items()))
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.lib()
-        t0 = time.time()
+        model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         op = oracle.OracleProblem(scene)
         op.intersect()
-        t_setup = time.time() - t0
         t0 = time.perf_counter()
         op.lm_step()
-        t_lm = time.perf_counter() - t0
-        cores = int(oracle.lib().orc_num_threads())
-        cpu = {"value": scene.K / t_lm, "unit": "obs/s", "cores": cores, "kind": "oracle",
+        t_all = time.perf_counter() - t0
+        # one thread: the sub-blocks in order until an eighth of the observations
+        ksub = np.bincount(scene.cam_block[scene.obs_cam], minlength=scene.L)
+        act = np.zeros(scene.L, dtype=np.uint8)
+        tot = 0
+        for l in np.argsort(ksub):
+            if tot >= scene.K // 8:
+                break
+            act[l] = 1
+            tot += int(ksub[l])
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        op.lm_step(act)
+        t_one = time.perf_counter() - t0
+        oracle.set_num_threads(cores)
+        del op
+        cpu = {"value": scene.K / t_all, "unit": "obs/s", "cores": cores, "kind": "oracle",
                "sample": f"one LM step (Schur complement, dense Cholesky, back-substitution and cost) of all "
-                         f"{scene.L} sub-blocks of the same block after one intersection; {t_lm:.2f} s on {cores} "
-                         f"threads (setup + intersection {t_setup:.1f} s untimed); unit is observations per LM step "
-                         f"time, the GPU value's step also includes the intersection and the consensus"}
-        log(f"oracle LM step {t_lm:.2f} s on {cores} threads -> {scene.K / t_lm / 1e6:.3f} M obs/s")
+                         f"{scene.L} sub-blocks of the same block after one intersection: {t_all:.2f} s on {cores} "
+                         f"threads; obs/s = observations / LM step time (the GPU value's step also includes the "
+                         f"intersection and the consensus)",
+               "cpu_model": model, "build": build_kind,
+               "single_thread": {"value": tot / t_one, "unit": "obs/s", "cores": 1,
+                                 "sample": f"one LM step of the {int(act.sum())} smallest sub-blocks "
+                                           f"({tot} observations): {t_one:.2f} s on 1 thread"}}
+        log(f"oracle LM step {t_all:.2f} s on {cores} threads -> {scene.K / t_all / 1e6:.3f} M obs/s; "
+            f"1 thread {tot / t_one / 1e6:.3f} M obs/s ({model})")
 
     out = {
         "metric": "LM-iteration throughput (obs/s), mixed+learned vs FP64 plain, same final RMS",
@@ -355,23 +455,33 @@ def main():
                    "cameras": scene.M, "points": scene.N, "observations": scene.K, "subblocks": scene.L,
                    "path": args.path, "options": head["opts"],
                    "step": "intersect + subblock LM step + consensus (HIP graphs)", "seed": args.seed},
+        "headline_path": ("mixed precision (FP32 Jacobians and Schur accumulation, FP64 point inverses, state and "
+                          "reduced-camera factorisation); solver per sub-block as the autotuner chose "
+                          "(learned-preconditioner PCG is timed in 'learned_pcg')") if args.path == "mixed" else "FP64",
         "roofline": roof,
+        "roofline_schur": roof_schur,
         "cpu_baseline": cpu,
         "lm_step_ms": lm_ms,
         "phase_ms_per_step": per_step,
         "tuning": head["tuning"],
+        "final_rms_vs_oracle": oracle_rms,
     }
     if not args.no_compare:
         other = [p for p in out_paths if p != args.path][0]
         o = out_paths[other]
+        ratio = (head["value"] / out_paths["fp64"]["value"]) if "fp64" in out_paths else None
         out["compare"] = {
             other: {"value": o["value"], "ms_per_step": o["ms_per_step"], "options": o["opts"]},
-            "throughput_ratio_vs_fp64": (head["value"] / out_paths["fp64"]["value"]) if "fp64" in out_paths else None,
+            "throughput_ratio_vs_fp64": ratio,
             "final_rms_px": {p: out_paths[p]["schedule_rms"] for p in out_paths},
             "final_rms_rel_diff": abs(out_paths["mixed"]["schedule_rms"] - out_paths["fp64"]["schedule_rms"]) /
                                   out_paths["fp64"]["schedule_rms"],
             "schedule": {"outer_iterations": args.schedule[0], "lm_steps": args.schedule[1]},
         }
+        out["targets"] = {"throughput_ratio_vs_fp64": {"target": 5.0, "achieved": ratio},
+                          "schur_hbm_frac": {"target": 0.6, "achieved": roof_schur["frac"]},
+                          "final_rms_rel_vs_oracle": {"target": 1e-6, "achieved": (
+                              oracle_rms["rel_diff"].get(args.path) if oracle_rms else None)}}
     print(json.dumps(out), flush=True)
 
 

@@ -9,9 +9,9 @@
  * in camera i with 2x2 covariance C_xk (weight W_k = C_xk^-1), residual
  * v_k = g_k(P_i, X_j) - x_k with the calibrated pinhole
  *     p = R_i (X_j - C_i),  g = (f p1/p3 + cx, f p2/p3 + cy).
- * The cameras are split into L sub-blocks, each camera in exactly one
- * (Sec. 4, "every camera is just contained in one sub-block"); points seen by
- * cameras of two or more sub-blocks are tie points (TPs).
+ * The cameras are split into L sub-blocks and each camera belongs to exactly
+ * one of them (Sec. 4); points seen by cameras of two or more sub-blocks are
+ * tie points (TPs).
  *
  * One outer iteration of the method (Sec. 5) is
  *     rpba_intersect          eq:bars + refined re-weighting (Sec. 5.1)
@@ -50,7 +50,8 @@ typedef enum {
   RPBA_ERR_HIP = 2,        /* a HIP runtime call failed */
   RPBA_ERR_WORKSPACE = 3,  /* workspace too small or misaligned (256 B) */
   RPBA_ERR_NOT_SPD = 4,    /* a reduced camera system was not positive definite */
-  RPBA_ERR_STATE = 5       /* call not valid in the handle's state */
+  RPBA_ERR_STATE = 5,      /* call not valid in the handle's state */
+  RPBA_WARN_NONCONVERGED = 100 /* an iterative solve ended above its tolerance (rpba_step_status) */
 } rpba_status;
 
 /* precision policy */
@@ -114,7 +115,10 @@ rpba_status rpba_workspace_size(const rpba_problem_desc *desc, const rpba_option
  * TPs derived from it) and pack the observation streams into the workspace.
  * Checks: indices in range, every point observed at least twice, every
  * camera observed at least once, every sub-block non-empty, no repeated
- * (camera, point) pair, finite inputs.  `workspace` is a device buffer of at
+ * (camera, point) pair (host, on the topology arrays); every value of cam_R,
+ * cam_C, pts, obs_xy and obs_info finite and every obs_info matrix positive
+ * definite (one device reduction; RPBA_ERR_ARG names the counts).
+ * `workspace` is a device buffer of at
  * least rpba_workspace_size bytes, 256-byte aligned, owned by the caller for
  * the life of the handle.  `stream` is a hipStream_t (NULL = default).
  * *out is HOST. */
@@ -162,6 +166,28 @@ rpba_status rpba_get_robust(rpba_problem *h, double *sigma_cam, double *obs_weig
  *               (or NULL) */
 rpba_status rpba_subblock_lm_step(rpba_problem *h, const uint8_t *active, double *block_stats);
 
+/* Outcome of the last rpba_subblock_lm_step, per sub-block (synchronises the
+ * handle's stream).  A sub-block whose reduced camera system had a
+ * non-positive Cholesky pivot (or a non-positive-definite 6x6 diagonal block
+ * under PCG) is counted in *n_not_spd; its cameras and point copies were left
+ * unchanged (block_stats: cost after = cost before, iterations -1).  An
+ * iterative sub-block whose FP64 refinement residual |e - S x| / |e| ended
+ * above ir_tol is counted in *n_nonconverged; its step was applied.  Both
+ * outputs HOST, either may be NULL.  Returns RPBA_ERR_NOT_SPD if any
+ * sub-block failed, else RPBA_WARN_NONCONVERGED if any did not converge,
+ * else RPBA_OK. */
+rpba_status rpba_step_status(rpba_problem *h, int32_t *n_not_spd, int32_t *n_nonconverged);
+
+/* Improvement test that ends a loop (Sec. 5.4), for n loops at once (one per
+ * sub-block for the inner LM loop, or one for the outer loop on the RMS).
+ * HOST arrays, no GPU work.  For every loop q with active[q] != 0 the step
+ * with cost[q] is short when best[q] / cost[q] < ratio (1.01); the first
+ * short step is tolerated (grace[q] = 1), the second ends the loop
+ * (active[q] = 0); then best[q] = min(best[q], cost[q]).  Start a loop with
+ * best = the cost before its first step, grace = 0, active = 1.  Returns the
+ * number of loops still active, or -1 for a NULL array or n < 0. */
+int32_t rpba_ratio_update(int32_t n, const double *cost, double ratio, double *best, uint8_t *grace, uint8_t *active);
+
 /* Consensus exchange (Sec. 5): cameras go back to desc->cam_R / cam_C; every
  * point's start value for the next intersection is the mean of its sub-block
  * copies (eq:admm8 form), written to desc->pts.
@@ -192,14 +218,33 @@ const char *rpba_last_error(void);
  * rpba_block_cameras: number of cameras of sub-block l. */
 int64_t rpba_num_copies(rpba_problem *h);
 rpba_status rpba_get_copies(rpba_problem *h, int32_t *blk, int32_t *pt, double *X, double *omega);
-rpba_status rpba_set_debug(rpba_problem *h, int32_t on);
 rpba_status rpba_get_block_rcs(rpba_problem *h, int32_t l, double *S, double *e);
 int32_t rpba_block_cameras(rpba_problem *h, int32_t l);
 /* rpba_get_block_solution: the camera step (n6 values) of sub-block l from the
  * last rpba_subblock_lm_step, cameras in ascending original index.
- * rpba_block_solver: 0 = Cholesky, 1 = iterative. */
+ * rpba_block_solver: 0 = Cholesky, 1 = iterative.
+ * rpba_camera_order: cam_orig[M] = the caller's index of every camera in the
+ *   library's order (the order of the preconditioner's probe vectors and
+ *   training samples).
+ * rpba_get_precond_blocks: the 6x6 CG preconditioner blocks (row-major) of the
+ *   cameras of iterative sub-block l used by the last rpba_subblock_lm_step,
+ *   P [ncam][36], cameras in ascending original index. */
 rpba_status rpba_get_block_solution(rpba_problem *h, int32_t l, double *x);
 int32_t rpba_block_solver(rpba_problem *h, int32_t l);
+rpba_status rpba_camera_order(rpba_problem *h, int32_t *cam_orig);
+/* rpba_factor_flops: work of one factorisation of the sub-blocks solved by
+ *   Cholesky (Sec. 2), HOST out[3]:
+ *   [0] the method's FP64 operations on the tiles the factor can hold (tiles
+ *       that stay zero are skipped): T^3/3 per diagonal factor, T^3 per panel
+ *       solve, 2 T^3 per tile product below the diagonal and T^3 per product
+ *       onto a diagonal tile, plus the forward substitution folded into the
+ *       right-hand-side row (2 T^2 per product, T^2 per solve);
+ *   [1] the dense count sum over the sub-blocks of (6n)^3/3 + (6n)^2;
+ *   [2] the FP64 matrix-core operations the persistent launch issues: 2 T^3
+ *       per tile product and panel solve (right-hand-side row included) and
+ *       the 16 x 16 block products inside every diagonal tile. */
+rpba_status rpba_factor_flops(rpba_problem *h, double *out);
+rpba_status rpba_get_precond_blocks(rpba_problem *h, int32_t l, double *P);
 
 /* ------------------------------------------------ learned block preconditioner
  * With RPBA_SOLVER_PCG_LEARNED the CG preconditioner keeps the block-diagonal
@@ -251,10 +296,6 @@ rpba_status rpba_precond_train_step(const float *samples, int32_t nsamp, int32_t
 rpba_status rpba_set_graph(rpba_problem *h, int32_t on);
 rpba_status rpba_set_timing(rpba_problem *h, int32_t on);
 int32_t rpba_get_timing(rpba_problem *h, double *ms, int64_t *launches, int64_t *calls, int32_t n);
-
-/* Self-test of the FP64 matrix-core tile product used by the Cholesky:
- * C = A B^T for 64 x 64 row-major device tiles, one workgroup on `stream`. */
-rpba_status rpba_selftest_gemm(const double *A, const double *B, double *C, void *stream);
 
 #ifdef __cplusplus
 }

@@ -19,16 +19,19 @@ LIB_PATH = os.path.join(PKG, "librpba.so")
 RPBA_FP64, RPBA_MIXED = 0, 1
 RPBA_SOLVER_CHOL, RPBA_SOLVER_PCG_BJ, RPBA_SOLVER_PCG_LEARNED, RPBA_SOLVER_AUTO = 0, 1, 2, 3
 RPBA_CHOL_DEFAULT, RPBA_CHOL_STEPWISE, RPBA_CHOL_DATAFLOW = 0, 1, 2
-STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_WORKSPACE", 4: "ERR_NOT_SPD", 5: "ERR_STATE"}
+RPBA_OK, RPBA_ERR_NOT_SPD, RPBA_WARN_NONCONVERGED = 0, 4, 100
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_WORKSPACE", 4: "ERR_NOT_SPD", 5: "ERR_STATE",
+                100: "WARN_NONCONVERGED"}
 
-# every symbol include/rpba.h declares
+# every symbol include/rpba.h and include/rpba_testing.h declare
 EXPORTS = [
     "rpba_default_options", "rpba_workspace_size", "rpba_create", "rpba_intersect", "rpba_robust_reweight",
     "rpba_subblock_lm_step", "rpba_consensus", "rpba_destroy", "rpba_last_error", "rpba_num_copies",
-    "rpba_get_copies", "rpba_set_debug", "rpba_get_block_rcs", "rpba_block_cameras", "rpba_selftest_gemm",
+    "rpba_get_copies", "rpba_get_block_rcs", "rpba_block_cameras", "rpba_selftest_gemm",
     "rpba_set_graph", "rpba_set_timing", "rpba_get_timing", "rpba_get_block_solution", "rpba_block_solver",
     "rpba_precond_num_params", "rpba_set_precond_weights", "rpba_precond_num_samples", "rpba_precond_sample_stride",
     "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
+    "rpba_step_status", "rpba_ratio_update", "rpba_camera_order", "rpba_get_precond_blocks", "rpba_factor_flops",
 ]
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
           "robust", "iterative_solve", "schur_pairs", "intersect_export"]
@@ -86,7 +89,6 @@ def load_library(path: str = LIB_PATH):
     L.rpba_num_copies.restype = i64
     L.rpba_num_copies.argtypes = [vp]
     L.rpba_get_copies.argtypes = [vp, vp, vp, vp, vp]
-    L.rpba_set_debug.argtypes = [vp, i32]
     L.rpba_get_block_rcs.argtypes = [vp, i32, vp, vp]
     L.rpba_block_cameras.restype = i32
     L.rpba_block_cameras.argtypes = [vp, i32]
@@ -105,6 +107,12 @@ def load_library(path: str = LIB_PATH):
     L.rpba_get_block_solution.argtypes = [vp, i32, vp]
     L.rpba_block_solver.restype = i32
     L.rpba_block_solver.argtypes = [vp, i32]
+    L.rpba_step_status.argtypes = [vp, vp, vp]
+    L.rpba_ratio_update.restype = i32
+    L.rpba_ratio_update.argtypes = [i32, vp, ctypes.c_double, vp, vp, vp]
+    L.rpba_camera_order.argtypes = [vp, vp]
+    L.rpba_get_precond_blocks.argtypes = [vp, i32, vp]
+    L.rpba_factor_flops.argtypes = [vp, vp]
     L.rpba_set_graph.argtypes = [vp, i32]
     L.rpba_set_timing.argtypes = [vp, i32]
     L.rpba_get_timing.restype = i32
@@ -112,7 +120,7 @@ def load_library(path: str = LIB_PATH):
     for name in EXPORTS:
         if name not in ("rpba_last_error", "rpba_num_copies", "rpba_block_cameras", "rpba_get_timing",
                         "rpba_block_solver", "rpba_precond_num_params", "rpba_precond_num_samples",
-                        "rpba_precond_sample_stride", "rpba_precond_train_scratch"):
+                        "rpba_precond_sample_stride", "rpba_precond_train_scratch", "rpba_ratio_update"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -154,6 +162,21 @@ def precond_train_step(samples, nz, W, m, v, t, lr, scratch, grad, loss, apply=T
 
 def precond_train_scratch_bytes(nsamp):
     return int(load_library().rpba_precond_train_scratch(int(nsamp)))
+
+
+def ratio_update(cost, best, grace, active, ratio=1.01):
+    """Improvement test of Sec. 5.4 for len(cost) loops at once, in the
+    library (rpba_ratio_update): updates best (float64), grace and active
+    (uint8) in place and returns the number of loops still active."""
+    L = load_library()
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    for a, t in ((best, np.float64), (grace, np.uint8), (active, np.uint8)):
+        assert a.dtype == t and a.flags.c_contiguous and a.shape == cost.shape
+    n = L.rpba_ratio_update(int(cost.size), cost.ctypes.data, float(ratio), best.ctypes.data, grace.ctypes.data,
+                            active.ctypes.data)
+    if n < 0:
+        raise RpbaError("rpba_ratio_update: bad arguments")
+    return int(n)
 
 
 def selftest_gemm(A, B):
@@ -335,6 +358,37 @@ class Problem:
     def block_solver(self, l):
         return int(self.L_.rpba_block_solver(self.h, l))
 
+    def step_status(self):
+        """(status code, sub-blocks not positive definite, iterative sub-blocks
+        above the refinement tolerance) of the last LM step."""
+        a = ctypes.c_int32(0)
+        b = ctypes.c_int32(0)
+        rc = int(self.L_.rpba_step_status(self.h, ctypes.byref(a), ctypes.byref(b)))
+        if rc not in (RPBA_OK, RPBA_ERR_NOT_SPD, RPBA_WARN_NONCONVERGED):
+            _check(rc, "rpba_step_status")
+        return rc, a.value, b.value
+
+    def factor_flops(self):
+        """(method's FP64 operations on the factor's nonzero tiles, dense
+        count, matrix-core operations issued) of one factorisation."""
+        out = np.zeros(3)
+        _check(self.L_.rpba_factor_flops(self.h, out.ctypes.data), "rpba_factor_flops")
+        return dict(executed=float(out[0]), dense=float(out[1]), mfma_issued=float(out[2]))
+
+    def camera_order(self):
+        """Caller index of every camera in the library's order."""
+        o = np.zeros(self.M, dtype=np.int32)
+        _check(self.L_.rpba_camera_order(self.h, o.ctypes.data), "rpba_camera_order")
+        return o
+
+    def precond_blocks(self, l):
+        """CG preconditioner blocks (ncam, 6, 6) of iterative sub-block l from
+        the last LM step, cameras in ascending caller index."""
+        n = int(self.L_.rpba_block_cameras(self.h, l))
+        P = np.zeros((n, 6, 6))
+        _check(self.L_.rpba_get_precond_blocks(self.h, l, P.ctypes.data), "rpba_get_precond_blocks")
+        return P
+
     def cameras(self):
         self.stream.synchronize()
         return self.cam_R.cpu().numpy(), self.cam_C.cpu().numpy()
@@ -382,50 +436,36 @@ def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, graph=Fals
 
 
 def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, graph=False, **opts):
-    """Schedule driven by the improvement test of the method (Sec. 5.4): a
-    loop continues while best-cost-so-far / current-cost reaches `ratio`; the
-    first step that falls short is tolerated once, the second ends the loop.
-    The inner loop runs per sub-block on its cost, a stopped sub-block being
-    masked out of the later steps of the outer iteration (the `active` mask
-    of rpba_subblock_lm_step); the outer loop runs on the reprojection RMS of
-    the intersections.  Returns the problem and per outer iteration the
-    number of LM steps each sub-block took."""
+    """Schedule driven by the improvement test of the method (Sec. 5.4,
+    rpba_ratio_update): inner loop per sub-block on its cost, a stopped
+    sub-block being masked out of the later steps of the outer iteration (the
+    `active` mask of rpba_subblock_lm_step); outer loop on the reprojection
+    RMS of the intersections.  Returns the problem and per outer iteration
+    the number of LM steps each sub-block took."""
     import torch
     p = Problem(scene, **opts)
     if graph:
         p.set_graph(True)
     L = scene.L
     hist = []
-    best_out, grace_out = np.inf, False
+    o_best, o_grace, o_act = np.zeros(1), np.zeros(1, np.uint8), np.ones(1, np.uint8)
     act_dev = torch.ones(L, dtype=torch.uint8, device=p.dev)
     for t in range(T_max):
         st = _host(p, p.rpba_intersect())
-        rms = st[2]
-        if t > 0:
-            if best_out / rms < ratio:
-                if grace_out:
-                    break
-                grace_out = True
-        best_out = min(best_out, rms)
+        if t == 0:
+            o_best[0] = st[2]
+        elif ratio_update(st[2:3], o_best, o_grace, o_act, ratio) == 0:
+            break
         active = np.ones(L, dtype=np.uint8)
         steps = np.zeros(L, dtype=np.int64)
-        best = None
-        grace = np.zeros(L, dtype=bool)
+        best = grace = None
         for s in range(I_max):
             act_dev.copy_(torch.as_tensor(active))
             bs = _host(p, p.rpba_subblock_lm_step(act_dev))
-            on = active.astype(bool)
-            steps[on] += 1
+            steps[active.astype(bool)] += 1
             if best is None:
-                best = bs[:, 0].copy()
-            cost = bs[:, 1]
-            with np.errstate(divide="ignore", invalid="ignore"):
-                slow = on & (best / np.where(on, cost, 1.0) < ratio)
-            stop = slow & grace
-            grace |= slow
-            best = np.where(on, np.minimum(best, cost), best)
-            active[stop] = 0
-            if not active.any():
+                best, grace = bs[:, 0].copy(), np.zeros(L, np.uint8)
+            if ratio_update(bs[:, 1], best, grace, active, ratio) == 0:
                 break
         p.rpba_consensus()
         hist.append(dict(t=t, int_stats=st, steps=steps))

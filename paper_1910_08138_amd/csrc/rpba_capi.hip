@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/rpba.h"
+#include "../../include/rpba_testing.h"
 #include "rpba_internal.hpp"
 #include "rpba_plan.hpp"
 
@@ -50,7 +51,7 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info;
+      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk;
   size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -103,6 +104,8 @@ WsMap layout_for(const Plan& P) {
   m.upd_items = L.add(i4 * P.upd_items.size());
   m.pot_items = L.add(i4 * P.pot_items.size());
   m.blk_fail = L.add(i4 * P.L);
+  m.blk_nc = L.add(i4 * P.L);
+  m.chk = L.add(i4 * 4);
   m.pb_row = L.add(i4 * P.pb_row.size());
   m.pb_ent_off = L.add(i8 * P.pb_ent_off.size());
   m.pb_ent = L.add(i4 * P.pb_ent.size());
@@ -629,11 +632,24 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.diag_off = (const int64_t*)(w + m.diag_off);
   D.vec_off = (const int64_t*)(w + m.vec_off);
   D.blk_fail = I(m.blk_fail);
+  D.blk_nc = I(m.blk_nc);
   D.acc_int = F(m.acc_int);
   D.acc_blk = F(m.acc_blk);
   D.acc_cons = F(m.acc_cons);
   D.acc_rob = F(m.acc_rob);
 
+  // finite inputs, positive definite information matrices
+  {
+    int32_t* cnt = I(m.chk);
+    launch_zero_i32(cnt, 2, st);
+    launch_check_inputs(D, cnt, st);
+    int32_t hc[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hc[0] || hc[1])
+      return fail(RPBA_ERR_ARG, std::to_string(hc[0]) + " non-finite input values (cam_R, cam_C, pts, obs_xy, obs_info), " +
+                                    std::to_string(hc[1]) + " obs_info matrices not positive definite");
+  }
   // packing kernels, zero state, identity padding
   launch_gather(D, st);
   launch_zero(D.Xc, 3 * D.NC, st);
@@ -646,6 +662,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero(D.ys, p.vec_total, st);
   launch_zero(D.x, p.vec_total, st);
   launch_zero_i32(D.blk_fail, D.L, st);
+  launch_zero_i32(D.blk_nc, D.L, st);
   launch_zero_i32((int32_t*)(w + m.df_flags), p.rcs_total / ((int64_t)p.T * p.T), st);
   launch_zero_i32((int32_t*)(w + m.df_ctl), 4, st);
   launch_df_reset((int32_t*)(w + m.df_ctl), st);
@@ -851,11 +868,6 @@ int32_t rpba_block_cameras(rpba_problem* h, int32_t l) {
   return h->plan->blk_cam_off[l + 1] - h->plan->blk_cam_off[l];
 }
 
-rpba_status rpba_set_debug(rpba_problem* h, int32_t on) {
-  (void)on;
-  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
-  return RPBA_OK;
-}
 
 rpba_status rpba_get_copies(rpba_problem* h, int32_t* blk, int32_t* pt, double* X, double* omega) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
@@ -958,6 +970,101 @@ rpba_status rpba_get_block_solution(rpba_problem* h, int32_t l, double* x) {
 int32_t rpba_block_solver(rpba_problem* h, int32_t l) {
   if (!h || l < 0 || l >= h->plan->L) return -1;
   return h->blk_pcg[l] ? 1 : 0;
+}
+
+rpba_status rpba_camera_order(rpba_problem* h, int32_t* cam_orig) {
+  if (!h || !cam_orig) return fail(RPBA_ERR_ARG, "NULL argument");
+  std::memcpy(cam_orig, h->plan->cam_orig.data(), 4 * (size_t)h->plan->M);
+  return RPBA_OK;
+}
+
+rpba_status rpba_factor_flops(rpba_problem* h, double* out) {
+  if (!h || !out) return fail(RPBA_ERR_ARG, "NULL argument");
+  const Plan& p = *h->plan;
+  const double T = p.T, T2 = T * T, T3 = T2 * T;
+  // 16 x 16 block products inside one diagonal tile: trailing updates of
+  // the panels plus the blocks of the inverse, 2 * 16^3 operations each
+  const int nbk = p.T / 16;
+  int64_t blk16 = 0;
+  for (int kb = 0; kb < nbk; ++kb) blk16 += (int64_t)(nbk - 1 - kb) * (nbk - kb) / 2;
+  for (int r = 1; r < nbk; ++r)
+    for (int j = 0; j < r; ++j) blk16 += r - j + 1;
+  const double diag_mfma = 2.0 * 4096.0 * (double)blk16;
+  double alg = 0.0, dense = 0.0, mfma = 0.0;
+  for (int l = 0; l < p.L; ++l) {
+    if (h->blk_pcg[l]) continue;
+    const double n6 = 6.0 * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
+    dense += n6 * n6 * n6 / 3.0 + n6 * n6;
+    const int nt = p.nt[l];
+    const uint8_t* z = p.tile_nz.data() + p.rcs_off[l] / ((int64_t)p.T * p.T);
+    auto nz = [&](int i, int j) { return z[(int64_t)i * (i + 1) / 2 + j] != 0; };
+    for (int j = 0; j < nt; ++j)
+      for (int i = j; i <= nt; ++i) {
+        if (!nz(i, j)) continue;
+        int64_t prods = 0;
+        for (int k = 0; k < j; ++k) prods += nz(i, k) && nz(j, k);
+        if (i == nt) {
+          alg += 2.0 * T2 * prods + T2;
+        } else if (i == j) {
+          alg += T3 * prods + T3 / 3.0;
+        } else {
+          alg += 2.0 * T3 * prods + T3;
+        }
+        mfma += 2.0 * T3 * prods + (i == j ? diag_mfma : 2.0 * T3);
+      }
+  }
+  out[0] = alg;
+  out[1] = dense;
+  out[2] = mfma;
+  return RPBA_OK;
+}
+
+rpba_status rpba_get_precond_blocks(rpba_problem* h, int32_t l, double* P) {
+  if (!h || !P) return fail(RPBA_ERR_ARG, "NULL argument");
+  const Plan& p = *h->plan;
+  if (l < 0 || l >= p.L) return fail(RPBA_ERR_ARG, "sub-block out of range");
+  if (!h->blk_pcg[l]) return fail(RPBA_ERR_STATE, "sub-block is not solved iteratively");
+  const int32_t b = p.blk_cam_off[l], n = p.blk_cam_off[l + 1] - b;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  std::vector<float> t((size_t)36 * n);
+  HIP_TRY(hipMemcpy(t.data(), h->d.Pblk + (size_t)36 * b, 4 * t.size(), hipMemcpyDeviceToHost));
+  const std::vector<int32_t> rank = block_caller_rank(p, l);
+  for (int32_t a = 0; a < n; ++a)
+    for (int q = 0; q < 36; ++q) P[(size_t)36 * rank[a] + q] = t[(size_t)36 * a + q];
+  return RPBA_OK;
+}
+
+rpba_status rpba_step_status(rpba_problem* h, int32_t* n_not_spd, int32_t* n_nonconverged) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  const int L = h->plan->L;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  std::vector<int32_t> f(L), nc(L);
+  HIP_TRY(hipMemcpy(f.data(), h->d.blk_fail, 4 * (size_t)L, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(nc.data(), h->d.blk_nc, 4 * (size_t)L, hipMemcpyDeviceToHost));
+  int32_t a = 0, b = 0;
+  for (int l = 0; l < L; ++l) {
+    a += f[l] != 0;
+    b += nc[l] != 0;
+  }
+  if (n_not_spd) *n_not_spd = a;
+  if (n_nonconverged) *n_nonconverged = b;
+  if (a) return fail(RPBA_ERR_NOT_SPD, std::to_string(a) + " sub-block(s) with a reduced camera system that is not positive definite");
+  if (b) return fail(RPBA_WARN_NONCONVERGED, std::to_string(b) + " iterative sub-block(s) above the refinement tolerance");
+  return RPBA_OK;
+}
+
+int32_t rpba_ratio_update(int32_t n, const double* cost, double ratio, double* best, uint8_t* grace, uint8_t* active) {
+  if (n < 0 || (n > 0 && (!cost || !best || !grace || !active))) return -1;
+  int32_t live = 0;
+  for (int32_t q = 0; q < n; ++q) {
+    if (!active[q]) continue;
+    const bool slow = best[q] / cost[q] < ratio;
+    if (slow && grace[q]) active[q] = 0;
+    if (slow) grace[q] = 1;
+    best[q] = std::min(best[q], cost[q]);
+    live += active[q] != 0;
+  }
+  return live;
 }
 
 int32_t rpba_precond_num_params(void) { return mlp_num_params(); }

@@ -111,7 +111,8 @@ struct Dev {
   const uint8_t* tile_nz;  // [rcs_total / T^2] tile of the factor may be nonzero (plan's numbering)
   const int64_t* diag_off;
   const int64_t* vec_off;
-  int32_t* blk_fail;      // [L]
+  int32_t* blk_fail;      // [L] factorisation failed (non-positive pivot): step not applied
+  int32_t* blk_nc;        // [L] iterative solve ended above its refinement tolerance
   const uint8_t* active;  // [L] or null (set per call)
 
   // accumulators
@@ -144,6 +145,10 @@ __host__ __device__ __forceinline__ int64_t rcs_elem(const Dev& d, int l, int ro
 
 // kernel launchers (all asynchronous on `st`)
 void launch_gather(const Dev& d, hipStream_t st);
+// counts into cnt[0] the non-finite values of the caller's state and
+// observation arrays and into cnt[1] the information matrices that are not
+// positive definite (cnt zeroed by the caller)
+void launch_check_inputs(const Dev& d, int32_t* cnt, hipStream_t st);
 void launch_init_rcs(const Dev& d, hipStream_t st);
 // the intersection itself (point records, and covariances if want_cov), then
 // the caller-order export of points, covariances, statuses and the statistics

@@ -94,6 +94,32 @@ __global__ void k_gather_obs(Dev d) {
   d.res[2 * k + 1] = 0.0;
 }
 
+// input check of rpba_create: non-finite values of the caller's arrays, and
+// information matrices that are not positive definite (w11 > 0, det > 0)
+__global__ void k_check_inputs(Dev d, int32_t* cnt) {
+  const int64_t n1 = 9 * (int64_t)d.M, n2 = n1 + 3 * (int64_t)d.M, n3 = n2 + 3 * (int64_t)d.N,
+                n4 = n3 + 2 * (int64_t)d.K, n5 = n4 + (d.u_info ? 3 * (int64_t)d.K : 0);
+  int bad = 0, npd = 0;
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n5; t += (int64_t)gridDim.x * NT) {
+    const double v = t < n1 ? d.u_camR[t] : t < n2 ? d.u_camC[t - n1] : t < n3 ? d.u_pts[t - n2]
+                   : t < n4 ? d.u_xy[t - n3] : d.u_info[t - n4];
+    bad += !isfinite(v);
+  }
+  if (d.u_info)
+    for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < d.K; k += (int64_t)gridDim.x * NT) {
+      const double a = d.u_info[k], b = d.u_info[(int64_t)d.K + k], c = d.u_info[2 * (int64_t)d.K + k];
+      npd += !(a > 0.0 && a * c - b * b > 0.0);
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    bad += __shfl_xor(bad, o);
+    npd += __shfl_xor(npd, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (bad) atomicAdd(&cnt[0], bad);
+    if (npd) atomicAdd(&cnt[1], npd);
+  }
+}
+
 // camera-major copies of the pixels and weights (after k_gather_obs)
 __global__ void k_gather_cm(Dev d) {
   const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -1008,6 +1034,10 @@ void launch_gather(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
 }
 
+void launch_check_inputs(const Dev& d, int32_t* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_inputs, dim3(1024), dim3(NT), 0, st, d, cnt);
+}
+
 void launch_init_rcs(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_pad_identity, dim3(d.L), dim3(NT), 0, st, d);
 }
@@ -1027,6 +1057,7 @@ void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, dou
 void launch_copy_prep(const Dev& d, hipStream_t st) {
   launch_zero(d.acc_blk, 4 * (int64_t)d.L, st);
   launch_zero_i32(d.blk_fail, d.L, st);
+  launch_zero_i32(d.blk_nc, d.L, st);
   hipLaunchKernelGGL(k_copy_prep, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
 }
 

@@ -169,8 +169,16 @@ __global__ __launch_bounds__(PT) void k_pcg(Dev d, const int32_t* __restrict__ b
     for (int t = threadIdx.x; t < n; t += PT) r[t] = e[t] - r[t];
     __syncthreads();
   }
+  // the refinement residual the sweeps ended with (r = e - S x of the last
+  // sweep, or e itself when no sweep ran)
+  double rf = 0.0;
+  for (int t = threadIdx.x; t < n; t += PT) rf += r[t] * r[t];
+  rf = sqrt(wg_sum(rf, red));
   for (int t = threadIdx.x; t < n; t += PT) d.x[vb + t] = x[t];
-  if (threadIdx.x == 0) d.acc_blk[4 * l + 3] = (double)iters;
+  if (threadIdx.x == 0) {
+    d.acc_blk[4 * l + 3] = (double)iters;
+    if (d.blk_fail[l] == 0 && !(rf <= ir_tol * ne)) d.blk_nc[l] = 1;
+  }
 }
 
 }  // namespace

@@ -139,7 +139,8 @@ def test_fixed_schedule_parity(rp, name, T, I, graph):
             assert fails == 0
             assert np.allclose(bg[:, 0], bo[:, 0], rtol=TOL, atol=0)
             assert np.allclose(bg[:, 1], bo[:, 1], rtol=TOL, atol=0)
-            assert np.allclose(bg[:, 2], bo[:, 2], rtol=1e-7, atol=1e-12)
+            print(f"step norm rel err {np.max(np.abs(bg[:, 2] - bo[:, 2]) / np.maximum(bo[:, 2], 1e-300)):.2e}")
+            assert np.allclose(bg[:, 2], bo[:, 2], rtol=TOL, atol=1e-15)
         if "consensus" in g:
             assert g["consensus"][1] == o["consensus"][1]
             assert abs(g["consensus"][0] - o["consensus"][0]) <= TOL * _extent(s)
@@ -167,7 +168,7 @@ def test_active_mask_skips_subblocks(rp):
     gp.sync()
     bg = bg.cpu().numpy()
     bo, _ = op.lm_step(act)
-    assert np.allclose(bg, bo, rtol=1e-7, atol=0)
+    assert np.allclose(bg, bo, rtol=TOL, atol=0)
     gR, gC = gp.cameras()
     oR, oC = op.cameras()
     # the GPU writes cameras back at consensus

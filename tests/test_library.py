@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "rpba.h")).read()
+    txt = "".join(open(os.path.join(ROOT, "include", h)).read() for h in ("rpba.h", "rpba_testing.h"))
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(rpba_[a-z_]+)\s*\(", txt)))
 
@@ -100,3 +100,37 @@ def test_validation_rejects_empty_subblock_and_bad_tile():
     assert rc == 1 and "chol_tile" in msg
     rc, _, msg = _size(s, chol_schedule=7)
     assert rc == 1 and "chol_schedule" in msg
+
+
+@pytest.mark.parametrize("first,costs,steps", [
+    # the hand-worked sequences of the oracle's pin (tests/test_oracle_hand_pins.py)
+    (100.0, [50.0, 49.8, 30.0, 29.9, 10.0], 4),
+    (100.0, [99.5, 99.2, 50.0], 2),
+    (10.0, [11.0, 9.0, 8.99, 1.0], 3),
+    (100.0, [90.0, 80.0, 70.0], 3),
+    (101.0, [100.0, 99.0], 2),
+])
+def test_library_ratio_rule_hand_sequences(first, costs, steps):
+    """Sec. 5.4 improvement test in the library (host code, no GPU work):
+    a step with best-so-far / cost below 1.01 is tolerated once, the second
+    ends the loop."""
+    best, grace, act = np.array([first]), np.zeros(1, np.uint8), np.ones(1, np.uint8)
+    taken = 0
+    for c in costs:
+        taken += 1
+        if binding.ratio_update(np.array([c]), best, grace, act) == 0:
+            break
+    assert taken == steps
+
+
+def test_library_ratio_rule_many_loops_at_once():
+    """Loops are independent and an inactive loop is left untouched."""
+    best = np.array([100.0, 100.0, 5.0])
+    grace = np.array([0, 1, 0], np.uint8)
+    act = np.array([1, 1, 0], np.uint8)
+    n = binding.ratio_update(np.array([99.5, 99.5, 1.0]), best, grace, act)
+    # loop 0: short, first time -> grace; loop 1: short with grace -> stops;
+    # loop 2: inactive, unchanged
+    assert n == 1
+    assert act.tolist() == [1, 0, 0] and grace.tolist() == [1, 1, 0]
+    assert best.tolist() == [99.5, 99.5, 5.0]
