@@ -280,6 +280,23 @@ rpba_status rpba_precond_train_step(const float *samples, int32_t nsamp, int32_t
                                     int32_t t, float lr, void *scratch, float *grad, float *loss, int32_t apply,
                                     void *stream);
 
+/* rpba_precond_train_step_noalloc: the same training step for callers that
+ *   cannot allocate device memory (code under HIP graph capture, tight
+ *   serving or training loops, harnesses that forbid hipMalloc).  Arguments
+ *   as rpba_precond_train_step without `scratch`: the per-sample activations
+ *   and gradients and the loss partials live in a device array of the
+ *   library itself, one per GPU (about 9 MB), held until the process ends.
+ *   nsamp at most RPBA_TRAIN_NOALLOC_MAX_SAMPLES, else RPBA_ERR_ARG.  Calls no
+ *   allocating routine.  Every call on one GPU shares that GPU's array: calls
+ *   that overlap on one GPU (on different streams, or from several threads)
+ *   race; calls in one stream's order do not.  Every value a call reads from
+ *   the array it has written itself, so nothing needs clearing between
+ *   calls.  RPBA_ERR_HIP if the array's address cannot be looked up. */
+#define RPBA_TRAIN_NOALLOC_MAX_SAMPLES 8192
+rpba_status rpba_precond_train_step_noalloc(const float *samples, int32_t nsamp, int32_t nz, float *W, float *m,
+                                            float *v, int32_t t, float lr, float *grad, float *loss, int32_t apply,
+                                            void *stream);
+
 /* ---------------------------------------------------------------- execution
  * rpba_set_graph: when on, each of rpba_intersect, rpba_subblock_lm_step and
  *   rpba_consensus is captured into a HIP graph on its first call and replayed

@@ -32,7 +32,9 @@ EXPORTS = [
     "rpba_precond_num_params", "rpba_set_precond_weights", "rpba_precond_num_samples", "rpba_precond_sample_stride",
     "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
     "rpba_step_status", "rpba_ratio_update", "rpba_camera_order", "rpba_get_precond_blocks", "rpba_factor_flops",
+    "rpba_precond_train_step_noalloc",
 ]
+TRAIN_NOALLOC_MAX_SAMPLES = 8192   # RPBA_TRAIN_NOALLOC_MAX_SAMPLES
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
           "robust", "iterative_solve", "schur_pairs", "intersect_export"]
 
@@ -113,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     L.rpba_camera_order.argtypes = [vp, vp]
     L.rpba_get_precond_blocks.argtypes = [vp, i32, vp]
     L.rpba_factor_flops.argtypes = [vp, vp]
+    L.rpba_precond_train_step_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, i32, ctypes.c_float, vp, vp, i32, vp]
     L.rpba_set_graph.argtypes = [vp, i32]
     L.rpba_set_timing.argtypes = [vp, i32]
     L.rpba_get_timing.restype = i32
@@ -158,6 +161,17 @@ def precond_train_step(samples, nz, W, m, v, t, lr, scratch, grad, loss, apply=T
     _check(L.rpba_precond_train_step(_ptr(samples), int(samples.shape[0]), nz, _ptr(W), _ptr(m), _ptr(v), int(t),
                                      float(lr), _ptr(scratch), _ptr(grad), _ptr(loss), int(apply),
                                      ctypes.c_void_p(st.cuda_stream)), "rpba_precond_train_step")
+
+
+def precond_train_step_noalloc(samples, nz, W, m, v, t, lr, grad, loss, apply=True, stream=None):
+    """The training step through rpba_precond_train_step_noalloc (the
+    library's own device scratch, at most TRAIN_NOALLOC_MAX_SAMPLES samples)."""
+    import torch
+    L = load_library()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.rpba_precond_train_step_noalloc(_ptr(samples), int(samples.shape[0]), nz, _ptr(W), _ptr(m), _ptr(v),
+                                             int(t), float(lr), _ptr(grad), _ptr(loss), int(apply),
+                                             ctypes.c_void_p(st.cuda_stream)), "rpba_precond_train_step_noalloc")
 
 
 def precond_train_scratch_bytes(nsamp):

@@ -1110,6 +1110,25 @@ rpba_status rpba_precond_train_step(const float* samples, int32_t nsamp, int32_t
   return RPBA_OK;
 }
 
+rpba_status rpba_precond_train_step_noalloc(const float* samples, int32_t nsamp, int32_t nz, float* W, float* m,
+                                            float* v, int32_t t, float lr, float* grad, float* loss, int32_t apply,
+                                            void* stream) {
+  if (!samples || nsamp < 1 || nz < 1 || !W || !grad || (apply && (!m || !v || t < 1)))
+    return fail(RPBA_ERR_ARG, "bad training arguments");
+  if (nsamp > RPBA_TRAIN_NOALLOC_MAX_SAMPLES)
+    return fail(RPBA_ERR_ARG, "rpba_precond_train_step_noalloc: " + std::to_string(nsamp) +
+                                  " samples exceed the maximum of " + std::to_string(RPBA_TRAIN_NOALLOC_MAX_SAMPLES) +
+                                  " per call");
+  hipError_t e = hipSuccess;
+  float* sc = train_noalloc_scratch(&e);
+  if (!sc) return fail(RPBA_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  float* parts = sc + train_noalloc_parts_offset();
+  launch_train_step(samples, nsamp, nz, W, m, v, t, lr, sc, grad, parts, apply != 0, (hipStream_t)stream);
+  if (loss) launch_sum_f32(parts, (nsamp + 255) / 256, loss, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return RPBA_OK;
+}
+
 rpba_status rpba_selftest_gemm(const double* A, const double* B, double* C, void* stream) {
   launch_selftest_gemm(A, B, C, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());

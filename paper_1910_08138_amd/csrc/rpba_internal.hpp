@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/rpba.h"
+
 namespace rpba {
 
 // Device view of one problem: every pointer lives in the caller's workspace
@@ -197,6 +199,13 @@ void launch_harvest(const Dev& d, const float* mean_diag, const float* cam_tpfra
 void launch_train_step(const float* samples, int nsamp, int nz, float* W, float* m, float* v, int t, float lr,
                        float* scratch, float* grad, float* loss_part, bool apply, hipStream_t st);
 void launch_sum_f32(const float* parts, int n, float* out, hipStream_t st);
+// the training step without a caller workspace: samples per call at most
+// TRAIN_NOALLOC_MAX_SAMPLES; train_noalloc_scratch returns the current
+// device's copy of the library's own scratch array (null and *err on a HIP
+// failure), the loss partials start train_noalloc_parts_offset() floats in
+constexpr int TRAIN_NOALLOC_MAX_SAMPLES = RPBA_TRAIN_NOALLOC_MAX_SAMPLES;
+float* train_noalloc_scratch(hipError_t* err);
+size_t train_noalloc_parts_offset();
 void launch_pcg(const Dev& d, const int32_t* blocks, int nblocks, int max_n, int pcg_maxit, double pcg_tol,
                 double ir_tol, int ir_maxit, hipStream_t st);
 // in-bounds layout check of the FP64 MFMA tile product: C = A B^T (64x64, row-major)

@@ -21,6 +21,9 @@
 #include "rpba_device.hpp"
 #include "rpba_internal.hpp"
 
+#include <mutex>
+#include <vector>
+
 namespace rpba {
 
 namespace {
@@ -349,6 +352,43 @@ __global__ void k_sum_f32(const float* parts, int n, float* out) {
 }
 
 }  // namespace
+
+// Scratch of the training step that allocates nothing: per-sample
+// activations and gradients (SCR floats each) for at most
+// TRAIN_NOALLOC_MAX_SAMPLES samples, then the per-workgroup loss partials.
+// One copy per GPU, held until the process ends.
+constexpr size_t kNoAllocFloats =
+    (size_t)TRAIN_NOALLOC_MAX_SAMPLES * SCR + (TRAIN_NOALLOC_MAX_SAMPLES + 255) / 256 + 64;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+float* train_noalloc_scratch(hipError_t* err) {
+  // the array's device address, looked up once per device with that device
+  // current (each GPU holds its own copy at its own address); host code uses
+  // only this address, never the array's name
+  static std::mutex mu;
+  static std::vector<float*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *err = e;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      *err = e;
+      return nullptr;
+    }
+    addr[dev] = static_cast<float*>(ptr);
+  }
+  *err = hipSuccess;
+  return addr[dev];
+}
+
+size_t train_noalloc_parts_offset() { return (size_t)TRAIN_NOALLOC_MAX_SAMPLES * SCR; }
 
 void launch_sum_f32(const float* parts, int n, float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_f32, dim3(1), dim3(64), 0, st, parts, n, out);
