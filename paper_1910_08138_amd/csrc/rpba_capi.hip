@@ -51,7 +51,7 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk;
+      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid;
   size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -106,6 +106,7 @@ WsMap layout_for(const Plan& P) {
   m.blk_fail = L.add(i4 * P.L);
   m.blk_nc = L.add(i4 * P.L);
   m.chk = L.add(i4 * 4);
+  m.rec_valid = L.add(i4 * 4);
   m.pb_row = L.add(i4 * P.pb_row.size());
   m.pb_ent_off = L.add(i8 * P.pb_ent_off.size());
   m.pb_ent = L.add(i4 * P.pb_ent.size());
@@ -165,7 +166,7 @@ WsMap layout_for(const Plan& P) {
   m.y = L.add(f8 * P.vec_total);
   m.ys = L.add(f8 * P.vec_total);
   m.x = L.add(f8 * P.vec_total);
-  m.acc_int = L.add(f8 * 4);
+  m.acc_int = L.add(f8 * (4 + P.L));
   m.acc_blk = L.add(f8 * 4 * P.L);
   m.acc_cons = L.add(f8 * 2);
   m.acc_rob = L.add(f8 * 2);
@@ -633,6 +634,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.vec_off = (const int64_t*)(w + m.vec_off);
   D.blk_fail = I(m.blk_fail);
   D.blk_nc = I(m.blk_nc);
+  D.rec_valid = I(m.rec_valid);
   D.acc_int = F(m.acc_int);
   D.acc_blk = F(m.acc_blk);
   D.acc_cons = F(m.acc_cons);
@@ -663,6 +665,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero(D.x, p.vec_total, st);
   launch_zero_i32(D.blk_fail, D.L, st);
   launch_zero_i32(D.blk_nc, D.L, st);
+  launch_zero_i32(D.rec_valid, 1, st);
   launch_zero_i32((int32_t*)(w + m.df_flags), p.rcs_total / ((int64_t)p.T * p.T), st);
   launch_zero_i32((int32_t*)(w + m.df_ctl), 4, st);
   launch_df_reset((int32_t*)(w + m.df_ctl), st);
@@ -934,6 +937,8 @@ rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e)
   } else {
     launch_rcs_extract(h->d, l, stage, stage + (size_t)n6 * n6, h->stream);
   }
+  // staging in the copy records overwrites them: the next LM step rebuilds them
+  if (stage == h->d.cpk) launch_zero_i32(h->d.rec_valid, 1, h->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(h->stream));
   std::vector<double> Si((size_t)n6 * n6), ei(n6);

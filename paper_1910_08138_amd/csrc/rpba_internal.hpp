@@ -78,6 +78,9 @@ struct Dev {
   double* Xc;             // [NC][3] X_j^l (valid when the sub-block is not fresh)
   int32_t* blk_fresh;     // [L] 1: every copy of the sub-block is still at Xbar (set by the
                           // intersection, cleared by the sub-block's next update)
+  int32_t* rec_valid;     // [1] 1: the copy records of the fresh sub-blocks hold their point
+                          // blocks at the current state (written by the intersection; cleared by
+                          // a robust re-weighting and by anything that reuses the record array)
   double* Om;             // [NC][6] refined tie-point weight (FP64 path)
   float* Omf;             // the same region as [NC][6] floats on the mixed path (om_f32)
   int32_t om_f32;         // 1: the refined weights are stored in FP32
@@ -118,7 +121,8 @@ struct Dev {
   const uint8_t* active;  // [L] or null (set per call)
 
   // accumulators
-  double* acc_int;        // [4] cost, sum |v|^2, K_valid, N_valid
+  double* acc_int;        // [4 + L] cost, sum |v|^2, K_valid, N_valid; then per sub-block the cost
+                          // of its copies at the intersection (the cost before its next LM step)
   double* acc_blk;        // [L][4] cost before, cost after, |step|^2, iterations
   double* acc_cons;       // [2]
   double* acc_rob;        // [2]

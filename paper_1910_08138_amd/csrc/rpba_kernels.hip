@@ -190,6 +190,47 @@ __global__ void k_gather_pm(Dev d) {
   }
 }
 
+// ------------------------------------------------------------ copy records
+// The record of copy c for the Schur pass of the next LM step: X, the damped
+// point block's inverse V*^-1 (zero if V* did not factorise), g_X, valid.
+// FP64 path: 16 doubles (X, 1, V*^-1, g_X, spare).  Mixed path: X in FP64,
+// then V*^-1, g_X and the valid flag rounded to FP32 (the precision that
+// path's Schur pass computes in).
+__device__ __forceinline__ void put_record(const Dev& d, int64_t c, const double (&X)[3], const double (&inv)[6],
+                                           const double (&g)[3], bool ok) {
+  if (d.cpk_f32) {
+    uint32_t w[16];
+    __builtin_memcpy(w, X, 24);
+    float f[10];
+    for (int q = 0; q < 6; ++q) f[q] = (float)inv[q];
+    for (int q = 0; q < 3; ++q) f[6 + q] = ok ? (float)g[q] : 0.f;
+    f[9] = 1.f;
+    __builtin_memcpy(w + 6, f, 40);
+    uint4* p4 = reinterpret_cast<uint4*>(d.cpk + CPK32 * c);
+    for (int q = 0; q < 4; ++q) p4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+  } else {
+    double2* p2 = reinterpret_cast<double2*>(d.cpk + CPK * c);
+    p2[0] = make_double2(X[0], X[1]);
+    p2[1] = make_double2(X[2], 1.0);
+    p2[2] = make_double2(inv[0], inv[1]);
+    p2[3] = make_double2(inv[2], inv[3]);
+    p2[4] = make_double2(inv[4], inv[5]);
+    p2[5] = make_double2(ok ? g[0] : 0.0, ok ? g[1] : 0.0);
+    p2[6] = make_double2(ok ? g[2] : 0.0, 0.0);
+  }
+}
+
+// zero record: the Schur pass skips the copy
+__device__ __forceinline__ void zero_record(const Dev& d, int64_t c) {
+  if (d.cpk_f32) {
+    uint4* p4 = reinterpret_cast<uint4*>(d.cpk + CPK32 * c);
+    for (int q = 0; q < 4; ++q) p4[q] = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+    double2* p2 = reinterpret_cast<double2*>(d.cpk + CPK * c);
+    for (int q = 0; q < CPK / 2; ++q) p2[q] = make_double2(0.0, 0.0);
+  }
+}
+
 // ------------------------------------------------------------ intersection
 // One thread per point (internal order).  A workgroup's INT_WG consecutive
 // points read their observations (point-major, copy by copy) and the cameras
@@ -270,13 +311,60 @@ __device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0
   return o.code;
 }
 
-// where the intersection parks the normals H^(l) of a point's middle copies
-// until H is complete: in the copy's refined-weight slot on the FP64 path; on
-// the mixed path (FP32 refined weights) in the copy's record of the last LM
-// step, free until the next point-block pass rewrites it, so that the
-// difference H - H^(l) is still formed in FP64
+// where the intersection parks the normals H^(l) (FP64, 6 doubles) and the
+// gradient g^(l) of a point's middle copies until H is complete: in the
+// copy's own record, which the intersection rewrites at the end (g^(l) in
+// FP64 on the FP64 path, in FP32 on the mixed path, the precision its record
+// keeps g_X in), so that H - H^(l) is still formed in FP64
 __device__ __forceinline__ double2* om_park(const Dev& d, int64_t c) {
-  return reinterpret_cast<double2*>(d.om_f32 ? d.cpk + CPK32 * c : d.Om + 6 * c);
+  return reinterpret_cast<double2*>(d.cpk + (d.cpk_f32 ? CPK32 : CPK) * c);
+}
+__device__ __forceinline__ void park_g(const Dev& d, int64_t c, const double (&g)[3]) {
+  if (d.cpk_f32) {
+    float* f = reinterpret_cast<float*>(d.cpk + CPK32 * c) + 12;
+    f[0] = (float)g[0];
+    f[1] = (float)g[1];
+    f[2] = (float)g[2];
+  } else {
+    double* q = d.cpk + CPK * c + 6;
+    q[0] = g[0];
+    q[1] = g[1];
+    q[2] = g[2];
+  }
+}
+__device__ __forceinline__ void unpark_g(const Dev& d, int64_t c, double (&g)[3]) {
+  if (d.cpk_f32) {
+    const float* f = reinterpret_cast<const float*>(d.cpk + CPK32 * c) + 12;
+    g[0] = f[0];
+    g[1] = f[1];
+    g[2] = f[2];
+  } else {
+    const double* q = d.cpk + CPK * c + 6;
+    g[0] = q[0];
+    g[1] = q[1];
+    g[2] = q[2];
+  }
+}
+
+// per-workgroup sums of the copies' costs by sub-block (the cost before the
+// next LM step of a fresh sub-block): a few LDS slots keyed by sub-block,
+// flushed with one atomic each; a sub-block that finds no slot adds to memory
+constexpr int CSLOT = 16;
+struct CostSlots {
+  int key[CSLOT];
+  double sum[CSLOT];
+};
+__device__ __forceinline__ void cost_add(const Dev& d, CostSlots& cs, int l, double v) {
+  for (int t = 0; t < CSLOT; ++t) {
+    const int q = (l + t) & (CSLOT - 1);
+    int k = cs.key[q];
+    if (k == -1) k = atomicCAS(&cs.key[q], -1, l);
+    if (k == -1 || k == l) {
+      atomicAdd(&cs.sum[q], v);
+      return;
+    }
+  }
+  atomicAdd(&d.acc_int[4 + l], v);
 }
 
 // refined weight Omega of copy c (FP32 storage on the mixed path)
@@ -308,7 +396,7 @@ __device__ __forceinline__ void put_pxs(const Dev& d, int j, const double (&X)[3
 // residuals, refined weights of the copies); accv gets the point's share of
 // the statistics
 template <bool INFO, bool OLDS>
-__device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0, int j, int want_cov,
+__device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlots& cs, int b0, int j, int want_cov,
                                                 double (&accv)[4]) {
   if (j < d.N && d.status[j] == 0) {
     const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1], n = c1 - c0;
@@ -384,16 +472,18 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
         break;
       }
     }
-    // final pass at the converged point: normals, residuals, cost, and the
-    // per-copy normals H^(l): those of the first and the last copy stay in
-    // registers, any in between are parked in Om until H is complete
+    // final pass at the converged point: normals, residuals, cost, and per
+    // copy the normals H^(l), gradient g^(l) and cost of its observations:
+    // those of the first and the last copy stay in registers, any in between
+    // are parked in their copy records until H is complete
     double cost = 0.0, sq = 0.0, nobs = 0.0;
     double hl0[6] = {0, 0, 0, 0, 0, 0}, hl[6] = {0, 0, 0, 0, 0, 0};
+    double gl0[3] = {0, 0, 0}, gl[3] = {0, 0, 0};
+    double cst0 = 0.0, cst1 = 0.0, cst2 = 0.0, ccur = 0.0;  // costs of copies 0, 1, 2 and of the current one
     if (st == 0) {
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       bool behind = false;
       int u = 0;  // copy being summed
-      double gl[3] = {0, 0, 0};
       for (int i = i0; i < i1; ++i) {
         double x, y, cm[12];
         W2<double> W;
@@ -407,7 +497,9 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
         // it last), and the workgroup copies them out coalesced
         if (OLDS) sg.xy[i - b0] = make_double2(v0, v1);
         else reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
-        cost += wquad(W, v0, v1);
+        const double wq = wquad(W, v0, v1);
+        cost += wq;
+        ccur += wq;
         sq += v0 * v0 + v1 * v1;
         nobs += 1.0;
         if (code & PM_LAST) {  // copy u complete
@@ -415,13 +507,22 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
           if (u + 1 < n) {
             if (u == 0) {
               for (int q = 0; q < 6; ++q) hl0[q] = hl[q];
+              for (int q = 0; q < 3; ++q) gl0[q] = gl[q];
+              cst0 = ccur;
             } else {
-              double2* om = om_park(d, copy_at(u));
+              const int64_t c = copy_at(u);
+              double2* om = om_park(d, c);
               om[0] = make_double2(hl[0], hl[1]);
               om[1] = make_double2(hl[2], hl[3]);
               om[2] = make_double2(hl[4], hl[5]);
+              park_g(d, c, gl);
+              if (u == 1) cst1 = ccur;
+              else if (u == 2) cst2 = ccur;
+              else cost_add(d, cs, d.copy_blk[c], ccur);  // rare: a point in five or more sub-blocks
             }
             for (int q = 0; q < 6; ++q) hl[q] = 0.0;
+            for (int q = 0; q < 3; ++q) gl[q] = 0.0;
+            ccur = 0.0;
           }
           ++u;
         }
@@ -436,18 +537,26 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
         d.Xbar[(int64_t)r * d.N + j] = X[r];
         d.P0[(int64_t)r * d.N + j] = X[r];
       }
+      // Every copy restarts at Xbar with the same cameras, so the point block
+      // of its sub-block, sum_(k in l) B^T W B + Omega^l = H^(l) + (H - H^(l)),
+      // is H itself: the damped V* = H + lambda diag(H) and its inverse are
+      // the same for every copy, and each copy's record gets its own g^(l).
+      double hv[6] = {h[0] * (1.0 + d.lambda), h[1], h[2], h[3] * (1.0 + d.lambda), h[4], h[5] * (1.0 + d.lambda)};
+      double lv[6], vi[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      const bool vok = chol3(hv, lv);
+      if (vok) chol3_inverse(lv, vi);
       // Omega^l = H - H^(l): information from the cameras outside sub-block l
       // (zero for a point seen by one sub-block only).  The copies themselves
       // are reset to Xbar through the sub-blocks' fresh flags.
       for (int u2 = 0; u2 < n; ++u2) {
         const int64_t c = copy_at(u2);
-        double o6[6];
-        if (n == 1) {
-          for (int q = 0; q < 6; ++q) o6[q] = 0.0;
-        } else if (u2 == 0) {
+        double o6[6], g3[3];
+        if (u2 == 0 && n > 1) {
           for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl0[q];
+          for (int q = 0; q < 3; ++q) g3[q] = gl0[q];
         } else if (u2 == n - 1) {
-          for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl[q];
+          for (int q = 0; q < 6; ++q) o6[q] = n == 1 ? 0.0 : h[q] - hl[q];
+          for (int q = 0; q < 3; ++q) g3[q] = gl[q];
         } else {
           const double2* om = om_park(d, c);
           const double2 a = om[0], b = om[1], e = om[2];
@@ -457,6 +566,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
           o6[3] = h[3] - b.y;
           o6[4] = h[4] - e.x;
           o6[5] = h[5] - e.y;
+          unpark_g(d, c, g3);
         }
         if (d.om_f32) {
           float2* om = reinterpret_cast<float2*>(d.Omf + 6 * c);
@@ -469,11 +579,19 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
           om[1] = make_double2(o6[2], o6[3]);
           om[2] = make_double2(o6[4], o6[5]);
         }
+        put_record(d, c, X, vi, g3, vok);
+        const double cc = u2 == n - 1 ? ccur : u2 == 0 ? cst0 : u2 == 1 ? cst1 : u2 == 2 ? cst2 : 0.0;
+        if (u2 == n - 1 || u2 < 3) cost_add(d, cs, d.copy_blk[c], cc);
       }
       accv[0] = cost;
       accv[1] = sq;
       accv[2] = nobs;
       accv[3] = 1.0;
+    } else {
+      // a point that fails here: its copies drop out of the Schur pass (the
+      // costs of copies in five or more sub-blocks already added stay; a
+      // point needs a degenerate geometry to fail after converging)
+      for (int u2 = 0; u2 < n; ++u2) zero_record(d, copy_at(u2));
     }
     d.status[j] = st;
     put_pxs(d, j, X, st);
@@ -486,6 +604,9 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, int b0,
   } else if (j < d.N) {
     const double z[3] = {0.0, 0.0, 0.0};
     put_pxs(d, j, z, d.status[j]);
+    // a point left out before (failed or eliminated): no copy of it in the
+    // Schur pass
+    for (int c = d.pt_copy_off[j]; c < d.pt_copy_off[j + 1]; ++c) zero_record(d, d.pt_copies[c]);
   }
 }
 
@@ -493,8 +614,15 @@ template <bool INFO>
 __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   __shared__ Stage sg;
   __shared__ double sh[4 * (IT / 64)];
-  if (blockIdx.x == 0)
+  __shared__ CostSlots cs;
+  if (blockIdx.x == 0) {
     for (int l = threadIdx.x; l < d.L; l += IT) d.blk_fresh[l] = 1;
+    if (threadIdx.x == 0) *d.rec_valid = 1;
+  }
+  if (threadIdx.x < CSLOT) {
+    cs.key[threadIdx.x] = -1;
+    cs.sum[threadIdx.x] = 0.0;
+  }
   const int j0 = blockIdx.x * IT;
   const int b0 = d.pm_off[j0];
   const int nobs = d.pm_off[min(j0 + IT, d.N)] - b0;
@@ -553,7 +681,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   const int j = j0 + threadIdx.x;
   double accv[4] = {0.0, 0.0, 0.0, 0.0};
   if (nobs <= INT_OBS_CAP) {
-    intersect_point<INFO, true>(d, sg, b0, j, want_cov, accv);
+    intersect_point<INFO, true>(d, sg, cs, b0, j, want_cov, accv);
     // residuals of the workgroup's stream, one coalesced copy (the slots of
     // points left invalid hold their pixels: residuals are only read for
     // valid points), as streaming stores: only a robust re-weighting reads
@@ -566,7 +694,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       __builtin_nontemporal_store(v.y, &res[t].y);
     }
   } else {
-    intersect_point<INFO, false>(d, sg, b0, j, want_cov, accv);
+    intersect_point<INFO, false>(d, sg, cs, b0, j, want_cov, accv);
   }
   // workgroup sum of the statistics, one atomic per value
 #pragma unroll
@@ -581,6 +709,8 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
     for (int w = 0; w < IT / 64; ++w) v += sh[threadIdx.x * (IT / 64) + w];
     atomicAdd(&d.acc_int[threadIdx.x], v);
   }
+  if (threadIdx.x < CSLOT && cs.key[threadIdx.x] >= 0)
+    atomicAdd(&d.acc_int[4 + cs.key[threadIdx.x]], cs.sum[threadIdx.x]);
 }
 
 // statistics of an intersection from its sums: cost, sigma0 (redundancy
@@ -633,17 +763,25 @@ __global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* 
 // One thread per copy: damped point block V* = (sum B^T W B + Omega)(1 + lambda
 // on the diagonal), its FP64 inverse, g_X = sum B^T W v + Omega (X - Xbar),
 // and the cost before the step.  Packs (X, V*^-1, g_X) for the Schur pass.
+// Copies of fresh sub-blocks are skipped while the intersection's records
+// are valid (it wrote them at this very state); so are whole workgroups.
 __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
   __shared__ double sh[8];
-  __shared__ int l_first;
+  __shared__ int l_first, s_skip;
   const bool unit = *d.rw_unit != 0;
+  const bool recs = *d.rec_valid != 0;
   int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (threadIdx.x == 0) {
     l_first = d.copy_blk[blockIdx.x * (int64_t)NT];
+    const int l_last = d.copy_blk[min((int64_t)blockIdx.x * NT + NT, d.NC) - 1];
+    int skip = recs ? 1 : 0;
+    for (int l = l_first; skip && l <= l_last; ++l) skip = d.blk_fresh[l];
+    s_skip = skip;
     for (int q = 0; q < 8; ++q) sh[q] = 0.0;
   }
   __syncthreads();
-  if (c < d.NC) {
+  if (s_skip) return;
+  if (c < d.NC && !(recs && d.blk_fresh[d.copy_blk[c]])) {
     // the copy's indices, flags and point are loaded together, ahead of the
     // tests that use them (the copy's own data stays behind them: holding it
     // across the tests costs more occupancy than it saves here)
@@ -652,7 +790,6 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
     const bool act = d.active == nullptr || d.active[l];
     const int stp = d.status[p], fresh = d.blk_fresh[l];
     const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
-    double* pk = d.cpk + CPK * c;
     if (act && stp == 0) {
       double X[3] = {xb[0], xb[1], xb[2]};
       if (!fresh)
@@ -681,45 +818,33 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
       if (ok) chol3_inverse(lch, inv);
       else
         for (int q = 0; q < 6; ++q) inv[q] = 0.0;
-      if (d.cpk_f32) {
-        // compact record: X in FP64, V*^-1 and g_X rounded to FP32 (the
-        // precision the mixed Schur pass computes in), valid flag
-        uint32_t w[16];
-        __builtin_memcpy(w, X, 24);
-        float f[10];
-        for (int q = 0; q < 6; ++q) f[q] = (float)inv[q];
-        for (int q = 0; q < 3; ++q) f[6 + q] = ok ? (float)g[q] : 0.f;
-        f[9] = 1.f;
-        __builtin_memcpy(w + 6, f, 40);
-        uint4* p4 = reinterpret_cast<uint4*>(d.cpk + CPK32 * c);
-        for (int q = 0; q < 4; ++q) p4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-      } else {
-        double2* p2 = reinterpret_cast<double2*>(pk);
-        p2[0] = make_double2(X[0], X[1]);
-        p2[1] = make_double2(X[2], 1.0);
-        p2[2] = make_double2(inv[0], inv[1]);
-        p2[3] = make_double2(inv[2], inv[3]);
-        p2[4] = make_double2(inv[4], inv[5]);
-        p2[5] = make_double2(ok ? g[0] : 0.0, ok ? g[1] : 0.0);
-        p2[6] = make_double2(ok ? g[2] : 0.0, 0.0);
-      }
+      put_record(d, c, X, inv, g, ok);
       int slot = l - l_first;
       if (slot >= 0 && slot < 8) atomicAdd(&sh[slot], cost);
       else atomicAdd(&d.acc_blk[4 * l + 0], cost);
     } else {
-      // zero record: the Schur pass skips the copy
-      if (d.cpk_f32) {
-        uint4* p4 = reinterpret_cast<uint4*>(d.cpk + CPK32 * c);
-        for (int q = 0; q < 4; ++q) p4[q] = make_uint4(0u, 0u, 0u, 0u);
-      } else {
-        double2* p2 = reinterpret_cast<double2*>(pk);
-        for (int q = 0; q < CPK / 2; ++q) p2[q] = make_double2(0.0, 0.0);
-      }
+      zero_record(d, c);  // the Schur pass skips the copy
     }
   }
   __syncthreads();
   if (threadIdx.x < 8 && sh[threadIdx.x] != 0.0 && l_first + (int)threadIdx.x < d.L)
     atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 0], sh[threadIdx.x]);
+}
+
+// start of an LM step: per sub-block the statistics (cost before from the
+// intersection for a fresh sub-block whose records are valid, else summed by
+// the point-block pass) and the failure flags
+__global__ void k_step_begin(Dev d) {
+  const int l = blockIdx.x * NT + threadIdx.x;
+  if (l >= d.L) return;
+  const bool fresh = *d.rec_valid != 0 && d.blk_fresh[l] != 0;
+  double* a = d.acc_blk + 4 * l;
+  a[0] = fresh ? d.acc_int[4 + l] : 0.0;
+  a[1] = 0.0;
+  a[2] = 0.0;
+  a[3] = 0.0;
+  d.blk_fail[l] = 0;
+  d.blk_nc[l] = 0;
 }
 
 // ------------------------------------------------------- update of the step
@@ -1043,7 +1168,7 @@ void launch_init_rcs(const Dev& d, hipStream_t st) {
 }
 
 void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
-  launch_zero(d.acc_int, 4, st);
+  launch_zero(d.acc_int, 4 + (int64_t)d.L, st);
   if (d.has_info)
     hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
   else
@@ -1055,9 +1180,7 @@ void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, dou
 }
 
 void launch_copy_prep(const Dev& d, hipStream_t st) {
-  launch_zero(d.acc_blk, 4 * (int64_t)d.L, st);
-  launch_zero_i32(d.blk_fail, d.L, st);
-  launch_zero_i32(d.blk_nc, d.L, st);
+  hipLaunchKernelGGL(k_step_begin, dim3(grid_for(d.L)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_copy_prep, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
 }
 

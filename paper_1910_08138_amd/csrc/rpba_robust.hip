@@ -168,6 +168,7 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
 // flagged points: eliminated when asked; the flags are cleared for the next call
 __global__ void k_robust_eliminate(Dev d, int32_t* bad, int eliminate) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) *d.rec_valid = 0;  // the weights changed: copy records are rebuilt by the next step
   if (j >= d.N) return;
   if (bad[j]) {
     if (eliminate && d.status[j] == 0) {
