@@ -102,6 +102,9 @@ typedef struct {
   double down_weight;    /* weight multiplier of flagged observations: 1e-4 */
   int32_t chol_tile;     /* Cholesky tile edge, 32 or 64 (0 = library choice) */
   int32_t chol_schedule; /* RPBA_CHOL_*; DEFAULT = dataflow */
+  int32_t robust;        /* 1: the intersection keeps its residuals for rpba_robust_reweight (Sec. 5.3);
+                            0: it does not, and rpba_robust_reweight returns RPBA_ERR_STATE: 0 */
+  int32_t pair_lanes;    /* lanes per camera-pair block in the Schur pass: 4, 8 or 16 (0 = 8) */
 } rpba_options;
 
 /* Fill *opt with the defaults listed above.  HOST pointer. */
@@ -139,7 +142,8 @@ rpba_status rpba_create(const rpba_problem_desc *desc, const rpba_options *opt, 
  * Writes Xbar to desc->pts. */
 rpba_status rpba_intersect(rpba_problem *h, double *cov, int32_t *status, double *stats);
 
-/* Parallel robust variant (Sec. 5.3): per camera, sigma0_i = 1.4826 MAD of the
+/* Parallel robust variant (Sec. 5.3), for a handle created with
+ * opt->robust = 1 (else RPBA_ERR_STATE): per camera, sigma0_i = 1.4826 MAD of the
  * whitened residual components of the last intersection; an observation with
  * sqrt(v^T W v) / sigma0_i > t_v gets the weight multiplier down_weight,
  * every other observation 1.  With `eliminate`, points with a flagged

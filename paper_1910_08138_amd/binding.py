@@ -60,6 +60,7 @@ class Options(ctypes.Structure):
         ("pcg_tol", ctypes.c_double), ("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
         ("pcg_min_cams", ctypes.c_int32), ("t_v", ctypes.c_double), ("down_weight", ctypes.c_double),
         ("chol_tile", ctypes.c_int32), ("chol_schedule", ctypes.c_int32),
+        ("robust", ctypes.c_int32), ("pair_lanes", ctypes.c_int32),
     ]
 
 
@@ -424,6 +425,8 @@ def _host(p, t):
 def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, graph=False, **opts):
     """Fixed schedule on the GPU: T outer iterations of (intersect [, robust,
     re-intersect], I LM steps, consensus), then a final intersection."""
+    if robust:
+        opts.setdefault("robust", 1)
     p = Problem(scene, **opts)
     if graph:
         p.set_graph(True)

@@ -72,7 +72,7 @@ int64_t robust_spill_values(const Plan& P, std::vector<int64_t>* off = nullptr) 
   return tot;
 }
 
-WsMap layout_for(const Plan& P) {
+WsMap layout_for(const Plan& P, bool keep_res) {
   Layout L;
   WsMap m;
   const size_t i4 = 4, i8 = 8, f8 = 8;
@@ -156,7 +156,7 @@ WsMap layout_for(const Plan& P) {
   m.xy = L.add(f8 * 2 * P.K);
   m.info = L.add(P.has_info ? f8 * 3 * P.K : 0);
   m.rw = L.add(f8 * P.K);
-  m.res = L.add(f8 * 2 * P.K);
+  m.res = L.add(keep_res ? f8 * 2 * P.K : 0);
   m.Xc = L.add(f8 * 3 * P.NC);
   m.Om = L.add(f8 * 6 * P.NC);
   m.cpk = L.add(f8 * CPK * P.NC);
@@ -214,6 +214,9 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
   if (o->chol_tile != 0 && o->chol_tile != 32 && o->chol_tile != 64) return fail(RPBA_ERR_ARG, "chol_tile must be 0, 32 or 64");
   if (o->chol_schedule < RPBA_CHOL_DEFAULT || o->chol_schedule > RPBA_CHOL_DATAFLOW)
     return fail(RPBA_ERR_ARG, "chol_schedule must be RPBA_CHOL_DEFAULT, _STEPWISE or _DATAFLOW");
+  if (o->robust != 0 && o->robust != 1) return fail(RPBA_ERR_ARG, "robust must be 0 or 1");
+  if (o->pair_lanes != 0 && o->pair_lanes != 4 && o->pair_lanes != 8 && o->pair_lanes != 16)
+    return fail(RPBA_ERR_ARG, "pair_lanes must be 0, 4, 8 or 16");
   return RPBA_OK;
 }
 
@@ -355,6 +358,8 @@ rpba_status rpba_default_options(rpba_options* o) {
   o->down_weight = 1e-4;
   o->chol_tile = 0;
   o->chol_schedule = RPBA_CHOL_DEFAULT;
+  o->robust = 0;
+  o->pair_lanes = 0;
   return RPBA_OK;
 }
 
@@ -365,7 +370,7 @@ rpba_status rpba_workspace_size(const rpba_problem_desc* d, const rpba_options* 
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  *bytes = layout_for(*P).total;
+  *bytes = layout_for(*P, o->robust != 0).total;
   return RPBA_OK;
 }
 
@@ -379,7 +384,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  WsMap m = layout_for(*P);
+  WsMap m = layout_for(*P, o->robust != 0);
   if (bytes < m.total) return fail(RPBA_ERR_WORKSPACE, "workspace too small: need " + std::to_string(m.total));
   size_t lds = 0;
 
@@ -430,7 +435,15 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   HIP_TRY(up(m.pb_row, p.pb_row.data(), 4 * p.pb_row.size()));
   HIP_TRY(up(m.pb_ent_off, p.pb_ent_off.data(), 8 * p.pb_ent_off.size()));
   HIP_TRY(up(m.pb_ent, p.pb_ent.data(), 4 * p.pb_ent.size()));
-  HIP_TRY(up(m.od_pb, p.od_pb.data(), 4 * p.od_pb.size()));
+  {
+    // camera-pair blocks by the number of rounds of a lane group, most first
+    // (the plan orders them for 8 lanes; the order stays stable inside a class)
+    const int G = o->pair_lanes == 0 ? 8 : o->pair_lanes;
+    std::vector<int32_t> od = p.od_pb;
+    auto rounds = [&](int32_t q) { return (p.pb_ent_off[q + 1] - p.pb_ent_off[q] + G - 1) / G; };
+    if (G != 8) std::stable_sort(od.begin(), od.end(), [&](int32_t a, int32_t b) { return rounds(a) > rounds(b); });
+    HIP_TRY(up(m.od_pb, od.data(), 4 * od.size()));
+  }
   HIP_TRY(up(m.pb_bsr, p.pb_bsr.data(), 4 * p.pb_bsr.size()));
   HIP_TRY(up(m.pb_bsr_t, p.pb_bsr_t.data(), 4 * p.pb_bsr_t.size()));
   HIP_TRY(up(m.bsr_row_off, p.bsr_row_off.data(), 4 * p.bsr_row_off.size()));
@@ -582,7 +595,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.xy = F(m.xy);
   D.info = p.has_info ? F(m.info) : nullptr;
   D.rw = F(m.rw);
-  D.res = F(m.res);
+  D.res = o->robust ? F(m.res) : nullptr;
   D.obs_cam = I(m.obs_cam);
   D.obs_copy = I(m.obs_copy);
   D.obs_orig = I(m.obs_orig);
@@ -614,6 +627,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.pb_ent = I(m.pb_ent);
   D.od_pb = I(m.od_pb);
   D.n_od = (int64_t)p.od_pb.size();
+  D.pb_lanes = o->pair_lanes == 0 ? 8 : o->pair_lanes;
   D.pb_bsr = I(m.pb_bsr);
   D.pb_bsr_t = I(m.pb_bsr_t);
   D.blk_pcg = (const uint8_t*)(w + m.blk_pcg);
@@ -836,6 +850,7 @@ int32_t rpba_get_timing(rpba_problem* h, double* ms, int64_t* launches, int64_t*
 
 rpba_status rpba_robust_reweight(rpba_problem* h, int32_t eliminate, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  if (!h->opt.robust) return fail(RPBA_ERR_STATE, "the handle was created without opt->robust: no residuals are kept");
   if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run before rpba_robust_reweight");
   CallGraph& g = eliminate ? h->g_rob_elim : h->g_rob;
   return run_call(h, g, stats, nullptr, nullptr, [&]() -> rpba_status {

@@ -72,6 +72,40 @@ __device__ __forceinline__ void linearise(const T* __restrict__ R, const T* __re
   linearise_d<T>(R, X[0] - C[0], X[1] - C[1], X[2] - C[2], f, cx, cy, o);
 }
 
+// Projection and residual in FP64, Jacobians in J (the mixed path's split:
+// FP64 state and residuals, FP32 Jacobians and per-observation products).
+// For J = double the arithmetic is that of linearise<double>.  o.g0, o.g1
+// and o.z hold the projection rounded to J; g0, g1 the FP64 projection.
+template <typename J>
+__device__ __forceinline__ void linearise_split(const double* __restrict__ R, const double* __restrict__ C,
+                                                const double X[3], double f, double cx, double cy, Lin<J>& o,
+                                                double& g0, double& g1, double& z) {
+  const double d0 = X[0] - C[0], d1 = X[1] - C[1], d2 = X[2] - C[2];
+  const double p0 = R[0] * d0 + R[1] * d1 + R[2] * d2;
+  const double p1 = R[3] * d0 + R[4] * d1 + R[5] * d2;
+  const double p2 = R[6] * d0 + R[7] * d1 + R[8] * d2;
+  z = p2;
+  const double iz = recip(p2);
+  const double u = p0 * iz, w = p1 * iz;
+  g0 = f * u + cx;
+  g1 = f * w + cy;
+  const J fz = (J)(f * iz), uj = (J)u, wj = (J)w, fj = (J)f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    o.B[0][c] = fz * ((J)R[c] - uj * (J)R[6 + c]);
+    o.B[1][c] = fz * ((J)R[3 + c] - wj * (J)R[6 + c]);
+  }
+  o.Ar[0][0] = -fj * uj * wj;
+  o.Ar[0][1] = fj * (J(1) + uj * uj);
+  o.Ar[0][2] = -fj * wj;
+  o.Ar[1][0] = -fj * (J(1) + wj * wj);
+  o.Ar[1][1] = fj * uj * wj;
+  o.Ar[1][2] = fj * uj;
+  o.g0 = (J)g0;
+  o.g1 = (J)g1;
+  o.z = (J)z;
+}
+
 // weight matrix of one observation [[a, b], [b, c]]
 template <typename T>
 struct W2 {

@@ -47,7 +47,8 @@ struct Dev {
   double* xy;             // [K][2]
   double* info;           // [K][3] or null
   double* rw;             // [K] robust weight multiplier
-  double* res;            // [K][2] residuals of the last intersection, point-major (valid points only)
+  double* res;            // [K][2] residuals of the last intersection, point-major (valid points
+                          // only), or null when the handle keeps none (no robust re-weighting)
   const int32_t* obs_cam;
   const int32_t* obs_copy;
   const int32_t* obs_orig;
@@ -96,6 +97,7 @@ struct Dev {
   const int32_t* pb_ent;
   const int32_t* od_pb;
   int64_t n_od;
+  int32_t pb_lanes;        // lanes per camera-pair block (4, 8 or 16)
   const int32_t* pb_bsr;
   const int32_t* pb_bsr_t;
   const uint8_t* blk_pcg;  // [L] 1 = iterative solver (block-sparse output)

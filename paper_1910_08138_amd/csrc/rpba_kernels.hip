@@ -90,8 +90,10 @@ __global__ void k_gather_obs(Dev d) {
     d.info[3 * k + 2] = d.u_info[2 * (int64_t)d.K + o];
   }
   d.rw[k] = 1.0;
-  d.res[2 * k] = 0.0;
-  d.res[2 * k + 1] = 0.0;
+  if (d.res) {
+    d.res[2 * k] = 0.0;
+    d.res[2 * k + 1] = 0.0;
+  }
 }
 
 // input check of rpba_create: non-finite values of the caller's arrays, and
@@ -496,7 +498,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         // the residual takes the place of the pixel in LDS (this pass reads
         // it last), and the workgroup copies them out coalesced
         if (OLDS) sg.xy[i - b0] = make_double2(v0, v1);
-        else reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
+        else if (d.res) reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
         const double wq = wquad(W, v0, v1);
         cost += wq;
         ccur += wq;
@@ -688,7 +690,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
     // them, long after
     __syncthreads();
     double2* res = reinterpret_cast<double2*>(d.res) + b0;
-    for (int t = threadIdx.x; t < nobs; t += IT) {
+    for (int t = threadIdx.x; d.res && t < nobs; t += IT) {
       const double2 v = sg.xy[t];
       __builtin_nontemporal_store(v.x, &res[t].x);
       __builtin_nontemporal_store(v.y, &res[t].y);
@@ -765,6 +767,10 @@ __global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* 
 // and the cost before the step.  Packs (X, V*^-1, g_X) for the Schur pass.
 // Copies of fresh sub-blocks are skipped while the intersection's records
 // are valid (it wrote them at this very state); so are whole workgroups.
+// J: arithmetic of the Jacobians and of the per-observation products (FP32
+// on the mixed path, with the projection, the residual and the cost in FP64
+// and the sums added to the FP64 prior before the FP64 inverse).
+template <typename J>
 __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
   __shared__ double sh[8];
   __shared__ int l_first, s_skip;
@@ -797,19 +803,27 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
       double om[6];
       om_load(d, c, om);
       double dx[3] = {X[0] - xb[0], X[1] - xb[1], X[2] - xb[2]};
-      double h[6], g[3];
-      for (int q = 0; q < 6; ++q) h[q] = om[q];
-      sym3_mul(om, dx, g);
-      double cost = dx[0] * g[0] + dx[1] * g[1] + dx[2] * g[2];
+      double gp[3];
+      sym3_mul(om, dx, gp);
+      double cost = dx[0] * gp[0] + dx[1] * gp[1] + dx[2] * gp[2];
+      // in FP64 the sums start from the prior (the oracle's order); in FP32
+      // they start from zero and the prior is added in FP64
+      J hj[6], gj[3];
+      for (int q = 0; q < 6; ++q) hj[q] = sizeof(J) == 8 ? (J)om[q] : J(0);
+      for (int q = 0; q < 3; ++q) gj[q] = sizeof(J) == 8 ? (J)gp[q] : J(0);
       for (int k = k0; k < k1; ++k) {
         const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
-        Lin<double> L;
-        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
-        double v0 = L.g0 - d.xy[2 * k], v1 = L.g1 - d.xy[2 * k + 1];
-        W2<double> W = obs_weight(d, k, unit);
-        add_point_normals<double>(L, W, v0, v1, h, g);
+        Lin<J> L;
+        double g0, g1, z;
+        linearise_split<J>(cm, cm + 9, X, d.f, d.cx, d.cy, L, g0, g1, z);
+        const double v0 = g0 - d.xy[2 * k], v1 = g1 - d.xy[2 * k + 1];
+        const W2<double> W = obs_weight(d, k, unit);
+        add_point_normals<J>(L, W2<J>{(J)W.a, (J)W.b, (J)W.c}, (J)v0, (J)v1, hj, gj);
         cost += wquad(W, v0, v1);
       }
+      double h[6], g[3];
+      for (int q = 0; q < 6; ++q) h[q] = sizeof(J) == 8 ? (double)hj[q] : om[q] + (double)hj[q];
+      for (int q = 0; q < 3; ++q) g[q] = sizeof(J) == 8 ? (double)gj[q] : gp[q] + (double)gj[q];
       h[0] *= 1.0 + d.lambda;
       h[3] *= 1.0 + d.lambda;
       h[5] *= 1.0 + d.lambda;
@@ -882,6 +896,10 @@ __global__ void k_cam_update(Dev d) {
 
 // One thread per copy: dX = V*^-1 (-g_X - sum_k Y_k^T dC_i(k)) with Y_k at the
 // old cameras, X^l += dX, and the cost after the step at the new cameras.
+// J: arithmetic of the Jacobians and per-observation products of the first
+// pass (FP32 on the mixed path; residuals, the 3x3 solve, the point and the
+// cost after the step stay FP64).
+template <typename J>
 __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
   __shared__ double sh[16];
   __shared__ int l_first;
@@ -910,31 +928,41 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       if (!fresh)
         for (int r = 0; r < 3; ++r) X[r] = xc[r];
       double dx0[3] = {X[0] - xb[0], X[1] - xb[1], X[2] - xb[2]};
-      double h[6], g[3], bt[3] = {0.0, 0.0, 0.0};
-      for (int q = 0; q < 6; ++q) h[q] = om[q];
-      sym3_mul(om, dx0, g);
+      double gp[3];
+      sym3_mul(om, dx0, gp);
+      // in FP64 the sums start from the prior (the oracle's order); in FP32
+      // they start from zero and the prior is added in FP64
+      J hj[6], gj[3], bt[3] = {J(0), J(0), J(0)};
+      for (int q = 0; q < 6; ++q) hj[q] = sizeof(J) == 8 ? (J)om[q] : J(0);
+      for (int q = 0; q < 3; ++q) gj[q] = sizeof(J) == 8 ? (J)gp[q] : J(0);
       const int base = d.blk_cam_off[l];
       const double* xs = d.x + d.vec_off[l];
       for_copy_obs(d, d.cam, k0, k1, unit, [&](const CopyObs& o) {
-        Lin<double> L;
-        linearise<double>(o.cm, o.cm + 9, X, d.f, d.cx, d.cy, L);
-        const W2<double> W = o.W;
-        add_point_normals<double>(L, W, L.g0 - o.x, L.g1 - o.y, h, g);
-        const double* dC = xs + 6 * (o.cam - base);
+        Lin<J> L;
+        double g0, g1, z;
+        linearise_split<J>(o.cm, o.cm + 9, X, d.f, d.cx, d.cy, L, g0, g1, z);
+        const W2<J> W{(J)o.W.a, (J)o.W.b, (J)o.W.c};
+        add_point_normals<J>(L, W, (J)(g0 - o.x), (J)(g1 - o.y), hj, gj);
+        const double* dCd = xs + 6 * (o.cam - base);
+        J dC[6];
+        for (int q = 0; q < 6; ++q) dC[q] = (J)dCd[q];
         // t = A dC = Ar w - B dc ; Y^T dC = B^T W t
-        double t0 = L.Ar[0][0] * dC[0] + L.Ar[0][1] * dC[1] + L.Ar[0][2] * dC[2] -
-                    (L.B[0][0] * dC[3] + L.B[0][1] * dC[4] + L.B[0][2] * dC[5]);
-        double t1 = L.Ar[1][0] * dC[0] + L.Ar[1][1] * dC[1] + L.Ar[1][2] * dC[2] -
-                    (L.B[1][0] * dC[3] + L.B[1][1] * dC[4] + L.B[1][2] * dC[5]);
-        double wt0 = W.a * t0 + W.b * t1, wt1 = W.b * t0 + W.c * t1;
+        J t0 = L.Ar[0][0] * dC[0] + L.Ar[0][1] * dC[1] + L.Ar[0][2] * dC[2] -
+               (L.B[0][0] * dC[3] + L.B[0][1] * dC[4] + L.B[0][2] * dC[5]);
+        J t1 = L.Ar[1][0] * dC[0] + L.Ar[1][1] * dC[1] + L.Ar[1][2] * dC[2] -
+               (L.B[1][0] * dC[3] + L.B[1][1] * dC[4] + L.B[1][2] * dC[5]);
+        J wt0 = W.a * t0 + W.b * t1, wt1 = W.b * t0 + W.c * t1;
         for (int s = 0; s < 3; ++s) bt[s] += L.B[0][s] * wt0 + L.B[1][s] * wt1;
       });
+      double h[6], g[3];
+      for (int q = 0; q < 6; ++q) h[q] = sizeof(J) == 8 ? (double)hj[q] : om[q] + (double)hj[q];
+      for (int q = 0; q < 3; ++q) g[q] = sizeof(J) == 8 ? (double)gj[q] : gp[q] + (double)gj[q];
       h[0] *= 1.0 + d.lambda;
       h[3] *= 1.0 + d.lambda;
       h[5] *= 1.0 + d.lambda;
       double lch[6], dX[3] = {0.0, 0.0, 0.0};
       if (chol3(h, lch)) {
-        double rhs[3] = {-g[0] - bt[0], -g[1] - bt[1], -g[2] - bt[2]};
+        double rhs[3] = {-g[0] - (double)bt[0], -g[1] - (double)bt[1], -g[2] - (double)bt[2]};
         chol3_solve(lch, rhs, dX);
       }
       double Xn[3] = {X[0] + dX[0], X[1] + dX[1], X[2] + dX[2]};
@@ -1181,12 +1209,14 @@ void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, dou
 
 void launch_copy_prep(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_step_begin, dim3(grid_for(d.L)), dim3(NT), 0, st, d);
-  hipLaunchKernelGGL(k_copy_prep, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  if (d.cpk_f32) hipLaunchKernelGGL(k_copy_prep<float>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  else hipLaunchKernelGGL(k_copy_prep<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
 }
 
 void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
   hipLaunchKernelGGL(k_cam_update, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
-  hipLaunchKernelGGL(k_back_update, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  if (d.cpk_f32) hipLaunchKernelGGL(k_back_update<float>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  else hipLaunchKernelGGL(k_back_update<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_update_finish, dim3(grid_for(std::max<int64_t>((int64_t)CAM_STRIDE * d.M, d.L))), dim3(NT), 0,
                      st, d, block_stats);
 }

@@ -9,7 +9,8 @@
 // Each 6x6 block is owned by one group of lanes that sums the contributions of
 // its observation pairs in registers and writes the block once: no atomics,
 // deterministic order.  Diagonal blocks (one 64-lane wave per camera) also
-// reduce U*, g_C and e; off-diagonal blocks take a 16-lane group each.
+// reduce U*, g_C and e; off-diagonal blocks take a group of 4, 8 or 16 lanes
+// each (an option the autotuner picks).
 //
 // T is the arithmetic of the Jacobians and of the accumulation: double on the
 // FP64 path, float on the mixed path (X - C is formed in FP64 first).  Output
@@ -310,11 +311,11 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
   }
 }
 
-// One PB_LANES-lane group per off-diagonal pair block (i, i2), i2 < i in the sub-block.
-template <typename T>
+// One G-lane group per off-diagonal pair block (i, i2), i2 < i in the sub-block.
+template <typename T, int G>
 __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
-  const int gl = threadIdx.x & (PB_LANES - 1);
-  const int64_t t = (int64_t)blockIdx.x * (NT / PB_LANES) + (threadIdx.x / PB_LANES);
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t t = (int64_t)blockIdx.x * (NT / G) + (threadIdx.x / G);
   if (t >= d.n_od) return;  // uniform over the lane group
   const int q = d.od_pb[t];
   const int i1 = d.pb_row[q];
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
   T acc[36];
 #pragma unroll
   for (int u = 0; u < 36; ++u) acc[u] = T(0);
-  for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += PB_LANES) {
+  for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += G) {
     const int c = d.pb_ent[3 * e], t1 = d.pb_ent[3 * e + 1], t2 = d.pb_ent[3 * e + 2];
     ObsIn<T> o;
     obs_in_load<T, false>(d, t1, c, true, unit, o);
@@ -348,12 +349,12 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
       for (int s = 0; s < 6; ++s) acc[6 * r + s] -= Z1[r][0] * Y2[s][0] + Z1[r][1] * Y2[s][1] + Z1[r][2] * Y2[s][2];
   }
 #pragma unroll
-  for (int u = 0; u < 36; ++u) acc[u] = group_sum<PB_LANES>(acc[u]);
+  for (int u = 0; u < 36; ++u) acc[u] = group_sum<G>(acc[u]);
   const int a1 = i1 - base;
   const bool sparse = d.blk_pcg && d.blk_pcg[l];
 #pragma unroll
   for (int u = 0; u < 36; ++u) {
-    if ((u & (PB_LANES - 1)) != gl) continue;
+    if ((u & (G - 1)) != gl) continue;
     const int r = u / 6, s = u % 6;
     if (sparse) {
       d.bsr[(int64_t)d.pb_bsr[q] * 36 + u] = (float)acc[u];
@@ -378,11 +379,18 @@ void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, h
   else hipLaunchKernelGGL(k_schur_diag<double>, dim3(gd), dim3(NT), 0, st, d);
 }
 
-void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st) {
-  const unsigned go = (unsigned)((d.n_od + NT / PB_LANES - 1) / (NT / PB_LANES));
+template <int G>
+static void launch_offdiag_lanes(const Dev& d, bool fp32, hipStream_t st) {
+  const unsigned go = (unsigned)((d.n_od + NT / G - 1) / (NT / G));
   if (!go) return;
-  if (fp32) hipLaunchKernelGGL(k_schur_offdiag<float>, dim3(go), dim3(NT), 0, st, d);
-  else hipLaunchKernelGGL(k_schur_offdiag<double>, dim3(go), dim3(NT), 0, st, d);
+  if (fp32) hipLaunchKernelGGL((k_schur_offdiag<float, G>), dim3(go), dim3(NT), 0, st, d);
+  else hipLaunchKernelGGL((k_schur_offdiag<double, G>), dim3(go), dim3(NT), 0, st, d);
+}
+
+void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st) {
+  if (d.pb_lanes == 4) launch_offdiag_lanes<4>(d, fp32, st);
+  else if (d.pb_lanes == 16) launch_offdiag_lanes<16>(d, fp32, st);
+  else launch_offdiag_lanes<8>(d, fp32, st);
 }
 
 }  // namespace rpba

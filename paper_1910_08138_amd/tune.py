@@ -7,9 +7,15 @@ configuration, and keeps the fastest one whose steps all factorise:
 
   * the Cholesky tile edge (32 or 64) and the factorisation schedule (one
     persistent dataflow launch, or three launches per tile column);
+  * then, with the best of those, the lanes per camera-pair block of the
+    Schur pass (4, 8 or 16);
   * on the mixed-precision path also the cut between sub-blocks solved
     directly and those solved by block-Jacobi PCG with iterative refinement
-    (``pcg_min_cams``; None = every sub-block direct).
+    (``pcg_min_cams`` 300, 200 or 150 cameras; None = every sub-block
+    direct).
+
+The search is coordinate-wise: each stage keeps the best configuration of
+the previous one and varies one choice.
 
 Results are cached in a JSON file keyed by a signature of the problem's shape
 (camera, point and observation counts and the sorted sub-block sizes) and the
@@ -37,19 +43,20 @@ def signature(scene, precision) -> str:
     return h.hexdigest()[:20]
 
 
-def candidates(precision):
-    base = [dict(chol_tile=t, chol_schedule=s)
-            for t in (64, 32) for s in (binding.RPBA_CHOL_DATAFLOW, binding.RPBA_CHOL_STEPWISE)]
-    if precision != binding.RPBA_MIXED:
-        return base
-    out = [dict(c, pcg_min_cams=None) for c in base]
-    for cut in (300, 200):
-        out.append(dict(chol_tile=64, chol_schedule=binding.RPBA_CHOL_DATAFLOW, pcg_min_cams=cut))
+def stages(precision):
+    """The candidate configurations of each search stage; a stage's entries
+    override the best configuration found so far."""
+    out = [[dict(chol_tile=t, chol_schedule=sc, pair_lanes=8, pcg_min_cams=None)
+            for t in (64, 32) for sc in (binding.RPBA_CHOL_DATAFLOW, binding.RPBA_CHOL_STEPWISE)],
+           [dict(pair_lanes=g) for g in (4, 16)]]
+    if precision == binding.RPBA_MIXED:
+        out.append([dict(pcg_min_cams=c) for c in (300, 200, 150)])
     return out
 
 
 def _options(cand, precision):
-    opts = dict(precision=precision, chol_tile=cand["chol_tile"], chol_schedule=cand["chol_schedule"])
+    opts = dict(precision=precision, chol_tile=cand["chol_tile"], chol_schedule=cand["chol_schedule"],
+                pair_lanes=cand.get("pair_lanes", 8))
     if cand.get("pcg_min_cams") is not None:
         opts.update(solver=binding.RPBA_SOLVER_AUTO, pcg_min_cams=cand["pcg_min_cams"])
     return opts
@@ -98,15 +105,24 @@ def tune(scene, precision=binding.RPBA_FP64, cache_path=DEFAULT_CACHE, steps=5, 
         ent = cache[key]
         return _options(ent["choice"], precision), ent["table"]
     table = []
-    for cand in candidates(precision):
-        t0 = time.time()
-        ms, fails = measure(scene, _options(cand, precision), steps=steps)
-        table.append(dict(cand, ms=ms, fails=fails))
-        if log:
-            log(f"tune {cand}: {ms:.3f} ms per LM step ({time.time() - t0:.1f} s)")
-    ok = [r for r in table if r["fails"] == 0] or table
-    best = min(ok, key=lambda r: r["ms"])
-    choice = {k: best[k] for k in ("chol_tile", "chol_schedule", "pcg_min_cams") if k in best}
+    best = None
+    for stage in stages(precision):
+        base = dict(best) if best else {}
+        for k in ("ms", "fails"):
+            base.pop(k, None)
+        for over in stage:
+            cand = dict(base, **over)
+            t0 = time.time()
+            ms, fails = measure(scene, _options(cand, precision), steps=steps)
+            row = dict(cand, ms=ms, fails=fails)
+            table.append(row)
+            if log:
+                log(f"tune {cand}: {ms:.3f} ms per LM step ({time.time() - t0:.1f} s)")
+            if fails == 0 and (best is None or ms < best["ms"]):
+                best = row
+    if best is None:
+        best = min(table, key=lambda r: r["ms"])
+    choice = {k: best[k] for k in ("chol_tile", "chol_schedule", "pair_lanes", "pcg_min_cams") if k in best}
     if cache_path:
         cache[key] = dict(choice=choice, table=table)
         try:

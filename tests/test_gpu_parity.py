@@ -259,3 +259,30 @@ def test_banded_factor_skips_zero_tiles(rp):
     oR, oC = op.cameras()
     assert np.abs(gC - oC).max() <= TOL * _extent(s)
     assert _rot_angle(gR, oR) <= TOL
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+def test_pair_lane_groups_give_the_same_rcs(rp, lanes):
+    """The camera-pair blocks summed by groups of 4 or 16 lanes (an autotuner
+    choice) against the oracle, on a scene with long pair lists."""
+    s = _scene("oblique-small", 4)
+    gp = rp.Problem(s, pair_lanes=lanes)
+    op = oracle.OracleProblem(s)
+    gp.rpba_intersect()
+    op.intersect()
+    gp.rpba_subblock_lm_step()
+    op.lm_step()
+    for l in range(s.L):
+        Sg, eg = gp.block_rcs(l)
+        So, eo = op.block_rcs(l, Sg.shape[0])
+        assert np.abs(np.tril(Sg) - np.tril(So)).max() <= TOL * np.abs(So).max(), l
+
+
+def test_robust_reweight_needs_the_robust_option(rp):
+    """Without opt.robust the intersection keeps no residuals and the
+    re-weighting is refused (RPBA_ERR_STATE)."""
+    s = _scene("ring", 2)
+    gp = rp.Problem(s)
+    gp.rpba_intersect()
+    with pytest.raises(rp.RpbaError, match="ERR_STATE"):
+        gp.rpba_robust_reweight(False)

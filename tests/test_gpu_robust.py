@@ -29,7 +29,7 @@ def rp():
 
 
 def _one_reweight(rp, s, eliminate):
-    gp = rp.Problem(s)
+    gp = rp.Problem(s, robust=1)
     op = oracle.OracleProblem(s)
     gp.rpba_intersect()
     op.intersect()

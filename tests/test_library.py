@@ -100,6 +100,20 @@ def test_validation_rejects_empty_subblock_and_bad_tile():
     assert rc == 1 and "chol_tile" in msg
     rc, _, msg = _size(s, chol_schedule=7)
     assert rc == 1 and "chol_schedule" in msg
+    rc, _, msg = _size(s, pair_lanes=5)
+    assert rc == 1 and "pair_lanes" in msg
+    rc, _, msg = _size(s, robust=2)
+    assert rc == 1 and "robust" in msg
+
+
+def test_residuals_take_workspace_only_when_kept():
+    """A handle without the robust option keeps no residuals (16 bytes per
+    observation less)."""
+    s = scenes.config_scene(1, 0)
+    rc0, n0, _ = _size(s, robust=0)
+    rc1, n1, _ = _size(s, robust=1)
+    assert rc0 == 0 and rc1 == 0
+    assert n1 - n0 >= 16 * s.K
 
 
 @pytest.mark.parametrize("first,costs,steps", [
