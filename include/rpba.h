@@ -68,8 +68,26 @@ enum {
   RPBA_PT_NOT_CONVERGED = 1, /* Gauss-Newton did not reach int_tol in int_maxit iterations */
   RPBA_PT_BEHIND = 2,        /* some p3 <= 0 */
   RPBA_PT_ILL = 3,           /* 3x3 Cholesky pivot <= 1e-12 * largest diagonal */
-  RPBA_PT_ELIMINATED = 4     /* removed by the robust step */
+  RPBA_PT_ELIMINATED = 4,    /* removed by the robust step */
+  RPBA_PT_FILTERED = 5       /* plain variants: |X| > 1e10 or a reprojection error above filter_px */
 };
+/* variant of the method (Sec. 4 and the comparisons of Sec. 6.3-6.4):
+ *   EXTENDED       the covariance-weighted consensus: every point intersected
+ *                  (eq:bars), tie-point copies weighted by the information
+ *                  from the cameras outside their sub-block (Sec. 5.1)
+ *   ALL_CAMERAS    as EXTENDED, tie-point copies weighted by the information
+ *                  from all cameras (Omega = H)
+ *   SCALAR         as EXTENDED, tie-point copies weighted by rho_t I
+ *   PLAIN          ADMM consensus (eq:admm7-eq:admm9): no intersection; a
+ *                  tie-point copy is pulled towards X_j - Xtilde_j^l with
+ *                  weight rho_t I, the consensus averages the copies (X_j)
+ *                  and updates Xtilde_j^l += X_j^l - X_j; rpba_intersect only
+ *                  evaluates the residuals at X_j (and applies the filters)
+ *   PLAIN_REFINED  PLAIN with the tie-point weights of Sec. 5.1 evaluated at
+ *                  X_j (Omega = H - H^(l), points not moved)
+ * rho_t = rho * rho_growth^t after t calls of rpba_consensus. */
+enum { RPBA_VARIANT_EXTENDED = 0, RPBA_VARIANT_ALL_CAMERAS = 1, RPBA_VARIANT_SCALAR = 2, RPBA_VARIANT_PLAIN = 3,
+       RPBA_VARIANT_PLAIN_REFINED = 4 };
 
 typedef struct rpba_problem rpba_problem;
 
@@ -105,6 +123,10 @@ typedef struct {
   int32_t robust;        /* 1: the intersection keeps its residuals for rpba_robust_reweight (Sec. 5.3);
                             0: it does not, and rpba_robust_reweight returns RPBA_ERR_STATE: 0 */
   int32_t pair_lanes;    /* lanes per camera-pair block in the Schur pass: 4, 8 or 16 (0 = 8) */
+  int32_t variant;       /* RPBA_VARIANT_*: EXTENDED */
+  double rho;            /* scalar tie-point weight of SCALAR / PLAIN variants [1/unit^2]: 1000 */
+  double rho_growth;     /* factor applied to rho at every rpba_consensus (Sec. 6.3): 1.01 */
+  double filter_px;      /* PLAIN variants: a point with a reprojection error above this is filtered: 1000 */
 } rpba_options;
 
 /* Fill *opt with the defaults listed above.  HOST pointer. */
@@ -194,7 +216,9 @@ int32_t rpba_ratio_update(int32_t n, const double *cost, double ratio, double *b
 
 /* Consensus exchange (Sec. 5): cameras go back to desc->cam_R / cam_C; every
  * point's start value for the next intersection is the mean of its sub-block
- * copies (eq:admm8 form), written to desc->pts.
+ * copies (eq:admm8 form), written to desc->pts.  PLAIN variants also update
+ * the copies' dual offsets (eq:admm9); every variant then multiplies rho_t by
+ * rho_growth.
  *   stats [2]: largest distance of a copy from its point's mean, number of TPs
  *         (or NULL) */
 rpba_status rpba_consensus(rpba_problem *h, double *stats);

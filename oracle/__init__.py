@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["rpba_oracle.cpp", "rpba_oracle_solvers.cpp"]
 LIB = os.path.join(HERE, "liboracle.so")
 
-ST_OK, ST_NOT_CONVERGED, ST_BEHIND, ST_ILL, ST_ELIMINATED = 0, 1, 2, 3, 4
+ST_OK, ST_NOT_CONVERGED, ST_BEHIND, ST_ILL, ST_ELIMINATED, ST_FILTERED = 0, 1, 2, 3, 4, 5
+V_EXTENDED, V_ALL_CAMERAS, V_SCALAR, V_PLAIN, V_PLAIN_REFINED = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True, native: bool = False, path: str | None = None) -> str:
@@ -70,7 +71,9 @@ _up = ctypes.POINTER(ctypes.c_uint8)
 def _declare(L):
     L.orc_create.restype = ctypes.c_void_p
     L.orc_create.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 4 + [_dp] * 4 + [_ip, _ip, _dp, _ip,
-                                                                                     ctypes.c_double, ctypes.c_double, ctypes.c_int]
+                                                                                     ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                                                     ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                                                     ctypes.c_double]
     L.orc_destroy.argtypes = [ctypes.c_void_p]
     L.orc_intersect.argtypes = [ctypes.c_void_p, _dp]
     L.orc_robust_reweight.restype = ctypes.c_int
@@ -87,6 +90,7 @@ def _declare(L):
     L.orc_get_copies.argtypes = [ctypes.c_void_p, _ip, _ip, _dp, _dp]
     L.orc_get_weights.argtypes = [ctypes.c_void_p, _dp]
     L.orc_set_copies.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_get_duals.argtypes = [ctypes.c_void_p, _dp]
     L.orc_set_residuals.argtypes = [ctypes.c_void_p, _dp]
     L.orc_get_residuals.argtypes = [ctypes.c_void_p, _dp]
     L.orc_block_rcs.restype = ctypes.c_int
@@ -132,7 +136,8 @@ def i32(a):
 class OracleProblem:
     """Stateful oracle run on one scene (same call sequence as the library)."""
 
-    def __init__(self, scene, lam=1e-4, int_tol=1e-12, int_maxit=20, obs_info=None):
+    def __init__(self, scene, lam=1e-4, int_tol=1e-12, int_maxit=20, obs_info=None, variant=V_EXTENDED, rho=1000.0,
+                 rho_growth=1.01, filter_px=1000.0):
         L = lib()
         self._keep = dict(R=f64(scene.cam_R), C=f64(scene.cam_C), X=f64(scene.pts), xy=f64(scene.obs_xy),
                           cam=i32(scene.obs_cam), pt=i32(scene.obs_pt), blk=i32(scene.cam_block),
@@ -141,7 +146,8 @@ class OracleProblem:
         self.M, self.N, self.K, self.L = scene.M, scene.N, scene.K, scene.L
         self.h = L.orc_create(self.M, self.N, self.K, self.L, scene.f, scene.cx, scene.cy, scene.sigma_px,
                               _p(k["R"]), _p(k["C"]), _p(k["X"]), _p(k["xy"]), _p(k["cam"], _ip), _p(k["pt"], _ip),
-                              _p(k["info"]), _p(k["blk"], _ip), lam, int_tol, int_maxit)
+                              _p(k["info"]), _p(k["blk"], _ip), lam, int_tol, int_maxit, int(variant), float(rho),
+                              float(rho_growth), float(filter_px))
         self._lib = L
 
     def __del__(self):
@@ -206,6 +212,12 @@ class OracleProblem:
         X = f64(X)
         assert X.shape == (self._lib.orc_num_copies(self.h), 3)
         self._lib.orc_set_copies(self.h, _p(X))
+
+    def duals(self):
+        """Dual offsets Xtilde [n_copies][3] of the plain variants."""
+        Xt = np.zeros((self._lib.orc_num_copies(self.h), 3))
+        self._lib.orc_get_duals(self.h, _p(Xt))
+        return Xt
 
     def set_residuals(self, res):
         """Test hook: residuals [2][K] of the last intersection (pixels)."""

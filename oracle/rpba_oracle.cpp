@@ -59,7 +59,20 @@
 
 namespace {
 
-enum PointStatus { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BEHIND = 2, ST_ILL = 3, ST_ELIMINATED = 4 };
+enum PointStatus { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BEHIND = 2, ST_ILL = 3, ST_ELIMINATED = 4, ST_FILTERED = 5 };
+
+// Variants of the method compared in the paper (Sec. 4, Sec. 6.3-6.4):
+//   EXTENDED      covariance-weighted consensus (Sec. 5, 5.1): points
+//                 intersected, tie-point copies weighted by the information
+//                 from the cameras outside their sub-block
+//   ALL_CAMERAS   the same with the information from all cameras
+//   SCALAR        the same with the scalar weight rho_t I
+//   PLAIN         ADMM consensus (eq:admm7 to eq:admm9): no intersection,
+//                 copies pulled towards X_j - Xtilde_j^l with weight rho_t I,
+//                 X_j = mean of the copies, Xtilde_j^l += X_j^l - X_j
+//   PLAIN_REFINED PLAIN with the weights of Sec. 5.1 at the mean point
+// rho_t grows by a constant factor per outer iteration (Sec. 6.3).
+enum Variant { V_EXTENDED = 0, V_ALL_CAMERAS = 1, V_SCALAR = 2, V_PLAIN = 3, V_PLAIN_REFINED = 4 };
 
 // ---------------------------------------------------------------- 3x3 / small
 struct Cam {
@@ -220,6 +233,8 @@ struct Problem {
   double f, cx, cy, sigma;
   double lambda, int_tol;
   int int_maxit;
+  int variant = V_EXTENDED;
+  double rho_t = 1000.0, rho_growth = 1.01, filter_px = 1000.0;
   std::vector<Cam> cams;
   std::vector<double> X;        // [N][3] global point (start value / intersection result)
   std::vector<double> Xbar;     // [N][3] last intersection result
@@ -237,6 +252,7 @@ struct Problem {
   std::vector<std::vector<int>> blk_copies;
   std::vector<std::vector<int>> pt_copies;
   std::vector<double> last_res;            // [K][2] residuals of the last intersection
+  std::vector<double> Xt;                  // [copies][3] dual offsets of the plain variants
 };
 
 Obs2 weight_of(const Problem& P, int k) {
@@ -271,6 +287,7 @@ void intersect_point(Problem& P, int j) {
   if (P.status[j] != ST_OK) return;
   const std::vector<int>& ol = P.pt_obs[j];
   double X[3] = {P.X[3 * j], P.X[3 * j + 1], P.X[3 * j + 2]};
+  const bool plain = P.variant == V_PLAIN || P.variant == V_PLAIN_REFINED;
   int st = ST_NOT_CONVERGED;
   auto normals = [&](const double* Xc, double H[3][3], double g[3], bool& behind) {
     std::memset(H, 0, sizeof(double) * 9);
@@ -284,7 +301,10 @@ void intersect_point(Problem& P, int j) {
       add_point_normals(li, weight_of(P, k), v, H, g);
     }
   };
-  for (int it = 0; it < P.int_maxit; ++it) {
+  // the plain variants do not move the point: they evaluate at the consensus
+  // point X_j
+  if (plain) st = ST_OK;
+  for (int it = 0; !plain && it < P.int_maxit; ++it) {
     double H[3][3], g[3], Lc[3][3];
     bool behind;
     normals(X, H, g, behind);
@@ -311,8 +331,17 @@ void intersect_point(Problem& P, int j) {
     double H[3][3], g[3], Lc[3][3];
     bool behind;
     normals(X, H, g, behind);
+    double vmax = 0;  // largest reprojection error, for the filters of the plain variants
+    for (int k : ol) {
+      if (!plain) break;
+      Lin li;
+      linearise(P.cams[P.ocam[k]], X, P.f, P.cx, P.cy, li);
+      vmax = std::max(vmax, std::hypot(li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]));
+    }
     if (behind) st = ST_BEHIND;
     else if (!chol3(H, Lc)) st = ST_ILL;
+    else if (plain && (!(std::sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]) <= 1e10) || vmax > P.filter_px))
+      st = ST_FILTERED;
     else {
       double Inv[3][3];
       chol3_inverse(Lc, Inv);
@@ -330,9 +359,20 @@ void intersect_point(Problem& P, int j) {
           double v[2] = {li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]};
           add_point_normals(li, weight_of(P, k), v, Hl, gl);
         }
+        // tie-point weight by variant; zero for a point seen by one sub-block
+        const bool tp = P.pt_copies[j].size() > 1;
         for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c) cp.Om[r][c] = H[r][c] - Hl[r][c];
-        for (int r = 0; r < 3; ++r) cp.X[r] = X[r];  // X^l starts at Xbar
+          for (int c = 0; c < 3; ++c) {
+            double o = 0;
+            if (tp) {
+              if (P.variant == V_EXTENDED || P.variant == V_PLAIN_REFINED) o = H[r][c] - Hl[r][c];
+              else if (P.variant == V_ALL_CAMERAS) o = H[r][c];
+              else o = r == c ? P.rho_t : 0.0;
+            }
+            cp.Om[r][c] = o;
+          }
+        if (!plain)
+          for (int r = 0; r < 3; ++r) cp.X[r] = X[r];  // X^l starts at Xbar
       }
       for (int k : ol) {
         Lin li;
@@ -378,6 +418,14 @@ struct BlockSystem {
   bool ok = true;
 };
 
+// centre of the tie-point prior of a copy: Xbar, or for the plain variants
+// X_j - Xtilde_j^l (eq:admm7)
+void prior_centre(const Problem& P, const Copy& cp, double xb[3]) {
+  const bool plain = P.variant == V_PLAIN || P.variant == V_PLAIN_REFINED;
+  const int id = (int)(&cp - P.copies.data());
+  for (int r = 0; r < 3; ++r) xb[r] = plain ? P.X[3 * cp.pt + r] - P.Xt[3 * (size_t)id + r] : P.Xbar[3 * cp.pt + r];
+}
+
 double copy_cost(const Problem& P, const Copy& cp) {
   double c = 0;
   for (int k : cp.obs) {
@@ -386,7 +434,8 @@ double copy_cost(const Problem& P, const Copy& cp) {
     double v[2] = {li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]};
     c += wnorm2(weight_of(P, k), v);
   }
-  const double* xb = &P.Xbar[3 * cp.pt];
+  double xb[3];
+  prior_centre(P, cp, xb);
   double d[3] = {cp.X[0] - xb[0], cp.X[1] - xb[1], cp.X[2] - xb[2]};
   for (int r = 0; r < 3; ++r)
     for (int s = 0; s < 3; ++s) c += d[r] * cp.Om[r][s] * d[s];
@@ -420,7 +469,8 @@ void build_block(const Problem& P, int l, BlockSystem& B) {
     double V[3][3], gx[3];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) V[r][c] = cp.Om[r][c];
-    const double* xb = &P.Xbar[3 * cp.pt];
+    double xb[3];
+    prior_centre(P, cp, xb);
     double d[3] = {cp.X[0] - xb[0], cp.X[1] - xb[1], cp.X[2] - xb[2]};
     for (int r = 0; r < 3; ++r) gx[r] = cp.Om[r][0] * d[0] + cp.Om[r][1] * d[1] + cp.Om[r][2] * d[2];
     for (int r = 0; r < 3; ++r)
@@ -540,7 +590,8 @@ void apply_update(Problem& P, int l, const BlockSystem& B, const std::vector<dou
     rodrigues(w, Rw);
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) Rn[r][c] = Rw[r][0] * cm.R[0][c] + Rw[r][1] * cm.R[1][c] + Rw[r][2] * cm.R[2][c];
-    std::memcpy(cm.R, Rn, sizeof(Rn));
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) cm.R[r][c] = Rn[r][c];
     for (int r = 0; r < 3; ++r) cm.C[r] += dC[6 * a + 3 + r];
   }
   for (int q = 0; q < B.nc; ++q) {
@@ -589,9 +640,14 @@ struct orc_problem {
 orc_problem* orc_create(int M, int N, int K, int L, double f, double cx, double cy, double sigma_px,
                         const double* cam_R, const double* cam_C, const double* pts, const double* obs_xy,
                         const int32_t* obs_cam, const int32_t* obs_pt, const double* obs_info,
-                        const int32_t* cam_block, double lambda, double int_tol, int int_maxit) {
+                        const int32_t* cam_block, double lambda, double int_tol, int int_maxit, int variant,
+                        double rho, double rho_growth, double filter_px) {
   orc_problem* h = new orc_problem;
   Problem& P = h->P;
+  P.variant = variant;
+  P.rho_t = rho;
+  P.rho_growth = rho_growth;
+  P.filter_px = filter_px;
   P.M = M; P.N = N; P.K = K; P.L = L;
   P.f = f; P.cx = cx; P.cy = cy; P.sigma = sigma_px;
   P.lambda = lambda; P.int_tol = int_tol; P.int_maxit = int_maxit;
@@ -656,6 +712,7 @@ orc_problem* orc_create(int M, int N, int K, int L, double f, double cx, double 
     P.blk_copies[l].push_back(id);
     P.pt_copies[j].push_back(id);
   }
+  P.Xt.assign(3 * P.copies.size(), 0.0);
   return h;
 }
 
@@ -751,7 +808,12 @@ void orc_consensus(orc_problem* h, double* stats) {
       dmax = std::max(dmax, d);
     }
     for (int r = 0; r < 3; ++r) P.X[3 * j + r] = m[r];
+    // plain variants: dual update Xtilde_j^l += X_j^l - X_j (eq:admm9)
+    if (P.variant == V_PLAIN || P.variant == V_PLAIN_REFINED)
+      for (int ci : cl)
+        for (int r = 0; r < 3; ++r) P.Xt[3 * (size_t)ci + r] += P.copies[ci].X[r] - m[r];
   }
+  P.rho_t *= P.rho_growth;  // the scalar weight of the next outer iteration (Sec. 6.3)
   if (stats) {
     stats[0] = dmax;
     stats[1] = (double)ntp;
@@ -829,6 +891,12 @@ void orc_set_residuals(orc_problem* h, const double* res) {
     P.last_res[2 * k] = res[k];
     P.last_res[2 * k + 1] = res[(size_t)P.K + k];
   }
+}
+
+// Dual offsets Xtilde of the copies of the plain variants ([n][3], copies in
+// (sub-block, point) order).
+void orc_get_duals(orc_problem* h, double* Xt) {
+  std::memcpy(Xt, h->P.Xt.data(), sizeof(double) * h->P.Xt.size());
 }
 
 void orc_get_weights(orc_problem* h, double* w) {

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(PKG, "librpba.so")
 RPBA_FP64, RPBA_MIXED = 0, 1
 RPBA_SOLVER_CHOL, RPBA_SOLVER_PCG_BJ, RPBA_SOLVER_PCG_LEARNED, RPBA_SOLVER_AUTO = 0, 1, 2, 3
 RPBA_CHOL_DEFAULT, RPBA_CHOL_STEPWISE, RPBA_CHOL_DATAFLOW = 0, 1, 2
+(RPBA_VARIANT_EXTENDED, RPBA_VARIANT_ALL_CAMERAS, RPBA_VARIANT_SCALAR, RPBA_VARIANT_PLAIN,
+ RPBA_VARIANT_PLAIN_REFINED) = 0, 1, 2, 3, 4
 RPBA_OK, RPBA_ERR_NOT_SPD, RPBA_WARN_NONCONVERGED = 0, 4, 100
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_WORKSPACE", 4: "ERR_NOT_SPD", 5: "ERR_STATE",
                 100: "WARN_NONCONVERGED"}
@@ -60,7 +62,8 @@ class Options(ctypes.Structure):
         ("pcg_tol", ctypes.c_double), ("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
         ("pcg_min_cams", ctypes.c_int32), ("t_v", ctypes.c_double), ("down_weight", ctypes.c_double),
         ("chol_tile", ctypes.c_int32), ("chol_schedule", ctypes.c_int32),
-        ("robust", ctypes.c_int32), ("pair_lanes", ctypes.c_int32),
+        ("robust", ctypes.c_int32), ("pair_lanes", ctypes.c_int32), ("variant", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("rho_growth", ctypes.c_double), ("filter_px", ctypes.c_double),
     ]
 
 

@@ -51,7 +51,7 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid;
+      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt;
   size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -72,7 +72,7 @@ int64_t robust_spill_values(const Plan& P, std::vector<int64_t>* off = nullptr) 
   return tot;
 }
 
-WsMap layout_for(const Plan& P, bool keep_res) {
+WsMap layout_for(const Plan& P, bool keep_res, bool plain) {
   Layout L;
   WsMap m;
   const size_t i4 = 4, i8 = 8, f8 = 8;
@@ -107,6 +107,8 @@ WsMap layout_for(const Plan& P, bool keep_res) {
   m.blk_nc = L.add(i4 * P.L);
   m.chk = L.add(i4 * 4);
   m.rec_valid = L.add(i4 * 4);
+  m.rho_t = L.add(f8 * 2);
+  m.Xt = L.add(plain ? f8 * 3 * P.NC : 0);
   m.pb_row = L.add(i4 * P.pb_row.size());
   m.pb_ent_off = L.add(i8 * P.pb_ent_off.size());
   m.pb_ent = L.add(i4 * P.pb_ent.size());
@@ -215,6 +217,11 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
   if (o->chol_schedule < RPBA_CHOL_DEFAULT || o->chol_schedule > RPBA_CHOL_DATAFLOW)
     return fail(RPBA_ERR_ARG, "chol_schedule must be RPBA_CHOL_DEFAULT, _STEPWISE or _DATAFLOW");
   if (o->robust != 0 && o->robust != 1) return fail(RPBA_ERR_ARG, "robust must be 0 or 1");
+  if (o->variant < RPBA_VARIANT_EXTENDED || o->variant > RPBA_VARIANT_PLAIN_REFINED)
+    return fail(RPBA_ERR_ARG, "unknown variant");
+  if (!(o->rho > 0) || !std::isfinite(o->rho) || !(o->rho_growth > 0) || !std::isfinite(o->rho_growth) ||
+      !(o->filter_px > 0))
+    return fail(RPBA_ERR_ARG, "rho, rho_growth and filter_px must be positive and finite");
   if (o->pair_lanes != 0 && o->pair_lanes != 4 && o->pair_lanes != 8 && o->pair_lanes != 16)
     return fail(RPBA_ERR_ARG, "pair_lanes must be 0, 4, 8 or 16");
   return RPBA_OK;
@@ -360,6 +367,10 @@ rpba_status rpba_default_options(rpba_options* o) {
   o->chol_schedule = RPBA_CHOL_DEFAULT;
   o->robust = 0;
   o->pair_lanes = 0;
+  o->variant = RPBA_VARIANT_EXTENDED;
+  o->rho = 1000.0;
+  o->rho_growth = 1.01;
+  o->filter_px = 1000.0;
   return RPBA_OK;
 }
 
@@ -370,7 +381,7 @@ rpba_status rpba_workspace_size(const rpba_problem_desc* d, const rpba_options* 
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  *bytes = layout_for(*P, o->robust != 0).total;
+  *bytes = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN).total;
   return RPBA_OK;
 }
 
@@ -384,7 +395,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  WsMap m = layout_for(*P, o->robust != 0);
+  WsMap m = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN);
   if (bytes < m.total) return fail(RPBA_ERR_WORKSPACE, "workspace too small: need " + std::to_string(m.total));
   size_t lds = 0;
 
@@ -649,6 +660,11 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.blk_fail = I(m.blk_fail);
   D.blk_nc = I(m.blk_nc);
   D.rec_valid = I(m.rec_valid);
+  D.variant = o->variant;
+  D.rho_t = F(m.rho_t);
+  D.rho_growth = o->rho_growth;
+  D.filter_px = o->filter_px;
+  D.Xt = o->variant >= RPBA_VARIANT_PLAIN ? F(m.Xt) : nullptr;
   D.acc_int = F(m.acc_int);
   D.acc_blk = F(m.acc_blk);
   D.acc_cons = F(m.acc_cons);
@@ -688,6 +704,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero_i32((int32_t*)(w + m.rob_bad), D.N, st);
   launch_zero((double*)(w + m.rob_sigma), D.M, st);
   launch_init_rcs(D, st);
+  HIP_TRY(hipMemcpyAsync(D.rho_t, &o->rho, sizeof(double), hipMemcpyHostToDevice, st));
+  if (o->variant >= RPBA_VARIANT_PLAIN) launch_init_copies(D, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   *out = h.release();

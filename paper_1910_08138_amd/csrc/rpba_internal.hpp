@@ -79,6 +79,11 @@ struct Dev {
   double* Xc;             // [NC][3] X_j^l (valid when the sub-block is not fresh)
   int32_t* blk_fresh;     // [L] 1: every copy of the sub-block is still at Xbar (set by the
                           // intersection, cleared by the sub-block's next update)
+  int32_t variant;        // RPBA_VARIANT_*
+  double* rho_t;          // [1] scalar tie-point weight of this outer iteration (SCALAR, PLAIN)
+  double rho_growth;      // factor applied to rho_t by every consensus
+  double filter_px;       // PLAIN variants: reprojection error above which a point is filtered
+  double* Xt;             // [NC][3] PLAIN variants: dual offset Xtilde of every copy (eq:admm9)
   int32_t* rec_valid;     // [1] 1: the copy records of the fresh sub-blocks hold their point
                           // blocks at the current state (written by the intersection; cleared by
                           // a robust re-weighting and by anything that reuses the record array)
@@ -186,6 +191,8 @@ void launch_df_reset(int* ctl, hipStream_t st);
 void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, hipStream_t st);
 void launch_update(const Dev& d, double* block_stats, hipStream_t st);
 void launch_consensus(const Dev& d, double* stats, hipStream_t st);
+// PLAIN variants: every copy starts at its point's start value, duals zero
+void launch_init_copies(const Dev& d, hipStream_t st);
 void launch_zero(double* p, int64_t n, hipStream_t st);
 void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);

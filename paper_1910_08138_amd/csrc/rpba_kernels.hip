@@ -192,6 +192,22 @@ __global__ void k_gather_pm(Dev d) {
   }
 }
 
+// ------------------------------------------------------------ prior centre
+// Centre of the tie-point prior of copy c of point p: the intersected point
+// Xbar (the method and its ablations), or for the plain variants the
+// consensus point minus the copy's dual offset, X_j - Xtilde_j^l (eq:admm7)
+__device__ __forceinline__ void prior_centre(const Dev& d, int p, int64_t c, double (&xb)[3]) {
+  if (d.Xt) {
+    xb[0] = d.P0[p] - d.Xt[3 * c];
+    xb[1] = d.P0[(int64_t)d.N + p] - d.Xt[3 * c + 1];
+    xb[2] = d.P0[2 * (int64_t)d.N + p] - d.Xt[3 * c + 2];
+  } else {
+    xb[0] = d.Xbar[p];
+    xb[1] = d.Xbar[(int64_t)d.N + p];
+    xb[2] = d.Xbar[2 * (int64_t)d.N + p];
+  }
+}
+
 // ------------------------------------------------------------ copy records
 // The record of copy c for the Schur pass of the next LM step: X, the damped
 // point block's inverse V*^-1 (zero if V* did not factorise), g_X, valid.
@@ -397,9 +413,14 @@ __device__ __forceinline__ void put_pxs(const Dev& d, int j, const double (&X)[3
 // one point: Gauss-Newton to convergence, then the final pass (covariance,
 // residuals, refined weights of the copies); accv gets the point's share of
 // the statistics
-template <bool INFO, bool OLDS>
+// VAR: the variant of the method (RPBA_VARIANT_*): the tie-point weights
+// Omega of the copies, and for the plain variants an evaluation at the
+// consensus point instead of Gauss-Newton (no copy records: their copies are
+// never reset)
+template <bool INFO, bool OLDS, int VAR>
 __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlots& cs, int b0, int j, int want_cov,
                                                 double (&accv)[4]) {
+  constexpr bool PLAIN = VAR >= RPBA_VARIANT_PLAIN;
   if (j < d.N && d.status[j] == 0) {
     const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1], n = c1 - c0;
     const int i0 = d.pm_off[j], i1 = d.pm_off[j + 1];
@@ -412,9 +433,9 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
     auto copy_at = [&](int u) {
       return u == 0 ? cpy[0] : u == 1 ? cpy[1] : u == 2 ? cpy[2] : u == 3 ? cpy[3] : d.pt_copies[c0 + u];
     };
-    int st = 1;  // not converged
+    int st = PLAIN ? 0 : 1;  // not converged (the plain variants evaluate at the consensus point)
     double h[6], g[3], lch[6];
-    for (int it = 0; it < d.int_maxit; ++it) {
+    for (int it = 0; !PLAIN && it < d.int_maxit; ++it) {
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       g[0] = g[1] = g[2] = 0.0;
       bool behind = false;
@@ -482,6 +503,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
     double hl0[6] = {0, 0, 0, 0, 0, 0}, hl[6] = {0, 0, 0, 0, 0, 0};
     double gl0[3] = {0, 0, 0}, gl[3] = {0, 0, 0};
     double cst0 = 0.0, cst1 = 0.0, cst2 = 0.0, ccur = 0.0;  // costs of copies 0, 1, 2 and of the current one
+    double vmax = 0.0;                                        // largest squared reprojection error (filters)
     if (st == 0) {
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
       bool behind = false;
@@ -502,6 +524,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         const double wq = wquad(W, v0, v1);
         cost += wq;
         ccur += wq;
+        if (PLAIN) vmax = fmax(vmax, v0 * v0 + v1 * v1);
         sq += v0 * v0 + v1 * v1;
         nobs += 1.0;
         if (code & PM_LAST) {  // copy u complete
@@ -520,7 +543,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
               park_g(d, c, gl);
               if (u == 1) cst1 = ccur;
               else if (u == 2) cst2 = ccur;
-              else cost_add(d, cs, d.copy_blk[c], ccur);  // rare: a point in five or more sub-blocks
+              else if (!PLAIN) cost_add(d, cs, d.copy_blk[c], ccur);  // rare: a point in five or more sub-blocks
             }
             for (int q = 0; q < 6; ++q) hl[q] = 0.0;
             for (int q = 0; q < 3; ++q) gl[q] = 0.0;
@@ -531,6 +554,10 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
       }
       if (behind) st = 2;
       else if (!chol3(h, lch)) st = 3;
+      // filters of the plain variants (Sec. 6.3): very far points, and points
+      // with a reprojection error above filter_px
+      else if (PLAIN && (!(X[0] * X[0] + X[1] * X[1] + X[2] * X[2] <= 1e20) || vmax > d.filter_px * d.filter_px))
+        st = 5;
     }
     double inv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (st == 0) {
@@ -539,36 +566,51 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         d.Xbar[(int64_t)r * d.N + j] = X[r];
         d.P0[(int64_t)r * d.N + j] = X[r];
       }
+      const double rho = (VAR == RPBA_VARIANT_SCALAR || VAR == RPBA_VARIANT_PLAIN) ? *d.rho_t : 0.0;
       // Every copy restarts at Xbar with the same cameras, so the point block
       // of its sub-block, sum_(k in l) B^T W B + Omega^l = H^(l) + (H - H^(l)),
       // is H itself: the damped V* = H + lambda diag(H) and its inverse are
       // the same for every copy, and each copy's record gets its own g^(l).
       double hv[6] = {h[0] * (1.0 + d.lambda), h[1], h[2], h[3] * (1.0 + d.lambda), h[4], h[5] * (1.0 + d.lambda)};
       double lv[6], vi[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      const bool vok = chol3(hv, lv);
-      if (vok) chol3_inverse(lv, vi);
+      bool vok = false;
+      if (VAR == RPBA_VARIANT_EXTENDED) {
+        vok = chol3(hv, lv);
+        if (vok) chol3_inverse(lv, vi);
+      }
       // Omega^l = H - H^(l): information from the cameras outside sub-block l
       // (zero for a point seen by one sub-block only).  The copies themselves
       // are reset to Xbar through the sub-blocks' fresh flags.
       for (int u2 = 0; u2 < n; ++u2) {
         const int64_t c = copy_at(u2);
-        double o6[6], g3[3];
+        double hu[6], g3[3];  // H^(l) and g^(l) of this copy
         if (u2 == 0 && n > 1) {
-          for (int q = 0; q < 6; ++q) o6[q] = h[q] - hl0[q];
+          for (int q = 0; q < 6; ++q) hu[q] = hl0[q];
           for (int q = 0; q < 3; ++q) g3[q] = gl0[q];
         } else if (u2 == n - 1) {
-          for (int q = 0; q < 6; ++q) o6[q] = n == 1 ? 0.0 : h[q] - hl[q];
+          for (int q = 0; q < 6; ++q) hu[q] = hl[q];
           for (int q = 0; q < 3; ++q) g3[q] = gl[q];
         } else {
           const double2* om = om_park(d, c);
           const double2 a = om[0], b = om[1], e = om[2];
-          o6[0] = h[0] - a.x;
-          o6[1] = h[1] - a.y;
-          o6[2] = h[2] - b.x;
-          o6[3] = h[3] - b.y;
-          o6[4] = h[4] - e.x;
-          o6[5] = h[5] - e.y;
+          hu[0] = a.x;
+          hu[1] = a.y;
+          hu[2] = b.x;
+          hu[3] = b.y;
+          hu[4] = e.x;
+          hu[5] = e.y;
           unpark_g(d, c, g3);
+        }
+        // Omega of a tie-point copy: information from the cameras outside l
+        // (EXTENDED, PLAIN_REFINED), from all cameras (ALL_CAMERAS), or rho_t I
+        // (SCALAR, PLAIN); zero for a point seen by one sub-block only
+        double o6[6];
+        for (int q = 0; q < 6; ++q) {
+          const double sc = (q == 0 || q == 3 || q == 5) ? rho : 0.0;
+          o6[q] = n == 1 ? 0.0
+                  : (VAR == RPBA_VARIANT_EXTENDED || VAR == RPBA_VARIANT_PLAIN_REFINED) ? h[q] - hu[q]
+                  : VAR == RPBA_VARIANT_ALL_CAMERAS ? h[q]
+                                                    : sc;
         }
         if (d.om_f32) {
           float2* om = reinterpret_cast<float2*>(d.Omf + 6 * c);
@@ -581,15 +623,29 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
           om[1] = make_double2(o6[2], o6[3]);
           om[2] = make_double2(o6[4], o6[5]);
         }
-        put_record(d, c, X, vi, g3, vok);
-        const double cc = u2 == n - 1 ? ccur : u2 == 0 ? cst0 : u2 == 1 ? cst1 : u2 == 2 ? cst2 : 0.0;
-        if (u2 == n - 1 || u2 < 3) cost_add(d, cs, d.copy_blk[c], cc);
+        if (!PLAIN) {
+          if (VAR == RPBA_VARIANT_EXTENDED) {
+            put_record(d, c, X, vi, g3, vok);
+          } else {
+            // the copy's own point block H^(l) + Omega^l, damped
+            double hv2[6], lv2[6], vi2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < 6; ++q) hv2[q] = hu[q] + o6[q];
+            hv2[0] *= 1.0 + d.lambda;
+            hv2[3] *= 1.0 + d.lambda;
+            hv2[5] *= 1.0 + d.lambda;
+            const bool ok2 = chol3(hv2, lv2);
+            if (ok2) chol3_inverse(lv2, vi2);
+            put_record(d, c, X, vi2, g3, ok2);
+          }
+          const double cc = u2 == n - 1 ? ccur : u2 == 0 ? cst0 : u2 == 1 ? cst1 : u2 == 2 ? cst2 : 0.0;
+          if (u2 == n - 1 || u2 < 3) cost_add(d, cs, d.copy_blk[c], cc);
+        }
       }
       accv[0] = cost;
       accv[1] = sq;
       accv[2] = nobs;
       accv[3] = 1.0;
-    } else {
+    } else if (!PLAIN) {
       // a point that fails here: its copies drop out of the Schur pass (the
       // costs of copies in five or more sub-blocks already added stay; a
       // point needs a degenerate geometry to fail after converging)
@@ -608,18 +664,22 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
     put_pxs(d, j, z, d.status[j]);
     // a point left out before (failed or eliminated): no copy of it in the
     // Schur pass
-    for (int c = d.pt_copy_off[j]; c < d.pt_copy_off[j + 1]; ++c) zero_record(d, d.pt_copies[c]);
+    if (!PLAIN)
+      for (int c = d.pt_copy_off[j]; c < d.pt_copy_off[j + 1]; ++c) zero_record(d, d.pt_copies[c]);
   }
 }
 
-template <bool INFO>
+template <bool INFO, int VAR>
 __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   __shared__ Stage sg;
   __shared__ double sh[4 * (IT / 64)];
   __shared__ CostSlots cs;
   if (blockIdx.x == 0) {
-    for (int l = threadIdx.x; l < d.L; l += IT) d.blk_fresh[l] = 1;
-    if (threadIdx.x == 0) *d.rec_valid = 1;
+    // the copies restart at Xbar (their records written below); the plain
+    // variants keep their copies where the sub-blocks left them
+    if (VAR < RPBA_VARIANT_PLAIN)
+      for (int l = threadIdx.x; l < d.L; l += IT) d.blk_fresh[l] = 1;
+    if (threadIdx.x == 0) *d.rec_valid = VAR < RPBA_VARIANT_PLAIN ? 1 : 0;
   }
   if (threadIdx.x < CSLOT) {
     cs.key[threadIdx.x] = -1;
@@ -683,7 +743,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   const int j = j0 + threadIdx.x;
   double accv[4] = {0.0, 0.0, 0.0, 0.0};
   if (nobs <= INT_OBS_CAP) {
-    intersect_point<INFO, true>(d, sg, cs, b0, j, want_cov, accv);
+    intersect_point<INFO, true, VAR>(d, sg, cs, b0, j, want_cov, accv);
     // residuals of the workgroup's stream, one coalesced copy (the slots of
     // points left invalid hold their pixels: residuals are only read for
     // valid points), as streaming stores: only a robust re-weighting reads
@@ -696,7 +756,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       __builtin_nontemporal_store(v.y, &res[t].y);
     }
   } else {
-    intersect_point<INFO, false>(d, sg, cs, b0, j, want_cov, accv);
+    intersect_point<INFO, false, VAR>(d, sg, cs, b0, j, want_cov, accv);
   }
   // workgroup sum of the statistics, one atomic per value
 #pragma unroll
@@ -795,7 +855,8 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
     const int k0 = d.copy_off[c], k1 = d.copy_off[c + 1];
     const bool act = d.active == nullptr || d.active[l];
     const int stp = d.status[p], fresh = d.blk_fresh[l];
-    const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
+    double xb[3];
+    prior_centre(d, p, c, xb);
     if (act && stp == 0) {
       double X[3] = {xb[0], xb[1], xb[2]};
       if (!fresh)
@@ -916,7 +977,8 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
     const int k0 = d.copy_off[c], k1 = d.copy_off[c + 1];
     const bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
     const int stp = d.status[p], fresh = d.blk_fresh[l];
-    const double xb[3] = {d.Xbar[p], d.Xbar[(int64_t)d.N + p], d.Xbar[2 * (int64_t)d.N + p]};
+    double xb[3];
+    prior_centre(d, p, c, xb);
     const double xc[3] = {d.Xc[3 * c], d.Xc[3 * c + 1], d.Xc[3 * c + 2]};
     double om[6];
     om_load(d, c, om);
@@ -1096,6 +1158,14 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
         double e0 = x[0] - m[0], e1 = x[1] - m[1], e2 = x[2] - m[2];
         dmax = fmax(dmax, sqrt(e0 * e0 + e1 * e1 + e2 * e2));
       }
+      // plain variants: the dual offsets Xtilde_j^l += X_j^l - X_j (eq:admm9)
+      // (their copies are never fresh)
+      if (d.Xt) {
+        for (int u = 0; u < n; ++u) {
+          const int64_t c = d.pt_copies[c0 + u];
+          for (int r = 0; r < 3; ++r) d.Xt[3 * c + r] += d.Xc[3 * c + r] - m[r];
+        }
+      }
       for (int r = 0; r < 3; ++r) d.P0[(int64_t)r * d.N + j] = m[r];
       put_pxs(d, j, m, 0);
     } else {
@@ -1125,6 +1195,7 @@ __global__ void k_consensus_cams(Dev d, double* stats) {
     stats[0] = d.acc_cons[0];
     stats[1] = d.acc_cons[1];
   }
+  if (i == 0) *d.rho_t *= d.rho_growth;  // the scalar weight of the next outer iteration
   if (i >= d.M) return;
   int o = d.cam_orig[i];
   const double* c = d.cam + (int64_t)CAM_STRIDE * i;
@@ -1195,12 +1266,23 @@ void launch_init_rcs(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_pad_identity, dim3(d.L), dim3(NT), 0, st, d);
 }
 
+template <int VAR>
+static void launch_intersect_var(const Dev& d, bool want_cov, hipStream_t st) {
+  if (d.has_info)
+    hipLaunchKernelGGL((k_intersect<true, VAR>), dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
+  else
+    hipLaunchKernelGGL((k_intersect<false, VAR>), dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
+}
+
 void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
   launch_zero(d.acc_int, 4 + (int64_t)d.L, st);
-  if (d.has_info)
-    hipLaunchKernelGGL(k_intersect<true>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
-  else
-    hipLaunchKernelGGL(k_intersect<false>, dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
+  switch (d.variant) {
+    case RPBA_VARIANT_ALL_CAMERAS: launch_intersect_var<RPBA_VARIANT_ALL_CAMERAS>(d, want_cov, st); break;
+    case RPBA_VARIANT_SCALAR: launch_intersect_var<RPBA_VARIANT_SCALAR>(d, want_cov, st); break;
+    case RPBA_VARIANT_PLAIN: launch_intersect_var<RPBA_VARIANT_PLAIN>(d, want_cov, st); break;
+    case RPBA_VARIANT_PLAIN_REFINED: launch_intersect_var<RPBA_VARIANT_PLAIN_REFINED>(d, want_cov, st); break;
+    default: launch_intersect_var<RPBA_VARIANT_EXTENDED>(d, want_cov, st); break;
+  }
 }
 
 void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
@@ -1219,6 +1301,20 @@ void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
   else hipLaunchKernelGGL(k_back_update<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_update_finish, dim3(grid_for(std::max<int64_t>((int64_t)CAM_STRIDE * d.M, d.L))), dim3(NT), 0,
                      st, d, block_stats);
+}
+
+__global__ void k_init_copies(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (c >= d.NC) return;
+  const int p = d.copy_pt[c];
+  for (int r = 0; r < 3; ++r) {
+    d.Xc[3 * c + r] = d.P0[(int64_t)r * d.N + p];
+    d.Xt[3 * c + r] = 0.0;
+  }
+}
+
+void launch_init_copies(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_copies, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
 }
 
 void launch_consensus(const Dev& d, double* stats, hipStream_t st) {
