@@ -88,6 +88,8 @@ enum {
  * rho_t = rho * rho_growth^t after t calls of rpba_consensus. */
 enum { RPBA_VARIANT_EXTENDED = 0, RPBA_VARIANT_ALL_CAMERAS = 1, RPBA_VARIANT_SCALAR = 2, RPBA_VARIANT_PLAIN = 3,
        RPBA_VARIANT_PLAIN_REFINED = 4 };
+/* what rpba_robust_reweight does with flagged observations (Sec. 5.3) */
+enum { RPBA_ROBUST_WEIGHT = 0, RPBA_ROBUST_ELIMINATE_POINTS = 1, RPBA_ROBUST_DELETE_OBS = 2 };
 
 typedef struct rpba_problem rpba_problem;
 
@@ -116,7 +118,8 @@ typedef struct {
   double ir_tol;         /* iterative refinement relative residual (FP64): 1e-10 */
   int32_t ir_maxit;      /* refinement sweeps: 6 */
   int32_t pcg_min_cams;  /* RPBA_SOLVER_AUTO: sub-blocks with at least this many cameras use PCG: 150 */
-  double t_v;            /* robust threshold on the normalised residual (Sec. 5.3, parallel variant): 4 */
+  double t_v;            /* robust threshold on the normalised residual (Sec. 5.3): 4 (parallel variant; the
+                            serial variant uses 3) */
   double down_weight;    /* weight multiplier of flagged observations: 1e-4 */
   int32_t chol_tile;     /* Cholesky tile edge, 32 or 64 (0 = library choice) */
   int32_t chol_schedule; /* RPBA_CHOL_*; DEFAULT = dataflow */
@@ -164,14 +167,24 @@ rpba_status rpba_create(const rpba_problem_desc *desc, const rpba_options *opt, 
  * Writes Xbar to desc->pts. */
 rpba_status rpba_intersect(rpba_problem *h, double *cov, int32_t *status, double *stats);
 
-/* Parallel robust variant (Sec. 5.3), for a handle created with
- * opt->robust = 1 (else RPBA_ERR_STATE): per camera, sigma0_i = 1.4826 MAD of the
- * whitened residual components of the last intersection; an observation with
- * sqrt(v^T W v) / sigma0_i > t_v gets the weight multiplier down_weight,
- * every other observation 1.  With `eliminate`, points with a flagged
- * observation get RPBA_PT_ELIMINATED.  stats [2]: flagged observations,
- * eliminated points (or NULL). */
-rpba_status rpba_robust_reweight(rpba_problem *h, int32_t eliminate, double *stats);
+/* Robust estimation (Sec. 5.3), for a handle created with opt->robust = 1
+ * (else RPBA_ERR_STATE), after rpba_intersect: per camera, sigma0_i = 1.4826
+ * MAD of the whitened residual components of the last intersection (over the
+ * observations of valid points that are not deleted); an observation with
+ * sqrt(v^T W v) / sigma0_i > opt->t_v is flagged.  mode:
+ *   RPBA_ROBUST_WEIGHT: flagged observations get the weight multiplier
+ *     opt->down_weight, every other observation 1 (both variants, after basic
+ *     convergence);
+ *   RPBA_ROBUST_ELIMINATE_POINTS: the same, and every point with a flagged
+ *     observation gets RPBA_PT_ELIMINATED (parallel variant, at the end;
+ *     t_v = 4);
+ *   RPBA_ROBUST_DELETE_OBS: flagged observations are deleted (multiplier 0)
+ *     and a flagged point left with fewer than two observations gets
+ *     RPBA_PT_ELIMINATED (serial variant, at the end; t_v = 3).
+ * A deleted observation stays deleted in later calls: it enters no scale,
+ * flag, cost or statistic.  Any other mode: RPBA_ERR_ARG.
+ * stats [2]: flagged observations, eliminated points (or NULL). */
+rpba_status rpba_robust_reweight(rpba_problem *h, int32_t mode, double *stats);
 
 /* Result of the last rpba_robust_reweight: sigma_cam [M] the per-camera
  * scales sigma0_i (0 for a camera without a valid observation), obs_weight

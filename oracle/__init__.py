@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 ST_OK, ST_NOT_CONVERGED, ST_BEHIND, ST_ILL, ST_ELIMINATED, ST_FILTERED = 0, 1, 2, 3, 4, 5
 V_EXTENDED, V_ALL_CAMERAS, V_SCALAR, V_PLAIN, V_PLAIN_REFINED = 0, 1, 2, 3, 4
+ROBUST_WEIGHT, ROBUST_ELIMINATE_POINTS, ROBUST_DELETE_OBS = 0, 1, 2
 
 
 def build(force: bool = True, native: bool = False, path: str | None = None) -> str:
@@ -160,9 +161,12 @@ class OracleProblem:
         self._lib.orc_intersect(self.h, _p(s))
         return s
 
-    def robust_reweight(self, t_v=4.0, down_weight=1e-4, eliminate=False):
+    def robust_reweight(self, t_v=4.0, down_weight=1e-4, mode=ROBUST_WEIGHT):
+        """Per-camera MAD scales and flags (Sec. 5.3); mode ROBUST_WEIGHT,
+        ROBUST_ELIMINATE_POINTS (parallel variant) or ROBUST_DELETE_OBS
+        (serial variant).  Returns (flagged observations, scales [M])."""
         sc = np.zeros(self.M)
-        n = self._lib.orc_robust_reweight(self.h, t_v, down_weight, int(eliminate), _p(sc))
+        n = self._lib.orc_robust_reweight(self.h, t_v, down_weight, int(mode), _p(sc))
         return n, sc
 
     def lm_step(self, active=None):
@@ -328,16 +332,31 @@ def mlp_loss_grad(Ginv, feat, params, zw):
     return loss, grad
 
 
-def run_schedule(scene, T=6, I=4, robust=False, t_r=2, t_v=4.0, down_weight=1e-4, callback=None, **kw):
-    """Fixed schedule: T outer iterations of (intersect [, robust, re-intersect],
-    I LM steps, consensus), then a final intersection.  Returns the oracle
+def _robust_mode(robust, t_v):
+    """(final mode, t_v) of the robust cycle (Sec. 5.3): parallel variant
+    (True or "parallel"): points eliminated, t_v = 4; serial ("serial"):
+    observations deleted, t_v = 3."""
+    if not robust:
+        return None, t_v
+    if robust not in (True, "parallel", "serial"):
+        raise ValueError("robust must be False, True, 'parallel' or 'serial'")
+    if robust == "serial":
+        return ROBUST_DELETE_OBS, 3.0 if t_v is None else t_v
+    return ROBUST_ELIMINATE_POINTS, 4.0 if t_v is None else t_v
+
+
+def run_schedule(scene, T=6, I=4, robust=False, t_r=2, t_v=None, down_weight=1e-4, callback=None, **kw):
+    """Fixed schedule: T outer iterations of (intersect [, robust re-weighting,
+    re-intersect], I LM steps, consensus), then a final intersection [, the
+    final robust step of the variant, intersection].  Returns the oracle
     problem and a list of per-iteration records."""
+    final_mode, t_v = _robust_mode(robust, t_v)
     op = OracleProblem(scene, **kw)
     hist = []
     for t in range(T):
         st = op.intersect()
         if robust and t >= t_r:
-            op.robust_reweight(t_v, down_weight, eliminate=False)
+            op.robust_reweight(t_v, down_weight, ROBUST_WEIGHT)
             st = op.intersect()
         rec = dict(t=t, int_stats=st, steps=[])
         for s in range(I):
@@ -349,7 +368,7 @@ def run_schedule(scene, T=6, I=4, robust=False, t_r=2, t_v=4.0, down_weight=1e-4
             callback(op, rec)
     if robust:
         op.intersect()
-        op.robust_reweight(t_v, down_weight, eliminate=True)
+        op.robust_reweight(t_v, down_weight, final_mode)
     final = op.intersect()
     hist.append(dict(t=T, int_stats=final))
     return op, hist
@@ -377,39 +396,57 @@ class RatioRule:
         return True
 
 
-def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, **kw):
+def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, robust=False, t_v=None, down_weight=1e-4, **kw):
     """Schedule driven by the improvement test (RatioRule): inner loop per
     sub-block on its cost (a sub-block that stops is left out of the later
     steps of this outer iteration), outer loop on the reprojection RMS of the
     intersections.  Returns the problem and per outer iteration the number of
-    steps each sub-block took."""
+    steps each sub-block took.
+
+    With `robust` (True / "parallel" or "serial"), the robust cycle of Sec.
+    5.3: after this basic convergence, a second outer loop that re-weights
+    after each intersection and intersects again, stopped by the same test on
+    the weighted cost sum v^T W v; then the final robust step of the variant
+    and a last intersection."""
+    final_mode, t_v = _robust_mode(robust, t_v)
     op = OracleProblem(scene, **kw)
     L = scene.L
     hist = []
-    outer = None
-    for t in range(T_max):
-        st = op.intersect()
-        rms = st[2]
-        if outer is None:
-            outer = RatioRule(rms, ratio)
-        elif not outer.step(rms):
-            break
-        active = np.ones(L, dtype=np.uint8)
-        steps = np.zeros(L, dtype=np.int64)
-        rules = None
-        for s in range(I_max):
-            bs, fails = op.lm_step(active)
-            if rules is None:
-                rules = [RatioRule(bs[l, 0], ratio) for l in range(L)]
-            for l in range(L):
-                if active[l]:
-                    steps[l] += 1
-                    if not rules[l].step(bs[l, 1]):
-                        active[l] = 0
-            if not active.any():
+
+    def outer_loop(weighted):
+        outer = None
+        for t in range(T_max):
+            st = op.intersect()
+            if weighted:
+                op.robust_reweight(t_v, down_weight, ROBUST_WEIGHT)
+                st = op.intersect()
+            crit = st[0] if weighted else st[2]
+            if outer is None:
+                outer = RatioRule(crit, ratio)
+            elif not outer.step(crit):
                 break
-        op.consensus()
-        hist.append(dict(t=t, int_stats=st, steps=steps))
+            active = np.ones(L, dtype=np.uint8)
+            steps = np.zeros(L, dtype=np.int64)
+            rules = None
+            for s in range(I_max):
+                bs, fails = op.lm_step(active)
+                if rules is None:
+                    rules = [RatioRule(bs[l, 0], ratio) for l in range(L)]
+                for l in range(L):
+                    if active[l]:
+                        steps[l] += 1
+                        if not rules[l].step(bs[l, 1]):
+                            active[l] = 0
+                if not active.any():
+                    break
+            op.consensus()
+            hist.append(dict(t=len(hist), int_stats=st, steps=steps, robust=weighted))
+
+    outer_loop(False)
+    if robust:
+        outer_loop(True)
+        op.intersect()
+        op.robust_reweight(t_v, down_weight, final_mode)
     final = op.intersect()
     hist.append(dict(t=len(hist), int_stats=final))
     return op, hist

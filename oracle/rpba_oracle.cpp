@@ -26,7 +26,10 @@
 //              while the point position uses all cameras.
 //   Sec. 5.3 -- sigma0 (eq:sigma0); per-camera MAD scale (factor 1.4826);
 //              parallel robust variant (weighting inside the intersection,
-//              threshold 4, down-weight 1e-4, whole points eliminated).
+//              threshold 4, down-weight 1e-4, whole points eliminated);
+//              serial variant (threshold 3, down-weight 1e-4, then the
+//              flagged observations deleted and points left in one camera
+//              eliminated).
 //   Sec. 5.4 -- outer products accumulated straight into the RCS; incremental
 //              three-parameter rotation; N + lambda diag(N), lambda = 1e-4;
 //              ratio rule for convergence; points whose intersection does not
@@ -296,7 +299,7 @@ void intersect_point(Problem& P, int j) {
     for (int k : ol) {
       Lin li;
       linearise(P.cams[P.ocam[k]], Xc, P.f, P.cx, P.cy, li);
-      if (!(li.p[2] > 0)) behind = true;
+      if (!(li.p[2] > 0) && P.rw[k] != 0) behind = true;  // a deleted observation does not count
       double v[2] = {li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]};
       add_point_normals(li, weight_of(P, k), v, H, g);
     }
@@ -334,6 +337,7 @@ void intersect_point(Problem& P, int j) {
     double vmax = 0;  // largest reprojection error, for the filters of the plain variants
     for (int k : ol) {
       if (!plain) break;
+      if (P.rw[k] == 0) continue;
       Lin li;
       linearise(P.cams[P.ocam[k]], X, P.f, P.cx, P.cy, li);
       vmax = std::max(vmax, std::hypot(li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]));
@@ -392,6 +396,7 @@ void point_stats(const Problem& P, double* stats) {
     if (P.status[j] != ST_OK) continue;
     ++nv;
     for (int k : P.pt_obs[j]) {
+      if (P.rw[k] == 0) continue;  // deleted by the robust step
       double v[2] = {P.last_res[2 * k], P.last_res[2 * k + 1]};
       wcost += wnorm2(weight_of(P, k), v);
       sq += v[0] * v[0] + v[1] * v[1];
@@ -726,15 +731,20 @@ void orc_intersect(orc_problem* h, double* stats) {
   if (stats) point_stats(P, stats);
 }
 
-// Per-camera MAD scale and robust down-weighting (parallel variant, Sec. 5.3),
-// from the residuals of the last intersection.  Returns the number of flagged
-// observations; with `eliminate`, points with a flagged observation get the
-// status ELIMINATED.
-int orc_robust_reweight(orc_problem* h, double t_v, double down_weight, int eliminate, double* sigma_cam) {
+// Per-camera MAD scale and robust flagging (Sec. 5.3), from the residuals of
+// the last intersection.  Returns the number of flagged observations.
+// mode 0: flagged observations weighted down by down_weight (both variants,
+//         after basic convergence);
+// mode 1: the same, and points with a flagged observation ELIMINATED
+//         (parallel variant);
+// mode 2: flagged observations deleted (weight 0), and points left with fewer
+//         than two observations ELIMINATED (serial variant).
+// Deleted observations stay deleted and take no part in scales or flags.
+int orc_robust_reweight(orc_problem* h, double t_v, double down_weight, int mode, double* sigma_cam) {
   Problem& P = h->P;
   std::vector<std::vector<double>> comp(P.M);
   for (int k = 0; k < P.K; ++k) {
-    if (P.status[P.opt[k]] != ST_OK) continue;
+    if (P.status[P.opt[k]] != ST_OK || P.rw[k] == 0) continue;
     const Obs2& w = P.info[k];
     double l11 = std::sqrt(w.w11), l21 = w.w12 / l11, l22 = std::sqrt(w.w22 - l21 * l21);
     double v0 = P.last_res[2 * k], v1 = P.last_res[2 * k + 1];
@@ -754,20 +764,24 @@ int orc_robust_reweight(orc_problem* h, double t_v, double down_weight, int elim
   int nflag = 0;
   std::vector<char> bad(P.N, 0);
   for (int k = 0; k < P.K; ++k) {
+    if (P.rw[k] == 0) continue;  // deleted earlier
     P.rw[k] = 1.0;
     if (P.status[P.opt[k]] != ST_OK) continue;
     double v[2] = {P.last_res[2 * k], P.last_res[2 * k + 1]};
     double vb = std::sqrt(wnorm2(P.info[k], v));
     double s = s0[P.ocam[k]];
     if (s > 0 && vb > t_v * s) {
-      P.rw[k] = down_weight;
+      P.rw[k] = mode == 2 ? 0.0 : down_weight;
       ++nflag;
       bad[P.opt[k]] = 1;
     }
   }
-  if (eliminate)
-    for (int j = 0; j < P.N; ++j)
-      if (bad[j] && P.status[j] == ST_OK) P.status[j] = ST_ELIMINATED;
+  for (int j = 0; j < P.N; ++j) {
+    if (!bad[j] || P.status[j] != ST_OK) continue;
+    int live = 0;
+    for (int k : P.pt_obs[j]) live += P.rw[k] != 0;
+    if (mode == 1 || (mode == 2 && live < 2)) P.status[j] = ST_ELIMINATED;
+  }
   return nflag;
 }
 

@@ -22,6 +22,7 @@ RPBA_CHOL_DEFAULT, RPBA_CHOL_STEPWISE, RPBA_CHOL_DATAFLOW = 0, 1, 2
 (RPBA_VARIANT_EXTENDED, RPBA_VARIANT_ALL_CAMERAS, RPBA_VARIANT_SCALAR, RPBA_VARIANT_PLAIN,
  RPBA_VARIANT_PLAIN_REFINED) = 0, 1, 2, 3, 4
 RPBA_OK, RPBA_ERR_NOT_SPD, RPBA_WARN_NONCONVERGED = 0, 4, 100
+RPBA_ROBUST_WEIGHT, RPBA_ROBUST_ELIMINATE_POINTS, RPBA_ROBUST_DELETE_OBS = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_WORKSPACE", 4: "ERR_NOT_SPD", 5: "ERR_STATE",
                 100: "WARN_NONCONVERGED"}
 
@@ -65,6 +66,7 @@ class Options(ctypes.Structure):
         ("robust", ctypes.c_int32), ("pair_lanes", ctypes.c_int32), ("variant", ctypes.c_int32),
         ("rho", ctypes.c_double), ("rho_growth", ctypes.c_double), ("filter_px", ctypes.c_double),
     ]
+
 
 
 _lib = None
@@ -302,9 +304,12 @@ class Problem:
                                       _ptr(self.int_stats)), "rpba_intersect")
         return self.int_stats
 
-    def rpba_robust_reweight(self, eliminate=False):
+    def rpba_robust_reweight(self, mode=0):
+        """mode: RPBA_ROBUST_WEIGHT (0 / False), RPBA_ROBUST_ELIMINATE_POINTS
+        (1 / True) or RPBA_ROBUST_DELETE_OBS (2).  Device stats [2]: flagged
+        observations, eliminated points."""
         self._order()
-        _check(self.L_.rpba_robust_reweight(self.h, int(eliminate), _ptr(self.rob_stats)), "rpba_robust_reweight")
+        _check(self.L_.rpba_robust_reweight(self.h, int(mode), _ptr(self.rob_stats)), "rpba_robust_reweight")
         return self.rob_stats
 
     def robust_result(self):
@@ -425,11 +430,28 @@ def _host(p, t):
     return t.cpu().numpy().copy()
 
 
+def _robust_setup(robust, opts):
+    """Final mode of the robust cycle (Sec. 5.3): the parallel variant (robust
+    True or "parallel", t_v = 4) eliminates whole points, the serial one
+    ("serial", t_v = 3) deletes observations."""
+    if not robust:
+        return None
+    if robust not in (True, "parallel", "serial"):
+        raise ValueError("robust must be False, True, 'parallel' or 'serial'")
+    opts.setdefault("robust", 1)
+    if robust == "serial":
+        opts.setdefault("t_v", 3.0)
+        return RPBA_ROBUST_DELETE_OBS
+    return RPBA_ROBUST_ELIMINATE_POINTS
+
+
 def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, graph=False, **opts):
-    """Fixed schedule on the GPU: T outer iterations of (intersect [, robust,
-    re-intersect], I LM steps, consensus), then a final intersection."""
-    if robust:
-        opts.setdefault("robust", 1)
+    """Fixed schedule on the GPU: T outer iterations of (intersect [, robust
+    re-weighting, re-intersect], I LM steps, consensus), then a final
+    intersection [, the final robust step of the variant, intersection].
+    robust: False, True / "parallel" or "serial"; re-weighting from outer
+    iteration t_r on."""
+    final_mode = _robust_setup(robust, opts)
     p = Problem(scene, **opts)
     if graph:
         p.set_graph(True)
@@ -437,7 +459,7 @@ def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, graph=Fals
     for t in range(T):
         st = _host(p, p.rpba_intersect())
         if robust and t >= t_r:
-            p.rpba_robust_reweight(False)
+            p.rpba_robust_reweight(RPBA_ROBUST_WEIGHT)
             st = _host(p, p.rpba_intersect())
         rec = dict(t=t, int_stats=st, steps=[])
         for s in range(I):
@@ -449,46 +471,66 @@ def run_schedule(scene, T=6, I=4, robust=False, t_r=2, callback=None, graph=Fals
             callback(p, rec)
     if robust:
         p.rpba_intersect()
-        p.rpba_robust_reweight(True)
+        p.rpba_robust_reweight(final_mode)
     final = _host(p, p.rpba_intersect())
     hist.append(dict(t=T, int_stats=final))
     return p, hist
 
 
-def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, graph=False, **opts):
+def run_ratio_rule(scene, T_max=10, I_max=10, ratio=1.01, graph=False, robust=False, **opts):
     """Schedule driven by the improvement test of the method (Sec. 5.4,
     rpba_ratio_update): inner loop per sub-block on its cost, a stopped
     sub-block being masked out of the later steps of the outer iteration (the
     `active` mask of rpba_subblock_lm_step); outer loop on the reprojection
     RMS of the intersections.  Returns the problem and per outer iteration
-    the number of LM steps each sub-block took."""
+    the number of LM steps each sub-block took.
+
+    With `robust` (True / "parallel" or "serial") the full robust cycle of
+    Sec. 5.3: after this basic convergence a second outer loop re-weights
+    after every intersection and re-intersects, its improvement test on the
+    weighted cost sum v^T W v (what the re-weighted adjustment minimises);
+    then the final robust step of the variant and a last intersection.  The
+    records of the second loop carry robust=True."""
     import torch
+    final_mode = _robust_setup(robust, opts)
     p = Problem(scene, **opts)
     if graph:
         p.set_graph(True)
     L = scene.L
     hist = []
-    o_best, o_grace, o_act = np.zeros(1), np.zeros(1, np.uint8), np.ones(1, np.uint8)
     act_dev = torch.ones(L, dtype=torch.uint8, device=p.dev)
-    for t in range(T_max):
-        st = _host(p, p.rpba_intersect())
-        if t == 0:
-            o_best[0] = st[2]
-        elif ratio_update(st[2:3], o_best, o_grace, o_act, ratio) == 0:
-            break
-        active = np.ones(L, dtype=np.uint8)
-        steps = np.zeros(L, dtype=np.int64)
-        best = grace = None
-        for s in range(I_max):
-            act_dev.copy_(torch.as_tensor(active))
-            bs = _host(p, p.rpba_subblock_lm_step(act_dev))
-            steps[active.astype(bool)] += 1
-            if best is None:
-                best, grace = bs[:, 0].copy(), np.zeros(L, np.uint8)
-            if ratio_update(bs[:, 1], best, grace, active, ratio) == 0:
+
+    def outer_loop(weighted):
+        o_best, o_grace, o_act = np.zeros(1), np.zeros(1, np.uint8), np.ones(1, np.uint8)
+        for t in range(T_max):
+            st = _host(p, p.rpba_intersect())
+            if weighted:
+                p.rpba_robust_reweight(RPBA_ROBUST_WEIGHT)
+                st = _host(p, p.rpba_intersect())
+            crit = st[0:1] if weighted else st[2:3]
+            if t == 0:
+                o_best[0] = crit[0]
+            elif ratio_update(crit, o_best, o_grace, o_act, ratio) == 0:
                 break
-        p.rpba_consensus()
-        hist.append(dict(t=t, int_stats=st, steps=steps))
+            active = np.ones(L, dtype=np.uint8)
+            steps = np.zeros(L, dtype=np.int64)
+            best = grace = None
+            for s in range(I_max):
+                act_dev.copy_(torch.as_tensor(active))
+                bs = _host(p, p.rpba_subblock_lm_step(act_dev))
+                steps[active.astype(bool)] += 1
+                if best is None:
+                    best, grace = bs[:, 0].copy(), np.zeros(L, np.uint8)
+                if ratio_update(bs[:, 1], best, grace, active, ratio) == 0:
+                    break
+            p.rpba_consensus()
+            hist.append(dict(t=len(hist), int_stats=st, steps=steps, robust=weighted))
+
+    outer_loop(False)
+    if robust:
+        outer_loop(True)
+        p.rpba_intersect()
+        p.rpba_robust_reweight(final_mode)
     final = _host(p, p.rpba_intersect())
     hist.append(dict(t=len(hist), int_stats=final))
     return p, hist

@@ -29,6 +29,13 @@ rpba_status fail(rpba_status s, const std::string& msg) {
   return s;
 }
 
+}  // namespace
+
+// the message rpba_last_error returns, for the host-only parts of the library
+rpba_status rpba::report_error(rpba_status s, const char* msg) { return fail(s, msg); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                         \
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \
@@ -266,7 +273,7 @@ struct rpba_problem {
   bool any_dense = true;
   bool intersected = false;
   bool use_graph = false;
-  CallGraph g_int, g_step, g_cons, g_rob, g_rob_elim;
+  CallGraph g_int, g_step, g_cons, g_rob[3];  // g_rob: one per RPBA_ROBUST_* mode
   bool timing = false;
   hipEvent_t ev[NPHASE + 1] = {};
   double ms[NPHASE] = {};
@@ -278,8 +285,7 @@ struct rpba_problem {
     g_int.reset();
     g_step.reset();
     g_cons.reset();
-    g_rob.reset();
-    g_rob_elim.reset();
+    for (CallGraph& g : g_rob) g.reset();
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
   }
@@ -866,16 +872,18 @@ int32_t rpba_get_timing(rpba_problem* h, double* ms, int64_t* launches, int64_t*
   return NPHASE;
 }
 
-rpba_status rpba_robust_reweight(rpba_problem* h, int32_t eliminate, double* stats) {
+rpba_status rpba_robust_reweight(rpba_problem* h, int32_t mode, double* stats) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  if (mode != RPBA_ROBUST_WEIGHT && mode != RPBA_ROBUST_ELIMINATE_POINTS && mode != RPBA_ROBUST_DELETE_OBS)
+    return fail(RPBA_ERR_ARG, "mode must be RPBA_ROBUST_WEIGHT, RPBA_ROBUST_ELIMINATE_POINTS or RPBA_ROBUST_DELETE_OBS");
   if (!h->opt.robust) return fail(RPBA_ERR_STATE, "the handle was created without opt->robust: no residuals are kept");
   if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run before rpba_robust_reweight");
-  CallGraph& g = eliminate ? h->g_rob_elim : h->g_rob;
+  CallGraph& g = h->g_rob[mode];
   return run_call(h, g, stats, nullptr, nullptr, [&]() -> rpba_status {
     PhaseTimer t(h, PH_ROBUST, stats ? 4 : 3);
     launch_robust(h->d, (double*)(h->ws + h->map.rob_vals), (const int64_t*)(h->ws + h->map.rob_off),
                   (int32_t*)(h->ws + h->map.rob_bad), (double*)(h->ws + h->map.rob_sigma), h->opt.t_v,
-                  h->opt.down_weight, eliminate, stats, h->stream);
+                  h->opt.down_weight, mode, stats, h->stream);
     return RPBA_OK;
   });
 }

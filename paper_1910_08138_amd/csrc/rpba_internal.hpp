@@ -7,6 +7,9 @@
 
 namespace rpba {
 
+// sets the message rpba_last_error returns (host-only parts of the library)
+rpba_status report_error(rpba_status s, const char* msg);
+
 // Device view of one problem: every pointer lives in the caller's workspace
 // (or is one of the caller's own arrays, prefix u_).
 struct Dev {
@@ -199,7 +202,7 @@ void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipSt
 void launch_bsr_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);
 int robust_lds_values();
 void launch_robust(const Dev& d, double* spill, const int64_t* spill_off, int32_t* bad, double* sigma_cam, double t_v,
-                   double down_weight, int eliminate, double* stats, hipStream_t st);
+                   double down_weight, int mode, double* stats, hipStream_t st);
 size_t pcg_lds_bytes(int max_n);
 int mlp_num_params();
 int mlp_num_features();

@@ -188,7 +188,7 @@ __global__ void k_gather_pm(Dev d) {
   if (d.has_info) {
     for (int q = 0; q < 3; ++q) d.pm_w[3 * i + q] = r * d.info[3 * k + q];
   } else {
-    d.pm_code[i] = (d.pm_code[i] & ~PM_DOWN) | (r != 1.0 ? PM_DOWN : 0);
+    d.pm_code[i] = (d.pm_code[i] & ~(PM_DOWN | PM_DEL)) | (r != 1.0 ? PM_DOWN : 0) | (r == 0.0 ? PM_DEL : 0);
   }
 }
 
@@ -295,7 +295,7 @@ __device__ __forceinline__ ObsHead obs_head(const Dev& d, const Stage& sg, int b
     const double* w = d.pm_w + 3 * (int64_t)i;
     o.W = {w[0], w[1], w[2]};
   } else {
-    const double w = (o.code & PM_DOWN) ? d.down_weight * d.w0 : d.w0;
+    const double w = (o.code & PM_DOWN) ? ((o.code & PM_DEL) ? 0.0 : d.down_weight * d.w0) : d.w0;
     o.W = {w, 0.0, w};
   }
   return o;
@@ -459,7 +459,8 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         Lin<double> La, Lb;
         linearise<double>(cma, cma + 9, X, d.f, d.cx, d.cy, La);
         linearise<double>(cmb, cmb + 9, X, d.f, d.cx, d.cy, Lb);
-        if (!(La.z > 0.0) || !(Lb.z > 0.0)) behind = true;
+        // a deleted observation (weight 0) neither counts nor fails the point
+        if ((!(La.z > 0.0) && ha.W.a > 0.0) || (!(Lb.z > 0.0) && hb.W.a > 0.0)) behind = true;
         add_point_normals<double>(La, ha.W, La.g0 - ha.x, La.g1 - ha.y, h, g);
         add_point_normals<double>(Lb, hb.W, Lb.g0 - hb.x, Lb.g1 - hb.y, h2, g2);
         ha = na;
@@ -470,7 +471,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         obs_cam(d, sg, ha.code, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
-        if (!(L.z > 0.0)) behind = true;
+        if (!(L.z > 0.0) && ha.W.a > 0.0) behind = true;
         add_point_normals<double>(L, ha.W, L.g0 - ha.x, L.g1 - ha.y, h, g);
       }
       for (int q = 0; q < 6; ++q) h[q] += h2[q];
@@ -514,7 +515,8 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         const int32_t code = obs_get<INFO, OLDS>(d, sg, b0, i, x, y, W, cm);
         Lin<double> L;
         linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
-        if (!(L.z > 0.0)) behind = true;
+        const bool live = W.a > 0.0;  // not deleted by the robust step
+        if (!(L.z > 0.0) && live) behind = true;
         const double v0 = L.g0 - x, v1 = L.g1 - y;
         add_point_normals<double>(L, W, v0, v1, hl, gl);
         // the residual takes the place of the pixel in LDS (this pass reads
@@ -524,9 +526,11 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         const double wq = wquad(W, v0, v1);
         cost += wq;
         ccur += wq;
-        if (PLAIN) vmax = fmax(vmax, v0 * v0 + v1 * v1);
-        sq += v0 * v0 + v1 * v1;
-        nobs += 1.0;
+        if (PLAIN && live) vmax = fmax(vmax, v0 * v0 + v1 * v1);
+        if (live) {
+          sq += v0 * v0 + v1 * v1;
+          nobs += 1.0;
+        }
         if (code & PM_LAST) {  // copy u complete
           for (int q = 0; q < 6; ++q) h[q] += hl[q];
           if (u + 1 < n) {

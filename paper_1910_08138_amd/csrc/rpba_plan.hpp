@@ -22,13 +22,14 @@ constexpr int INT_CAM_CAP = 192;   // cameras staged in LDS per intersection wor
 constexpr int INT_OBS_CAP = 768;   // observations staged in LDS per intersection workgroup
 constexpr int PB_LANES = 8;        // lanes per off-diagonal pair block in the pair Schur pass
 // intersection observation code: camera slot in the workgroup's LDS list, or
-// with PM_GLOBAL the camera index itself; PM_DOWN = robust down-weighting;
-// PM_LAST = last observation of its copy (the copies of a point follow each
-// other in the stream)
+// with PM_GLOBAL the camera index itself; PM_DOWN = robust down-weighting,
+// with PM_DEL as well = deleted (weight 0); PM_LAST = last observation of its
+// copy (the copies of a point follow each other in the stream)
+constexpr int32_t PM_DEL = 1 << 27;
 constexpr int32_t PM_LAST = 1 << 28;
 constexpr int32_t PM_GLOBAL = 1 << 29;
 constexpr int32_t PM_DOWN = 1 << 30;
-constexpr int32_t PM_FIELD = PM_LAST - 1;
+constexpr int32_t PM_FIELD = PM_DEL - 1;
 
 struct Plan {
   int32_t M = 0, N = 0, K = 0, L = 0;

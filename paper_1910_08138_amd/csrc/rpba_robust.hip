@@ -1,9 +1,16 @@
-// Robust re-weighting, parallel variant (paper Sec. 5.3): per camera the scale
-// sigma0_i = 1.4826 MAD of the whitened residual components of its
-// observations (from the last intersection); an observation whose normalised
-// residual sqrt(v^T W v) / sigma0_i exceeds t_v is down-weighted by a factor
-// (1e-4 by default), and with `eliminate` every point holding such an observation is
-// removed.  Whitening z = L^T v with W = L L^T (Cholesky of the 2x2 weight).
+// Robust re-weighting (paper Sec. 5.3): per camera the scale sigma0_i =
+// 1.4826 MAD of the whitened residual components of its observations (from
+// the last intersection); an observation whose normalised residual
+// sqrt(v^T W v) / sigma0_i exceeds t_v is flagged.  Three modes:
+//   RPBA_ROBUST_WEIGHT          flagged observations down-weighted by a
+//                               factor (1e-4 by default), the others 1;
+//   RPBA_ROBUST_ELIMINATE_POINTS the same, and every point holding a flagged
+//                               observation removed (parallel variant);
+//   RPBA_ROBUST_DELETE_OBS      flagged observations deleted (weight 0), and
+//                               points left with fewer than two observations
+//                               removed (serial variant).
+// A deleted observation stays deleted: it enters no scale, flag or count.
+// Whitening z = L^T v with W = L L^T (Cholesky of the 2x2 weight).
 //
 // The medians are exact order statistics: a radix select over the 64-bit
 // order-preserving keys of the doubles, one workgroup per camera, values
@@ -99,7 +106,7 @@ __device__ __forceinline__ W2<double> base_weight(const Dev& d, int64_t k) {
 }
 
 __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const int64_t* spill_off, double t_v,
-                                                     double down_weight, int32_t* bad,
+                                                     double down_weight, int mode, int32_t* bad,
                                                      double* sigma_cam) {
   __shared__ double lds[LDS_VALS];
   __shared__ uint32_t hist[256];
@@ -114,7 +121,7 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
   // whitened residual components of the camera's observations of valid points
   for (int t = o0 + threadIdx.x; t < o1; t += RT) {
     const int k = d.cam_obs[t];
-    if (d.status[d.copy_pt[d.obs_copy[k]]] != 0) continue;
+    if (d.status[d.copy_pt[d.obs_copy[k]]] != 0 || d.rw[k] == 0.0) continue;
     const W2<double> W = base_weight(d, k);
     const double l11 = sqrt(W.a), l21 = W.b / l11, l22 = sqrt(W.c - l21 * l21);
     const int64_t pos = d.pm_pos[k];  // residuals are stored point-major
@@ -138,13 +145,14 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
   for (int t = o0 + threadIdx.x; t < o1; t += RT) {
     const int k = d.cam_obs[t];
     const int pt = d.copy_pt[d.obs_copy[k]];
-    double w = 1.0;
-    if (d.status[pt] == 0) {
+    const bool deleted = d.rw[k] == 0.0;
+    double w = deleted ? 0.0 : 1.0;
+    if (d.status[pt] == 0 && !deleted) {
       const int64_t pos = d.pm_pos[k];
       const double v0 = d.res[2 * pos], v1 = d.res[2 * pos + 1];
       const double vb = sqrt(wquad(base_weight(d, k), v0, v1));
       if (s0 > 0.0 && vb > t_v * s0) {
-        w = down_weight;
+        w = mode == RPBA_ROBUST_DELETE_OBS ? 0.0 : down_weight;
         nflag += 1.0;
         bad[pt] = 1;
       }
@@ -156,7 +164,7 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
     if (d.has_info) {
       for (int q = 0; q < 3; ++q) d.pm_w[3 * pos + q] = w * d.info[3 * (int64_t)k + q];
     } else {
-      d.pm_code[pos] = (d.pm_code[pos] & ~PM_DOWN) | (w != 1.0 ? PM_DOWN : 0);
+      d.pm_code[pos] = (d.pm_code[pos] & ~(PM_DOWN | PM_DEL)) | (w != 1.0 ? PM_DOWN : 0) | (w == 0.0 ? PM_DEL : 0);
     }
   }
   for (int o = 32; o > 0; o >>= 1) nflag += __shfl_xor(nflag, o);
@@ -165,13 +173,20 @@ __global__ __launch_bounds__(RT) void k_robust_scale(Dev d, double* spill, const
   if (threadIdx.x == 0) atomicAdd(&d.acc_rob[0], sh_flag[0] + sh_flag[1] + sh_flag[2] + sh_flag[3]);
 }
 
-// flagged points: eliminated when asked; the flags are cleared for the next call
-__global__ void k_robust_eliminate(Dev d, int32_t* bad, int eliminate) {
+// flagged points: removed in the two eliminating modes (every one, or those
+// left with fewer than two observations); the flags are cleared for the next call
+__global__ void k_robust_eliminate(Dev d, int32_t* bad, int mode) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j == 0) *d.rec_valid = 0;  // the weights changed: copy records are rebuilt by the next step
   if (j >= d.N) return;
   if (bad[j]) {
-    if (eliminate && d.status[j] == 0) {
+    bool drop = mode == RPBA_ROBUST_ELIMINATE_POINTS;
+    if (mode == RPBA_ROBUST_DELETE_OBS) {
+      int live = 0;
+      for (int i = d.pm_off[j]; i < d.pm_off[j + 1]; ++i) live += d.rw[d.pm_k[i]] != 0.0;
+      drop = live < 2;
+    }
+    if (drop && d.status[j] == 0) {
       d.status[j] = 4;
       atomicAdd(&d.acc_rob[1], 1.0);
     }
@@ -191,11 +206,11 @@ __global__ void k_copy_stats2(const double* src, double* dst) {
 int robust_lds_values() { return LDS_VALS; }
 
 void launch_robust(const Dev& d, double* spill, const int64_t* spill_off, int32_t* bad, double* sigma_cam, double t_v,
-                   double down_weight, int eliminate, double* stats, hipStream_t st) {
+                   double down_weight, int mode, double* stats, hipStream_t st) {
   launch_zero(d.acc_rob, 2, st);
-  hipLaunchKernelGGL(k_robust_scale, dim3(d.M), dim3(RT), 0, st, d, spill, spill_off, t_v, down_weight, bad,
+  hipLaunchKernelGGL(k_robust_scale, dim3(d.M), dim3(RT), 0, st, d, spill, spill_off, t_v, down_weight, mode, bad,
                      sigma_cam);
-  hipLaunchKernelGGL(k_robust_eliminate, dim3((d.N + 255) / 256), dim3(256), 0, st, d, bad, eliminate);
+  hipLaunchKernelGGL(k_robust_eliminate, dim3((d.N + 255) / 256), dim3(256), 0, st, d, bad, mode);
   if (stats) hipLaunchKernelGGL(k_copy_stats2, dim3(1), dim3(64), 0, st, (const double*)d.acc_rob, stats);
 }
 

@@ -519,6 +519,24 @@ def oblique_scene(seed=0, n_strips=12, n_stations=100, H=100.0, along=40.0, acro
                    meta=dict(H=H, n_strips=n_strips, n_stations=n_stations), noise=noise)
 
 
+def add_gross_errors(scene: Scene, frac: float, seed: int, lo: float = 15.0, hi: float = 40.0) -> Scene:
+    """A copy of the scene with gross errors on round(frac K) observations
+    drawn without replacement: displacements of uniform length in [lo, hi] px
+    in a uniform direction (marked in `outlier`, together with any the scene
+    already had)."""
+    import dataclasses
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 7919]))
+    idx = rng.choice(scene.K, size=int(round(frac * scene.K)), replace=False)
+    ang = rng.uniform(0.0, 2.0 * math.pi, idx.size)
+    mag = rng.uniform(lo, hi, idx.size)
+    xy = scene.obs_xy.copy()
+    xy[0, idx] += mag * np.cos(ang)
+    xy[1, idx] += mag * np.sin(ang)
+    out = np.zeros(scene.K, dtype=bool) if scene.outlier is None else scene.outlier.copy()
+    out[idx] = True
+    return dataclasses.replace(scene, obs_xy=np.ascontiguousarray(xy), outlier=out)
+
+
 def harvest_partition(scene: Scene, seed: int) -> Scene:
     """Two compact sub-blocks of s and M-s cameras, s ~ U{200..300} (for M=500)."""
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(5)[4])

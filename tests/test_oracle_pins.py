@@ -392,7 +392,7 @@ def test_robust_mad_recovers_sigma_and_flags_outliers():
     bad_pts[s.obs_pt[out]] = True
     assert (flagged & ~bad_pts[s.obs_pt]).sum() < 0.01 * s.K
     op.intersect()
-    n2, _ = op.robust_reweight(4.0, 1e-4, eliminate=True)
+    n2, _ = op.robust_reweight(4.0, 1e-4, mode=oracle.ROBUST_ELIMINATE_POINTS)
     _, _, st = op.intersection()
     assert (st == oracle.ST_ELIMINATED).sum() > 0.8 * np.unique(s.obs_pt[out]).size
 
