@@ -338,6 +338,49 @@ rpba_status rpba_precond_train_step_noalloc(const float *samples, int32_t nsamp,
                                             float *v, int32_t t, float lr, float *grad, float *loss, int32_t apply,
                                             void *stream);
 
+/* ------------------------------------------------------- sub-block partition
+ * Sub-block construction (Sec. 5.2) by partitioning the visibility graph:
+ * one node per camera, an edge between two cameras weighted by the number of
+ * points both observe, node weight = cube root of the summed observation
+ * counts of the points the camera sees.  Multilevel recursive bisection
+ * (heavy-edge coarsening, greedy graph growing, Fiduccia-Mattheyses
+ * refinement) into `parts` sub-blocks of balanced node weight with few
+ * shared points; optionally followed by a pass that balances the cost model
+ * c_l = cost_cams3 n_l^3 + cost_obs K_l (n_l cameras and K_l observations of
+ * sub-block l) by moving boundary cameras out of the most expensive part.
+ * Host code only: no device memory, no stream. */
+typedef struct {
+  int32_t parts;         /* number of sub-blocks L, in [1, M]: 1 */
+  double imbalance;      /* allowed excess of a sub-block's node weight over its share: 0.05 */
+  int32_t min_cams;      /* fewer sub-blocks if they would average fewer cameras than this (0: no
+                            limit); the paper uses 70: 0 */
+  int32_t refine_passes; /* refinement passes per level: 4 */
+  double cost_cams3;     /* cost model, see above; both 0 = no cost pass: 0 */
+  double cost_obs;       /*   : 0 */
+  uint64_t seed;         /* matching order and growing seeds: 0 */
+} rpba_partition_options;
+
+/* Fill *opt with the defaults listed above.  HOST pointer. */
+rpba_status rpba_partition_default_options(rpba_partition_options *opt);
+
+/* Partition the cameras.  All pointers HOST.
+ *   obs_cam, obs_pt [K]  camera and point of each observation
+ *   cam_block [M]        out: sub-block of each camera, in [0, L_used)
+ *   node_weight [M]      out: the node weights, or NULL
+ *   stats [8]            out, or NULL: L_used; edge cut (sum of the edge
+ *                        weights between sub-blocks); tie points (points seen
+ *                        in >= 2 sub-blocks); point copies (sum over points of
+ *                        the sub-blocks seeing them); largest sub-block node
+ *                        weight / mean; largest cost / mean cost (0 without a
+ *                        cost model); fewest and most cameras in a sub-block
+ * L_used = parts, or less with min_cams.  Every sub-block gets at least one
+ * camera.  The result depends only on the inputs and options (seed included).
+ * RPBA_ERR_ARG: M, N or K < 1, an index out of range, parts outside [1, M], a
+ * negative imbalance, min_cams, refine_passes or cost coefficient. */
+rpba_status rpba_partition(int32_t M, int32_t N, int32_t K, const int32_t *obs_cam, const int32_t *obs_pt,
+                           const rpba_partition_options *opt, int32_t *cam_block, double *node_weight,
+                           double *stats);
+
 /* ---------------------------------------------------------------- execution
  * rpba_set_graph: when on, each of rpba_intersect, rpba_subblock_lm_step and
  *   rpba_consensus is captured into a HIP graph on its first call and replayed

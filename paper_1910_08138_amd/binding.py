@@ -35,7 +35,7 @@ EXPORTS = [
     "rpba_precond_num_params", "rpba_set_precond_weights", "rpba_precond_num_samples", "rpba_precond_sample_stride",
     "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
     "rpba_step_status", "rpba_ratio_update", "rpba_camera_order", "rpba_get_precond_blocks", "rpba_factor_flops",
-    "rpba_precond_train_step_noalloc",
+    "rpba_precond_train_step_noalloc", "rpba_partition_default_options", "rpba_partition",
 ]
 TRAIN_NOALLOC_MAX_SAMPLES = 8192   # RPBA_TRAIN_NOALLOC_MAX_SAMPLES
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
@@ -67,6 +67,11 @@ class Options(ctypes.Structure):
         ("rho", ctypes.c_double), ("rho_growth", ctypes.c_double), ("filter_px", ctypes.c_double),
     ]
 
+
+class PartitionOptions(ctypes.Structure):
+    _fields_ = [("parts", ctypes.c_int32), ("imbalance", ctypes.c_double), ("min_cams", ctypes.c_int32),
+                ("refine_passes", ctypes.c_int32), ("cost_cams3", ctypes.c_double), ("cost_obs", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -122,6 +127,8 @@ def load_library(path: str = LIB_PATH):
     L.rpba_get_precond_blocks.argtypes = [vp, i32, vp]
     L.rpba_factor_flops.argtypes = [vp, vp]
     L.rpba_precond_train_step_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, i32, ctypes.c_float, vp, vp, i32, vp]
+    L.rpba_partition_default_options.argtypes = [ctypes.POINTER(PartitionOptions)]
+    L.rpba_partition.argtypes = [i32, i32, i32, vp, vp, ctypes.POINTER(PartitionOptions), vp, vp, vp]
     L.rpba_set_graph.argtypes = [vp, i32]
     L.rpba_set_timing.argtypes = [vp, i32]
     L.rpba_get_timing.restype = i32
@@ -207,6 +214,30 @@ def selftest_gemm(A, B):
     _check(L.rpba_selftest_gemm(_ptr(A), _ptr(B), _ptr(C), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
            "rpba_selftest_gemm")
     return C
+
+
+def partition(scene, parts, **opts):
+    """Sub-blocks from the visibility graph (rpba_partition, Sec. 5.2), on
+    the host.  Returns (cam_block [M] int32, node_weight [M], stats dict)."""
+    L = load_library()
+    o = PartitionOptions()
+    _check(L.rpba_partition_default_options(ctypes.byref(o)), "rpba_partition_default_options")
+    o.parts = int(parts)
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown partition option {k}")
+        setattr(o, k, v)
+    cam = np.ascontiguousarray(scene.obs_cam, dtype=np.int32)
+    pt = np.ascontiguousarray(scene.obs_pt, dtype=np.int32)
+    blk = np.zeros(scene.M, dtype=np.int32)
+    nw = np.zeros(scene.M)
+    st = np.zeros(8)
+    _check(L.rpba_partition(scene.M, scene.N, scene.K, cam.ctypes.data, pt.ctypes.data, ctypes.byref(o),
+                            blk.ctypes.data, nw.ctypes.data, st.ctypes.data), "rpba_partition")
+    names = ["parts", "edge_cut", "tie_points", "point_copies", "weight_max_over_mean", "cost_max_over_mean",
+             "min_cams", "max_cams"]
+    return blk, nw, {k: (int(v) if k not in ("weight_max_over_mean", "cost_max_over_mean") else float(v))
+                     for k, v in zip(names, st)}
 
 
 class Problem:
