@@ -77,6 +77,8 @@ def _declare(L):
                                                                                      ctypes.c_double]
     L.orc_destroy.argtypes = [ctypes.c_void_p]
     L.orc_intersect.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_covariance.restype = ctypes.c_int
+    L.orc_covariance.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp]
     L.orc_robust_reweight.restype = ctypes.c_int
     L.orc_robust_reweight.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
     L.orc_lm_step.restype = ctypes.c_int
@@ -238,6 +240,16 @@ class OracleProblem:
         r = np.zeros((2, self.K))
         self._lib.orc_get_residuals(self.h, _p(r))
         return r
+
+    def covariance(self, lam=1e-6):
+        """(camera covariances [M][6][6], copy covariances [n_copies][6]) of
+        the sub-block normal equations damped by lam (Sec. 2)."""
+        cc = np.zeros((self.M, 6, 6))
+        xc = np.zeros((self._lib.orc_num_copies(self.h), 6))
+        rc = self._lib.orc_covariance(self.h, float(lam), _p(cc), _p(xc))
+        if rc < 0:
+            raise np.linalg.LinAlgError(f"sub-block {-rc - 1} not positive definite")
+        return cc, xc
 
     def block_rcs(self, l, n6):
         S = np.zeros((n6, n6))

@@ -419,6 +419,7 @@ struct BlockSystem {
   std::vector<double> Vinv;                // [nc][3][3] of the damped V
   std::vector<double> gX;                  // [nc][3]
   std::vector<double> S, e;                // dense RCS and right-hand side
+  std::vector<std::vector<double>> Y;      // per copy, per observation: N_CX block (6 x 3)
   double cost = 0;
   bool ok = true;
 };
@@ -468,7 +469,8 @@ void build_block(const Problem& P, int l, BlockSystem& B) {
   const double lam = P.lambda;
 
   // camera blocks U_i, gradients g_C
-  std::vector<std::vector<double>> Ys(B.nc);
+  std::vector<std::vector<double>>& Ys = B.Y;
+  Ys.assign(B.nc, {});
   for (int q = 0; q < B.nc; ++q) {
     const Copy& cp = P.copies[B.cps[q]];
     double V[3][3], gx[3];
@@ -951,6 +953,77 @@ int orc_block_step(orc_problem* h, int l, double* dC_out, double* dX_out) {
   std::memcpy(dC_out, dC.data(), sizeof(double) * dC.size());
   std::memcpy(dX_out, dX.data(), sizeof(double) * dX.size());
   return B.nc;
+}
+
+// Covariances from the normal equations of every sub-block (Sec. 2: the
+// inverse of N through the Schur complement), with damping lam in place of
+// lambda.  cam_cov [M][6][6] (row-major, caller order): the camera's diagonal
+// block of M_CC = S^-1 of its sub-block.  copy_cov [n_copies][6] (xx, xy, xz,
+// yy, yz, zz): M_XX = V^-1 + V^-1 (sum_{i,k} Y_i^T M_ik Y_k) V^-1 of the copy,
+// V its damped point block (with the tie-point weight), Y_i the N_CX block of
+// its observation in camera i; zeros for copies of invalid points.  The
+// inverse S^-1 is formed column by column from the dense Cholesky factor.
+// Returns 0, or -(l + 1) if sub-block l cannot be factorised.
+int orc_covariance(orc_problem* h, double lam, double* cam_cov, double* copy_cov) {
+  Problem& P = h->P;
+  const double lam0 = P.lambda;
+  P.lambda = lam;
+  int rc = 0;
+  if (copy_cov) std::fill(copy_cov, copy_cov + 6 * P.copies.size(), 0.0);
+  for (int l = 0; l < P.L && rc == 0; ++l) {
+    BlockSystem B;
+    build_block(P, l, B);
+    std::vector<double> Lf = B.S;
+    if (!B.ok || !chol_dense(B.n6, Lf)) {
+      rc = -(l + 1);
+      break;
+    }
+    const int n = B.n6;
+    std::vector<double> Minv((size_t)n * n), col, unit(n, 0.0);
+    for (int c = 0; c < n; ++c) {
+      unit[c] = 1.0;
+      chol_dense_solve(n, Lf, unit, col);
+      unit[c] = 0.0;
+      for (int r = 0; r < n; ++r) Minv[(size_t)r * n + c] = col[r];
+    }
+    const std::vector<int>& cams = P.blk_cams[l];
+    if (cam_cov)
+      for (size_t a = 0; a < cams.size(); ++a)
+        for (int r = 0; r < 6; ++r)
+          for (int c = 0; c < 6; ++c) cam_cov[(size_t)cams[a] * 36 + r * 6 + c] = Minv[(6 * a + r) * n + 6 * a + c];
+    if (!copy_cov) continue;
+    for (int q = 0; q < B.nc; ++q) {
+      const int id = B.cps[q];
+      const Copy& cp = P.copies[id];
+      const double* Vi = &B.Vinv[(size_t)q * 9];
+      double Tm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // sum_{i,k} Y_i^T M_ik Y_k
+      const size_t m = cp.obs.size();
+      for (size_t t1 = 0; t1 < m; ++t1)
+        for (size_t t2 = 0; t2 < m; ++t2) {
+          const double* Y1 = &B.Y[q][t1 * 18];
+          const double* Y2 = &B.Y[q][t2 * 18];
+          const int a1 = P.cam_local[P.ocam[cp.obs[t1]]], a2 = P.cam_local[P.ocam[cp.obs[t2]]];
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+              double s = 0.0;
+              for (int u = 0; u < 6; ++u)
+                for (int v = 0; v < 6; ++v) s += Y1[u * 3 + r] * Minv[(size_t)(6 * a1 + u) * n + 6 * a2 + v] * Y2[v * 3 + c];
+              Tm[r][c] += s;
+            }
+        }
+      double VT[3][3], Mx[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) VT[r][c] = Vi[r * 3 + 0] * Tm[0][c] + Vi[r * 3 + 1] * Tm[1][c] + Vi[r * 3 + 2] * Tm[2][c];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          Mx[r][c] = Vi[r * 3 + c] + VT[r][0] * Vi[0 * 3 + c] + VT[r][1] * Vi[1 * 3 + c] + VT[r][2] * Vi[2 * 3 + c];
+      double* o = copy_cov + 6 * (size_t)id;
+      o[0] = Mx[0][0]; o[1] = Mx[0][1]; o[2] = Mx[0][2];
+      o[3] = Mx[1][1]; o[4] = Mx[1][2]; o[5] = Mx[2][2];
+    }
+  }
+  P.lambda = lam0;
+  return rc;
 }
 
 // Linearisation of one observation (for finite-difference pins).
