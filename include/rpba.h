@@ -130,6 +130,8 @@ typedef struct {
   double rho;            /* scalar tie-point weight of SCALAR / PLAIN variants [1/unit^2]: 1000 */
   double rho_growth;     /* factor applied to rho at every rpba_consensus (Sec. 6.3): 1.01 */
   double filter_px;      /* PLAIN variants: a point with a reprojection error above this is filtered: 1000 */
+  int32_t covariance;    /* 1: the workspace holds one more array of the size of the dense RCS, for
+                            rpba_covariance: 0 */
 } rpba_options;
 
 /* Fill *opt with the defaults listed above.  HOST pointer. */
@@ -185,6 +187,32 @@ rpba_status rpba_intersect(rpba_problem *h, double *cov, int32_t *status, double
  * flag, cost or statistic.  Any other mode: RPBA_ERR_ARG.
  * stats [2]: flagged observations, eliminated points (or NULL). */
 rpba_status rpba_robust_reweight(rpba_problem *h, int32_t mode, double *stats);
+
+/* Covariances of the sub-block adjustment (Sec. 2: M = N^-1 through the
+ * Schur complement; the paper sets lambda = 1e-6 after convergence for them,
+ * Sec. 5.4), for a handle created with opt->covariance = 1 (else
+ * RPBA_ERR_STATE), after rpba_intersect, with no sub-block solved by PCG
+ * (else RPBA_ERR_STATE).  At the current state (the cameras, and the copies
+ * as the next LM step would take them) the normal equations of every
+ * sub-block are assembled with damping `lambda` (N + lambda diag N), the
+ * reduced camera system S is factorised and inverted, and
+ *   cam_cov  [M][6][6]  DEVICE, row-major, caller camera order: the camera's
+ *                       diagonal block of S^-1 (rotation increment, then
+ *                       centre), or NULL;
+ *   copy_cov [NC][6]    DEVICE, copy order of rpba_get_copies: the point
+ *                       block M_XX = V^-1 + V^-1 (sum_{i,k} Y_i^T (S^-1)_ik
+ *                       Y_k) V^-1 of the copy (xx, xy, xz, yy, yz, zz), V its
+ *                       damped point block with the tie-point weight, Y_i
+ *                       the camera-point block of its observation in camera
+ *                       i; zeros for copies of invalid points; or NULL.
+ * The parameters of the camera and point blocks are those of the LM step.
+ * A camera or copy covariance is that of the sub-block's system, i.e. with
+ * the tie points weighted by the information from the other sub-blocks.
+ * RPBA_ERR_NOT_SPD if a system is not positive definite; RPBA_ERR_ARG for a
+ * negative or non-finite lambda.  Leaves the state unchanged; the next LM
+ * step re-assembles its system.  Asynchronous on the handle's stream after
+ * one synchronisation (the factorisation check). */
+rpba_status rpba_covariance(rpba_problem *h, double lambda, double *cam_cov, double *copy_cov);
 
 /* Result of the last rpba_robust_reweight: sigma_cam [M] the per-camera
  * scales sigma0_i (0 for a camera without a valid observation), obs_weight

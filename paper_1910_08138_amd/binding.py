@@ -35,7 +35,7 @@ EXPORTS = [
     "rpba_precond_num_params", "rpba_set_precond_weights", "rpba_precond_num_samples", "rpba_precond_sample_stride",
     "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
     "rpba_step_status", "rpba_ratio_update", "rpba_camera_order", "rpba_get_precond_blocks", "rpba_factor_flops",
-    "rpba_precond_train_step_noalloc", "rpba_partition_default_options", "rpba_partition",
+    "rpba_precond_train_step_noalloc", "rpba_partition_default_options", "rpba_partition", "rpba_covariance",
 ]
 TRAIN_NOALLOC_MAX_SAMPLES = 8192   # RPBA_TRAIN_NOALLOC_MAX_SAMPLES
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
@@ -65,6 +65,7 @@ class Options(ctypes.Structure):
         ("chol_tile", ctypes.c_int32), ("chol_schedule", ctypes.c_int32),
         ("robust", ctypes.c_int32), ("pair_lanes", ctypes.c_int32), ("variant", ctypes.c_int32),
         ("rho", ctypes.c_double), ("rho_growth", ctypes.c_double), ("filter_px", ctypes.c_double),
+        ("covariance", ctypes.c_int32),
     ]
 
 
@@ -129,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     L.rpba_precond_train_step_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, i32, ctypes.c_float, vp, vp, i32, vp]
     L.rpba_partition_default_options.argtypes = [ctypes.POINTER(PartitionOptions)]
     L.rpba_partition.argtypes = [i32, i32, i32, vp, vp, ctypes.POINTER(PartitionOptions), vp, vp, vp]
+    L.rpba_covariance.argtypes = [vp, ctypes.c_double, vp, vp]
     L.rpba_set_graph.argtypes = [vp, i32]
     L.rpba_set_timing.argtypes = [vp, i32]
     L.rpba_get_timing.restype = i32
@@ -342,6 +344,19 @@ class Problem:
         self._order()
         _check(self.L_.rpba_robust_reweight(self.h, int(mode), _ptr(self.rob_stats)), "rpba_robust_reweight")
         return self.rob_stats
+
+    def covariance(self, lam=1e-6):
+        """(camera covariances [M][6][6] caller order, copy covariances
+        [n_copies][6] in copies() order) of the sub-block systems damped by
+        lam (rpba_covariance; the handle needs covariance=1)."""
+        torch = self.torch
+        cc = torch.zeros((self.M, 6, 6), dtype=torch.float64, device=self.dev)
+        n = int(self.L_.rpba_num_copies(self.h))
+        xc = torch.zeros((n, 6), dtype=torch.float64, device=self.dev)
+        self._order()
+        _check(self.L_.rpba_covariance(self.h, float(lam), _ptr(cc), _ptr(xc)), "rpba_covariance")
+        self.sync()
+        return cc.cpu().numpy(), xc.cpu().numpy()
 
     def robust_result(self):
         """(sigma_cam [M], obs_weight [K]) of the last robust re-weighting,

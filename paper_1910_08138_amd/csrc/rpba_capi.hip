@@ -58,7 +58,7 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt;
+      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt, covY;
   size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -79,7 +79,7 @@ int64_t robust_spill_values(const Plan& P, std::vector<int64_t>* off = nullptr) 
   return tot;
 }
 
-WsMap layout_for(const Plan& P, bool keep_res, bool plain) {
+WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov) {
   Layout L;
   WsMap m;
   const size_t i4 = 4, i8 = 8, f8 = 8;
@@ -116,6 +116,7 @@ WsMap layout_for(const Plan& P, bool keep_res, bool plain) {
   m.rec_valid = L.add(i4 * 4);
   m.rho_t = L.add(f8 * 2);
   m.Xt = L.add(plain ? f8 * 3 * P.NC : 0);
+  m.covY = L.add(cov ? f8 * P.rcs_total : 0);
   m.pb_row = L.add(i4 * P.pb_row.size());
   m.pb_ent_off = L.add(i8 * P.pb_ent_off.size());
   m.pb_ent = L.add(i4 * P.pb_ent.size());
@@ -229,6 +230,7 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
   if (!(o->rho > 0) || !std::isfinite(o->rho) || !(o->rho_growth > 0) || !std::isfinite(o->rho_growth) ||
       !(o->filter_px > 0))
     return fail(RPBA_ERR_ARG, "rho, rho_growth and filter_px must be positive and finite");
+  if (o->covariance != 0 && o->covariance != 1) return fail(RPBA_ERR_ARG, "covariance must be 0 or 1");
   if (o->pair_lanes != 0 && o->pair_lanes != 4 && o->pair_lanes != 8 && o->pair_lanes != 16)
     return fail(RPBA_ERR_ARG, "pair_lanes must be 0, 4, 8 or 16");
   return RPBA_OK;
@@ -377,6 +379,7 @@ rpba_status rpba_default_options(rpba_options* o) {
   o->rho = 1000.0;
   o->rho_growth = 1.01;
   o->filter_px = 1000.0;
+  o->covariance = 0;
   return RPBA_OK;
 }
 
@@ -387,7 +390,7 @@ rpba_status rpba_workspace_size(const rpba_problem_desc* d, const rpba_options* 
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  *bytes = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN).total;
+  *bytes = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN, o->covariance != 0).total;
   return RPBA_OK;
 }
 
@@ -401,7 +404,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  WsMap m = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN);
+  WsMap m = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN, o->covariance != 0);
   if (bytes < m.total) return fail(RPBA_ERR_WORKSPACE, "workspace too small: need " + std::to_string(m.total));
   size_t lds = 0;
 
@@ -886,6 +889,41 @@ rpba_status rpba_robust_reweight(rpba_problem* h, int32_t mode, double* stats) {
                   h->opt.down_weight, mode, stats, h->stream);
     return RPBA_OK;
   });
+}
+
+rpba_status rpba_covariance(rpba_problem* h, double lambda, double* cam_cov, double* copy_cov) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(RPBA_ERR_ARG, "lambda must be finite and >= 0");
+  if (!h->opt.covariance) return fail(RPBA_ERR_STATE, "the handle was created without opt->covariance");
+  if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run before rpba_covariance");
+  if (h->n_pcg) return fail(RPBA_ERR_STATE, "a sub-block is solved by PCG: it has no factor to invert");
+  const Plan& p = *h->plan;
+  const double lam0 = h->d.lambda;
+  h->d.lambda = lambda;
+  // the intersection's fused copy records carry its damping: rebuild them
+  launch_zero_i32(h->d.rec_valid, 1, h->stream);
+  rpba_status s = assemble(h, nullptr);
+  if (s == RPBA_OK)
+    s = chol_forward(h, (const int32_t*)(h->ws + h->map.pot_items), (const int32_t*)(h->ws + h->map.fwd_items),
+                     (const int32_t*)(h->ws + h->map.upd_items));
+  // the dataflow launch hands its control words on through the step's last
+  // kernel: no backward substitution follows here, so finish it explicitly
+  if (s == RPBA_OK && h->dataflow) launch_df_finish(h->d, (int*)(h->ws + h->map.df_ctl), h->stream);
+  h->d.lambda = lam0;
+  h->d.active = nullptr;
+  if (s != RPBA_OK) return s;
+  std::vector<int32_t> bad(p.L);
+  HIP_TRY(hipMemcpyAsync(bad.data(), h->d.blk_fail, 4 * (size_t)p.L, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int l = 0; l < p.L; ++l)
+    if (bad[l]) return fail(RPBA_ERR_NOT_SPD, "sub-block " + std::to_string(l) + ": system not positive definite");
+  h->d.lambda = lambda;  // the copy pass rebuilds V with the same damping
+  launch_cov_inverse(h->d, (double*)(h->ws + h->map.covY), p.nt_max, h->stream);
+  launch_cov_outputs(h->d, cam_cov, copy_cov, h->stream);
+  h->d.lambda = lam0;
+  HIP_TRY(hipGetLastError());
+  // the RCS storage now holds S^-1: the next step assembles it afresh
+  return RPBA_OK;
 }
 
 rpba_status rpba_get_robust(rpba_problem* h, double* sigma_cam, double* obs_weight) {

@@ -782,6 +782,99 @@ __global__ __launch_bounds__(NT) void k_chol_backward_df(Dev d, const int32_t* _
   }
 }
 
+// ------------------------------------------------------------ covariance
+// Inverse of the reduced camera system of every dense sub-block from its
+// Cholesky factor (Sec. 2: M_CC = S^-1), in three launches:
+//   diag:    Y(J,J) = L(J,J)^-T, the stored inverse diagonal tile transposed;
+//   panel:   one workgroup per tile column J of a sub-block, down the column:
+//            Y(I,J) = -(sum_{K=J}^{I-1} Y(K,J) L(I,K)^T) L(I,I)^-T, I > J,
+//            so that Y = (L^-1)^T tile by tile (X = L^-1, Y(I,J) = X(I,J)^T);
+//   product: one workgroup per tile (I,J), I >= J:
+//            S^-1(I,J) = sum_{K>=I} X(K,I)^T X(K,J) = sum_K Y(K,I) Y(K,J)^T,
+//            written over the factor in the RCS storage.
+// Y has the tile layout of the RCS.  Every product runs on the FP64 matrix
+// cores; a tile column's chain stays in one workgroup, which reads the tiles
+// it wrote itself after a barrier.
+template <int T>
+__device__ __forceinline__ double* ytile(const Dev& d, double* Y, int l, int i, int j) {
+  return Y + d.rcs_off[l] + ((int64_t)i * (i + 1) / 2 + j) * (int64_t)T * T;
+}
+
+template <int T>
+__global__ __launch_bounds__(NT) void k_cov_diag(Dev d, double* Y) {
+  const int l = blockIdx.y, J = blockIdx.x;
+  if (J >= d.nt[l]) return;
+  const double* Li = d.Li + d.diag_off[l] + (int64_t)J * T * T;
+  double* y = ytile<T>(d, Y, l, J, J);
+  for (int idx = threadIdx.x; idx < T * T; idx += NT) {
+    const int blk = idx >> 6, w = idx & 63;
+    const int r = (blk / (T / 4)) * 16 + (w & 15), c = (blk % (T / 4)) * 4 + (w >> 4);
+    y[idx] = Li[mf_idx(T, c, r)];
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(NT) void k_cov_panel(Dev d, double* Y) {
+  __shared__ double stage[T * T];
+  const int l = blockIdx.y, J = blockIdx.x, nt = d.nt[l];
+  if (J >= nt) return;
+  for (int I = J + 1; I < nt; ++I) {
+    Acc<T> acc;
+    acc.zero();
+    for (int K = J; K < I; ++K) gemm_nt_mf<T>(ytile<T>(d, Y, l, K, J), tile_ptr<T>(d, l, I, K), acc);
+#pragma unroll
+    for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+      for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int r, c;
+          acc_rc<T>(p, q, e, r, c);
+          stage[mf_idx(T, r, c)] = acc.v[p][q][e];
+        }
+    __syncthreads();
+    Acc<T> out;
+    out.zero();
+    gemm_nt_mf<T, true>(stage, d.Li + d.diag_off[l] + (int64_t)I * T * T, out);
+    double* y = ytile<T>(d, Y, l, I, J);
+#pragma unroll
+    for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+      for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int r, c;
+          acc_rc<T>(p, q, e, r, c);
+          y[mf_idx(T, r, c)] = out.v[p][q][e];
+        }
+    __syncthreads();  // the tile is read by every wave in the next rows
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(NT) void k_cov_product(Dev d, const double* Y) {
+  const int l = blockIdx.y, nt = d.nt[l];
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= (int)blockIdx.x) ++I;
+  const int J = (int)blockIdx.x - I * (I + 1) / 2;
+  if (I >= nt) return;
+  Acc<T> acc;
+  acc.zero();
+  for (int K = I; K < nt; ++K)
+    gemm_nt_mf<T>(ytile<T>(d, const_cast<double*>(Y), l, K, I), ytile<T>(d, const_cast<double*>(Y), l, K, J), acc);
+  double* m = tile_ptr<T>(d, l, I, J);
+#pragma unroll
+  for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+    for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int r, c;
+        acc_rc<T>(p, q, e, r, c);
+        m[mf_idx(T, r, c)] = acc.v[p][q][e];
+      }
+}
+
 }  // namespace
 
 void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st) {
@@ -822,6 +915,10 @@ void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* fl
 
 void launch_df_reset(int* ctl, hipStream_t st) { hipLaunchKernelGGL(k_df_reset, dim3(1), dim3(64), 0, st, ctl); }
 
+void launch_df_finish(const Dev& d, int* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_df_finish, dim3(1), dim3(256), 0, st, d, ctl);
+}
+
 void launch_chol_backward_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* xflags, int* ctl,
                                    int nworkers, hipStream_t st) {
   if (ntask > 0) {
@@ -849,6 +946,19 @@ void launch_chol_backward(const Dev& d, const int32_t* items, int64_t n_items, h
 
 void launch_selftest_gemm(const double* A, const double* B, double* C, hipStream_t st) {
   hipLaunchKernelGGL(k_selftest_gemm, dim3(1), dim3(NT), 2 * 64 * 64 * sizeof(double), st, A, B, C);
+}
+
+template <int T>
+static void launch_cov_inverse_t(const Dev& d, double* Y, int nt_max, hipStream_t st) {
+  hipLaunchKernelGGL(k_cov_diag<T>, dim3((unsigned)nt_max, (unsigned)d.L), dim3(NT), 0, st, d, Y);
+  hipLaunchKernelGGL(k_cov_panel<T>, dim3((unsigned)nt_max, (unsigned)d.L), dim3(NT), 0, st, d, Y);
+  hipLaunchKernelGGL(k_cov_product<T>, dim3((unsigned)(nt_max * (nt_max + 1) / 2), (unsigned)d.L), dim3(NT), 0, st,
+                     d, (const double*)Y);
+}
+
+void launch_cov_inverse(const Dev& d, double* Y, int nt_max, hipStream_t st) {
+  if (d.T == 64) launch_cov_inverse_t<64>(d, Y, nt_max, st);
+  else launch_cov_inverse_t<32>(d, Y, nt_max, st);
 }
 
 }  // namespace rpba

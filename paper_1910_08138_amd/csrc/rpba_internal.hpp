@@ -171,6 +171,13 @@ void launch_init_rcs(const Dev& d, hipStream_t st);
 void launch_intersect(const Dev& d, bool want_cov, hipStream_t st);
 void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st);
 void launch_copy_prep(const Dev& d, hipStream_t st);
+// covariances (rpba_covariance): Y [rcs_total] scratch of the RCS tile
+// layout; the inverse S^-1 of every dense sub-block replaces its factor in S
+void launch_cov_inverse(const Dev& d, double* Y, int nt_max, hipStream_t st);
+// ends a dataflow factorisation that no backward launch follows: failure
+// flags from exhausted waits, control words readied for the next step
+void launch_df_finish(const Dev& d, int* ctl, hipStream_t st);
+void launch_cov_outputs(const Dev& d, double* cam_cov, double* copy_cov, hipStream_t st);
 void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, hipStream_t st);
 void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st);
 void launch_chol_potrf(const Dev& d, int k, const int32_t* pot, int64_t npot, hipStream_t st);

@@ -1237,6 +1237,121 @@ __global__ void k_bsr_extract(Dev d, int l, double* S_out, double* e_out) {
   }
 }
 
+// ------------------------------------------------------------ covariance
+// element (r, c) of the symmetric matrix held as a lower triangle in the RCS
+// storage of sub-block l
+__device__ __forceinline__ double rcs_sym(const Dev& d, int l, int r, int c) {
+  return r >= c ? d.S[rcs_elem(d, l, r, c)] : d.S[rcs_elem(d, l, c, r)];
+}
+
+// Camera covariance: the camera's 6 x 6 diagonal block of S^-1 of its
+// sub-block (the RCS storage holds S^-1 after the inverse launches), written
+// row-major in the caller's camera order.
+__global__ void k_cov_cams(Dev d, double* out) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= d.M) return;
+  const int l = d.cam_blk[i], a = i - d.blk_cam_off[l];
+  double* o = out + 36 * (int64_t)d.cam_orig[i];
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) o[6 * r + c] = rcs_sym(d, l, 6 * a + r, 6 * a + c);
+}
+
+// Point-copy covariance (Sec. 2): M_XX = V^-1 + V^-1 (sum_{k,k'} Y_k^T
+// M(i_k, i_k') Y_k') V^-1 with M = S^-1 of the copy's sub-block, V the damped
+// point block with the tie-point weight and Y_k = A_k^T W_k B_k of the copy's
+// observation k in camera i_k, at the state the system was assembled at (FP64
+// on both paths).  One thread per copy, the sum as sum_k Y_k^T (sum_k' M Y_k');
+// zeros for copies of invalid points.  Output (xx, xy, xz, yy, yz, zz) in copy
+// order.
+__device__ __forceinline__ void cov_obs(const Dev& d, int64_t k, const double (&X)[3], bool unit, double (&Y)[6][3],
+                                        double (&BtWB)[6]) {
+  const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
+  Lin<double> L;
+  linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+  const W2<double> W = obs_weight(d, k, unit);
+  double WB[2][3];
+  for (int c = 0; c < 3; ++c) {
+    WB[0][c] = W.a * L.B[0][c] + W.b * L.B[1][c];
+    WB[1][c] = W.b * L.B[0][c] + W.c * L.B[1][c];
+  }
+  for (int c = 0; c < 3; ++c) {
+    for (int u = 0; u < 3; ++u) {
+      Y[u][c] = L.Ar[0][u] * WB[0][c] + L.Ar[1][u] * WB[1][c];
+      Y[3 + u][c] = -(L.B[0][u] * WB[0][c] + L.B[1][u] * WB[1][c]);
+    }
+  }
+  BtWB[0] = L.B[0][0] * WB[0][0] + L.B[1][0] * WB[1][0];
+  BtWB[1] = L.B[0][0] * WB[0][1] + L.B[1][0] * WB[1][1];
+  BtWB[2] = L.B[0][0] * WB[0][2] + L.B[1][0] * WB[1][2];
+  BtWB[3] = L.B[0][1] * WB[0][1] + L.B[1][1] * WB[1][1];
+  BtWB[4] = L.B[0][1] * WB[0][2] + L.B[1][1] * WB[1][2];
+  BtWB[5] = L.B[0][2] * WB[0][2] + L.B[1][2] * WB[1][2];
+}
+
+__global__ __launch_bounds__(NT) void k_cov_copies(Dev d, double* out) {
+  const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (c >= d.NC) return;
+  double* o = out + 6 * c;
+  const int l = d.copy_blk[c], p = d.copy_pt[c];
+  double Mx[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (d.status[p] == 0) {
+    const bool unit = *d.rw_unit != 0;
+    const int k0 = d.copy_off[c], k1 = d.copy_off[c + 1], b0 = d.blk_cam_off[l];
+    double xb[3];
+    prior_centre(d, p, c, xb);
+    double X[3] = {xb[0], xb[1], xb[2]};
+    if (!d.blk_fresh[l])
+      for (int r = 0; r < 3; ++r) X[r] = d.Xc[3 * c + r];
+    double h[6];
+    om_load(d, c, h);
+    double Y[6][3], bwb[6];
+    for (int k = k0; k < k1; ++k) {
+      cov_obs(d, k, X, unit, Y, bwb);
+      for (int q = 0; q < 6; ++q) h[q] += bwb[q];
+    }
+    h[0] *= 1.0 + d.lambda;
+    h[3] *= 1.0 + d.lambda;
+    h[5] *= 1.0 + d.lambda;
+    double lch[6], vi[6];
+    if (chol3(h, lch)) {
+      chol3_inverse(lch, vi);
+      double T3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int k1i = k0; k1i < k1; ++k1i) {
+        double Y1[6][3];
+        cov_obs(d, k1i, X, unit, Y1, bwb);
+        const int a1 = d.obs_cam[k1i] - b0;
+        double G[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int k2i = k0; k2i < k1; ++k2i) {
+          double Y2[6][3];
+          cov_obs(d, k2i, X, unit, Y2, bwb);
+          const int a2 = d.obs_cam[k2i] - b0;
+          for (int u = 0; u < 6; ++u)
+            for (int v = 0; v < 6; ++v) {
+              const double m = rcs_sym(d, l, 6 * a1 + u, 6 * a2 + v);
+              for (int q = 0; q < 3; ++q) G[u][q] += m * Y2[v][q];
+            }
+        }
+        for (int r = 0; r < 3; ++r)
+          for (int q = 0; q < 3; ++q) {
+            double sacc = 0.0;
+            for (int u = 0; u < 6; ++u) sacc += Y1[u][r] * G[u][q];
+            T3[r][q] += sacc;
+          }
+      }
+      const double V[3][3] = {{vi[0], vi[1], vi[2]}, {vi[1], vi[3], vi[4]}, {vi[2], vi[4], vi[5]}};
+      double VT[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) VT[r][q] = V[r][0] * T3[0][q] + V[r][1] * T3[1][q] + V[r][2] * T3[2][q];
+      const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+      for (int e = 0; e < 6; ++e) {
+        const int r = rr[e], q = cc[e];
+        Mx[e] = V[r][q] + VT[r][0] * V[0][q] + VT[r][1] * V[1][q] + VT[r][2] * V[2][q];
+      }
+    }
+  }
+  for (int e = 0; e < 6; ++e) o[e] = Mx[e];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
@@ -1291,6 +1406,11 @@ void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
 
 void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, cov, status_out, stats);
+}
+
+void launch_cov_outputs(const Dev& d, double* cam_cov, double* copy_cov, hipStream_t st) {
+  if (cam_cov) hipLaunchKernelGGL(k_cov_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d, cam_cov);
+  if (copy_cov) hipLaunchKernelGGL(k_cov_copies, dim3(grid_for(d.NC)), dim3(NT), 0, st, d, copy_cov);
 }
 
 void launch_copy_prep(const Dev& d, hipStream_t st) {
