@@ -77,6 +77,10 @@ def _declare(L):
                                                                                      ctypes.c_double]
     L.orc_destroy.argtypes = [ctypes.c_void_p]
     L.orc_intersect.argtypes = [ctypes.c_void_p, _dp]
+    L.orc_set_damping.restype = None
+    L.orc_set_damping.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_double] * 4
+    L.orc_get_damping.restype = None
+    L.orc_get_damping.argtypes = [ctypes.c_void_p, _dp, _ip]
     L.orc_covariance.restype = ctypes.c_int
     L.orc_covariance.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp]
     L.orc_robust_reweight.restype = ctypes.c_int
@@ -240,6 +244,17 @@ class OracleProblem:
         r = np.zeros((2, self.K))
         self._lib.orc_get_residuals(self.h, _p(r))
         return r
+
+    def set_damping(self, mode=1, up=10.0, down=10.0, lam_min=1e-12, lam_max=1e8):
+        """Adaptive damping per sub-block (mode 1) or the fixed lambda (0)."""
+        self._lib.orc_set_damping(self.h, int(mode), float(up), float(down), float(lam_min), float(lam_max))
+
+    def damping(self):
+        """(lambda [L], last step rejected [L])."""
+        lam = np.zeros(self.L)
+        rej = np.zeros(self.L, dtype=np.int32)
+        self._lib.orc_get_damping(self.h, _p(lam), _p(rej, _ip))
+        return lam, rej
 
     def covariance(self, lam=1e-6):
         """(camera covariances [M][6][6], copy covariances [n_copies][6]) of

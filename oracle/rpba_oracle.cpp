@@ -51,6 +51,7 @@
 //     points get weight zero from then on.
 //   * sigma0 redundancy r = 2 K_valid - 6 M - 3 N_valid, unit weights, pixels.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -238,6 +239,13 @@ struct Problem {
   int int_maxit;
   int variant = V_EXTENDED;
   double rho_t = 1000.0, rho_growth = 1.01, filter_px = 1000.0;
+  // adaptive damping (Sec. 5.4, 7): per sub-block lambda, a step that raises
+  // the sub-block's cost is taken back and lambda multiplied by lam_up, an
+  // accepted step divides it by lam_down, within [lam_min, lam_max]
+  int damping = 0;
+  double lam_up = 10.0, lam_down = 10.0, lam_min = 1e-12, lam_max = 1e8;
+  std::vector<double> lam_blk;
+  std::vector<int> rejected;
   std::vector<Cam> cams;
   std::vector<double> X;        // [N][3] global point (start value / intersection result)
   std::vector<double> Xbar;     // [N][3] last intersection result
@@ -466,7 +474,7 @@ void build_block(const Problem& P, int l, BlockSystem& B) {
   B.e.assign(B.n6, 0.0);
   B.cost = 0;
   B.ok = true;
-  const double lam = P.lambda;
+  const double lam = P.damping ? P.lam_blk[l] : P.lambda;
 
   // camera blocks U_i, gradients g_C
   std::vector<std::vector<double>>& Ys = B.Y;
@@ -607,16 +615,36 @@ void apply_update(Problem& P, int l, const BlockSystem& B, const std::vector<dou
   }
 }
 
+// raise or lower the sub-block's damping after a rejected / accepted step
+void adapt_lambda(Problem& P, int l, bool rejected) {
+  if (!P.damping) return;
+  P.rejected[l] = rejected ? 1 : 0;
+  P.lam_blk[l] = rejected ? std::min(P.lam_blk[l] * P.lam_up, P.lam_max) : std::max(P.lam_blk[l] / P.lam_down, P.lam_min);
+}
+
 int lm_step_block(Problem& P, int l, double* bs) {
   BlockSystem B;
   build_block(P, l, B);
   bs[0] = B.cost;
-  if (!B.ok) return 1;
+  if (!B.ok) {
+    adapt_lambda(P, l, true);
+    return 1;
+  }
   std::vector<double> Lf = B.S;
-  if (!chol_dense(B.n6, Lf)) return 2;
+  if (!chol_dense(B.n6, Lf)) {
+    adapt_lambda(P, l, true);
+    return 2;
+  }
   std::vector<double> dC, dX;
   chol_dense_solve(B.n6, Lf, B.e, dC);
   back_substitute(P, l, B, dC, dX);
+  // the state before the step, to take a rejected step back exactly
+  std::vector<Cam> cams0;
+  std::vector<std::array<double, 3>> X0;
+  if (P.damping) {
+    for (int i : P.blk_cams[l]) cams0.push_back(P.cams[i]);
+    for (int ci : B.cps) X0.push_back({P.copies[ci].X[0], P.copies[ci].X[1], P.copies[ci].X[2]});
+  }
   apply_update(P, l, B, dC, dX);
   double c = 0, nrm = 0;
   for (int ci : B.cps) c += copy_cost(P, P.copies[ci]);
@@ -625,6 +653,17 @@ int lm_step_block(Problem& P, int l, double* bs) {
   bs[1] = c;
   bs[2] = std::sqrt(nrm);
   bs[3] = 1.0;
+  if (P.damping) {
+    const bool rej = c > bs[0];
+    if (rej) {
+      for (size_t a = 0; a < cams0.size(); ++a) P.cams[P.blk_cams[l][a]] = cams0[a];
+      for (size_t q = 0; q < X0.size(); ++q)
+        for (int r = 0; r < 3; ++r) P.copies[B.cps[q]].X[r] = X0[q][r];
+      bs[1] = bs[0];
+      bs[2] = 0.0;
+    }
+    adapt_lambda(P, l, rej);
+  }
   return 0;
 }
 
@@ -967,7 +1006,9 @@ int orc_block_step(orc_problem* h, int l, double* dC_out, double* dX_out) {
 int orc_covariance(orc_problem* h, double lam, double* cam_cov, double* copy_cov) {
   Problem& P = h->P;
   const double lam0 = P.lambda;
+  const int damping0 = P.damping;
   P.lambda = lam;
+  P.damping = 0;
   int rc = 0;
   if (copy_cov) std::fill(copy_cov, copy_cov + 6 * P.copies.size(), 0.0);
   for (int l = 0; l < P.L && rc == 0; ++l) {
@@ -1023,7 +1064,29 @@ int orc_covariance(orc_problem* h, double lam, double* cam_cov, double* copy_cov
     }
   }
   P.lambda = lam0;
+  P.damping = damping0;
   return rc;
+}
+
+// Adaptive damping on (mode 1) or off (0); every sub-block starts at lambda.
+void orc_set_damping(orc_problem* h, int mode, double up, double down, double lmin, double lmax) {
+  Problem& P = h->P;
+  P.damping = mode;
+  P.lam_up = up;
+  P.lam_down = down;
+  P.lam_min = lmin;
+  P.lam_max = lmax;
+  P.lam_blk.assign(P.L, P.lambda);
+  P.rejected.assign(P.L, 0);
+}
+
+// Per sub-block damping and whether its last step was rejected.
+void orc_get_damping(orc_problem* h, double* lam, int32_t* rejected) {
+  Problem& P = h->P;
+  for (int l = 0; l < P.L; ++l) {
+    if (lam) lam[l] = P.damping ? P.lam_blk[l] : P.lambda;
+    if (rejected) rejected[l] = P.damping ? P.rejected[l] : 0;
+  }
 }
 
 // Linearisation of one observation (for finite-difference pins).
