@@ -88,6 +88,12 @@ enum {
  * rho_t = rho * rho_growth^t after t calls of rpba_consensus. */
 enum { RPBA_VARIANT_EXTENDED = 0, RPBA_VARIANT_ALL_CAMERAS = 1, RPBA_VARIANT_SCALAR = 2, RPBA_VARIANT_PLAIN = 3,
        RPBA_VARIANT_PLAIN_REFINED = 4 };
+/* damping of the LM steps (Sec. 5.4 fixes lambda; adapting it is the
+ * alternative the paper names, Sec. 5.4 and 7): ADAPTIVE keeps one lambda per
+ * sub-block, starting at opt->lambda; a step that raises the sub-block's cost
+ * (or whose system cannot be factorised) is taken back and lambda multiplied
+ * by lambda_up, an accepted step divides it by lambda_down. */
+enum { RPBA_DAMPING_FIXED = 0, RPBA_DAMPING_ADAPTIVE = 1 };
 /* what rpba_robust_reweight does with flagged observations (Sec. 5.3) */
 enum { RPBA_ROBUST_WEIGHT = 0, RPBA_ROBUST_ELIMINATE_POINTS = 1, RPBA_ROBUST_DELETE_OBS = 2 };
 
@@ -132,6 +138,11 @@ typedef struct {
   double filter_px;      /* PLAIN variants: a point with a reprojection error above this is filtered: 1000 */
   int32_t covariance;    /* 1: the workspace holds one more array of the size of the dense RCS, for
                             rpba_covariance: 0 */
+  int32_t damping;       /* RPBA_DAMPING_FIXED (lambda throughout) or RPBA_DAMPING_ADAPTIVE: FIXED */
+  double lambda_up;      /* adaptive: factor on a sub-block's lambda after a rejected step: 10 */
+  double lambda_down;    /* adaptive: divisor after an accepted step: 10 */
+  double lambda_min;     /* adaptive: bounds of lambda: 1e-12 */
+  double lambda_max;     /*   : 1e8 */
 } rpba_options;
 
 /* Fill *opt with the defaults listed above.  HOST pointer. */
@@ -214,6 +225,11 @@ rpba_status rpba_robust_reweight(rpba_problem *h, int32_t mode, double *stats);
  * one synchronisation (the factorisation check). */
 rpba_status rpba_covariance(rpba_problem *h, double lambda, double *cam_cov, double *copy_cov);
 
+/* Per sub-block damping (HOST lambda [L]) and whether its last step was
+ * taken back (HOST rejected [L]); with RPBA_DAMPING_FIXED lambda and 0.
+ * Either may be NULL.  Synchronises the handle's stream. */
+rpba_status rpba_get_damping(rpba_problem *h, double *lambda, int32_t *rejected);
+
 /* Result of the last rpba_robust_reweight: sigma_cam [M] the per-camera
  * scales sigma0_i (0 for a camera without a valid observation), obs_weight
  * [K] the weight multipliers (1 or down_weight), both HOST, in the caller's
@@ -227,7 +243,10 @@ rpba_status rpba_get_robust(rpba_problem *h, double *sigma_cam, double *obs_weig
  * N + lambda diag(N); Schur complement onto the cameras (reduced camera system
  * S, outer products accumulated straight into S); S solved by Cholesky
  * (FP64 MFMA) or PCG; back-substitution; update R <- Exp([w]x) R, C += dc,
- * X^l += dX.  Every step is accepted.
+ * X^l += dX.  With RPBA_DAMPING_FIXED every step is accepted; with
+ * RPBA_DAMPING_ADAPTIVE a step that raises its sub-block's cost is taken back
+ * (block_stats: cost after = cost before, step norm 0) and the sub-block's
+ * lambda adapted (rpba_get_damping).
  *   active      [L] uint8 (0 = skip) or NULL for all
  *   block_stats [L][4]: cost before, cost after, step norm, solver iterations
  *               (or NULL) */

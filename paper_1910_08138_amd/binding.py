@@ -23,6 +23,7 @@ RPBA_CHOL_DEFAULT, RPBA_CHOL_STEPWISE, RPBA_CHOL_DATAFLOW = 0, 1, 2
  RPBA_VARIANT_PLAIN_REFINED) = 0, 1, 2, 3, 4
 RPBA_OK, RPBA_ERR_NOT_SPD, RPBA_WARN_NONCONVERGED = 0, 4, 100
 RPBA_ROBUST_WEIGHT, RPBA_ROBUST_ELIMINATE_POINTS, RPBA_ROBUST_DELETE_OBS = 0, 1, 2
+RPBA_DAMPING_FIXED, RPBA_DAMPING_ADAPTIVE = 0, 1
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_WORKSPACE", 4: "ERR_NOT_SPD", 5: "ERR_STATE",
                 100: "WARN_NONCONVERGED"}
 
@@ -36,6 +37,7 @@ EXPORTS = [
     "rpba_precond_harvest", "rpba_precond_train_scratch", "rpba_precond_train_step", "rpba_get_robust",
     "rpba_step_status", "rpba_ratio_update", "rpba_camera_order", "rpba_get_precond_blocks", "rpba_factor_flops",
     "rpba_precond_train_step_noalloc", "rpba_partition_default_options", "rpba_partition", "rpba_covariance",
+    "rpba_get_damping",
 ]
 TRAIN_NOALLOC_MAX_SAMPLES = 8192   # RPBA_TRAIN_NOALLOC_MAX_SAMPLES
 PHASES = ["intersect", "point_blocks", "schur_rows", "chol_forward", "chol_backward", "update", "consensus",
@@ -65,7 +67,8 @@ class Options(ctypes.Structure):
         ("chol_tile", ctypes.c_int32), ("chol_schedule", ctypes.c_int32),
         ("robust", ctypes.c_int32), ("pair_lanes", ctypes.c_int32), ("variant", ctypes.c_int32),
         ("rho", ctypes.c_double), ("rho_growth", ctypes.c_double), ("filter_px", ctypes.c_double),
-        ("covariance", ctypes.c_int32),
+        ("covariance", ctypes.c_int32), ("damping", ctypes.c_int32), ("lambda_up", ctypes.c_double),
+        ("lambda_down", ctypes.c_double), ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
     ]
 
 
@@ -131,6 +134,7 @@ def load_library(path: str = LIB_PATH):
     L.rpba_partition_default_options.argtypes = [ctypes.POINTER(PartitionOptions)]
     L.rpba_partition.argtypes = [i32, i32, i32, vp, vp, ctypes.POINTER(PartitionOptions), vp, vp, vp]
     L.rpba_covariance.argtypes = [vp, ctypes.c_double, vp, vp]
+    L.rpba_get_damping.argtypes = [vp, vp, vp]
     L.rpba_set_graph.argtypes = [vp, i32]
     L.rpba_set_timing.argtypes = [vp, i32]
     L.rpba_get_timing.restype = i32
@@ -154,8 +158,11 @@ def default_options(**kw) -> Options:
     L = load_library()
     o = Options()
     _check(L.rpba_default_options(ctypes.byref(o)), "rpba_default_options")
+    names = {f[0] for f in Options._fields_}
     for k, v in kw.items():
-        setattr(o, "lam" if k == "lam" else k, v)
+        if k not in names:
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
     return o
 
 
@@ -357,6 +364,13 @@ class Problem:
         _check(self.L_.rpba_covariance(self.h, float(lam), _ptr(cc), _ptr(xc)), "rpba_covariance")
         self.sync()
         return cc.cpu().numpy(), xc.cpu().numpy()
+
+    def damping(self):
+        """(lambda [L], last step taken back [L]) of the sub-blocks."""
+        lam = np.zeros(self.L)
+        rej = np.zeros(self.L, dtype=np.int32)
+        _check(self.L_.rpba_get_damping(self.h, lam.ctypes.data, rej.ctypes.data), "rpba_get_damping")
+        return lam, rej
 
     def robust_result(self):
         """(sigma_cam [M], obs_weight [K]) of the last robust re-weighting,

@@ -58,7 +58,8 @@ struct WsMap {
       bwd_items, upd_items, pot_items, blk_fail, pb_row, pb_ent_off, pb_ent, od_pb, pb_bsr, pb_bsr_t, blk_pcg, bsr_row_off, bsr_col, bsr,
       Pblk, pcg_list, mean_diag, cam_tpfrac, mlp_w, pcg_cams, rob_bad, rob_off, rob_vals, rob_sigma, pm_off, pm_k,
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
-      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt, covY;
+      df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt, covY,
+      lam_blk, blk_rej, XcOld;
   size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
       acc_rob;
   size_t total;
@@ -79,7 +80,7 @@ int64_t robust_spill_values(const Plan& P, std::vector<int64_t>* off = nullptr) 
   return tot;
 }
 
-WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov) {
+WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov, bool adaptive) {
   Layout L;
   WsMap m;
   const size_t i4 = 4, i8 = 8, f8 = 8;
@@ -117,6 +118,9 @@ WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov) {
   m.rho_t = L.add(f8 * 2);
   m.Xt = L.add(plain ? f8 * 3 * P.NC : 0);
   m.covY = L.add(cov ? f8 * P.rcs_total : 0);
+  m.lam_blk = L.add(f8 * P.L);
+  m.blk_rej = L.add(i4 * P.L);
+  m.XcOld = L.add(adaptive ? f8 * 3 * P.NC : 0);
   m.pb_row = L.add(i4 * P.pb_row.size());
   m.pb_ent_off = L.add(i8 * P.pb_ent_off.size());
   m.pb_ent = L.add(i4 * P.pb_ent.size());
@@ -231,6 +235,12 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
       !(o->filter_px > 0))
     return fail(RPBA_ERR_ARG, "rho, rho_growth and filter_px must be positive and finite");
   if (o->covariance != 0 && o->covariance != 1) return fail(RPBA_ERR_ARG, "covariance must be 0 or 1");
+  if (o->damping != RPBA_DAMPING_FIXED && o->damping != RPBA_DAMPING_ADAPTIVE)
+    return fail(RPBA_ERR_ARG, "damping must be RPBA_DAMPING_FIXED or RPBA_DAMPING_ADAPTIVE");
+  if (o->damping == RPBA_DAMPING_ADAPTIVE &&
+      (!(o->lambda_up > 1.0) || !(o->lambda_down > 1.0) || !(o->lambda_min > 0.0) || !(o->lambda_max >= o->lambda_min) ||
+       !std::isfinite(o->lambda_up) || !std::isfinite(o->lambda_down) || !std::isfinite(o->lambda_max)))
+    return fail(RPBA_ERR_ARG, "adaptive damping needs lambda_up, lambda_down > 1 and 0 < lambda_min <= lambda_max, finite");
   if (o->pair_lanes != 0 && o->pair_lanes != 4 && o->pair_lanes != 8 && o->pair_lanes != 16)
     return fail(RPBA_ERR_ARG, "pair_lanes must be 0, 4, 8 or 16");
   return RPBA_OK;
@@ -380,6 +390,11 @@ rpba_status rpba_default_options(rpba_options* o) {
   o->rho_growth = 1.01;
   o->filter_px = 1000.0;
   o->covariance = 0;
+  o->damping = RPBA_DAMPING_FIXED;
+  o->lambda_up = 10.0;
+  o->lambda_down = 10.0;
+  o->lambda_min = 1e-12;
+  o->lambda_max = 1e8;
   return RPBA_OK;
 }
 
@@ -390,7 +405,8 @@ rpba_status rpba_workspace_size(const rpba_problem_desc* d, const rpba_options* 
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  *bytes = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN, o->covariance != 0).total;
+  *bytes = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN, o->covariance != 0,
+                      o->damping == RPBA_DAMPING_ADAPTIVE).total;
   return RPBA_OK;
 }
 
@@ -404,7 +420,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   std::shared_ptr<Plan> P;
   s = get_plan(d, o, P);
   if (s != RPBA_OK) return s;
-  WsMap m = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN, o->covariance != 0);
+  WsMap m = layout_for(*P, o->robust != 0, o->variant >= RPBA_VARIANT_PLAIN, o->covariance != 0,
+                      o->damping == RPBA_DAMPING_ADAPTIVE);
   if (bytes < m.total) return fail(RPBA_ERR_WORKSPACE, "workspace too small: need " + std::to_string(m.total));
   size_t lds = 0;
 
@@ -674,6 +691,14 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.rho_growth = o->rho_growth;
   D.filter_px = o->filter_px;
   D.Xt = o->variant >= RPBA_VARIANT_PLAIN ? F(m.Xt) : nullptr;
+  const bool adaptive = o->damping == RPBA_DAMPING_ADAPTIVE;
+  D.lam_blk = adaptive ? F(m.lam_blk) : nullptr;
+  D.blk_rej = I(m.blk_rej);
+  D.XcOld = adaptive ? F(m.XcOld) : nullptr;
+  D.lam_up = o->lambda_up;
+  D.lam_down = o->lambda_down;
+  D.lam_min = o->lambda_min;
+  D.lam_max = o->lambda_max;
   D.acc_int = F(m.acc_int);
   D.acc_blk = F(m.acc_blk);
   D.acc_cons = F(m.acc_cons);
@@ -714,6 +739,12 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero((double*)(w + m.rob_sigma), D.M, st);
   launch_init_rcs(D, st);
   HIP_TRY(hipMemcpyAsync(D.rho_t, &o->rho, sizeof(double), hipMemcpyHostToDevice, st));
+  launch_zero_i32(D.blk_rej, D.L, st);
+  if (adaptive) {
+    const std::vector<double> lam0(p.L, o->lambda);
+    HIP_TRY(hipMemcpyAsync(D.lam_blk, lam0.data(), 8 * (size_t)p.L, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // lam0 is a host temporary
+  }
   if (o->variant >= RPBA_VARIANT_PLAIN) launch_init_copies(D, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
@@ -899,7 +930,9 @@ rpba_status rpba_covariance(rpba_problem* h, double lambda, double* cam_cov, dou
   if (h->n_pcg) return fail(RPBA_ERR_STATE, "a sub-block is solved by PCG: it has no factor to invert");
   const Plan& p = *h->plan;
   const double lam0 = h->d.lambda;
+  double* const lam_blk0 = h->d.lam_blk;
   h->d.lambda = lambda;
+  h->d.lam_blk = nullptr;  // one damping for every sub-block here
   // the intersection's fused copy records carry its damping: rebuild them
   launch_zero_i32(h->d.rec_valid, 1, h->stream);
   rpba_status s = assemble(h, nullptr);
@@ -910,6 +943,7 @@ rpba_status rpba_covariance(rpba_problem* h, double lambda, double* cam_cov, dou
   // kernel: no backward substitution follows here, so finish it explicitly
   if (s == RPBA_OK && h->dataflow) launch_df_finish(h->d, (int*)(h->ws + h->map.df_ctl), h->stream);
   h->d.lambda = lam0;
+  h->d.lam_blk = lam_blk0;
   h->d.active = nullptr;
   if (s != RPBA_OK) return s;
   std::vector<int32_t> bad(p.L);
@@ -918,11 +952,30 @@ rpba_status rpba_covariance(rpba_problem* h, double lambda, double* cam_cov, dou
   for (int l = 0; l < p.L; ++l)
     if (bad[l]) return fail(RPBA_ERR_NOT_SPD, "sub-block " + std::to_string(l) + ": system not positive definite");
   h->d.lambda = lambda;  // the copy pass rebuilds V with the same damping
+  h->d.lam_blk = nullptr;
   launch_cov_inverse(h->d, (double*)(h->ws + h->map.covY), p.nt_max, h->stream);
   launch_cov_outputs(h->d, cam_cov, copy_cov, h->stream);
   h->d.lambda = lam0;
+  h->d.lam_blk = lam_blk0;
   HIP_TRY(hipGetLastError());
   // the RCS storage now holds S^-1: the next step assembles it afresh
+  return RPBA_OK;
+}
+
+rpba_status rpba_get_damping(rpba_problem* h, double* lambda, int32_t* rejected) {
+  if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
+  const int L = h->plan->L;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (lambda) {
+    if (h->d.lam_blk) HIP_TRY(hipMemcpy(lambda, h->d.lam_blk, 8 * (size_t)L, hipMemcpyDeviceToHost));
+    else
+      for (int l = 0; l < L; ++l) lambda[l] = h->d.lambda;
+  }
+  if (rejected) {
+    if (h->d.lam_blk) HIP_TRY(hipMemcpy(rejected, h->d.blk_rej, 4 * (size_t)L, hipMemcpyDeviceToHost));
+    else
+      for (int l = 0; l < L; ++l) rejected[l] = 0;
+  }
   return RPBA_OK;
 }
 

@@ -129,6 +129,11 @@ struct Dev {
   int32_t* blk_fail;      // [L] factorisation failed (non-positive pivot): step not applied
   int32_t* blk_nc;        // [L] iterative solve ended above its refinement tolerance
   const uint8_t* active;  // [L] or null (set per call)
+  // adaptive damping: per sub-block lambda, or null for the fixed d.lambda
+  double* lam_blk;        // [L]
+  int32_t* blk_rej;       // [L] the last step was taken back
+  double* XcOld;          // [3 NC] the copies before the step
+  double lam_up, lam_down, lam_min, lam_max;
 
   // accumulators
   double* acc_int;        // [4 + L] cost, sum |v|^2, K_valid, N_valid; then per sub-block the cost
@@ -137,6 +142,9 @@ struct Dev {
   double* acc_cons;       // [2]
   double* acc_rob;        // [2]
 };
+
+// damping of sub-block l's normal equations
+__host__ __device__ __forceinline__ double lam_of(const Dev& d, int l) { return d.lam_blk ? d.lam_blk[l] : d.lambda; }
 
 // one 128-byte record per copy for the current LM step (64 bytes, CPK32
 // doubles, on the mixed path)

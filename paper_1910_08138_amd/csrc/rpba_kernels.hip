@@ -683,7 +683,9 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
     // variants keep their copies where the sub-blocks left them
     if (VAR < RPBA_VARIANT_PLAIN)
       for (int l = threadIdx.x; l < d.L; l += IT) d.blk_fresh[l] = 1;
-    if (threadIdx.x == 0) *d.rec_valid = VAR < RPBA_VARIANT_PLAIN ? 1 : 0;
+    // (with adaptive damping every sub-block has its own lambda: the point
+    // blocks are rebuilt by the point-block pass instead)
+    if (threadIdx.x == 0) *d.rec_valid = VAR < RPBA_VARIANT_PLAIN && !d.lam_blk ? 1 : 0;
   }
   if (threadIdx.x < CSLOT) {
     cs.key[threadIdx.x] = -1;
@@ -889,9 +891,10 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
       double h[6], g[3];
       for (int q = 0; q < 6; ++q) h[q] = sizeof(J) == 8 ? (double)hj[q] : om[q] + (double)hj[q];
       for (int q = 0; q < 3; ++q) g[q] = sizeof(J) == 8 ? (double)gj[q] : gp[q] + (double)gj[q];
-      h[0] *= 1.0 + d.lambda;
-      h[3] *= 1.0 + d.lambda;
-      h[5] *= 1.0 + d.lambda;
+      const double lam = lam_of(d, l);
+      h[0] *= 1.0 + lam;
+      h[3] *= 1.0 + lam;
+      h[5] *= 1.0 + lam;
       double lch[6], inv[6];
       bool ok = chol3(h, lch);
       if (ok) chol3_inverse(lch, inv);
@@ -1023,15 +1026,18 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       double h[6], g[3];
       for (int q = 0; q < 6; ++q) h[q] = sizeof(J) == 8 ? (double)hj[q] : om[q] + (double)hj[q];
       for (int q = 0; q < 3; ++q) g[q] = sizeof(J) == 8 ? (double)gj[q] : gp[q] + (double)gj[q];
-      h[0] *= 1.0 + d.lambda;
-      h[3] *= 1.0 + d.lambda;
-      h[5] *= 1.0 + d.lambda;
+      const double lam = lam_of(d, l);
+      h[0] *= 1.0 + lam;
+      h[3] *= 1.0 + lam;
+      h[5] *= 1.0 + lam;
       double lch[6], dX[3] = {0.0, 0.0, 0.0};
       if (chol3(h, lch)) {
         double rhs[3] = {-g[0] - (double)bt[0], -g[1] - (double)bt[1], -g[2] - (double)bt[2]};
         chol3_solve(lch, rhs, dX);
       }
       double Xn[3] = {X[0] + dX[0], X[1] + dX[1], X[2] + dX[2]};
+      if (d.XcOld)  // adaptive damping: the copy before the step, to take it back
+        for (int r = 0; r < 3; ++r) d.XcOld[3 * c + r] = X[r];
       d.Xc[3 * c] = Xn[0];
       d.Xc[3 * c + 1] = Xn[1];
       d.Xc[3 * c + 2] = Xn[2];
@@ -1062,22 +1068,47 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
   }
 }
 
-// after the update: the new cameras become the current ones, and the
-// per-sub-block statistics of the step are written out
+// adaptive damping: a step that raised its sub-block's cost, or could not
+// be factorised, is taken back (cameras not committed, copies restored by
+// k_restore_copies) and the sub-block's lambda grows by lam_up; an accepted
+// step divides it by lam_down (within [lam_min, lam_max])
+__device__ __forceinline__ bool step_rejected(const Dev& d, int l) {
+  const double* a = d.acc_blk + 4 * l;
+  return d.lam_blk && (d.active == nullptr || d.active[l]) && (d.blk_fail[l] != 0 || a[1] > a[0]);
+}
+
+// after the update: the new cameras become the current ones (those of an
+// accepted step), and the per-sub-block statistics of the step are written
+// out
 __global__ void k_update_finish(Dev d, double* bs) {
   const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (t < (int64_t)CAM_STRIDE * d.M) d.cam[t] = d.camN[t];
+  if (t < (int64_t)CAM_STRIDE * d.M && !step_rejected(d, d.cam_blk[t / CAM_STRIDE])) d.cam[t] = d.camN[t];
   if (t >= d.L) return;
   const int l = (int)t;
   bool act = d.active == nullptr || d.active[l];
   const double* a = d.acc_blk + 4 * l;
-  if (act && d.blk_fail[l] == 0) d.blk_fresh[l] = 0;  // its copies were written by the update
+  const bool rej = step_rejected(d, l);
+  if (act && d.blk_fail[l] == 0 && !rej) d.blk_fresh[l] = 0;  // its copies were written by the update
+  if (d.lam_blk && act) {
+    d.blk_rej[l] = rej ? 1 : 0;
+    d.lam_blk[l] = rej ? fmin(d.lam_blk[l] * d.lam_up, d.lam_max) : fmax(d.lam_blk[l] / d.lam_down, d.lam_min);
+  }
   if (bs) {
     bs[4 * l + 0] = act ? a[0] : 0.0;
-    bs[4 * l + 1] = act ? (d.blk_fail[l] ? a[0] : a[1]) : 0.0;
-    bs[4 * l + 2] = act ? sqrt(a[2]) : 0.0;
+    bs[4 * l + 1] = act ? (d.blk_fail[l] || rej ? a[0] : a[1]) : 0.0;
+    bs[4 * l + 2] = act && !rej ? sqrt(a[2]) : 0.0;
     bs[4 * l + 3] = act ? (d.blk_fail[l] ? -1.0 : (a[3] > 0 ? a[3] : 1.0)) : 0.0;
   }
+}
+
+// adaptive damping: copies of a sub-block whose step was taken back return
+// to where they were before it
+__global__ void k_restore_copies(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (c >= d.NC) return;
+  const int l = d.copy_blk[c];
+  if ((d.active == nullptr || d.active[l]) && d.blk_rej[l] && d.blk_fail[l] == 0 && d.status[d.copy_pt[c]] == 0)
+    for (int r = 0; r < 3; ++r) d.Xc[3 * c + r] = d.XcOld[3 * c + r];
 }
 
 // --------------------------------------------------------------- consensus
@@ -1425,6 +1456,7 @@ void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
   else hipLaunchKernelGGL(k_back_update<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_update_finish, dim3(grid_for(std::max<int64_t>((int64_t)CAM_STRIDE * d.M, d.L))), dim3(NT), 0,
                      st, d, block_stats);
+  if (d.lam_blk) hipLaunchKernelGGL(k_restore_copies, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
 }
 
 __global__ void k_init_copies(Dev d) {

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
         uv = (double)U[q];
         av = (double)acc[q];
       }
-    if (r == s) uv = (uv == 0.0) ? 1.0 : uv * (1.0 + d.lambda);
+    if (r == s) uv = (uv == 0.0) ? 1.0 : uv * (1.0 + lam_of(d, l));
     const double val = uv + av;
     if (d.blk_pcg && d.blk_pcg[l]) {
       d.bsr[(int64_t)d.pb_bsr[d.nb_off[i + 1] - 1] * 36 + lane] = (float)val;
