@@ -56,8 +56,12 @@ typedef enum {
 
 /* precision policy */
 enum { RPBA_FP64 = 0, RPBA_MIXED = 1 };
-/* solver of the reduced camera system */
-enum { RPBA_SOLVER_CHOL = 0, RPBA_SOLVER_PCG_BJ = 1, RPBA_SOLVER_PCG_LEARNED = 2, RPBA_SOLVER_AUTO = 3 };
+/* solver of the reduced camera system: Cholesky everywhere; PCG everywhere
+ * (block-Jacobi or learned blocks); AUTO: PCG with block-Jacobi on the
+ * sub-blocks of at least pcg_min_cams cameras, Cholesky on the others;
+ * AUTO_LEARNED: the same cut, PCG with the learned blocks */
+enum { RPBA_SOLVER_CHOL = 0, RPBA_SOLVER_PCG_BJ = 1, RPBA_SOLVER_PCG_LEARNED = 2, RPBA_SOLVER_AUTO = 3,
+       RPBA_SOLVER_AUTO_LEARNED = 4 };
 /* schedule of the dense Cholesky factorisation: one persistent launch over
  * a tile task list with per-tile ready flags (dataflow), or three launches
  * per tile column (stepwise) */
@@ -123,7 +127,7 @@ typedef struct {
   double pcg_tol;        /* PCG relative residual: 1e-8 */
   double ir_tol;         /* iterative refinement relative residual (FP64): 1e-10 */
   int32_t ir_maxit;      /* refinement sweeps: 6 */
-  int32_t pcg_min_cams;  /* RPBA_SOLVER_AUTO: sub-blocks with at least this many cameras use PCG: 150 */
+  int32_t pcg_min_cams;  /* RPBA_SOLVER_AUTO(_LEARNED): sub-blocks with at least this many cameras use PCG: 150 */
   double t_v;            /* robust threshold on the normalised residual (Sec. 5.3): 4 (parallel variant; the
                             serial variant uses 3) */
   double down_weight;    /* weight multiplier of flagged observations: 1e-4 */
@@ -335,7 +339,7 @@ rpba_status rpba_factor_flops(rpba_problem *h, double *out);
 rpba_status rpba_get_precond_blocks(rpba_problem *h, int32_t l, double *P);
 
 /* ------------------------------------------------ learned block preconditioner
- * With RPBA_SOLVER_PCG_LEARNED the CG preconditioner keeps the block-diagonal
+ * With RPBA_SOLVER_PCG_LEARNED or _AUTO_LEARNED the CG preconditioner keeps the block-diagonal
  * form of block-Jacobi (paper Sec. 3 and 5.4) with blocks
  * P_i = G^-T L L^T G^-1, S_ii = G G^T, L = I + strict lower part from a
  * 26 -> 64 -> 64 -> 21 network (tanh) on per-camera features, exp(.) on the

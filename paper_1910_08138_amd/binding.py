@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "librpba.so")
 
 RPBA_FP64, RPBA_MIXED = 0, 1
-RPBA_SOLVER_CHOL, RPBA_SOLVER_PCG_BJ, RPBA_SOLVER_PCG_LEARNED, RPBA_SOLVER_AUTO = 0, 1, 2, 3
+RPBA_SOLVER_CHOL, RPBA_SOLVER_PCG_BJ, RPBA_SOLVER_PCG_LEARNED, RPBA_SOLVER_AUTO, RPBA_SOLVER_AUTO_LEARNED = 0, 1, 2, 3, 4
 RPBA_CHOL_DEFAULT, RPBA_CHOL_STEPWISE, RPBA_CHOL_DATAFLOW = 0, 1, 2
 (RPBA_VARIANT_EXTENDED, RPBA_VARIANT_ALL_CAMERAS, RPBA_VARIANT_SCALAR, RPBA_VARIANT_PLAIN,
  RPBA_VARIANT_PLAIN_REFINED) = 0, 1, 2, 3, 4

@@ -224,6 +224,7 @@ rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
   if (!d->obs_info && !(d->sigma_px > 0)) return fail(RPBA_ERR_ARG, "sigma_px must be > 0 without obs_info");
   if (!d->cam_R || !d->cam_C || !d->pts || !d->obs_xy) return fail(RPBA_ERR_ARG, "state and observation arrays must be non-NULL");
   if (o->precision != RPBA_FP64 && o->precision != RPBA_MIXED) return fail(RPBA_ERR_ARG, "unknown precision");
+  if (o->solver < RPBA_SOLVER_CHOL || o->solver > RPBA_SOLVER_AUTO_LEARNED) return fail(RPBA_ERR_ARG, "unknown solver");
   if (!(o->lambda >= 0) || !(o->int_tol > 0) || o->int_maxit < 1) return fail(RPBA_ERR_ARG, "bad LM / intersection options");
   if (o->chol_tile != 0 && o->chol_tile != 32 && o->chol_tile != 64) return fail(RPBA_ERR_ARG, "chol_tile must be 0, 32 or 64");
   if (o->chol_schedule < RPBA_CHOL_DEFAULT || o->chol_schedule > RPBA_CHOL_DATAFLOW)
@@ -491,7 +492,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   for (int l = 0; l < p.L; ++l) {
     const int ncam = p.blk_cam_off[l + 1] - p.blk_cam_off[l];
     bool it = o->solver == RPBA_SOLVER_PCG_BJ || o->solver == RPBA_SOLVER_PCG_LEARNED ||
-              (o->solver == RPBA_SOLVER_AUTO && ncam >= o->pcg_min_cams);
+              ((o->solver == RPBA_SOLVER_AUTO || o->solver == RPBA_SOLVER_AUTO_LEARNED) && ncam >= o->pcg_min_cams);
     if (it) {
       h->blk_pcg[l] = 1;
       pcg_list.push_back(l);
@@ -842,7 +843,7 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
       }
     }
     if (h->n_pcg) {
-      const bool learned = h->opt.solver == RPBA_SOLVER_PCG_LEARNED;
+      const bool learned = h->opt.solver == RPBA_SOLVER_PCG_LEARNED || h->opt.solver == RPBA_SOLVER_AUTO_LEARNED;
       PhaseTimer t(h, PH_SOLVE_IT, learned ? 3 : 2);
       if (learned) launch_mean_diag(h->d, (float*)(h->ws + h->map.mean_diag), h->stream);
       launch_precond_learned(h->d, learned ? (const float*)(h->ws + h->map.mlp_w) : nullptr,

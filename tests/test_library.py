@@ -104,6 +104,25 @@ def test_validation_rejects_empty_subblock_and_bad_tile():
     assert rc == 1 and "pair_lanes" in msg
     rc, _, msg = _size(s, robust=2)
     assert rc == 1 and "robust" in msg
+    rc, _, msg = _size(s, solver=5)
+    assert rc == 1 and "solver" in msg
+    rc, _, msg = _size(s, covariance=2)
+    assert rc == 1 and "covariance" in msg
+    rc, _, msg = _size(s, damping=binding.RPBA_DAMPING_ADAPTIVE, lambda_down=0.5)
+    assert rc == 1 and "adaptive damping" in msg
+    with pytest.raises(TypeError, match="unknown option"):
+        binding.default_options(lamda=1e-3)
+
+
+def test_optional_arrays_take_workspace_only_when_asked():
+    """The covariance array (one more dense RCS) and the adaptive-damping
+    copy positions (24 bytes per copy) are laid out only with their options."""
+    s = scenes.config_scene(1, 0)
+    rc0, n0, _ = _size(s)
+    rc1, n1, _ = _size(s, covariance=1)
+    rc2, n2, _ = _size(s, damping=binding.RPBA_DAMPING_ADAPTIVE)
+    assert rc0 == rc1 == rc2 == 0
+    assert n1 > n0 and n2 - n0 >= 24 * s.N   # at least one copy per point
 
 
 def test_residuals_take_workspace_only_when_kept():
