@@ -60,7 +60,7 @@ struct WsMap {
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
       df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt, covY,
       lam_blk, blk_rej, XcOld;
-  size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons,
+  size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons, cons_part, int_part,
       acc_rob;
   size_t total;
 };
@@ -183,6 +183,8 @@ WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov, bool adapti
   m.acc_int = L.add(f8 * (4 + P.L));
   m.acc_blk = L.add(f8 * 4 * P.L);
   m.acc_cons = L.add(f8 * 2);
+  m.cons_part = L.add(f8 * 2 * ((P.N + 255) / 256));
+  m.int_part = L.add(f8 * 4 * ((P.N + INT_WG - 1) / INT_WG));
   m.acc_rob = L.add(f8 * 2);
   m.total = L.total;
   return m;
@@ -703,6 +705,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.acc_int = F(m.acc_int);
   D.acc_blk = F(m.acc_blk);
   D.acc_cons = F(m.acc_cons);
+  D.cons_part = F(m.cons_part);
+  D.int_part = F(m.int_part);
   D.acc_rob = F(m.acc_rob);
 
   // finite inputs, positive definite information matrices
@@ -762,7 +766,7 @@ rpba_status rpba_intersect(rpba_problem* h, double* cov, int32_t* status, double
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   rpba_status s = run_call(h, h->g_int, cov, status, stats, [&]() -> rpba_status {
     {
-      PhaseTimer t(h, PH_INTERSECT, 2);
+      PhaseTimer t(h, PH_INTERSECT, 3);
       launch_intersect(h->d, cov != nullptr, h->stream);
     }
     PhaseTimer t(h, PH_INT_EXPORT, 1);

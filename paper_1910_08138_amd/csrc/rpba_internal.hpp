@@ -140,6 +140,8 @@ struct Dev {
                           // of its copies at the intersection (the cost before its next LM step)
   double* acc_blk;        // [L][4] cost before, cost after, |step|^2, iterations
   double* acc_cons;       // [2]
+  double* cons_part;      // [2 * ceil(N / 256)] per-workgroup partials of the consensus statistics
+  double* int_part;       // [4 * ceil(N / INT_WG)] per-workgroup partials of the intersection statistics
   double* acc_rob;        // [2]
 };
 

@@ -764,7 +764,9 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   } else {
     intersect_point<INFO, false, VAR>(d, sg, cs, b0, j, want_cov, accv);
   }
-  // workgroup sum of the statistics, one atomic per value
+  // workgroup sum of the statistics, one partial per value (k_int_reduce
+  // adds them up: atomics of every workgroup on the same four words would
+  // queue up in the cache)
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -775,7 +777,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   if (threadIdx.x < 4) {
     double v = 0.0;
     for (int w = 0; w < IT / 64; ++w) v += sh[threadIdx.x * (IT / 64) + w];
-    atomicAdd(&d.acc_int[threadIdx.x], v);
+    d.int_part[4 * (int64_t)blockIdx.x + threadIdx.x] = v;
   }
   if (threadIdx.x < CSLOT && cs.key[threadIdx.x] >= 0)
     atomicAdd(&d.acc_int[4 + cs.key[threadIdx.x]], cs.sum[threadIdx.x]);
@@ -1218,9 +1220,61 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
     sh[4 + wv] = ntp;
   }
   __syncthreads();
+  // one partial per workgroup (k_consensus_reduce sums them: atomics of every
+  // workgroup on the same two words would queue up in the cache)
   if (threadIdx.x == 0) {
-    atomic_max_nonneg(&d.acc_cons[0], fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3])));
-    atomicAdd(&d.acc_cons[1], sh[4] + sh[5] + sh[6] + sh[7]);
+    d.cons_part[2 * blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    d.cons_part[2 * blockIdx.x + 1] = sh[4] + sh[5] + sh[6] + sh[7];
+  }
+}
+
+// the four statistics of an intersection from the per-workgroup partials
+// (one workgroup of 1,024 threads, a fixed order: the sums are reproducible)
+__global__ __launch_bounds__(1024) void k_int_reduce(Dev d, int nwg) {
+  __shared__ double sh[4 * 16];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < nwg; t += blockDim.x)
+    for (int q = 0; q < 4; ++q) v[q] += d.int_part[4 * (int64_t)t + q];
+  for (int q = 0; q < 4; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int q = 0; q < 4; ++q) sh[16 * q + wv] = v[q];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[16 * threadIdx.x + w];
+    d.acc_int[threadIdx.x] = s;
+  }
+}
+
+// largest copy spread and tie-point count from the per-workgroup partials
+// (one workgroup of 1,024 threads)
+__global__ __launch_bounds__(1024) void k_consensus_reduce(Dev d, int nwg) {
+  __shared__ double sh[32];
+  double mx = 0.0, sum = 0.0;
+  for (int t = threadIdx.x; t < nwg; t += blockDim.x) {
+    mx = fmax(mx, d.cons_part[2 * t]);
+    sum += d.cons_part[2 * t + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o));
+    sum += __shfl_xor(sum, o);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wv] = mx;
+    sh[16 + wv] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m2 = 0.0, s2 = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      m2 = fmax(m2, sh[q]);
+      s2 += sh[16 + q];
+    }
+    d.acc_cons[0] = m2;
+    d.acc_cons[1] = s2;
   }
 }
 
@@ -1433,6 +1487,7 @@ void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
     case RPBA_VARIANT_PLAIN_REFINED: launch_intersect_var<RPBA_VARIANT_PLAIN_REFINED>(d, want_cov, st); break;
     default: launch_intersect_var<RPBA_VARIANT_EXTENDED>(d, want_cov, st); break;
   }
+  hipLaunchKernelGGL(k_int_reduce, dim3(1), dim3(1024), 0, st, d, (int)grid_for(d.N, IT));
 }
 
 void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
@@ -1474,8 +1529,8 @@ void launch_init_copies(const Dev& d, hipStream_t st) {
 }
 
 void launch_consensus(const Dev& d, double* stats, hipStream_t st) {
-  launch_zero(d.acc_cons, 2, st);
   hipLaunchKernelGGL(k_consensus_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_consensus_reduce, dim3(1), dim3(1024), 0, st, d, (int)grid_for(d.N));
   hipLaunchKernelGGL(k_export_pts, dim3(grid_for(d.N)), dim3(NT), 0, st, d, (double*)nullptr, (int32_t*)nullptr,
                      (double*)nullptr);
   hipLaunchKernelGGL(k_consensus_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d, stats);
