@@ -60,7 +60,7 @@ struct WsMap {
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
       df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt, covY,
       lam_blk, blk_rej, XcOld;
-  size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons, cons_part, int_part,
+  size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons, cons_part, int_part, upd_part,
       acc_rob;
   size_t total;
 };
@@ -185,6 +185,7 @@ WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov, bool adapti
   m.acc_cons = L.add(f8 * 2);
   m.cons_part = L.add(f8 * 2 * ((P.N + 255) / 256));
   m.int_part = L.add(f8 * 4 * ((P.N + INT_WG - 1) / INT_WG));
+  m.upd_part = L.add(f8 * 16 * ((P.NC + 255) / 256));
   m.acc_rob = L.add(f8 * 2);
   m.total = L.total;
   return m;
@@ -707,6 +708,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.acc_cons = F(m.acc_cons);
   D.cons_part = F(m.cons_part);
   D.int_part = F(m.int_part);
+  D.upd_part = F(m.upd_part);
   D.acc_rob = F(m.acc_rob);
 
   // finite inputs, positive definite information matrices
@@ -857,7 +859,7 @@ rpba_status rpba_subblock_lm_step(rpba_problem* h, const uint8_t* active, double
                  h->opt.pcg_tol, h->opt.ir_tol, h->opt.ir_maxit, h->stream);
     }
     {
-      PhaseTimer t(h, PH_UPDATE, 3);
+      PhaseTimer t(h, PH_UPDATE, 4);
       launch_update(h->d, block_stats, h->stream);
     }
     return RPBA_OK;

@@ -142,6 +142,7 @@ struct Dev {
   double* acc_cons;       // [2]
   double* cons_part;      // [2 * ceil(N / 256)] per-workgroup partials of the consensus statistics
   double* int_part;       // [4 * ceil(N / INT_WG)] per-workgroup partials of the intersection statistics
+  double* upd_part;       // [16 * ceil(NC / 256)] per-workgroup, per-slot partials of the update's costs
   double* acc_rob;        // [2]
 };
 

@@ -854,7 +854,10 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
     for (int q = 0; q < 8; ++q) sh[q] = 0.0;
   }
   __syncthreads();
-  if (s_skip) return;
+  if (s_skip) {
+    if (threadIdx.x < 8) d.upd_part[16 * (int64_t)blockIdx.x + threadIdx.x] = 0.0;
+    return;
+  }
   if (c < d.NC && !(recs && d.blk_fresh[d.copy_blk[c]])) {
     // the copy's indices, flags and point are loaded together, ahead of the
     // tests that use them (the copy's own data stays behind them: holding it
@@ -911,8 +914,8 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
     }
   }
   __syncthreads();
-  if (threadIdx.x < 8 && sh[threadIdx.x] != 0.0 && l_first + (int)threadIdx.x < d.L)
-    atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 0], sh[threadIdx.x]);
+  // the workgroup's sums per slot, added up per sub-block by k_slots_reduce
+  if (threadIdx.x < 8) d.upd_part[16 * (int64_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x];
 }
 
 // start of an LM step: per sub-block the statistics (cost before from the
@@ -1064,9 +1067,45 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
     }
   }
   __syncthreads();
-  if (threadIdx.x < 8 && l_first + (int)threadIdx.x < d.L) {
-    if (sh[threadIdx.x] != 0.0) atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 1], sh[threadIdx.x]);
-    if (sh[8 + threadIdx.x] != 0.0) atomicAdd(&d.acc_blk[4 * (l_first + threadIdx.x) + 2], sh[8 + threadIdx.x]);
+  // the workgroup's sums per slot, added up per sub-block by k_slots_reduce
+  // (atomics of the many workgroups of one sub-block on its two words would
+  // queue up in the cache)
+  if (threadIdx.x < 16) d.upd_part[16 * (int64_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x];
+}
+
+// per sub-block sums of the copy passes' slots: the cost before the step
+// (point-block pass, UPD false) or the cost after it and the squared step of
+// the copies (update pass, UPD true), from the slots of the workgroups that
+// hold the sub-block's copies (one wave per sub-block, lanes over the
+// workgroups); added to what is already there (the camera steps' squares,
+// the cost before of fresh sub-blocks, and the rare overflow adds)
+template <bool UPD>
+__global__ void k_slots_reduce(Dev d) {
+  const int l = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (l >= d.L) return;
+  const int64_t c0 = d.blk_copy_off[l], c1 = d.blk_copy_off[l + 1];
+  double a = 0.0, b = 0.0;
+  if (c1 > c0) {
+    const int64_t w0 = c0 / NT, w1 = (c1 - 1) / NT;
+    for (int64_t w = w0 + lane; w <= w1; w += 64) {
+      const int slot = l - d.copy_blk[w * NT];
+      if (slot >= 0 && slot < 8) {
+        a += d.upd_part[16 * w + slot];
+        if (UPD) b += d.upd_part[16 * w + 8 + slot];
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    if (UPD) b += __shfl_xor(b, o);
+  }
+  if (lane == 0) {
+    if (UPD) {
+      d.acc_blk[4 * l + 1] += a;
+      d.acc_blk[4 * l + 2] += b;
+    } else {
+      d.acc_blk[4 * l + 0] += a;
+    }
   }
 }
 
@@ -1503,12 +1542,14 @@ void launch_copy_prep(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_step_begin, dim3(grid_for(d.L)), dim3(NT), 0, st, d);
   if (d.cpk_f32) hipLaunchKernelGGL(k_copy_prep<float>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
   else hipLaunchKernelGGL(k_copy_prep<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_slots_reduce<false>, dim3(grid_for(d.L, NT / 64)), dim3(NT), 0, st, d);
 }
 
 void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
   hipLaunchKernelGGL(k_cam_update, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
   if (d.cpk_f32) hipLaunchKernelGGL(k_back_update<float>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
   else hipLaunchKernelGGL(k_back_update<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_slots_reduce<true>, dim3(grid_for(d.L, NT / 64)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_update_finish, dim3(grid_for(std::max<int64_t>((int64_t)CAM_STRIDE * d.M, d.L))), dim3(NT), 0,
                      st, d, block_stats);
   if (d.lam_blk) hipLaunchKernelGGL(k_restore_copies, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
