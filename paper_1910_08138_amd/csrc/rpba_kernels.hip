@@ -854,10 +854,9 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
     for (int q = 0; q < 8; ++q) sh[q] = 0.0;
   }
   __syncthreads();
-  if (s_skip) {
-    if (threadIdx.x < 8) d.upd_part[16 * (int64_t)blockIdx.x + threadIdx.x] = 0.0;
-    return;
-  }
+  // a skipped workgroup holds copies of fresh sub-blocks only, whose sums
+  // the reduction does not read: its slots are left as they are
+  if (s_skip) return;
   if (c < d.NC && !(recs && d.blk_fresh[d.copy_blk[c]])) {
     // the copy's indices, flags and point are loaded together, ahead of the
     // tests that use them (the copy's own data stays behind them: holding it
@@ -1083,6 +1082,9 @@ template <bool UPD>
 __global__ void k_slots_reduce(Dev d) {
   const int l = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (l >= d.L) return;
+  // the point-block pass skipped every copy of a fresh sub-block whose
+  // records the intersection wrote: nothing to add
+  if (!UPD && *d.rec_valid != 0 && d.blk_fresh[l]) return;
   const int64_t c0 = d.blk_copy_off[l], c1 = d.blk_copy_off[l + 1];
   double a = 0.0, b = 0.0;
   if (c1 > c0) {
