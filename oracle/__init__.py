@@ -105,6 +105,9 @@ def _declare(L):
     L.orc_block_step.restype = ctypes.c_int
     L.orc_block_step.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     L.orc_linearise.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    L.orc_linearise_cal.argtypes = [_dp, _dp, _dp] + [ctypes.c_double] * 4 + [_dp, _dp, _dp]
+    L.orc_set_intrinsics.argtypes = [ctypes.c_void_p, _dp, _dp]
+    L.orc_get_intrinsics.argtypes = [ctypes.c_void_p, _dp, _dp]
     L.orc_rodrigues.argtypes = [_dp, _dp]
     L.orc_cholesky.restype = ctypes.c_int
     L.orc_cholesky.argtypes = [ctypes.c_int, _dp]
@@ -156,6 +159,13 @@ class OracleProblem:
                               _p(k["info"]), _p(k["blk"], _ip), lam, int_tol, int_maxit, int(variant), float(rho),
                               float(rho_growth), float(filter_px))
         self._lib = L
+        # intrinsics (f and k1 per camera, estimated with the poses) when the
+        # scene carries them
+        self.np = 6
+        if getattr(scene, "cam_f", None) is not None:
+            f, k1 = f64(scene.cam_f), f64(scene.cam_k1)
+            L.orc_set_intrinsics(self.h, _p(f), _p(k1))
+            self.np = 8
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -191,6 +201,14 @@ class OracleProblem:
         C = np.zeros((3, self.M))
         self._lib.orc_get_cameras(self.h, _p(R), _p(C))
         return R, C
+
+    def intrinsics(self):
+        """(f [M], k1 [M]): the cameras' own focal lengths and distortions
+        with intrinsics, else the shared f and zeros."""
+        f = np.zeros(self.M)
+        k1 = np.zeros(self.M)
+        self._lib.orc_get_intrinsics(self.h, _p(f), _p(k1))
+        return f, k1
 
     def set_cameras(self, R, C):
         R, C = f64(R), f64(C)
@@ -257,9 +275,10 @@ class OracleProblem:
         return lam, rej
 
     def covariance(self, lam=1e-6):
-        """(camera covariances [M][6][6], copy covariances [n_copies][6]) of
-        the sub-block normal equations damped by lam (Sec. 2)."""
-        cc = np.zeros((self.M, 6, 6))
+        """(camera covariances [M][np][np], copy covariances [n_copies][6])
+        of the sub-block normal equations damped by lam (Sec. 2); np = 6, or 8
+        with intrinsics."""
+        cc = np.zeros((self.M, self.np, self.np))
         xc = np.zeros((self._lib.orc_num_copies(self.h), 6))
         rc = self._lib.orc_covariance(self.h, float(lam), _p(cc), _p(xc))
         if rc < 0:
@@ -289,6 +308,17 @@ def linearise(R9, C3, X3, f=1000.0, cx=500.0, cy=500.0):
     A = np.zeros((2, 6))
     B = np.zeros((2, 3))
     lib().orc_linearise(_p(R9), _p(C3), _p(X3), f, cx, cy, _p(g), _p(A), _p(B))
+    return g, A, B
+
+
+def linearise_cal(R9, C3, X3, f=1000.0, k1=0.0, cx=500.0, cy=500.0):
+    """Projection with the camera's own f and k1: (g [2], A [2][8] =
+    dg/d(w, C, f, k1), B [2][3])."""
+    R9, C3, X3 = f64(R9), f64(C3), f64(X3)
+    g = np.zeros(2)
+    A = np.zeros((2, 8))
+    B = np.zeros((2, 3))
+    lib().orc_linearise_cal(_p(R9), _p(C3), _p(X3), f, k1, cx, cy, _p(g), _p(A), _p(B))
     return g, A, B
 
 

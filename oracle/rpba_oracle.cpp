@@ -40,6 +40,10 @@
 //   * camera model: calibrated pinhole, p = R (X - C), pixel f p/p3 + c;
 //     rotation update R <- Exp([w]x) R (Rodrigues), centre update C <- C + dc;
 //     per-camera parameter order (w_x, w_y, w_z, c_x, c_y, c_z).
+//   * intrinsics (the f + k1 per camera of the Final data sets, Sec. 6):
+//     pixel f (1 + k1 r2) q + c with q = (p1/p3, p2/p3), r2 = |q|^2, the
+//     principal point shared and fixed; f and k1 updated additively and
+//     appended to the camera's parameters (w, c, f, k1).
 //   * the tie-point term of eq:bact is the squared Mahalanobis distance
 //     (X - Xbar)^T Omega (X - Xbar).
 //   * damping multiplies the diagonal of the full N (including Omega) and is
@@ -49,7 +53,8 @@
 //     at most maxit iterations; statuses NOT_CONVERGED, BEHIND_CAMERA,
 //     ILL_CONDITIONED (3x3 Cholesky pivot <= 1e-12 * max diagonal); failed
 //     points get weight zero from then on.
-//   * sigma0 redundancy r = 2 K_valid - 6 M - 3 N_valid, unit weights, pixels.
+//   * sigma0 redundancy r = 2 K_valid - n_p M - 3 N_valid (n_p = 6, or 8 with
+//     intrinsics), unit weights, pixels.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -82,6 +87,7 @@ enum Variant { V_EXTENDED = 0, V_ALL_CAMERAS = 1, V_SCALAR = 2, V_PLAIN = 3, V_P
 struct Cam {
   double R[3][3];
   double C[3];
+  double f = 0.0, k1 = 0.0;  // own focal length and radial distortion (estimated with intrinsics only)
 };
 
 // Rodrigues' formula for the rotation of the axis-angle vector w
@@ -117,11 +123,12 @@ struct Obs2 {  // weight matrix of one observation: [[w11, w12], [w12, w22]]
 //   p = R (X - C); g = (f p1/p3 + cx, f p2/p3 + cy)
 //   dg/dp = (f/p3) [[1, 0, -p1/p3], [0, 1, -p2/p3]]
 //   dp/dw = -[p]x (rotation increment left-multiplied), dp/dC = -R, dp/dX = R
-// A = dg/d(w, C) (2x6), B = dg/dX (2x3).
+// A = dg/d(w, C) (2x6), B = dg/dX (2x3).  With intrinsics A has two more
+// columns, dg/df and dg/dk1 (see linearise_cal); they are zero otherwise.
 struct Lin {
   double g[2];
   double p[3];
-  double A[2][6];
+  double A[2][8];
   double B[2][3];
 };
 
@@ -144,6 +151,48 @@ void linearise(const Cam& cam, const double X[3], double f, double cx, double cy
       o.A[r][c] = sW;
       o.A[r][3 + c] = -sB;
     }
+    o.A[r][6] = o.A[r][7] = 0.0;
+  }
+}
+
+// Projection with the camera's own focal length f and first (quadratic)
+// radial distortion parameter k1, both estimated with the pose (Sec. 6: the
+// Final data sets, n (6 + 2) camera parameters).  The distortion acts on the
+// normalised image coordinates q = (p1/p3, p2/p3), r2 = |q|^2:
+//   g = f (1 + k1 r2) q + c
+//   dg/dq = f ((1 + k1 r2) I + 2 k1 q q^T),  dq/dp = (1/p3) [[1, 0, -q1], [0, 1, -q2]]
+//   dg/df = (1 + k1 r2) q,  dg/dk1 = f r2 q
+// Camera parameter order (w_x, w_y, w_z, c_x, c_y, c_z, f, k1).
+void linearise_cal(const Cam& cam, const double X[3], double cx, double cy, Lin& o) {
+  double d[3] = {X[0] - cam.C[0], X[1] - cam.C[1], X[2] - cam.C[2]};
+  for (int r = 0; r < 3; ++r) o.p[r] = cam.R[r][0] * d[0] + cam.R[r][1] * d[1] + cam.R[r][2] * d[2];
+  double z = o.p[2];
+  double q[2] = {o.p[0] / z, o.p[1] / z};
+  double r2 = q[0] * q[0] + q[1] * q[1];
+  double s = 1.0 + cam.k1 * r2;
+  o.g[0] = cam.f * s * q[0] + cx;
+  o.g[1] = cam.f * s * q[1] + cy;
+  double Dq[2][2];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) Dq[r][c] = cam.f * ((r == c ? s : 0.0) + 2.0 * cam.k1 * q[r] * q[c]);
+  double dqdp[2][3] = {{1.0 / z, 0.0, -q[0] / z}, {0.0, 1.0 / z, -q[1] / z}};
+  double Jp[2][3];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) Jp[r][c] = Dq[r][0] * dqdp[0][c] + Dq[r][1] * dqdp[1][c];
+  double mpx[3][3] = {{0, o.p[2], -o.p[1]}, {-o.p[2], 0, o.p[0]}, {o.p[1], -o.p[0], 0}};  // -[p]x
+  for (int r = 0; r < 2; ++r) {
+    for (int c = 0; c < 3; ++c) {
+      double sB = 0, sW = 0;
+      for (int m = 0; m < 3; ++m) {
+        sB += Jp[r][m] * cam.R[m][c];
+        sW += Jp[r][m] * mpx[m][c];
+      }
+      o.B[r][c] = sB;
+      o.A[r][c] = sW;
+      o.A[r][3 + c] = -sB;
+    }
+    o.A[r][6] = s * q[r];
+    o.A[r][7] = cam.f * r2 * q[r];
   }
 }
 
@@ -234,6 +283,7 @@ struct Copy {        // a point as seen inside one sub-block
 
 struct Problem {
   int M, N, K, L;
+  int ncp = 6;  // parameters per camera: 6 (pose), 8 with intrinsics (pose, f, k1)
   double f, cx, cy, sigma;
   double lambda, int_tol;
   int int_maxit;
@@ -274,6 +324,13 @@ Obs2 weight_of(const Problem& P, int k) {
   return w;
 }
 
+// projection of observation k's camera at X: the shared pinhole, or with
+// intrinsics the camera's own f and k1
+void lin_obs(const Problem& P, int k, const double X[3], Lin& o) {
+  if (P.ncp == 8) linearise_cal(P.cams[P.ocam[k]], X, P.cx, P.cy, o);
+  else linearise(P.cams[P.ocam[k]], X, P.f, P.cx, P.cy, o);
+}
+
 double wnorm2(const Obs2& w, const double v[2]) {
   return w.w11 * v[0] * v[0] + 2 * w.w12 * v[0] * v[1] + w.w22 * v[1] * v[1];
 }
@@ -306,7 +363,7 @@ void intersect_point(Problem& P, int j) {
     behind = false;
     for (int k : ol) {
       Lin li;
-      linearise(P.cams[P.ocam[k]], Xc, P.f, P.cx, P.cy, li);
+      lin_obs(P, k, Xc, li);
       if (!(li.p[2] > 0) && P.rw[k] != 0) behind = true;  // a deleted observation does not count
       double v[2] = {li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]};
       add_point_normals(li, weight_of(P, k), v, H, g);
@@ -347,7 +404,7 @@ void intersect_point(Problem& P, int j) {
       if (!plain) break;
       if (P.rw[k] == 0) continue;
       Lin li;
-      linearise(P.cams[P.ocam[k]], X, P.f, P.cx, P.cy, li);
+      lin_obs(P, k, X, li);
       vmax = std::max(vmax, std::hypot(li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]));
     }
     if (behind) st = ST_BEHIND;
@@ -367,7 +424,7 @@ void intersect_point(Problem& P, int j) {
         double Hl[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, gl[3] = {0, 0, 0};
         for (int k : cp.obs) {
           Lin li;
-          linearise(P.cams[P.ocam[k]], X, P.f, P.cx, P.cy, li);
+          lin_obs(P, k, X, li);
           double v[2] = {li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]};
           add_point_normals(li, weight_of(P, k), v, Hl, gl);
         }
@@ -388,7 +445,7 @@ void intersect_point(Problem& P, int j) {
       }
       for (int k : ol) {
         Lin li;
-        linearise(P.cams[P.ocam[k]], X, P.f, P.cx, P.cy, li);
+        lin_obs(P, k, X, li);
         P.last_res[2 * k] = li.g[0] - P.xy[2 * k];
         P.last_res[2 * k + 1] = li.g[1] - P.xy[2 * k + 1];
       }
@@ -411,7 +468,7 @@ void point_stats(const Problem& P, double* stats) {
       ++kv;
     }
   }
-  double red = 2.0 * kv - 6.0 * P.M - 3.0 * nv;
+  double red = 2.0 * kv - (double)P.ncp * P.M - 3.0 * nv;
   stats[0] = wcost;
   stats[1] = red > 0 ? std::sqrt(sq / red) : 0.0;
   stats[2] = kv > 0 ? std::sqrt(sq / (2.0 * kv)) : 0.0;
@@ -420,14 +477,15 @@ void point_stats(const Problem& P, double* stats) {
 
 // ------------------------------------------------- sub-block LM step (eq:bact)
 struct BlockSystem {
-  int n6 = 0, nc = 0;
+  int n6 = 0, nc = 0;                      // n6: rows of the RCS, np per camera
+  int np = 6;                              // parameters per camera
   std::vector<int> cps;                    // valid copies of the block
-  std::vector<double> U;                   // [ncam][6][6] damped
-  std::vector<double> gC;                  // [ncam][6]
+  std::vector<double> U;                   // [ncam][np][np] damped
+  std::vector<double> gC;                  // [ncam][np]
   std::vector<double> Vinv;                // [nc][3][3] of the damped V
   std::vector<double> gX;                  // [nc][3]
   std::vector<double> S, e;                // dense RCS and right-hand side
-  std::vector<std::vector<double>> Y;      // per copy, per observation: N_CX block (6 x 3)
+  std::vector<std::vector<double>> Y;      // per copy, per observation: N_CX block (np x 3)
   double cost = 0;
   bool ok = true;
 };
@@ -444,7 +502,7 @@ double copy_cost(const Problem& P, const Copy& cp) {
   double c = 0;
   for (int k : cp.obs) {
     Lin li;
-    linearise(P.cams[P.ocam[k]], cp.X, P.f, P.cx, P.cy, li);
+    lin_obs(P, k, cp.X, li);
     double v[2] = {li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]};
     c += wnorm2(weight_of(P, k), v);
   }
@@ -461,13 +519,15 @@ double copy_cost(const Problem& P, const Copy& cp) {
 void build_block(const Problem& P, int l, BlockSystem& B) {
   const std::vector<int>& cams = P.blk_cams[l];
   int nca = (int)cams.size();
-  B.n6 = 6 * nca;
+  const int np = P.ncp;
+  B.np = np;
+  B.n6 = np * nca;
   B.cps.clear();
   for (int ci : P.blk_copies[l])
     if (P.status[P.copies[ci].pt] == ST_OK) B.cps.push_back(ci);
   B.nc = (int)B.cps.size();
-  B.U.assign((size_t)nca * 36, 0.0);
-  B.gC.assign((size_t)nca * 6, 0.0);
+  B.U.assign((size_t)nca * np * np, 0.0);
+  B.gC.assign((size_t)nca * np, 0.0);
   B.Vinv.assign((size_t)B.nc * 9, 0.0);
   B.gX.assign((size_t)B.nc * 3, 0.0);
   B.S.assign((size_t)B.n6 * B.n6, 0.0);
@@ -490,17 +550,17 @@ void build_block(const Problem& P, int l, BlockSystem& B) {
     for (int r = 0; r < 3; ++r) gx[r] = cp.Om[r][0] * d[0] + cp.Om[r][1] * d[1] + cp.Om[r][2] * d[2];
     for (int r = 0; r < 3; ++r)
       for (int s = 0; s < 3; ++s) B.cost += d[r] * cp.Om[r][s] * d[s];
-    Ys[q].assign(cp.obs.size() * 18, 0.0);
+    Ys[q].assign(cp.obs.size() * np * 3, 0.0);
     for (size_t t = 0; t < cp.obs.size(); ++t) {
       int k = cp.obs[t];
       int a = P.cam_local[P.ocam[k]];
       Lin li;
-      linearise(P.cams[P.ocam[k]], cp.X, P.f, P.cx, P.cy, li);
+      lin_obs(P, k, cp.X, li);
       double v[2] = {li.g[0] - P.xy[2 * k], li.g[1] - P.xy[2 * k + 1]};
       Obs2 w = weight_of(P, k);
       B.cost += wnorm2(w, v);
-      double WA[2][6], WB[2][3], Wv[2];
-      for (int c = 0; c < 6; ++c) {
+      double WA[2][8], WB[2][3], Wv[2];
+      for (int c = 0; c < np; ++c) {
         WA[0][c] = w.w11 * li.A[0][c] + w.w12 * li.A[1][c];
         WA[1][c] = w.w12 * li.A[0][c] + w.w22 * li.A[1][c];
       }
@@ -510,11 +570,11 @@ void build_block(const Problem& P, int l, BlockSystem& B) {
       }
       Wv[0] = w.w11 * v[0] + w.w12 * v[1];
       Wv[1] = w.w12 * v[0] + w.w22 * v[1];
-      double* U = &B.U[(size_t)a * 36];
-      for (int r = 0; r < 6; ++r) {
-        for (int c = 0; c < 6; ++c) U[r * 6 + c] += li.A[0][r] * WA[0][c] + li.A[1][r] * WA[1][c];
-        B.gC[a * 6 + r] += li.A[0][r] * Wv[0] + li.A[1][r] * Wv[1];
-        for (int c = 0; c < 3; ++c) Ys[q][t * 18 + r * 3 + c] = li.A[0][r] * WB[0][c] + li.A[1][r] * WB[1][c];
+      double* U = &B.U[(size_t)a * np * np];
+      for (int r = 0; r < np; ++r) {
+        for (int c = 0; c < np; ++c) U[r * np + c] += li.A[0][r] * WA[0][c] + li.A[1][r] * WA[1][c];
+        B.gC[a * np + r] += li.A[0][r] * Wv[0] + li.A[1][r] * Wv[1];
+        for (int c = 0; c < 3; ++c) Ys[q][(t * np + r) * 3 + c] = li.A[0][r] * WB[0][c] + li.A[1][r] * WB[1][c];
       }
       for (int r = 0; r < 3; ++r) {
         for (int c = 0; c < 3; ++c) V[r][c] += li.B[0][r] * WB[0][c] + li.B[1][r] * WB[1][c];
@@ -535,14 +595,14 @@ void build_block(const Problem& P, int l, BlockSystem& B) {
   }
   // damped camera blocks on the diagonal of S
   for (int a = 0; a < nca; ++a) {
-    double* U = &B.U[(size_t)a * 36];
-    for (int r = 0; r < 6; ++r) {
-      if (U[r * 6 + r] == 0.0) U[r * 6 + r] = 1.0;  // camera without any valid observation: parameter held
-      else U[r * 6 + r] *= (1.0 + lam);
+    double* U = &B.U[(size_t)a * np * np];
+    for (int r = 0; r < np; ++r) {
+      if (U[r * np + r] == 0.0) U[r * np + r] = 1.0;  // camera without any valid observation: parameter held
+      else U[r * np + r] *= (1.0 + lam);
     }
-    for (int r = 0; r < 6; ++r) {
-      for (int c = 0; c < 6; ++c) B.S[(size_t)(6 * a + r) * B.n6 + 6 * a + c] += U[r * 6 + c];
-      B.e[6 * a + r] -= B.gC[a * 6 + r];
+    for (int r = 0; r < np; ++r) {
+      for (int c = 0; c < np; ++c) B.S[(size_t)(np * a + r) * B.n6 + np * a + c] += U[r * np + c];
+      B.e[np * a + r] -= B.gC[a * np + r];
     }
   }
   // outer products of every pair of observations of a copy (Sec. 5.4)
@@ -552,18 +612,18 @@ void build_block(const Problem& P, int l, BlockSystem& B) {
     const double* gx = &B.gX[q * 3];
     size_t m = cp.obs.size();
     for (size_t t1 = 0; t1 < m; ++t1) {
-      const double* Y1 = &Ys[q][t1 * 18];
+      const double* Y1 = &Ys[q][t1 * np * 3];
       int a1 = P.cam_local[P.ocam[cp.obs[t1]]];
-      double Z[6][3];  // Z = Y1 V*^-1
-      for (int r = 0; r < 6; ++r)
+      double Z[8][3];  // Z = Y1 V*^-1
+      for (int r = 0; r < np; ++r)
         for (int c = 0; c < 3; ++c) Z[r][c] = Y1[r * 3 + 0] * Vi[0 * 3 + c] + Y1[r * 3 + 1] * Vi[1 * 3 + c] + Y1[r * 3 + 2] * Vi[2 * 3 + c];
-      for (int r = 0; r < 6; ++r) B.e[6 * a1 + r] += Z[r][0] * gx[0] + Z[r][1] * gx[1] + Z[r][2] * gx[2];
+      for (int r = 0; r < np; ++r) B.e[np * a1 + r] += Z[r][0] * gx[0] + Z[r][1] * gx[1] + Z[r][2] * gx[2];
       for (size_t t2 = 0; t2 < m; ++t2) {
-        const double* Y2 = &Ys[q][t2 * 18];
+        const double* Y2 = &Ys[q][t2 * np * 3];
         int a2 = P.cam_local[P.ocam[cp.obs[t2]]];
-        for (int r = 0; r < 6; ++r)
-          for (int c = 0; c < 6; ++c)
-            B.S[(size_t)(6 * a1 + r) * B.n6 + 6 * a2 + c] -= Z[r][0] * Y2[c * 3 + 0] + Z[r][1] * Y2[c * 3 + 1] + Z[r][2] * Y2[c * 3 + 2];
+        for (int r = 0; r < np; ++r)
+          for (int c = 0; c < np; ++c)
+            B.S[(size_t)(np * a1 + r) * B.n6 + np * a2 + c] -= Z[r][0] * Y2[c * 3 + 0] + Z[r][1] * Y2[c * 3 + 1] + Z[r][2] * Y2[c * 3 + 2];
       }
     }
   }
@@ -578,7 +638,7 @@ void back_substitute(const Problem& P, int l, const BlockSystem& B, const std::v
     for (int k : cp.obs) {
       int a = P.cam_local[P.ocam[k]];
       Lin li;
-      linearise(P.cams[P.ocam[k]], cp.X, P.f, P.cx, P.cy, li);
+      lin_obs(P, k, cp.X, li);
       Obs2 w = weight_of(P, k);
       double WB[2][3];
       for (int c = 0; c < 3; ++c) {
@@ -587,7 +647,7 @@ void back_substitute(const Problem& P, int l, const BlockSystem& B, const std::v
       }
       for (int c = 0; c < 3; ++c) {
         double s = 0;
-        for (int r = 0; r < 6; ++r) s += (li.A[0][r] * WB[0][c] + li.A[1][r] * WB[1][c]) * dC[6 * a + r];
+        for (int r = 0; r < B.np; ++r) s += (li.A[0][r] * WB[0][c] + li.A[1][r] * WB[1][c]) * dC[B.np * a + r];
         rhs[c] -= s;
       }
     }
@@ -599,15 +659,20 @@ void back_substitute(const Problem& P, int l, const BlockSystem& B, const std::v
 
 void apply_update(Problem& P, int l, const BlockSystem& B, const std::vector<double>& dC, const std::vector<double>& dX) {
   const std::vector<int>& cams = P.blk_cams[l];
+  const int np = B.np;
   for (size_t a = 0; a < cams.size(); ++a) {
     Cam& cm = P.cams[cams[a]];
-    double w[3] = {dC[6 * a], dC[6 * a + 1], dC[6 * a + 2]}, Rw[3][3], Rn[3][3];
+    double w[3] = {dC[np * a], dC[np * a + 1], dC[np * a + 2]}, Rw[3][3], Rn[3][3];
     rodrigues(w, Rw);
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) Rn[r][c] = Rw[r][0] * cm.R[0][c] + Rw[r][1] * cm.R[1][c] + Rw[r][2] * cm.R[2][c];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) cm.R[r][c] = Rn[r][c];
-    for (int r = 0; r < 3; ++r) cm.C[r] += dC[6 * a + 3 + r];
+    for (int r = 0; r < 3; ++r) cm.C[r] += dC[np * a + 3 + r];
+    if (np == 8) {  // intrinsics: additive updates
+      cm.f += dC[np * a + 6];
+      cm.k1 += dC[np * a + 7];
+    }
   }
   for (int q = 0; q < B.nc; ++q) {
     Copy& cp = P.copies[B.cps[q]];
@@ -893,6 +958,26 @@ void orc_set_cameras(orc_problem* h, const double* cam_R, const double* cam_C) {
   }
 }
 
+// Intrinsics (Sec. 6, the Final data sets): every camera gets its own focal
+// length f [M] and radial distortion k1 [M], estimated with its pose from now
+// on (8 parameters per camera).
+void orc_set_intrinsics(orc_problem* h, const double* f, const double* k1) {
+  Problem& P = h->P;
+  P.ncp = 8;
+  for (int i = 0; i < P.M; ++i) {
+    P.cams[i].f = f[i];
+    P.cams[i].k1 = k1[i];
+  }
+}
+
+void orc_get_intrinsics(orc_problem* h, double* f, double* k1) {
+  Problem& P = h->P;
+  for (int i = 0; i < P.M; ++i) {
+    f[i] = P.ncp == 8 ? P.cams[i].f : P.f;
+    k1[i] = P.ncp == 8 ? P.cams[i].k1 : 0.0;
+  }
+}
+
 void orc_get_points(orc_problem* h, double* pts) {
   Problem& P = h->P;
   for (int j = 0; j < P.N; ++j)
@@ -966,8 +1051,9 @@ void orc_get_residuals(orc_problem* h, double* res /*[2][K]*/) {
   }
 }
 
-// Dense RCS and right-hand side of sub-block l at the current state (n6 x n6
-// row-major, both triangles).  Returns n6, or -1 if a point block is singular.
+// Dense RCS and right-hand side of sub-block l at the current state (n6 x n6,
+// n6 = parameters per camera x cameras; row-major, both triangles).  Returns
+// n6, or -1 if a point block is singular.
 int orc_block_rcs(orc_problem* h, int l, double* S, double* e) {
   BlockSystem B;
   build_block(h->P, l, B);
@@ -977,7 +1063,7 @@ int orc_block_rcs(orc_problem* h, int l, double* S, double* e) {
   return B.n6;
 }
 
-// The Schur-path step of sub-block l without applying it: dC [6 n_l], dX for
+// The Schur-path step of sub-block l without applying it: dC [np n_l], dX for
 // the block's valid copies in (point) order [3 nc].  Returns nc, or <0.
 int orc_block_step(orc_problem* h, int l, double* dC_out, double* dX_out) {
   Problem& P = h->P;
@@ -996,7 +1082,8 @@ int orc_block_step(orc_problem* h, int l, double* dC_out, double* dX_out) {
 
 // Covariances from the normal equations of every sub-block (Sec. 2: the
 // inverse of N through the Schur complement), with damping lam in place of
-// lambda.  cam_cov [M][6][6] (row-major, caller order): the camera's diagonal
+// lambda.  cam_cov [M][np][np] (np = 6, or 8 with intrinsics; row-major, caller
+// order): the camera's diagonal
 // block of M_CC = S^-1 of its sub-block.  copy_cov [n_copies][6] (xx, xy, xz,
 // yy, yz, zz): M_XX = V^-1 + V^-1 (sum_{i,k} Y_i^T M_ik Y_k) V^-1 of the copy,
 // V its damped point block (with the tie-point weight), Y_i the N_CX block of
@@ -1028,10 +1115,12 @@ int orc_covariance(orc_problem* h, double lam, double* cam_cov, double* copy_cov
       for (int r = 0; r < n; ++r) Minv[(size_t)r * n + c] = col[r];
     }
     const std::vector<int>& cams = P.blk_cams[l];
+    const int np = B.np;
     if (cam_cov)
       for (size_t a = 0; a < cams.size(); ++a)
-        for (int r = 0; r < 6; ++r)
-          for (int c = 0; c < 6; ++c) cam_cov[(size_t)cams[a] * 36 + r * 6 + c] = Minv[(6 * a + r) * n + 6 * a + c];
+        for (int r = 0; r < np; ++r)
+          for (int c = 0; c < np; ++c)
+            cam_cov[(size_t)cams[a] * np * np + r * np + c] = Minv[(np * a + r) * n + np * a + c];
     if (!copy_cov) continue;
     for (int q = 0; q < B.nc; ++q) {
       const int id = B.cps[q];
@@ -1041,14 +1130,14 @@ int orc_covariance(orc_problem* h, double lam, double* cam_cov, double* copy_cov
       const size_t m = cp.obs.size();
       for (size_t t1 = 0; t1 < m; ++t1)
         for (size_t t2 = 0; t2 < m; ++t2) {
-          const double* Y1 = &B.Y[q][t1 * 18];
-          const double* Y2 = &B.Y[q][t2 * 18];
+          const double* Y1 = &B.Y[q][t1 * np * 3];
+          const double* Y2 = &B.Y[q][t2 * np * 3];
           const int a1 = P.cam_local[P.ocam[cp.obs[t1]]], a2 = P.cam_local[P.ocam[cp.obs[t2]]];
           for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) {
               double s = 0.0;
-              for (int u = 0; u < 6; ++u)
-                for (int v = 0; v < 6; ++v) s += Y1[u * 3 + r] * Minv[(size_t)(6 * a1 + u) * n + 6 * a2 + v] * Y2[v * 3 + c];
+              for (int u = 0; u < np; ++u)
+                for (int v = 0; v < np; ++v) s += Y1[u * 3 + r] * Minv[(size_t)(np * a1 + u) * n + np * a2 + v] * Y2[v * 3 + c];
               Tm[r][c] += s;
             }
         }
@@ -1102,6 +1191,25 @@ void orc_linearise(const double* R9, const double* C3, const double* X3, double 
   g2[1] = li.g[1];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 6; ++c) A12[r * 6 + c] = li.A[r][c];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c) B6[r * 3 + c] = li.B[r][c];
+}
+
+// the same with the camera's own f and k1: A16 is dg/d(w, C, f, k1) (2x8)
+void orc_linearise_cal(const double* R9, const double* C3, const double* X3, double f, double k1, double cx,
+                       double cy, double* g2, double* A16, double* B6) {
+  Cam cm;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) cm.R[r][c] = R9[r * 3 + c];
+  for (int r = 0; r < 3; ++r) cm.C[r] = C3[r];
+  cm.f = f;
+  cm.k1 = k1;
+  Lin li;
+  linearise_cal(cm, X3, cx, cy, li);
+  g2[0] = li.g[0];
+  g2[1] = li.g[1];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 8; ++c) A16[r * 8 + c] = li.A[r][c];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 3; ++c) B6[r * 3 + c] = li.B[r][c];
 }

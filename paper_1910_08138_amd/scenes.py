@@ -181,6 +181,12 @@ class Scene:
     pts_true: np.ndarray
     outlier: np.ndarray | None = None   # (K,) bool, gross errors injected
     meta: dict = field(default_factory=dict)
+    # intrinsics estimated per camera (focal length f and radial distortion
+    # k1 of the normalised image coordinates), None for calibrated scenes
+    cam_f: np.ndarray | None = None     # (M,) initial
+    cam_k1: np.ndarray | None = None    # (M,) initial
+    cam_f_true: np.ndarray | None = None
+    cam_k1_true: np.ndarray | None = None
 
     @property
     def M(self):
@@ -535,6 +541,42 @@ def add_gross_errors(scene: Scene, frac: float, seed: int, lo: float = 15.0, hi:
     out = np.zeros(scene.K, dtype=bool) if scene.outlier is None else scene.outlier.copy()
     out[idx] = True
     return dataclasses.replace(scene, obs_xy=np.ascontiguousarray(xy), outlier=out)
+
+
+def render_distorted(R: np.ndarray, C: np.ndarray, X: np.ndarray, f: np.ndarray, k1: np.ndarray):
+    """Forward model with per-observation focal length f (n,) and radial
+    distortion k1 (n,) of the normalised coordinates q = p12 / p3:
+    pixel f (1 + k1 |q|^2) q + (CX, CY)."""
+    d = X - C
+    p = np.einsum("nij,nj->ni", R, d)
+    qx, qy = p[:, 0] / p[:, 2], p[:, 1] / p[:, 2]
+    s = f * (1.0 + k1 * (qx * qx + qy * qy))
+    return s * qx + CX, s * qy + CY
+
+
+def with_intrinsics(scene: Scene, seed: int, f_rel: float = 0.02, k1_max: float = 0.1,
+                    f_start_rel: float = 0.005) -> Scene:
+    """A copy of the scene whose cameras have their own focal length and
+    radial distortion, as in the paper's Final data sets (f and k1 per camera,
+    Sec. 6).  True values: f = F_PX (1 + f_rel N(0, 1)), k1 ~ U(-k1_max,
+    k1_max).  The observations are rendered again with them, keeping the
+    scene's noise (and gross errors); start values: f off by f_start_rel
+    N(0, 1) relative, k1 = 0."""
+    import dataclasses
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 104729]))
+    M = scene.M
+    f_true = F_PX * (1.0 + f_rel * rng.normal(size=M))
+    k1_true = rng.uniform(-k1_max, k1_max, size=M)
+    f0 = f_true * (1.0 + f_start_rel * rng.normal(size=M))
+    Rt = scene.cam_R_true.reshape(-1, 3, 3)[scene.obs_cam]
+    Ct = scene.cam_C_true.T[scene.obs_cam]
+    Xt = scene.pts_true.T[scene.obs_pt]
+    u0, v0, _ = render(Rt, Ct, Xt)
+    u1, v1 = render_distorted(Rt, Ct, Xt, f_true[scene.obs_cam], k1_true[scene.obs_cam])
+    xy = scene.obs_xy + np.stack([u1 - u0, v1 - v0])
+    return dataclasses.replace(scene, name=scene.name + "+intrinsics", obs_xy=np.ascontiguousarray(xy),
+                               cam_f=np.ascontiguousarray(f0), cam_k1=np.zeros(M),
+                               cam_f_true=f_true, cam_k1_true=k1_true)
 
 
 def harvest_partition(scene: Scene, seed: int) -> Scene:
