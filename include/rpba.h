@@ -115,6 +115,8 @@ typedef struct {
   const int32_t *obs_cam;    /* HOST [K] camera of each observation, in [0, M) */
   const int32_t *obs_pt;     /* HOST [K] point of each observation, in [0, N) */
   const int32_t *cam_block;  /* HOST [M] sub-block of each camera, in [0, L) */
+  double *cam_intr;          /* [2][M] (f, k1) of every camera (SoA) when opt->intrinsics = 1, else ignored (may be
+                                NULL); same ownership as cam_R */
 } rpba_problem_desc;
 
 typedef struct {
@@ -147,6 +149,12 @@ typedef struct {
   double lambda_down;    /* adaptive: divisor after an accepted step: 10 */
   double lambda_min;     /* adaptive: bounds of lambda: 1e-12 */
   double lambda_max;     /*   : 1e8 */
+  int32_t intrinsics;    /* 1: every camera has its own focal length f and first radial distortion parameter k1,
+                            estimated with its pose (Sec. 6, the n (6 + 2) camera parameters of the Final data
+                            sets): pixel f (1 + k1 |q|^2) q + (cx, cy) with q = (p1/p3, p2/p3), start values in
+                            desc->cam_intr, desc->f unused, 8 rows of the reduced camera system per camera.
+                            Needs RPBA_SOLVER_CHOL and RPBA_VARIANT_EXTENDED (RPBA_ERR_ARG otherwise).  0: the
+                            shared pinhole desc->f: 0 */
 } rpba_options;
 
 /* Fill *opt with the defaults listed above.  HOST pointer. */
@@ -179,7 +187,8 @@ rpba_status rpba_create(const rpba_problem_desc *desc, const rpba_options *opt, 
  *   cov    [6][N] (xx, xy, xz, yy, yz, zz) or NULL
  *   status [N] RPBA_PT_* or NULL
  *   stats  [4]: weighted cost sum v^T W v, sigma0 [px] (unit weights,
- *          redundancy 2K_valid - 6M - 3N_valid, eq:sigma0), RMS [px], N_valid;
+ *          redundancy 2K_valid - n_p M - 3N_valid, eq:sigma0, n_p = 6 or 8
+ *          with intrinsics), RMS [px], N_valid;
  *          or NULL
  * Writes Xbar to desc->pts. */
 rpba_status rpba_intersect(rpba_problem *h, double *cov, int32_t *status, double *stats);
@@ -211,9 +220,10 @@ rpba_status rpba_robust_reweight(rpba_problem *h, int32_t mode, double *stats);
  * as the next LM step would take them) the normal equations of every
  * sub-block are assembled with damping `lambda` (N + lambda diag N), the
  * reduced camera system S is factorised and inverted, and
- *   cam_cov  [M][6][6]  DEVICE, row-major, caller camera order: the camera's
- *                       diagonal block of S^-1 (rotation increment, then
- *                       centre), or NULL;
+ *   cam_cov  [M][n_p][n_p] DEVICE, row-major, caller camera order: the
+ *                       camera's diagonal block of S^-1 (rotation increment,
+ *                       centre, with intrinsics f and k1; n_p = 6 or 8), or
+ *                       NULL;
  *   copy_cov [NC][6]    DEVICE, copy order of rpba_get_copies: the point
  *                       block M_XX = V^-1 + V^-1 (sum_{i,k} Y_i^T (S^-1)_ik
  *                       Y_k) V^-1 of the copy (xx, xy, xz, yy, yz, zz), V its
@@ -278,7 +288,8 @@ rpba_status rpba_step_status(rpba_problem *h, int32_t *n_not_spd, int32_t *n_non
  * number of loops still active, or -1 for a NULL array or n < 0. */
 int32_t rpba_ratio_update(int32_t n, const double *cost, double ratio, double *best, uint8_t *grace, uint8_t *active);
 
-/* Consensus exchange (Sec. 5): cameras go back to desc->cam_R / cam_C; every
+/* Consensus exchange (Sec. 5): cameras go back to desc->cam_R / cam_C (and
+ * with intrinsics their f and k1 to desc->cam_intr); every
  * point's start value for the next intersection is the mean of its sub-block
  * copies (eq:admm8 form), written to desc->pts.  PLAIN variants also update
  * the copies' dual offsets (eq:admm9); every variant then multiplies rho_t by
@@ -304,7 +315,8 @@ const char *rpba_last_error(void);
  *   the current state (as an LM step would, without solving) and copies S of
  *   sub-block l (n6 x n6 row-major, both triangles: the mirrored lower
  *   triangle for Cholesky sub-blocks, the stored FP32 blocks for iterative
- *   ones) and e; n6 = 6 cameras of l, cameras in ascending original index
+ *   ones) and e; n6 = n_p cameras of l (n_p = 6, or 8 with intrinsics),
+ *   cameras in ascending original index
  *   (the library orders the cameras of a sub-block by its own rule and
  *   reorders the copy).
  * rpba_block_cameras: number of cameras of sub-block l. */
@@ -331,7 +343,7 @@ rpba_status rpba_camera_order(rpba_problem *h, int32_t *cam_orig);
  *       solve, 2 T^3 per tile product below the diagonal and T^3 per product
  *       onto a diagonal tile, plus the forward substitution folded into the
  *       right-hand-side row (2 T^2 per product, T^2 per solve);
- *   [1] the dense count sum over the sub-blocks of (6n)^3/3 + (6n)^2;
+ *   [1] the dense count sum over the sub-blocks of (n_p n)^3/3 + (n_p n)^2;
  *   [2] the FP64 matrix-core operations the persistent launch issues: 2 T^3
  *       per tile product and panel solve (right-hand-side row included) and
  *       the 16 x 16 block products inside every diagonal tile. */

@@ -55,6 +55,7 @@ class ProblemDesc(ctypes.Structure):
         ("cam_R", ctypes.c_void_p), ("cam_C", ctypes.c_void_p), ("pts", ctypes.c_void_p),
         ("obs_xy", ctypes.c_void_p), ("obs_info", ctypes.c_void_p),
         ("obs_cam", ctypes.c_void_p), ("obs_pt", ctypes.c_void_p), ("cam_block", ctypes.c_void_p),
+        ("cam_intr", ctypes.c_void_p),
     ]
 
 
@@ -69,6 +70,7 @@ class Options(ctypes.Structure):
         ("rho", ctypes.c_double), ("rho_growth", ctypes.c_double), ("filter_px", ctypes.c_double),
         ("covariance", ctypes.c_int32), ("damping", ctypes.c_int32), ("lambda_up", ctypes.c_double),
         ("lambda_down", ctypes.c_double), ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
+        ("intrinsics", ctypes.c_int32),
     ]
 
 
@@ -253,6 +255,9 @@ class Problem:
     """One problem on the GPU: device state tensors, workspace, handle."""
 
     def __init__(self, scene, device="cuda", obs_info=None, **opts):
+        """A scene with cam_f / cam_k1 (scenes.with_intrinsics) is adjusted
+        with its intrinsics (options intrinsics=1, solver Cholesky) unless
+        intrinsics=0 is given."""
         import torch
         self.torch = torch
         L = load_library()
@@ -269,6 +274,13 @@ class Problem:
         self._obs_cam = np.ascontiguousarray(scene.obs_cam, dtype=np.int32)
         self._obs_pt = np.ascontiguousarray(scene.obs_pt, dtype=np.int32)
         self._cam_block = np.ascontiguousarray(scene.cam_block, dtype=np.int32)
+        if getattr(scene, "cam_f", None) is not None and "intrinsics" not in opts:
+            opts["intrinsics"] = 1
+        self.np = 8 if opts.get("intrinsics", 0) else 6
+        self.cam_intr = None
+        if self.np == 8:
+            self.cam_intr = torch.as_tensor(np.ascontiguousarray(np.stack([scene.cam_f, scene.cam_k1])),
+                                            dtype=f64).to(dev)
         d = ProblemDesc()
         d.M, d.N, d.K, d.L = self.M, self.N, self.K, self.L
         d.f, d.cx, d.cy, d.sigma_px = scene.f, scene.cx, scene.cy, scene.sigma_px
@@ -278,6 +290,7 @@ class Problem:
         d.obs_cam = self._obs_cam.ctypes.data
         d.obs_pt = self._obs_pt.ctypes.data
         d.cam_block = self._cam_block.ctypes.data
+        d.cam_intr = None if self.cam_intr is None else self.cam_intr.data_ptr()
         self.desc = d
         self.opt = default_options(**opts)
         nbytes = ctypes.c_size_t(0)
@@ -353,11 +366,12 @@ class Problem:
         return self.rob_stats
 
     def covariance(self, lam=1e-6):
-        """(camera covariances [M][6][6] caller order, copy covariances
-        [n_copies][6] in copies() order) of the sub-block systems damped by
-        lam (rpba_covariance; the handle needs covariance=1)."""
+        """(camera covariances [M][np][np] caller order (np = 6, or 8 with
+        intrinsics), copy covariances [n_copies][6] in copies() order) of the
+        sub-block systems damped by lam (rpba_covariance; the handle needs
+        covariance=1)."""
         torch = self.torch
-        cc = torch.zeros((self.M, 6, 6), dtype=torch.float64, device=self.dev)
+        cc = torch.zeros((self.M, self.np, self.np), dtype=torch.float64, device=self.dev)
         n = int(self.L_.rpba_num_copies(self.h))
         xc = torch.zeros((n, 6), dtype=torch.float64, device=self.dev)
         self._order()
@@ -406,14 +420,14 @@ class Problem:
         return blk, pt, X, om
 
     def block_rcs(self, l):
-        n6 = 6 * int(self.L_.rpba_block_cameras(self.h, l))
+        n6 = self.np * int(self.L_.rpba_block_cameras(self.h, l))
         S = np.zeros((n6, n6))
         e = np.zeros(n6)
         _check(self.L_.rpba_get_block_rcs(self.h, l, S.ctypes.data, e.ctypes.data), "rpba_get_block_rcs")
         return S, e
 
     def block_solution(self, l):
-        n6 = 6 * int(self.L_.rpba_block_cameras(self.h, l))
+        n6 = self.np * int(self.L_.rpba_block_cameras(self.h, l))
         x = np.zeros(n6)
         _check(self.L_.rpba_get_block_solution(self.h, l, x.ctypes.data), "rpba_get_block_solution")
         return x
@@ -475,6 +489,15 @@ class Problem:
     def cameras(self):
         self.stream.synchronize()
         return self.cam_R.cpu().numpy(), self.cam_C.cpu().numpy()
+
+    def intrinsics(self):
+        """(f [M], k1 [M]) as the last rpba_consensus wrote them (with
+        intrinsics), else the shared f and zeros."""
+        self.stream.synchronize()
+        if self.cam_intr is None:
+            return np.full(self.M, self.desc.f), np.zeros(self.M)
+        a = self.cam_intr.cpu().numpy()
+        return a[0].copy(), a[1].copy()
 
     def points(self):
         self.stream.synchronize()

@@ -15,6 +15,7 @@
 
 #include "../../include/rpba.h"
 #include "../../include/rpba_testing.h"
+#include "rpba_device.hpp"
 #include "rpba_internal.hpp"
 #include "rpba_plan.hpp"
 
@@ -60,7 +61,7 @@ struct WsMap {
       pm_pos, pm_cam, iwg_cam_off, iwg_cams, pm_xy, pm_w, cam_obs_c, df_tasks, df_flags,
       df_ctl, blk_fresh, dfb_tasks, dfb_flags, cm_xy, cm_rw, rw_unit, cm_info, blk_nc, chk, rec_valid, rho_t, Xt, covY,
       lam_blk, blk_rej, XcOld;
-  size_t cam, camN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons, cons_part, int_part, upd_part,
+  size_t cam, camN, intr, intrN, P0, Xbar, pxs, covi, status, xy, info, rw, res, Xc, Om, cpk, S, Ld, Li, y, ys, x, acc_int, acc_blk, acc_cons, cons_part, int_part, upd_part,
       acc_rob;
   size_t total;
 };
@@ -160,8 +161,10 @@ WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov, bool adapti
   m.cm_rw = L.add(f8 * P.K);
   m.rw_unit = L.add(4);
   m.cm_info = L.add(P.has_info ? f8 * 3 * P.K : 0);
-  m.cam = L.add(f8 * 12 * P.M);
-  m.camN = L.add(f8 * 12 * P.M);
+  m.cam = L.add(f8 * CAM_STRIDE * P.M);
+  m.camN = L.add(f8 * CAM_STRIDE * P.M);
+  m.intr = L.add(P.np == 8 ? f8 * 2 * P.M : 0);  // (f, k1) per camera with intrinsics
+  m.intrN = L.add(P.np == 8 ? f8 * 2 * P.M : 0);
   m.P0 = L.add(f8 * 3 * P.N);
   m.Xbar = L.add(f8 * 3 * P.N);
   m.pxs = L.add(f8 * 4 * P.N);
@@ -198,8 +201,9 @@ std::shared_ptr<Plan> g_last_plan;
 
 rpba_status get_plan(const rpba_problem_desc* d, const rpba_options* o, std::shared_ptr<Plan>& out) {
   int tile = o->chol_tile == 0 ? 64 : o->chol_tile;
+  const int np = o->intrinsics ? 8 : 6;
   if (!d->obs_cam || !d->obs_pt || !d->cam_block) return fail(RPBA_ERR_ARG, "topology arrays must be non-NULL");
-  uint64_t key = topology_key(d->M, d->N, d->K, d->L, d->obs_cam, d->obs_pt, d->cam_block, tile);
+  uint64_t key = topology_key(d->M, d->N, d->K, d->L, d->obs_cam, d->obs_pt, d->cam_block, tile, np);
   {
     std::lock_guard<std::mutex> g(g_plan_mu);
     if (g_last_plan && g_last_plan->key == key) {
@@ -209,7 +213,7 @@ rpba_status get_plan(const rpba_problem_desc* d, const rpba_options* o, std::sha
     }
   }
   auto P = std::make_shared<Plan>();
-  std::string err = build_plan(d->M, d->N, d->K, d->L, d->obs_cam, d->obs_pt, d->cam_block, tile, *P);
+  std::string err = build_plan(d->M, d->N, d->K, d->L, d->obs_cam, d->obs_pt, d->cam_block, tile, np, *P);
   if (!err.empty()) return fail(RPBA_ERR_ARG, err);
   P->has_info = d->obs_info != nullptr;
   {
@@ -222,8 +226,14 @@ rpba_status get_plan(const rpba_problem_desc* d, const rpba_options* o, std::sha
 
 rpba_status check_desc(const rpba_problem_desc* d, const rpba_options* o) {
   if (!d || !o) return fail(RPBA_ERR_ARG, "desc and options must be non-NULL");
-  if (!(d->f > 0) || !std::isfinite(d->f) || !std::isfinite(d->cx) || !std::isfinite(d->cy))
+  if (o->intrinsics != 0 && o->intrinsics != 1) return fail(RPBA_ERR_ARG, "intrinsics must be 0 or 1");
+  if ((!o->intrinsics && (!(d->f > 0) || !std::isfinite(d->f))) || !std::isfinite(d->cx) || !std::isfinite(d->cy))
     return fail(RPBA_ERR_ARG, "intrinsics must be finite, f > 0");
+  if (o->intrinsics) {
+    if (!d->cam_intr) return fail(RPBA_ERR_ARG, "intrinsics = 1 needs desc->cam_intr");
+    if (o->solver != RPBA_SOLVER_CHOL) return fail(RPBA_ERR_ARG, "intrinsics = 1 needs RPBA_SOLVER_CHOL");
+    if (o->variant != RPBA_VARIANT_EXTENDED) return fail(RPBA_ERR_ARG, "intrinsics = 1 needs RPBA_VARIANT_EXTENDED");
+  }
   if (!d->obs_info && !(d->sigma_px > 0)) return fail(RPBA_ERR_ARG, "sigma_px must be > 0 without obs_info");
   if (!d->cam_R || !d->cam_C || !d->pts || !d->obs_xy) return fail(RPBA_ERR_ARG, "state and observation arrays must be non-NULL");
   if (o->precision != RPBA_FP64 && o->precision != RPBA_MIXED) return fail(RPBA_ERR_ARG, "unknown precision");
@@ -399,6 +409,7 @@ rpba_status rpba_default_options(rpba_options* o) {
   o->lambda_down = 10.0;
   o->lambda_min = 1e-12;
   o->lambda_max = 1e8;
+  o->intrinsics = 0;
   return RPBA_OK;
 }
 
@@ -479,7 +490,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   {
     // camera-pair blocks by the number of rounds of a lane group, most first
     // (the plan orders them for 8 lanes; the order stays stable inside a class)
-    const int G = o->pair_lanes == 0 ? 8 : o->pair_lanes;
+    // (with intrinsics the pair pass always takes eight lanes per block)
+    const int G = o->pair_lanes == 0 || o->intrinsics ? 8 : o->pair_lanes;
     std::vector<int32_t> od = p.od_pb;
     auto rounds = [&](int32_t q) { return (p.pb_ent_off[q + 1] - p.pb_ent_off[q] + G - 1) / G; };
     if (G != 8) std::stable_sort(od.begin(), od.end(), [&](int32_t a, int32_t b) { return rounds(a) > rounds(b); });
@@ -598,6 +610,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.L = p.L;
   D.NC = p.NC;
   D.T = p.T;
+  D.np = p.np;
   D.int_maxit = o->int_maxit;
   D.has_info = p.has_info ? 1 : 0;
   D.down_weight = o->down_weight;
@@ -610,6 +623,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.int_tol = o->int_tol;
   D.u_camR = d->cam_R;
   D.u_camC = d->cam_C;
+  D.u_intr = o->intrinsics ? d->cam_intr : nullptr;
   D.u_pts = d->pts;
   D.u_xy = d->obs_xy;
   D.u_info = d->obs_info;
@@ -617,6 +631,8 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   auto F = [&](size_t off) { return (double*)(w + off); };
   D.cam = F(m.cam);
   D.camN = F(m.camN);
+  D.intr = p.np == 8 ? F(m.intr) : nullptr;
+  D.intrN = p.np == 8 ? F(m.intrN) : nullptr;
   D.cam_blk = I(m.cam_blk);
   D.blk_cam_off = I(m.blk_cam_off);
   D.cam_orig = I(m.cam_orig);
@@ -668,7 +684,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   D.pb_ent = I(m.pb_ent);
   D.od_pb = I(m.od_pb);
   D.n_od = (int64_t)p.od_pb.size();
-  D.pb_lanes = o->pair_lanes == 0 ? 8 : o->pair_lanes;
+  D.pb_lanes = o->pair_lanes == 0 || o->intrinsics ? 8 : o->pair_lanes;
   D.pb_bsr = I(m.pb_bsr);
   D.pb_bsr_t = I(m.pb_bsr_t);
   D.blk_pcg = (const uint8_t*)(w + m.blk_pcg);
@@ -720,7 +736,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
     HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (hc[0] || hc[1])
-      return fail(RPBA_ERR_ARG, std::to_string(hc[0]) + " non-finite input values (cam_R, cam_C, pts, obs_xy, obs_info), " +
+      return fail(RPBA_ERR_ARG, std::to_string(hc[0]) + " non-finite input values (cam_R, cam_C, cam_intr, pts, obs_xy, obs_info), " +
                                     std::to_string(hc[1]) + " obs_info matrices not positive definite");
   }
   // packing kernels, zero state, identity padding
@@ -1062,7 +1078,8 @@ rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e)
   if (!h->intersected) return fail(RPBA_ERR_STATE, "rpba_intersect must run first");
   rpba_status s = assemble(h, nullptr);
   if (s != RPBA_OK) return s;
-  int n6 = 6 * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
+  const int np = p.np;
+  int n6 = np * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
   // stage through the x / ys vectors is not possible for a full matrix: use
   // the Ld array (free outside a step) when large enough, else the cpk array
   size_t need = (size_t)n6 * n6 + n6;
@@ -1089,7 +1106,7 @@ rpba_status rpba_get_block_rcs(rpba_problem* h, int32_t l, double* S, double* e)
     for (int r = 0; r < n6; ++r)
       for (int c = r + 1; c < n6; ++c) Si[(size_t)r * n6 + c] = Si[(size_t)c * n6 + r];
   const std::vector<int32_t> rank = block_caller_rank(p, l);
-  auto to = [&](int r) { return 6 * rank[r / 6] + r % 6; };
+  auto to = [&](int r) { return np * rank[r / np] + r % np; };
   if (S)
     for (int r = 0; r < n6; ++r)
       for (int c = 0; c < n6; ++c) S[(size_t)to(r) * n6 + to(c)] = Si[(size_t)r * n6 + c];
@@ -1102,12 +1119,13 @@ rpba_status rpba_get_block_solution(rpba_problem* h, int32_t l, double* x) {
   if (!h) return fail(RPBA_ERR_ARG, "NULL handle");
   const Plan& p = *h->plan;
   if (l < 0 || l >= p.L) return fail(RPBA_ERR_ARG, "sub-block out of range");
-  int n6 = 6 * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
+  const int np = p.np;
+  int n6 = np * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
   HIP_TRY(hipStreamSynchronize(h->stream));
   std::vector<double> xi(n6);
   HIP_TRY(hipMemcpy(xi.data(), h->d.x + p.vec_off[l], 8 * (size_t)n6, hipMemcpyDeviceToHost));
   const std::vector<int32_t> rank = block_caller_rank(p, l);
-  for (int r = 0; r < n6; ++r) x[6 * rank[r / 6] + r % 6] = xi[r];
+  for (int r = 0; r < n6; ++r) x[np * rank[r / np] + r % np] = xi[r];
   return RPBA_OK;
 }
 
@@ -1137,7 +1155,7 @@ rpba_status rpba_factor_flops(rpba_problem* h, double* out) {
   double alg = 0.0, dense = 0.0, mfma = 0.0;
   for (int l = 0; l < p.L; ++l) {
     if (h->blk_pcg[l]) continue;
-    const double n6 = 6.0 * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
+    const double n6 = (double)p.np * (p.blk_cam_off[l + 1] - p.blk_cam_off[l]);
     dense += n6 * n6 * n6 / 3.0 + n6 * n6;
     const int nt = p.nt[l];
     const uint8_t* z = p.tile_nz.data() + p.rcs_off[l] / ((int64_t)p.T * p.T);

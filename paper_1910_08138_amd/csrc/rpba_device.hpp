@@ -8,14 +8,25 @@
 //   dg/dC            = -B
 // The camera Jacobian A (2x6) is [Ar | -B] with parameter order
 // (rotation x, y, z, centre x, y, z).
+//
+// With intrinsics (Sec. 6: the focal length f and the first radial
+// distortion parameter k1 of every camera estimated with its pose) the pixel
+// is f (1 + k1 r2) q + c with q = (u, w), r2 = |q|^2.  With M = (1 + k1 r2) I
+// + 2 k1 q q^T, B and Ar are those of the pinhole with the camera's f,
+// multiplied by M on the left, and A gains the columns dg/df = (1 + k1 r2) q
+// and dg/dk1 = f r2 q: A (2x8) = [Ar | -B | Ai], parameter order (rotation,
+// centre, f, k1).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace rpba {
 
-// camera record in device memory: R (row-major, 9) then C (3)
+// camera record in device memory: R (row-major, 9) then C (3).  With
+// intrinsics the cameras' f and k1 are an array of their own ([M][2]); a
+// kernel that holds a camera in registers appends them at CAM_F, CAM_K1.
 constexpr int CAM_STRIDE = 12;
+constexpr int CAM_F = 12, CAM_K1 = 13;
 
 template <typename T>
 struct Lin {
@@ -23,6 +34,7 @@ struct Lin {
   T z;           // depth p3
   T B[2][3];     // dg/dX
   T Ar[2][3];    // dg/d(rotation increment)
+  T Ai[2][2];    // with intrinsics: dg/df, dg/dk1
 };
 
 // 1 / x: in FP64 the hardware reciprocal estimate refined by two Newton
@@ -66,6 +78,49 @@ __device__ __forceinline__ void linearise_d(const T* __restrict__ R, T d0, T d1,
   o.Ar[1][2] = f * u;
 }
 
+// with intrinsics: the pinhole Jacobians with the camera's f, then the
+// distortion (M on the left) and the two intrinsic columns
+template <typename T>
+__device__ __forceinline__ void distort(Lin<T>& o, T u, T w, T f, T k1) {
+  const T r2 = u * u + w * w, s = T(1) + k1 * r2;
+  const T m00 = s + T(2) * k1 * u * u, m01 = T(2) * k1 * u * w, m11 = s + T(2) * k1 * w * w;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T b0 = o.B[0][c], b1 = o.B[1][c], a0 = o.Ar[0][c], a1 = o.Ar[1][c];
+    o.B[0][c] = m00 * b0 + m01 * b1;
+    o.B[1][c] = m01 * b0 + m11 * b1;
+    o.Ar[0][c] = m00 * a0 + m01 * a1;
+    o.Ar[1][c] = m01 * a0 + m11 * a1;
+  }
+  o.Ai[0][0] = s * u;
+  o.Ai[1][0] = s * w;
+  o.Ai[0][1] = f * r2 * u;
+  o.Ai[1][1] = f * r2 * w;
+}
+
+template <typename T>
+__device__ __forceinline__ void linearise_cal_d(const T* __restrict__ R, T d0, T d1, T d2, T f, T k1, T cx, T cy,
+                                                Lin<T>& o) {
+  linearise_d<T>(R, d0, d1, d2, f, cx, cy, o);
+  const T iz = recip(o.z);
+  const T p0 = R[0] * d0 + R[1] * d1 + R[2] * d2, p1 = R[3] * d0 + R[4] * d1 + R[5] * d2;
+  const T u = p0 * iz, w = p1 * iz, s = T(1) + k1 * (u * u + w * w);
+  o.g0 = f * s * u + cx;
+  o.g1 = f * s * w + cy;
+  distort<T>(o, u, w, f, k1);
+}
+
+// camera record cm (CAM_STRIDE layout) at X: the pinhole with the shared f,
+// or with intrinsics (CAL) the camera's own f and k1 at fk
+template <bool CAL, typename T>
+__device__ __forceinline__ void linearise_cam(const T* __restrict__ cm, const T* __restrict__ fk, const T X[3], T f,
+                                              T cx, T cy, Lin<T>& o) {
+  if constexpr (CAL)
+    linearise_cal_d<T>(cm, X[0] - cm[9], X[1] - cm[10], X[2] - cm[11], fk[0], fk[1], cx, cy, o);
+  else
+    linearise_d<T>(cm, X[0] - cm[9], X[1] - cm[10], X[2] - cm[11], f, cx, cy, o);
+}
+
 template <typename T>
 __device__ __forceinline__ void linearise(const T* __restrict__ R, const T* __restrict__ C, const T X[3], T f,
                                           T cx, T cy, Lin<T>& o) {
@@ -104,6 +159,29 @@ __device__ __forceinline__ void linearise_split(const double* __restrict__ R, co
   o.g0 = (J)g0;
   o.g1 = (J)g1;
   o.z = (J)z;
+}
+
+// the same for a camera record (CAM_STRIDE layout); with intrinsics (CAL)
+// the camera's own f and k1 at fk: projection in FP64, Jacobians in J
+template <bool CAL, typename J>
+__device__ __forceinline__ void linearise_split_cam(const double* __restrict__ cm, const double* __restrict__ fk,
+                                                    const double X[3], double f, double cx, double cy, Lin<J>& o,
+                                                    double& g0, double& g1, double& z) {
+  if constexpr (!CAL) {
+    linearise_split<J>(cm, cm + 9, X, f, cx, cy, o, g0, g1, z);
+  } else {
+    const double fc = fk[0], k1 = fk[1];
+    linearise_split<J>(cm, cm + 9, X, fc, cx, cy, o, g0, g1, z);
+    const double iz = recip(z);
+    const double d0 = X[0] - cm[9], d1 = X[1] - cm[10], d2 = X[2] - cm[11];
+    const double u = (cm[0] * d0 + cm[1] * d1 + cm[2] * d2) * iz, w = (cm[3] * d0 + cm[4] * d1 + cm[5] * d2) * iz;
+    const double s = 1.0 + k1 * (u * u + w * w);
+    g0 = fc * s * u + cx;
+    g1 = fc * s * w + cy;
+    o.g0 = (J)g0;
+    o.g1 = (J)g1;
+    distort<J>(o, (J)u, (J)w, (J)fc, (J)k1);
+  }
 }
 
 // weight matrix of one observation [[a, b], [b, c]]

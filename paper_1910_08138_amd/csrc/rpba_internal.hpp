@@ -16,6 +16,7 @@ struct Dev {
   int32_t M, N, K, L;
   int64_t NC;
   int32_t T;              // Cholesky tile edge
+  int32_t np;             // parameters per camera: 6 (pose), 8 with intrinsics (pose, f, k1)
   int32_t int_maxit;
   int32_t has_info;
   double f, cx, cy, w0;   // w0 = 1 / sigma_px^2
@@ -24,13 +25,16 @@ struct Dev {
   // caller arrays (original order)
   double* u_camR;         // [M][9]
   double* u_camC;         // [3][M]
+  double* u_intr;         // [2][M] (f, k1) with intrinsics, else null
   double* u_pts;          // [3][N]
   const double* u_xy;     // [2][K]
   const double* u_info;   // [3][K] or null
 
   // cameras, internal (sub-block-major) order
-  double* cam;            // [M][12] R row-major, C
-  double* camN;           // [M][12] updated cameras of the current step
+  double* cam;            // [M][CAM_STRIDE] R row-major, C
+  double* camN;           // [M][CAM_STRIDE] updated cameras of the current step
+  double* intr;           // [M][2] (f, k1) with intrinsics, else null
+  double* intrN;          // [M][2] updated intrinsics of the current step, else null
   const int32_t* cam_blk;
   const int32_t* blk_cam_off;
   const int32_t* cam_orig;

@@ -27,14 +27,18 @@ __device__ __forceinline__ W2<double> obs_weight(const Dev& d, int64_t k, bool u
 }
 
 // one observation of a copy (LM order): camera index, pixel, weight and the
-// camera itself from `cams` (the cameras of the step or the updated ones)
+// camera itself from `cams` (the cameras of the step or the updated ones;
+// CAL: with its f and k1)
+template <bool CAL>
 struct CopyObs {
   int cam;
   double x, y;
   W2<double> W;
-  double cm[12];
+  double cm[CAL ? 14 : 12];
 };
-__device__ __forceinline__ void copy_obs(const Dev& d, const double* cams, int64_t k, bool unit, CopyObs& o) {
+template <bool CAL>
+__device__ __forceinline__ void copy_obs(const Dev& d, const double* cams, const double* intrs, int64_t k, bool unit,
+                                         CopyObs<CAL>& o) {
   o.cam = d.obs_cam[k];
   const double2 v = reinterpret_cast<const double2*>(d.xy)[k];
   o.x = v.x;
@@ -47,15 +51,22 @@ __device__ __forceinline__ void copy_obs(const Dev& d, const double* cams, int64
     o.cm[2 * q] = w.x;
     o.cm[2 * q + 1] = w.y;
   }
+  if constexpr (CAL) {
+    const double2 fk = reinterpret_cast<const double2*>(intrs)[o.cam];
+    o.cm[CAM_F] = fk.x;
+    o.cm[CAM_K1] = fk.y;
+  }
 }
 
 // f(observation) over the observations [k0, k1) of a copy, in order (one at
-// a time: a second one in flight costs more occupancy than it hides)
-template <typename F>
-__device__ __forceinline__ void for_copy_obs(const Dev& d, const double* cams, int k0, int k1, bool unit, F&& f) {
+// a time: a second one in flight costs more occupancy than it hides);
+// cameras from `cams` and, with intrinsics, their f and k1 from `intrs`
+template <bool CAL, typename F>
+__device__ __forceinline__ void for_copy_obs(const Dev& d, const double* cams, const double* intrs, int k0, int k1,
+                                             bool unit, F&& f) {
   for (int k = k0; k < k1; ++k) {
-    CopyObs a;
-    copy_obs(d, cams, k, unit, a);
+    CopyObs<CAL> a;
+    copy_obs<CAL>(d, cams, intrs, k, unit, a);
     f(a);
   }
 }
@@ -100,12 +111,14 @@ __global__ void k_gather_obs(Dev d) {
 // information matrices that are not positive definite (w11 > 0, det > 0)
 __global__ void k_check_inputs(Dev d, int32_t* cnt) {
   const int64_t n1 = 9 * (int64_t)d.M, n2 = n1 + 3 * (int64_t)d.M, n3 = n2 + 3 * (int64_t)d.N,
-                n4 = n3 + 2 * (int64_t)d.K, n5 = n4 + (d.u_info ? 3 * (int64_t)d.K : 0);
+                n4 = n3 + 2 * (int64_t)d.K, n5 = n4 + (d.u_info ? 3 * (int64_t)d.K : 0),
+                n6 = n5 + (d.u_intr ? 2 * (int64_t)d.M : 0);
   int bad = 0, npd = 0;
-  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n5; t += (int64_t)gridDim.x * NT) {
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n6; t += (int64_t)gridDim.x * NT) {
     const double v = t < n1 ? d.u_camR[t] : t < n2 ? d.u_camC[t - n1] : t < n3 ? d.u_pts[t - n2]
-                   : t < n4 ? d.u_xy[t - n3] : d.u_info[t - n4];
-    bad += !isfinite(v);
+                   : t < n4 ? d.u_xy[t - n3] : t < n5 ? d.u_info[t - n4] : d.u_intr[t - n5];
+    // (a focal length must be positive as well)
+    bad += !isfinite(v) || (t >= n5 && t < n5 + d.M && !(v > 0.0));
   }
   if (d.u_info)
     for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < d.K; k += (int64_t)gridDim.x * NT) {
@@ -142,6 +155,10 @@ __global__ void k_gather_cams(Dev d) {
   double* c = d.cam + (int64_t)CAM_STRIDE * i;
   for (int q = 0; q < 9; ++q) c[q] = d.u_camR[9 * (int64_t)o + q];
   for (int r = 0; r < 3; ++r) c[9 + r] = d.u_camC[(int64_t)r * d.M + o];
+  if (d.intr) {
+    d.intr[2 * (int64_t)i] = d.u_intr[o];
+    d.intr[2 * (int64_t)i + 1] = d.u_intr[(int64_t)d.M + o];
+  }
 }
 
 __global__ void k_gather_pts(Dev d) {
@@ -167,7 +184,7 @@ __global__ void k_zero_i32(int32_t* p, int64_t n) {
 // identity on the padded rows of the last diagonal tile of every sub-block
 __global__ void k_pad_identity(Dev d) {
   int l = blockIdx.x;
-  int n6 = 6 * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
+  int n6 = d.np * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
   int nt = d.nt[l];
   const int T = d.T;
   for (int r = threadIdx.x; r < T; r += NT) {
@@ -259,8 +276,10 @@ __device__ __forceinline__ void zero_record(const Dev& d, int64_t c) {
 // Omega^l = H - H^(l) of every copy (Sec. 5.1), residuals stored.
 constexpr int IT = INT_WG;  // threads per intersection workgroup
 
+// staged components of a camera: R, C, and with intrinsics its f and k1
+constexpr int STAGE_CM = 14;
 struct Stage {
-  double cams[INT_CAM_CAP * 12];  // component-major: component q of slot s at q * INT_CAM_CAP + s
+  double cams[INT_CAM_CAP * STAGE_CM];  // component-major: component q of slot s at q * INT_CAM_CAP + s
   double2 xy[INT_OBS_CAP];
   int32_t code[INT_OBS_CAP];
 };
@@ -301,12 +320,15 @@ __device__ __forceinline__ ObsHead obs_head(const Dev& d, const Stage& sg, int b
   return o;
 }
 
-__device__ __forceinline__ void obs_cam(const Dev& d, const Stage& sg, int32_t code, double (&cm)[12]) {
+// the camera of an observation code; CAL: with its f and k1 (intrinsics)
+template <bool CAL>
+__device__ __forceinline__ void obs_cam(const Dev& d, const Stage& sg, int32_t code, double (&cm)[CAL ? 14 : 12]) {
+  constexpr int NQ = CAL ? 14 : 12;
   const int f = code & PM_FIELD;
   const bool glb = (code & PM_GLOBAL) != 0;
   const int sl = glb ? 0 : f;
 #pragma unroll
-  for (int q = 0; q < 12; ++q) cm[q] = sg.cams[q * INT_CAM_CAP + sl];
+  for (int q = 0; q < NQ; ++q) cm[q] = sg.cams[q * INT_CAM_CAP + sl];
   if (__builtin_expect(glb, 0)) {
     const double2* g = reinterpret_cast<const double2*>(d.cam + (int64_t)CAM_STRIDE * f);
 #pragma unroll
@@ -315,17 +337,22 @@ __device__ __forceinline__ void obs_cam(const Dev& d, const Stage& sg, int32_t c
       cm[2 * q] = v.x;
       cm[2 * q + 1] = v.y;
     }
+    if constexpr (CAL) {
+      const double2 fk = reinterpret_cast<const double2*>(d.intr)[f];
+      cm[CAM_F] = fk.x;
+      cm[CAM_K1] = fk.y;
+    }
   }
 }
 
-template <bool INFO, bool OLDS>
+template <bool INFO, bool OLDS, bool CAL>
 __device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0, int i, double& x, double& y,
-                                           W2<double>& W, double (&cm)[12]) {
+                                           W2<double>& W, double (&cm)[CAL ? 14 : 12]) {
   const ObsHead o = obs_head<INFO, OLDS>(d, sg, b0, i);
   x = o.x;
   y = o.y;
   W = o.W;
-  obs_cam(d, sg, o.code, cm);
+  obs_cam<CAL>(d, sg, o.code, cm);
   return o.code;
 }
 
@@ -417,7 +444,7 @@ __device__ __forceinline__ void put_pxs(const Dev& d, int j, const double (&X)[3
 // Omega of the copies, and for the plain variants an evaluation at the
 // consensus point instead of Gauss-Newton (no copy records: their copies are
 // never reset)
-template <bool INFO, bool OLDS, int VAR>
+template <bool INFO, bool OLDS, int VAR, bool CAL>
 __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlots& cs, int b0, int j, int want_cov,
                                                 double (&accv)[4]) {
   constexpr bool PLAIN = VAR >= RPBA_VARIANT_PLAIN;
@@ -451,14 +478,14 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         hb = obs_head<INFO, OLDS>(d, sg, b0, min(i0 + 1, i1 - 1));
       }
       for (; i + 1 < i1; i += 2) {
-        double cma[12], cmb[12];
-        obs_cam(d, sg, ha.code, cma);
-        obs_cam(d, sg, hb.code, cmb);
+        double cma[CAL ? 14 : 12], cmb[CAL ? 14 : 12];
+        obs_cam<CAL>(d, sg, ha.code, cma);
+        obs_cam<CAL>(d, sg, hb.code, cmb);
         const ObsHead na = obs_head<INFO, OLDS>(d, sg, b0, min(i + 2, i1 - 1));
         const ObsHead nb = obs_head<INFO, OLDS>(d, sg, b0, min(i + 3, i1 - 1));
         Lin<double> La, Lb;
-        linearise<double>(cma, cma + 9, X, d.f, d.cx, d.cy, La);
-        linearise<double>(cmb, cmb + 9, X, d.f, d.cx, d.cy, Lb);
+        linearise_cam<CAL, double>(cma, cma + CAM_F, X, d.f, d.cx, d.cy, La);
+        linearise_cam<CAL, double>(cmb, cmb + CAM_F, X, d.f, d.cx, d.cy, Lb);
         // a deleted observation (weight 0) neither counts nor fails the point
         if ((!(La.z > 0.0) && ha.W.a > 0.0) || (!(Lb.z > 0.0) && hb.W.a > 0.0)) behind = true;
         add_point_normals<double>(La, ha.W, La.g0 - ha.x, La.g1 - ha.y, h, g);
@@ -467,10 +494,10 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         hb = nb;
       }
       if (i < i1) {  // ha holds the head of observation i
-        double cm[12];
-        obs_cam(d, sg, ha.code, cm);
+        double cm[CAL ? 14 : 12];
+        obs_cam<CAL>(d, sg, ha.code, cm);
         Lin<double> L;
-        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+        linearise_cam<CAL, double>(cm, cm + CAM_F, X, d.f, d.cx, d.cy, L);
         if (!(L.z > 0.0) && ha.W.a > 0.0) behind = true;
         add_point_normals<double>(L, ha.W, L.g0 - ha.x, L.g1 - ha.y, h, g);
       }
@@ -510,11 +537,11 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
       bool behind = false;
       int u = 0;  // copy being summed
       for (int i = i0; i < i1; ++i) {
-        double x, y, cm[12];
+        double x, y, cm[CAL ? 14 : 12];
         W2<double> W;
-        const int32_t code = obs_get<INFO, OLDS>(d, sg, b0, i, x, y, W, cm);
+        const int32_t code = obs_get<INFO, OLDS, CAL>(d, sg, b0, i, x, y, W, cm);
         Lin<double> L;
-        linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+        linearise_cam<CAL, double>(cm, cm + CAM_F, X, d.f, d.cx, d.cy, L);
         const bool live = W.a > 0.0;  // not deleted by the robust step
         if (!(L.z > 0.0) && live) behind = true;
         const double v0 = L.g0 - x, v1 = L.g1 - y;
@@ -673,7 +700,7 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
   }
 }
 
-template <bool INFO, int VAR>
+template <bool INFO, int VAR, bool CAL>
 __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   __shared__ Stage sg;
   __shared__ double sh[4 * (IT / 64)];
@@ -719,12 +746,14 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       ov[u] = gxy[t];
       oc[u] = d.pm_code[b0 + t];
     }
-    double2 cv[CS][6];
+    constexpr int NQ2 = CAL ? 7 : 6;  // double2 per staged camera (with intrinsics its f and k1 last)
+    double2 cv[CS][NQ2];
 #pragma unroll
     for (int u = 0; u < CS; ++u) {
       const double2* g = reinterpret_cast<const double2*>(d.cam + (int64_t)CAM_STRIDE * max(ci[u], 0));
 #pragma unroll
       for (int q = 0; q < 6; ++q) cv[u][q] = g[q];
+      if constexpr (CAL) cv[u][NQ2 - 1] = reinterpret_cast<const double2*>(d.intr)[max(ci[u], 0)];
     }
 #pragma unroll
     for (int u = 0; u < OS; ++u) {
@@ -739,7 +768,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       if (ci[u] >= 0) {
         const int sl = threadIdx.x + u * IT;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
+        for (int q = 0; q < NQ2; ++q) {
           sg.cams[(2 * q) * INT_CAM_CAP + sl] = cv[u][q].x;
           sg.cams[(2 * q + 1) * INT_CAM_CAP + sl] = cv[u][q].y;
         }
@@ -749,7 +778,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
   const int j = j0 + threadIdx.x;
   double accv[4] = {0.0, 0.0, 0.0, 0.0};
   if (nobs <= INT_OBS_CAP) {
-    intersect_point<INFO, true, VAR>(d, sg, cs, b0, j, want_cov, accv);
+    intersect_point<INFO, true, VAR, CAL>(d, sg, cs, b0, j, want_cov, accv);
     // residuals of the workgroup's stream, one coalesced copy (the slots of
     // points left invalid hold their pixels: residuals are only read for
     // valid points), as streaming stores: only a robust re-weighting reads
@@ -762,7 +791,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
       __builtin_nontemporal_store(v.y, &res[t].y);
     }
   } else {
-    intersect_point<INFO, false, VAR>(d, sg, cs, b0, j, want_cov, accv);
+    intersect_point<INFO, false, VAR, CAL>(d, sg, cs, b0, j, want_cov, accv);
   }
   // workgroup sum of the statistics, one partial per value (k_int_reduce
   // adds them up: atomics of every workgroup on the same four words would
@@ -787,7 +816,7 @@ __global__ __launch_bounds__(IT) void k_intersect(Dev d, int want_cov) {
 // 2 K_valid - 6 M - 3 N_valid), RMS reprojection error, valid points
 __device__ void intersect_stats(const Dev& d, double* stats) {
   double cost = d.acc_int[0], sq = d.acc_int[1], kv = d.acc_int[2], nv = d.acc_int[3];
-  double red = 2.0 * kv - 6.0 * d.M - 3.0 * nv;
+  double red = 2.0 * kv - (double)d.np * d.M - 3.0 * nv;
   stats[0] = cost;
   stats[1] = red > 0 ? sqrt(sq / red) : 0.0;
   stats[2] = kv > 0 ? sqrt(sq / (2.0 * kv)) : 0.0;
@@ -838,7 +867,7 @@ __global__ __launch_bounds__(NT) void k_export_pts(Dev d, double* cov, int32_t* 
 // J: arithmetic of the Jacobians and of the per-observation products (FP32
 // on the mixed path, with the projection, the residual and the cost in FP64
 // and the sums added to the FP64 prior before the FP64 inverse).
-template <typename J>
+template <typename J, bool CAL>
 __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
   __shared__ double sh[8];
   __shared__ int l_first, s_skip;
@@ -883,10 +912,11 @@ __global__ __launch_bounds__(NT) void k_copy_prep(Dev d) {
       for (int q = 0; q < 6; ++q) hj[q] = sizeof(J) == 8 ? (J)om[q] : J(0);
       for (int q = 0; q < 3; ++q) gj[q] = sizeof(J) == 8 ? (J)gp[q] : J(0);
       for (int k = k0; k < k1; ++k) {
-        const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
+        const int ic = d.obs_cam[k];
+        const double* cm = d.cam + (int64_t)CAM_STRIDE * ic;
         Lin<J> L;
         double g0, g1, z;
-        linearise_split<J>(cm, cm + 9, X, d.f, d.cx, d.cy, L, g0, g1, z);
+        linearise_split_cam<CAL, J>(cm, CAL ? d.intr + 2 * (int64_t)ic : nullptr, X, d.f, d.cx, d.cy, L, g0, g1, z);
         const double v0 = g0 - d.xy[2 * k], v1 = g1 - d.xy[2 * k + 1];
         const W2<double> W = obs_weight(d, k, unit);
         add_point_normals<J>(L, W2<J>{(J)W.a, (J)W.b, (J)W.c}, (J)v0, (J)v1, hj, gj);
@@ -945,14 +975,24 @@ __global__ void k_cam_update(Dev d) {
     double* n = d.camN + (int64_t)CAM_STRIDE * i;
     const bool act = (d.active == nullptr || d.active[l]) && d.blk_fail[l] == 0;
     if (!act) {
-      for (int q = 0; q < 12; ++q) n[q] = c[q];
+      for (int q = 0; q < CAM_STRIDE; ++q) n[q] = c[q];
+      if (d.intr) {
+        d.intrN[2 * (int64_t)i] = d.intr[2 * (int64_t)i];
+        d.intrN[2 * (int64_t)i + 1] = d.intr[2 * (int64_t)i + 1];
+      }
     } else {
       const int a = i - d.blk_cam_off[l];
-      const double* dx = d.x + d.vec_off[l] + 6 * a;
+      const double* dx = d.x + d.vec_off[l] + d.np * a;
       double w[3] = {dx[0], dx[1], dx[2]};
       rotate_left(w, c, n);
       for (int r = 0; r < 3; ++r) n[9 + r] = c[9 + r] + dx[3 + r];
       for (int q = 0; q < 6; ++q) s2 += dx[q] * dx[q];
+      // intrinsics: f and k1 updated additively
+      if (d.intr) {
+        d.intrN[2 * (int64_t)i] = d.intr[2 * (int64_t)i] + dx[6];
+        d.intrN[2 * (int64_t)i + 1] = d.intr[2 * (int64_t)i + 1] + dx[7];
+        s2 += dx[6] * dx[6] + dx[7] * dx[7];
+      }
     }
   }
   // the cameras of a sub-block are consecutive: a wave inside one sub-block
@@ -971,7 +1011,7 @@ __global__ void k_cam_update(Dev d) {
 // J: arithmetic of the Jacobians and per-observation products of the first
 // pass (FP32 on the mixed path; residuals, the 3x3 solve, the point and the
 // cost after the step stay FP64).
-template <typename J>
+template <typename J, bool CAL>
 __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
   __shared__ double sh[16];
   __shared__ int l_first;
@@ -1010,20 +1050,25 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       for (int q = 0; q < 3; ++q) gj[q] = sizeof(J) == 8 ? (J)gp[q] : J(0);
       const int base = d.blk_cam_off[l];
       const double* xs = d.x + d.vec_off[l];
-      for_copy_obs(d, d.cam, k0, k1, unit, [&](const CopyObs& o) {
+      constexpr int NP = CAL ? 8 : 6;
+      for_copy_obs<CAL>(d, d.cam, d.intr, k0, k1, unit, [&](const CopyObs<CAL>& o) {
         Lin<J> L;
         double g0, g1, z;
-        linearise_split<J>(o.cm, o.cm + 9, X, d.f, d.cx, d.cy, L, g0, g1, z);
+        linearise_split_cam<CAL, J>(o.cm, o.cm + CAM_F, X, d.f, d.cx, d.cy, L, g0, g1, z);
         const W2<J> W{(J)o.W.a, (J)o.W.b, (J)o.W.c};
         add_point_normals<J>(L, W, (J)(g0 - o.x), (J)(g1 - o.y), hj, gj);
-        const double* dCd = xs + 6 * (o.cam - base);
-        J dC[6];
-        for (int q = 0; q < 6; ++q) dC[q] = (J)dCd[q];
-        // t = A dC = Ar w - B dc ; Y^T dC = B^T W t
+        const double* dCd = xs + NP * (o.cam - base);
+        J dC[NP];
+        for (int q = 0; q < NP; ++q) dC[q] = (J)dCd[q];
+        // t = A dC = Ar w - B dc (+ Ai (df, dk1)) ; Y^T dC = B^T W t
         J t0 = L.Ar[0][0] * dC[0] + L.Ar[0][1] * dC[1] + L.Ar[0][2] * dC[2] -
                (L.B[0][0] * dC[3] + L.B[0][1] * dC[4] + L.B[0][2] * dC[5]);
         J t1 = L.Ar[1][0] * dC[0] + L.Ar[1][1] * dC[1] + L.Ar[1][2] * dC[2] -
                (L.B[1][0] * dC[3] + L.B[1][1] * dC[4] + L.B[1][2] * dC[5]);
+        if constexpr (CAL) {
+          t0 += L.Ai[0][0] * dC[6] + L.Ai[0][1] * dC[7];
+          t1 += L.Ai[1][0] * dC[6] + L.Ai[1][1] * dC[7];
+        }
         J wt0 = W.a * t0 + W.b * t1, wt1 = W.b * t0 + W.c * t1;
         for (int s = 0; s < 3; ++s) bt[s] += L.B[0][s] * wt0 + L.B[1][s] * wt1;
       });
@@ -1049,9 +1094,9 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
       double og[3];
       sym3_mul(om, dx, og);
       double cost = dx[0] * og[0] + dx[1] * og[1] + dx[2] * og[2];
-      for_copy_obs(d, d.camN, k0, k1, unit, [&](const CopyObs& o) {
+      for_copy_obs<CAL>(d, d.camN, d.intrN, k0, k1, unit, [&](const CopyObs<CAL>& o) {
         Lin<double> L;
-        linearise<double>(o.cm, o.cm + 9, Xn, d.f, d.cx, d.cy, L);
+        linearise_cam<CAL, double>(o.cm, o.cm + CAM_F, Xn, d.f, d.cx, d.cy, L);
         cost += wquad(o.W, L.g0 - o.x, L.g1 - o.y);
       });
       double s2 = dX[0] * dX[0] + dX[1] * dX[1] + dX[2] * dX[2];
@@ -1126,6 +1171,7 @@ __device__ __forceinline__ bool step_rejected(const Dev& d, int l) {
 __global__ void k_update_finish(Dev d, double* bs) {
   const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (t < (int64_t)CAM_STRIDE * d.M && !step_rejected(d, d.cam_blk[t / CAM_STRIDE])) d.cam[t] = d.camN[t];
+  if (d.intr && t < 2 * (int64_t)d.M && !step_rejected(d, d.cam_blk[t / 2])) d.intr[t] = d.intrN[t];
   if (t >= d.L) return;
   const int l = (int)t;
   bool act = d.active == nullptr || d.active[l];
@@ -1331,11 +1377,15 @@ __global__ void k_consensus_cams(Dev d, double* stats) {
   const double* c = d.cam + (int64_t)CAM_STRIDE * i;
   for (int q = 0; q < 9; ++q) d.u_camR[9 * (int64_t)o + q] = c[q];
   for (int r = 0; r < 3; ++r) d.u_camC[(int64_t)r * d.M + o] = c[9 + r];
+  if (d.intr) {
+    d.u_intr[o] = d.intr[2 * (int64_t)i];
+    d.u_intr[(int64_t)d.M + o] = d.intr[2 * (int64_t)i + 1];
+  }
 }
 
 // dense copy-out of one sub-block's RCS (row-major n6 x n6 lower) and rhs
 __global__ void k_rcs_extract(Dev d, int l, double* S_out, double* e_out) {
-  int n6 = 6 * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
+  int n6 = d.np * (d.blk_cam_off[l + 1] - d.blk_cam_off[l]);
   int64_t tot = (int64_t)n6 * n6;
   for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < tot; t += (int64_t)gridDim.x * NT) {
     int row = (int)(t / n6), col = (int)(t % n6);
@@ -1370,16 +1420,17 @@ __device__ __forceinline__ double rcs_sym(const Dev& d, int l, int r, int c) {
   return r >= c ? d.S[rcs_elem(d, l, r, c)] : d.S[rcs_elem(d, l, c, r)];
 }
 
-// Camera covariance: the camera's 6 x 6 diagonal block of S^-1 of its
+// Camera covariance: the camera's np x np diagonal block of S^-1 of its
 // sub-block (the RCS storage holds S^-1 after the inverse launches), written
 // row-major in the caller's camera order.
 __global__ void k_cov_cams(Dev d, double* out) {
   const int i = blockIdx.x * NT + threadIdx.x;
   if (i >= d.M) return;
+  const int np = d.np;
   const int l = d.cam_blk[i], a = i - d.blk_cam_off[l];
-  double* o = out + 36 * (int64_t)d.cam_orig[i];
-  for (int r = 0; r < 6; ++r)
-    for (int c = 0; c < 6; ++c) o[6 * r + c] = rcs_sym(d, l, 6 * a + r, 6 * a + c);
+  double* o = out + (int64_t)np * np * d.cam_orig[i];
+  for (int r = 0; r < np; ++r)
+    for (int c = 0; c < np; ++c) o[np * r + c] = rcs_sym(d, l, np * a + r, np * a + c);
 }
 
 // Point-copy covariance (Sec. 2): M_XX = V^-1 + V^-1 (sum_{k,k'} Y_k^T
@@ -1389,11 +1440,13 @@ __global__ void k_cov_cams(Dev d, double* out) {
 // on both paths).  One thread per copy, the sum as sum_k Y_k^T (sum_k' M Y_k');
 // zeros for copies of invalid points.  Output (xx, xy, xz, yy, yz, zz) in copy
 // order.
-__device__ __forceinline__ void cov_obs(const Dev& d, int64_t k, const double (&X)[3], bool unit, double (&Y)[6][3],
+template <int NP>
+__device__ __forceinline__ void cov_obs(const Dev& d, int64_t k, const double (&X)[3], bool unit, double (&Y)[NP][3],
                                         double (&BtWB)[6]) {
-  const double* cm = d.cam + (int64_t)CAM_STRIDE * d.obs_cam[k];
+  const int ic = d.obs_cam[k];
+  const double* cm = d.cam + (int64_t)CAM_STRIDE * ic;
   Lin<double> L;
-  linearise<double>(cm, cm + 9, X, d.f, d.cx, d.cy, L);
+  linearise_cam<NP == 8, double>(cm, NP == 8 ? d.intr + 2 * (int64_t)ic : nullptr, X, d.f, d.cx, d.cy, L);
   const W2<double> W = obs_weight(d, k, unit);
   double WB[2][3];
   for (int c = 0; c < 3; ++c) {
@@ -1405,6 +1458,8 @@ __device__ __forceinline__ void cov_obs(const Dev& d, int64_t k, const double (&
       Y[u][c] = L.Ar[0][u] * WB[0][c] + L.Ar[1][u] * WB[1][c];
       Y[3 + u][c] = -(L.B[0][u] * WB[0][c] + L.B[1][u] * WB[1][c]);
     }
+    if constexpr (NP == 8)
+      for (int u = 0; u < 2; ++u) Y[6 + u][c] = L.Ai[0][u] * WB[0][c] + L.Ai[1][u] * WB[1][c];
   }
   BtWB[0] = L.B[0][0] * WB[0][0] + L.B[1][0] * WB[1][0];
   BtWB[1] = L.B[0][0] * WB[0][1] + L.B[1][0] * WB[1][1];
@@ -1414,6 +1469,7 @@ __device__ __forceinline__ void cov_obs(const Dev& d, int64_t k, const double (&
   BtWB[5] = L.B[0][2] * WB[0][2] + L.B[1][2] * WB[1][2];
 }
 
+template <int NP>
 __global__ __launch_bounds__(NT) void k_cov_copies(Dev d, double* out) {
   const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (c >= d.NC) return;
@@ -1430,9 +1486,9 @@ __global__ __launch_bounds__(NT) void k_cov_copies(Dev d, double* out) {
       for (int r = 0; r < 3; ++r) X[r] = d.Xc[3 * c + r];
     double h[6];
     om_load(d, c, h);
-    double Y[6][3], bwb[6];
+    double Y[NP][3], bwb[6];
     for (int k = k0; k < k1; ++k) {
-      cov_obs(d, k, X, unit, Y, bwb);
+      cov_obs<NP>(d, k, X, unit, Y, bwb);
       for (int q = 0; q < 6; ++q) h[q] += bwb[q];
     }
     h[0] *= 1.0 + d.lambda;
@@ -1443,24 +1499,25 @@ __global__ __launch_bounds__(NT) void k_cov_copies(Dev d, double* out) {
       chol3_inverse(lch, vi);
       double T3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
       for (int k1i = k0; k1i < k1; ++k1i) {
-        double Y1[6][3];
-        cov_obs(d, k1i, X, unit, Y1, bwb);
+        double Y1[NP][3];
+        cov_obs<NP>(d, k1i, X, unit, Y1, bwb);
         const int a1 = d.obs_cam[k1i] - b0;
-        double G[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        double G[NP][3];
+        for (int u = 0; u < NP; ++u) G[u][0] = G[u][1] = G[u][2] = 0.0;
         for (int k2i = k0; k2i < k1; ++k2i) {
-          double Y2[6][3];
-          cov_obs(d, k2i, X, unit, Y2, bwb);
+          double Y2[NP][3];
+          cov_obs<NP>(d, k2i, X, unit, Y2, bwb);
           const int a2 = d.obs_cam[k2i] - b0;
-          for (int u = 0; u < 6; ++u)
-            for (int v = 0; v < 6; ++v) {
-              const double m = rcs_sym(d, l, 6 * a1 + u, 6 * a2 + v);
+          for (int u = 0; u < NP; ++u)
+            for (int v = 0; v < NP; ++v) {
+              const double m = rcs_sym(d, l, NP * a1 + u, NP * a2 + v);
               for (int q = 0; q < 3; ++q) G[u][q] += m * Y2[v][q];
             }
         }
         for (int r = 0; r < 3; ++r)
           for (int q = 0; q < 3; ++q) {
             double sacc = 0.0;
-            for (int u = 0; u < 6; ++u) sacc += Y1[u][r] * G[u][q];
+            for (int u = 0; u < NP; ++u) sacc += Y1[u][r] * G[u][q];
             T3[r][q] += sacc;
           }
       }
@@ -1511,12 +1568,12 @@ void launch_init_rcs(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_pad_identity, dim3(d.L), dim3(NT), 0, st, d);
 }
 
-template <int VAR>
+template <int VAR, bool CAL = false>
 static void launch_intersect_var(const Dev& d, bool want_cov, hipStream_t st) {
   if (d.has_info)
-    hipLaunchKernelGGL((k_intersect<true, VAR>), dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
+    hipLaunchKernelGGL((k_intersect<true, VAR, CAL>), dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
   else
-    hipLaunchKernelGGL((k_intersect<false, VAR>), dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
+    hipLaunchKernelGGL((k_intersect<false, VAR, CAL>), dim3(grid_for(d.N, IT)), dim3(IT), 0, st, d, (int)want_cov);
 }
 
 void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
@@ -1526,7 +1583,11 @@ void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
     case RPBA_VARIANT_SCALAR: launch_intersect_var<RPBA_VARIANT_SCALAR>(d, want_cov, st); break;
     case RPBA_VARIANT_PLAIN: launch_intersect_var<RPBA_VARIANT_PLAIN>(d, want_cov, st); break;
     case RPBA_VARIANT_PLAIN_REFINED: launch_intersect_var<RPBA_VARIANT_PLAIN_REFINED>(d, want_cov, st); break;
-    default: launch_intersect_var<RPBA_VARIANT_EXTENDED>(d, want_cov, st); break;
+    default:
+      // (intrinsics come with the extended variant only)
+      if (d.np == 8) launch_intersect_var<RPBA_VARIANT_EXTENDED, true>(d, want_cov, st);
+      else launch_intersect_var<RPBA_VARIANT_EXTENDED>(d, want_cov, st);
+      break;
   }
   hipLaunchKernelGGL(k_int_reduce, dim3(1), dim3(1024), 0, st, d, (int)grid_for(d.N, IT));
 }
@@ -1537,20 +1598,31 @@ void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, dou
 
 void launch_cov_outputs(const Dev& d, double* cam_cov, double* copy_cov, hipStream_t st) {
   if (cam_cov) hipLaunchKernelGGL(k_cov_cams, dim3(grid_for(d.M)), dim3(NT), 0, st, d, cam_cov);
-  if (copy_cov) hipLaunchKernelGGL(k_cov_copies, dim3(grid_for(d.NC)), dim3(NT), 0, st, d, copy_cov);
+  if (copy_cov && d.np == 8) hipLaunchKernelGGL(k_cov_copies<8>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d, copy_cov);
+  else if (copy_cov) hipLaunchKernelGGL(k_cov_copies<6>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d, copy_cov);
 }
 
 void launch_copy_prep(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_step_begin, dim3(grid_for(d.L)), dim3(NT), 0, st, d);
-  if (d.cpk_f32) hipLaunchKernelGGL(k_copy_prep<float>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
-  else hipLaunchKernelGGL(k_copy_prep<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  if (d.np == 8) {
+    if (d.cpk_f32) hipLaunchKernelGGL((k_copy_prep<float, true>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+    else hipLaunchKernelGGL((k_copy_prep<double, true>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  } else {
+    if (d.cpk_f32) hipLaunchKernelGGL((k_copy_prep<float, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+    else hipLaunchKernelGGL((k_copy_prep<double, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  }
   hipLaunchKernelGGL(k_slots_reduce<false>, dim3(grid_for(d.L, NT / 64)), dim3(NT), 0, st, d);
 }
 
 void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
   hipLaunchKernelGGL(k_cam_update, dim3(grid_for(d.M)), dim3(NT), 0, st, d);
-  if (d.cpk_f32) hipLaunchKernelGGL(k_back_update<float>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
-  else hipLaunchKernelGGL(k_back_update<double>, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  if (d.np == 8) {
+    if (d.cpk_f32) hipLaunchKernelGGL((k_back_update<float, true>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+    else hipLaunchKernelGGL((k_back_update<double, true>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  } else {
+    if (d.cpk_f32) hipLaunchKernelGGL((k_back_update<float, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+    else hipLaunchKernelGGL((k_back_update<double, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
+  }
   hipLaunchKernelGGL(k_slots_reduce<true>, dim3(grid_for(d.L, NT / 64)), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_update_finish, dim3(grid_for(std::max<int64_t>((int64_t)CAM_STRIDE * d.M, d.L))), dim3(NT), 0,
                      st, d, block_stats);

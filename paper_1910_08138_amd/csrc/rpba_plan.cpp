@@ -86,7 +86,7 @@ std::vector<int32_t> covisibility_rcm(int32_t M, int32_t N, int32_t K, int32_t L
 }  // namespace
 
 uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
-                      const int32_t* cam_block, int32_t tile) {
+                      const int32_t* cam_block, int32_t tile, int32_t np) {
   // FNV-1a over sizes and the three index arrays
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) {
@@ -98,13 +98,15 @@ uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t*
   mix((uint64_t)K);
   mix((uint64_t)L);
   mix((uint64_t)tile);
+  mix((uint64_t)np);
   for (int32_t k = 0; k < K; ++k) mix(((uint64_t)(uint32_t)obs_cam[k] << 32) | (uint32_t)obs_pt[k]);
   for (int32_t i = 0; i < M; ++i) mix((uint64_t)(uint32_t)cam_block[i]);
   return h;
 }
 
 std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
-                       const int32_t* cam_block, int32_t tile, Plan& P) {
+                       const int32_t* cam_block, int32_t tile, int32_t np, Plan& P) {
+  if (np != 6 && np != 8) return "6 or 8 parameters per camera";
   if (M <= 0 || N <= 0 || K <= 0 || L <= 0) return "M, N, K and L must be positive";
   if (M >= (1 << 20)) return "at most 2^20 - 1 cameras";
   if (N >= (1 << 28)) return "at most 2^28 - 1 points";
@@ -112,6 +114,7 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
   if (tile != 32 && tile != 64) return "Cholesky tile must be 32 or 64";
   if (!obs_cam || !obs_pt || !cam_block) return "topology arrays must be non-NULL host pointers";
   P = Plan();
+  P.np = np;
   P.M = M;
   P.N = N;
   P.K = K;
@@ -154,7 +157,7 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     }
   }
   for (int32_t l = 0; l < L; ++l) P.max_blk_cams = std::max(P.max_blk_cams, P.blk_cam_off[l + 1] - P.blk_cam_off[l]);
-  if (6 * P.max_blk_cams > 255 * tile) return "sub-block too large for the Cholesky tiling";
+  if (np * P.max_blk_cams > 255 * tile) return "sub-block too large for the Cholesky tiling";
 
   // points ordered by their lowest sub-block and, inside it, by their first
   // camera (cameras of a sub-block are in the caller's order, which for image
@@ -418,7 +421,7 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
   P.vec_off.resize(L);
   P.nt_max = 0;
   for (int32_t l = 0; l < L; ++l) {
-    int32_t n6 = 6 * (P.blk_cam_off[l + 1] - P.blk_cam_off[l]);
+    int32_t n6 = np * (P.blk_cam_off[l + 1] - P.blk_cam_off[l]);
     int32_t nt = (n6 + tile - 1) / tile;
     P.nt[l] = nt;
     P.nt_max = std::max(P.nt_max, nt);
@@ -429,8 +432,8 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     P.vec_off[l] = P.vec_total;
     P.vec_total += (int64_t)nt * tile;
   }
-  // tiles of each factor that can be nonzero: the tiles touched by a 6 x 6
-  // block of S (a camera's six rows may straddle two tiles), the diagonal
+  // tiles of each factor that can be nonzero: the tiles touched by an np x np
+  // block of S (a camera's np rows may straddle two tiles), the diagonal
   // tiles, then the fill of a Cholesky factorisation by tiles; the
   // right-hand-side tile row is full
   P.tile_nz.assign(P.rcs_total / T2, 0);
@@ -444,8 +447,8 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
       const int32_t a = c - P.blk_cam_off[l];
       for (int32_t q = P.nb_off[c]; q < P.nb_off[c + 1]; ++q) {
         const int32_t b = P.nb_cam[q];
-        for (int32_t ra : {6 * a / tile, (6 * a + 5) / tile})
-          for (int32_t rb : {6 * b / tile, (6 * b + 5) / tile}) at(ra, rb) = 1;
+        for (int32_t ra : {np * a / tile, (np * a + np - 1) / tile})
+          for (int32_t rb : {np * b / tile, (np * b + np - 1) / tile}) at(ra, rb) = 1;
       }
     }
     std::vector<int32_t> rows;
@@ -496,7 +499,7 @@ std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t
     P.bwd_off[s + 1] = (int64_t)P.bwd_items.size();
   }
   P.blk_pcg.assign(L, 0);
-  P.key = topology_key(M, N, K, L, obs_cam, obs_pt, cam_block, tile);
+  P.key = topology_key(M, N, K, L, obs_cam, obs_pt, cam_block, tile, np);
   return "";
 }
 

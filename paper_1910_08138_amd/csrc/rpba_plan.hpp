@@ -35,6 +35,7 @@ struct Plan {
   int32_t M = 0, N = 0, K = 0, L = 0;
   int64_t NC = 0;  // copies
   int32_t T = 64;  // Cholesky tile edge
+  int32_t np = 6;  // parameters per camera (RCS rows per camera): 6, or 8 with intrinsics
   bool has_info = false;
 
   // permutations (new -> original)
@@ -112,10 +113,10 @@ struct Plan {
 
 // Returns an empty string on success, else the reason.
 std::string build_plan(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
-                       const int32_t* cam_block, int32_t tile, Plan& P);
+                       const int32_t* cam_block, int32_t tile, int32_t np, Plan& P);
 
 uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t* obs_cam, const int32_t* obs_pt,
-                      const int32_t* cam_block, int32_t tile);
+                      const int32_t* cam_block, int32_t tile, int32_t np);
 
 // Task list of the persistent forward factorisation: every tile (i, j),
 // j <= i <= nt, j < nt, of the listed sub-blocks, packed (l << 16) | (i << 8)

@@ -6,7 +6,10 @@
 // with U*_i the damped camera block, Y_k = A_k^T W_k B_k, V*_c the damped point
 // block (its FP64 inverse comes from the point-block pass).
 //
-// Each 6x6 block is owned by one group of lanes that sums the contributions of
+// Camera blocks are NP x NP: NP = 6 (pose), or 8 with intrinsics (pose, the
+// camera's f and k1; Sec. 6).
+//
+// Each NP x NP block is owned by one group of lanes that sums the contributions of
 // its observation pairs in registers and writes the block once: no atomics,
 // deterministic order.  Diagonal blocks (one 64-lane wave per camera) also
 // reduce U*, g_C and e; off-diagonal blocks take a group of 4, 8 or 16 lanes
@@ -40,11 +43,13 @@ __device__ __forceinline__ W2<T> cm_weight_t(const Dev& d, int64_t t, bool unit)
   return {(T)(r * d.w0), T(0), (T)(r * d.w0)};
 }
 
-// camera i: rotation in T, centre in FP64
-template <typename T>
+// camera i: rotation in T, centre in FP64; with intrinsics (NP = 8) its f
+// and k1 in T
+template <typename T, int NP>
 struct CamReg {
   T R[9];
   double C[3];
+  T fk[2];
   __device__ void load(const Dev& d, int i) {
     const double* c = d.cam + (int64_t)CAM_STRIDE * i;
 #pragma unroll
@@ -52,15 +57,39 @@ struct CamReg {
     C[0] = c[9];
     C[1] = c[10];
     C[2] = c[11];
+    if constexpr (NP == 8) {
+      fk[0] = (T)d.intr[2 * (int64_t)i];
+      fk[1] = (T)d.intr[2 * (int64_t)i + 1];
+    }
   }
   __device__ void lin(const double X[3], const Dev& d, Lin<T>& L) const {
-    linearise_d<T>(R, (T)(X[0] - C[0]), (T)(X[1] - C[1]), (T)(X[2] - C[2]), (T)d.f, (T)d.cx, (T)d.cy, L);
+    const T d0 = (T)(X[0] - C[0]), d1 = (T)(X[1] - C[1]), d2 = (T)(X[2] - C[2]);
+    if constexpr (NP == 8) linearise_cal_d<T>(R, d0, d1, d2, fk[0], fk[1], (T)d.cx, (T)d.cy, L);
+    else linearise_d<T>(R, d0, d1, d2, (T)d.f, (T)d.cx, (T)d.cy, L);
   }
 };
 
-// Y = A^T W B (6x3) of one observation
-template <typename T>
-__device__ __forceinline__ void y_block(const Lin<T>& L, const W2<T>& W, T Y[6][3]) {
+// camera Jacobian A (2 x NP) = [Ar | -B | Ai] of one observation
+template <typename T, int NP>
+__device__ __forceinline__ void a_block(const Lin<T>& L, T A[2][NP]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    A[0][q] = L.Ar[0][q];
+    A[1][q] = L.Ar[1][q];
+    A[0][3 + q] = -L.B[0][q];
+    A[1][3 + q] = -L.B[1][q];
+  }
+  if constexpr (NP == 8) {
+    A[0][6] = L.Ai[0][0];
+    A[1][6] = L.Ai[1][0];
+    A[0][7] = L.Ai[0][1];
+    A[1][7] = L.Ai[1][1];
+  }
+}
+
+// Y = A^T W B (NP x 3) of one observation
+template <typename T, int NP>
+__device__ __forceinline__ void y_block(const Lin<T>& L, const W2<T>& W, T Y[NP][3]) {
   T WB0[3], WB1[3];
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -74,21 +103,28 @@ __device__ __forceinline__ void y_block(const Lin<T>& L, const W2<T>& W, T Y[6][
       Y[r][s] = L.Ar[0][r] * WB0[s] + L.Ar[1][r] * WB1[s];
       Y[3 + r][s] = -(L.B[0][r] * WB0[s] + L.B[1][r] * WB1[s]);
     }
+  if constexpr (NP == 8) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) Y[6 + r][s] = L.Ai[0][r] * WB0[s] + L.Ai[1][r] * WB1[s];
+  }
 }
 
 // Z = Y V^-1 with V^-1 symmetric (xx, xy, xz, yy, yz, zz)
-template <typename T>
-__device__ __forceinline__ void z_block(const T Y[6][3], const T Vi[6], T Z[6][3]) {
+template <typename T, int NP>
+__device__ __forceinline__ void z_block(const T Y[NP][3], const T Vi[6], T Z[NP][3]) {
 #pragma unroll
-  for (int r = 0; r < 6; ++r) {
+  for (int r = 0; r < NP; ++r) {
     Z[r][0] = Y[r][0] * Vi[0] + Y[r][1] * Vi[1] + Y[r][2] * Vi[2];
     Z[r][1] = Y[r][0] * Vi[1] + Y[r][1] * Vi[3] + Y[r][2] * Vi[4];
     Z[r][2] = Y[r][0] * Vi[2] + Y[r][1] * Vi[4] + Y[r][2] * Vi[5];
   }
 }
 
-// index of (r, s), r <= s, in a packed 6x6 upper triangle
-__host__ __device__ constexpr int up6(int r, int s) { return r * 6 - r * (r - 1) / 2 + (s - r); }
+// index of (r, s), r <= s, in a packed NP x NP upper triangle
+template <int NP>
+__host__ __device__ constexpr int upn(int r, int s) { return r * NP - r * (r - 1) / 2 + (s - r); }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -176,55 +212,50 @@ __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_
 
 // One wave per camera: diagonal block S_(i,i) = U*_i - sum_k Y_k V*^-1 Y_k^T
 // and e_i.
-template <typename T>
+template <typename T, int NP>
 __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
+  constexpr int NU = NP * (NP + 1) / 2;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   if (i >= d.M) return;
   const int l = d.cam_blk[i];
   if (d.active && !d.active[l]) return;
   const bool unit = *d.rw_unit != 0;
-  CamReg<T> cm;
+  CamReg<T, NP> cm;
   cm.load(d, i);
-  T acc[21], U[21], gC[6], ep[6];
+  T acc[NU], U[NU], gC[NP], ep[NP];
 #pragma unroll
-  for (int q = 0; q < 21; ++q) acc[q] = U[q] = T(0);
+  for (int q = 0; q < NU; ++q) acc[q] = U[q] = T(0);
 #pragma unroll
-  for (int q = 0; q < 6; ++q) gC[q] = ep[q] = T(0);
+  for (int q = 0; q < NP; ++q) gC[q] = ep[q] = T(0);
 
   auto process = [&](const ObsIn<T>& o) {
     Lin<T> L;
     cm.lin(o.X, d, L);
     const W2<T> W = o.W;
     const T v0 = L.g0 - o.x, v1 = L.g1 - o.y;
-    T A[2][6], WA[2][6];
+    T A[2][NP], WA[2][NP];
+    a_block<T, NP>(L, A);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      A[0][q] = L.Ar[0][q];
-      A[1][q] = L.Ar[1][q];
-      A[0][3 + q] = -L.B[0][q];
-      A[1][3 + q] = -L.B[1][q];
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
+    for (int q = 0; q < NP; ++q) {
       WA[0][q] = W.a * A[0][q] + W.b * A[1][q];
       WA[1][q] = W.b * A[0][q] + W.c * A[1][q];
     }
     const T Wv0 = W.a * v0 + W.b * v1, Wv1 = W.b * v0 + W.c * v1;
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
+    for (int r = 0; r < NP; ++r) {
 #pragma unroll
-      for (int s = r; s < 6; ++s) U[up6(r, s)] += A[0][r] * WA[0][s] + A[1][r] * WA[1][s];
+      for (int s = r; s < NP; ++s) U[upn<NP>(r, s)] += A[0][r] * WA[0][s] + A[1][r] * WA[1][s];
       gC[r] += A[0][r] * Wv0 + A[1][r] * Wv1;
     }
-    T Y[6][3], Z[6][3];
-    y_block<T>(L, W, Y);
-    z_block<T>(Y, o.Vi, Z);
+    T Y[NP][3], Z[NP][3];
+    y_block<T, NP>(L, W, Y);
+    z_block<T, NP>(Y, o.Vi, Z);
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
+    for (int r = 0; r < NP; ++r) {
       ep[r] += Z[r][0] * o.gX[0] + Z[r][1] * o.gX[1] + Z[r][2] * o.gX[2];
 #pragma unroll
-      for (int s = r; s < 6; ++s) acc[up6(r, s)] -= Z[r][0] * Y[s][0] + Z[r][1] * Y[s][1] + Z[r][2] * Y[s][2];
+      for (int s = r; s < NP; ++s) acc[upn<NP>(r, s)] -= Z[r][0] * Y[s][0] + Z[r][1] * Y[s][1] + Z[r][2] * Y[s][2];
     }
   };
   const int o0 = d.cam_obs_off[i], o1 = d.cam_obs_off[i + 1];
@@ -268,51 +299,51 @@ __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
     }
   }
 #pragma unroll
-  for (int q = 0; q < 21; ++q) {
+  for (int q = 0; q < NU; ++q) {
     acc[q] = wave_sum(acc[q]);
     U[q] = wave_sum(U[q]);
   }
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
+  for (int q = 0; q < NP; ++q) {
     gC[q] = wave_sum(gC[q]);
     ep[q] = wave_sum(ep[q]);
   }
   const int a = i - d.blk_cam_off[l];
-  if (lane < 36) {
-    const int r = lane / 6, s = lane % 6;
-    const int u = r <= s ? up6(r, s) : up6(s, r);
+  if (lane < NP * NP) {
+    const int r = lane / NP, s = lane % NP;
+    const int u = r <= s ? upn<NP>(r, s) : upn<NP>(s, r);
     // select the lane's entry from the register arrays
     double uv = 0.0, av = 0.0;
 #pragma unroll
-    for (int q = 0; q < 21; ++q)
+    for (int q = 0; q < NU; ++q)
       if (q == u) {
         uv = (double)U[q];
         av = (double)acc[q];
       }
     if (r == s) uv = (uv == 0.0) ? 1.0 : uv * (1.0 + lam_of(d, l));
     const double val = uv + av;
-    if (d.blk_pcg && d.blk_pcg[l]) {
+    if (NP == 6 && d.blk_pcg && d.blk_pcg[l]) {
       d.bsr[(int64_t)d.pb_bsr[d.nb_off[i + 1] - 1] * 36 + lane] = (float)val;
     } else if (s <= r) {
-      d.S[rcs_elem(d, l, 6 * a + r, 6 * a + s)] = val;
+      d.S[rcs_elem(d, l, NP * a + r, NP * a + s)] = val;
     }
   }
-  if (lane < 6) {
+  if (lane < NP) {
     double g = 0.0, e = 0.0;
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
+    for (int q = 0; q < NP; ++q)
       if (q == lane) {
         g = (double)gC[q];
         e = (double)ep[q];
       }
-    d.y[d.vec_off[l] + 6 * a + lane] = -g + e;
+    d.y[d.vec_off[l] + NP * a + lane] = -g + e;
     // dense sub-blocks: e^T is row 0 of the right-hand-side tile row
-    if (!(d.blk_pcg && d.blk_pcg[l])) d.S[rcs_elem(d, l, d.nt[l] * d.T, 6 * a + lane)] = -g + e;
+    if (!(NP == 6 && d.blk_pcg && d.blk_pcg[l])) d.S[rcs_elem(d, l, d.nt[l] * d.T, NP * a + lane)] = -g + e;
   }
 }
 
 // One G-lane group per off-diagonal pair block (i, i2), i2 < i in the sub-block.
-template <typename T, int G>
+template <typename T, int G, int NP>
 __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
   const int gl = threadIdx.x & (G - 1);
   const int64_t t = (int64_t)blockIdx.x * (NT / G) + (threadIdx.x / G);
@@ -325,12 +356,12 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
   const int a2 = d.nb_cam[q];
   const int i2 = base + a2;
   const bool unit = *d.rw_unit != 0;
-  CamReg<T> c1, c2;
+  CamReg<T, NP> c1, c2;
   c1.load(d, i1);
   c2.load(d, i2);
-  T acc[36];
+  T acc[NP * NP];
 #pragma unroll
-  for (int u = 0; u < 36; ++u) acc[u] = T(0);
+  for (int u = 0; u < NP * NP; ++u) acc[u] = T(0);
   for (int64_t e = d.pb_ent_off[q] + gl; e < d.pb_ent_off[q + 1]; e += G) {
     const int c = d.pb_ent[3 * e], t1 = d.pb_ent[3 * e + 1], t2 = d.pb_ent[3 * e + 2];
     ObsIn<T> o;
@@ -339,28 +370,30 @@ __global__ __launch_bounds__(NT) void k_schur_offdiag(Dev d) {
     Lin<T> L1, L2;
     c1.lin(o.X, d, L1);
     c2.lin(o.X, d, L2);
-    T Y1[6][3], Y2[6][3], Z1[6][3];
-    y_block<T>(L1, o.W, Y1);
-    y_block<T>(L2, cm_weight_t<T>(d, t2, unit), Y2);
-    z_block<T>(Y1, o.Vi, Z1);
+    T Y1[NP][3], Y2[NP][3], Z1[NP][3];
+    y_block<T, NP>(L1, o.W, Y1);
+    y_block<T, NP>(L2, cm_weight_t<T>(d, t2, unit), Y2);
+    z_block<T, NP>(Y1, o.Vi, Z1);
 #pragma unroll
-    for (int r = 0; r < 6; ++r)
+    for (int r = 0; r < NP; ++r)
 #pragma unroll
-      for (int s = 0; s < 6; ++s) acc[6 * r + s] -= Z1[r][0] * Y2[s][0] + Z1[r][1] * Y2[s][1] + Z1[r][2] * Y2[s][2];
+      for (int s = 0; s < NP; ++s) acc[NP * r + s] -= Z1[r][0] * Y2[s][0] + Z1[r][1] * Y2[s][1] + Z1[r][2] * Y2[s][2];
   }
 #pragma unroll
-  for (int u = 0; u < 36; ++u) acc[u] = group_sum<G>(acc[u]);
+  for (int u = 0; u < NP * NP; ++u) acc[u] = group_sum<G>(acc[u]);
   const int a1 = i1 - base;
-  const bool sparse = d.blk_pcg && d.blk_pcg[l];
+  // (the block-sparse matrix of the iterative solver holds 6 x 6 blocks:
+  // intrinsics are solved directly)
+  const bool sparse = NP == 6 && d.blk_pcg && d.blk_pcg[l];
 #pragma unroll
-  for (int u = 0; u < 36; ++u) {
+  for (int u = 0; u < NP * NP; ++u) {
     if ((u & (G - 1)) != gl) continue;
-    const int r = u / 6, s = u % 6;
+    const int r = u / NP, s = u % NP;
     if (sparse) {
       d.bsr[(int64_t)d.pb_bsr[q] * 36 + u] = (float)acc[u];
       d.bsr[(int64_t)d.pb_bsr_t[q] * 36 + 6 * s + r] = (float)acc[u];
     } else {
-      d.S[rcs_elem(d, l, 6 * a1 + r, 6 * a2 + s)] = (double)acc[u];
+      d.S[rcs_elem(d, l, NP * a1 + r, NP * a2 + s)] = (double)acc[u];
     }
   }
 }
@@ -375,22 +408,28 @@ void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, h
     launch_init_rcs(d, st);
   }
   const unsigned gd = (unsigned)((d.M + 3) / 4);
-  if (fp32) hipLaunchKernelGGL(k_schur_diag<float>, dim3(gd), dim3(NT), 0, st, d);
-  else hipLaunchKernelGGL(k_schur_diag<double>, dim3(gd), dim3(NT), 0, st, d);
+  if (d.np == 8) {
+    if (fp32) hipLaunchKernelGGL((k_schur_diag<float, 8>), dim3(gd), dim3(NT), 0, st, d);
+    else hipLaunchKernelGGL((k_schur_diag<double, 8>), dim3(gd), dim3(NT), 0, st, d);
+  } else {
+    if (fp32) hipLaunchKernelGGL((k_schur_diag<float, 6>), dim3(gd), dim3(NT), 0, st, d);
+    else hipLaunchKernelGGL((k_schur_diag<double, 6>), dim3(gd), dim3(NT), 0, st, d);
+  }
 }
 
-template <int G>
+template <int G, int NP>
 static void launch_offdiag_lanes(const Dev& d, bool fp32, hipStream_t st) {
   const unsigned go = (unsigned)((d.n_od + NT / G - 1) / (NT / G));
   if (!go) return;
-  if (fp32) hipLaunchKernelGGL((k_schur_offdiag<float, G>), dim3(go), dim3(NT), 0, st, d);
-  else hipLaunchKernelGGL((k_schur_offdiag<double, G>), dim3(go), dim3(NT), 0, st, d);
+  if (fp32) hipLaunchKernelGGL((k_schur_offdiag<float, G, NP>), dim3(go), dim3(NT), 0, st, d);
+  else hipLaunchKernelGGL((k_schur_offdiag<double, G, NP>), dim3(go), dim3(NT), 0, st, d);
 }
 
 void launch_schur_offdiag(const Dev& d, bool fp32, hipStream_t st) {
-  if (d.pb_lanes == 4) launch_offdiag_lanes<4>(d, fp32, st);
-  else if (d.pb_lanes == 16) launch_offdiag_lanes<16>(d, fp32, st);
-  else launch_offdiag_lanes<8>(d, fp32, st);
+  if (d.np == 8) launch_offdiag_lanes<8, 8>(d, fp32, st);  // intrinsics: eight lanes per block
+  else if (d.pb_lanes == 4) launch_offdiag_lanes<4, 6>(d, fp32, st);
+  else if (d.pb_lanes == 16) launch_offdiag_lanes<16, 6>(d, fp32, st);
+  else launch_offdiag_lanes<8, 6>(d, fp32, st);
 }
 
 }  // namespace rpba

@@ -20,7 +20,7 @@ int main(int argc, char** argv) {
     return 2;
   std::fclose(f);
   rpba::Plan P;
-  const std::string e = rpba::build_plan(M, N, K, L, oc.data(), op.data(), cb.data(), 64, P);
+  const std::string e = rpba::build_plan(M, N, K, L, oc.data(), op.data(), cb.data(), 64, 6, P);
   if (!e.empty()) {
     std::printf("error %s\n", e.c_str());
     return 1;

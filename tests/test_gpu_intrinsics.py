@@ -1,0 +1,163 @@
+"""Intrinsics on the GPU: every camera's focal length f and first radial
+distortion parameter k1 estimated with its pose (Sec. 6, the n (6 + 2)
+camera parameters of the Final data sets), 8 x 8 camera blocks in the
+reduced camera systems.  Against the FP64 oracle on the same seeded oblique
+block (100 cameras in 3 sub-blocks, 6,000 points, f off by about 0.5% and
+k1 = 0 at the start, rendered with k1 up to 0.1).
+
+Bars: FP64 path 1e-9 relative per result, as for the pose-only path (the
+reduced camera system element-wise, per-step costs and step norms, cameras,
+f and k1, points; covariances at lambda = 1e-4, and 1e-8 at lambda = 1e-6,
+see their test).  Mixed path: the final RMS within 1e-6 of the oracle's,
+and f and k1 within a tenth of their standard deviations."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_08138_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def rp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_08138_amd import binding
+    binding.load_library()
+    return binding
+
+
+def _scene(seed=5, noise=None, n_blocks=3):
+    base = scenes.oblique_scene(seed, n_strips=2, n_stations=10, n_pts=6000, n_blocks=n_blocks, size_range=(10, 60),
+                                noise=noise)
+    return scenes.with_intrinsics(base, seed)
+
+
+def _extent(s):
+    C = s.cam_C_true
+    return float(np.linalg.norm(C.max(axis=1) - C.min(axis=1))) + 1.0
+
+
+def _rot_angle(R1, R2):
+    d = np.linalg.norm((R1 - R2).reshape(-1, 9), axis=1)
+    return float(np.max(2 * np.arcsin(np.minimum(d / (2 * np.sqrt(2)), 1.0))))
+
+
+@pytest.mark.parametrize("tile", [64, 32])
+def test_reduced_camera_system_with_intrinsics(rp, tile):
+    s = _scene()
+    gp = rp.Problem(s, chol_tile=tile)
+    op = oracle.OracleProblem(s)
+    assert gp.np == 8 and op.np == 8
+    gp.rpba_intersect()
+    op.intersect()
+    gp.rpba_subblock_lm_step()
+    op.lm_step()
+    for l in range(s.L):
+        Sg, eg = gp.block_rcs(l)
+        So, eo = op.block_rcs(l, Sg.shape[0])
+        assert Sg.shape[0] == 8 * int(np.sum(s.cam_block == l))
+        lo = np.tril(So)
+        assert np.abs(np.tril(Sg) - lo).max() <= TOL * np.abs(lo).max(), l
+        assert np.abs(eg - eo).max() <= TOL * np.abs(eo).max(), l
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_schedule_with_intrinsics(rp, graph):
+    s = _scene()
+    gp, gh = rp.run_schedule(s, T=3, I=2, graph=graph)
+    op, oh = oracle.run_schedule(s, T=3, I=2)
+    for g, o in zip(gh, oh):
+        assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0), (g["t"], g["int_stats"], o["int_stats"])
+        for bg, (bo, fails) in zip(g.get("steps", []), o.get("steps", [])):
+            assert fails == 0
+            assert np.allclose(bg[:, :2], bo[:, :2], rtol=TOL, atol=0)
+            assert np.allclose(bg[:, 2], bo[:, 2], rtol=TOL, atol=1e-15)
+    gR, gC = gp.cameras()
+    oR, oC = op.cameras()
+    assert np.abs(gC - oC).max() <= TOL * _extent(s)
+    assert _rot_angle(gR, oR) <= TOL
+    gf, gk = gp.intrinsics()
+    of, ok = op.intrinsics()
+    assert np.abs(gf - of).max() <= TOL * np.abs(of).max()
+    assert np.abs(gk - ok).max() <= TOL
+    # the schedule moved them: k1 started at 0
+    assert np.abs(gk).max() > 0.02
+    gX, _, gst = gp.intersection()
+    oX, _, ost = op.intersection()
+    assert np.array_equal(gst, ost)
+    assert np.abs(gX - oX).max() <= TOL * _extent(s)
+
+
+def test_mixed_precision_with_intrinsics_against_fp64_oracle(rp):
+    """FP32 Jacobians perturb the normal equations by about 1e-7 relative;
+    along the nearly flat direction that trades a camera's f against its
+    distance the solution then moves by more than 1e-7 relative.  The bar is
+    statistical: no f or k1 moves by more than a tenth of its standard
+    deviation (from the oracle's covariance of the sub-block systems), and
+    the final RMS agrees to 1e-6."""
+    s = _scene()
+    gp, gh = rp.run_schedule(s, T=3, I=2, precision=rp.RPBA_MIXED)
+    op, oh = oracle.run_schedule(s, T=3, I=2)
+    rg, ro = gh[-1]["int_stats"][2], oh[-1]["int_stats"][2]
+    gf, gk = gp.intrinsics()
+    of, ok = op.intrinsics()
+    cc, _ = op.covariance(1e-6)
+    sf, sk = np.sqrt(cc[:, 6, 6]), np.sqrt(cc[:, 7, 7])
+    df, dk = np.abs(gf - of) / sf, np.abs(gk - ok) / sk
+    print(f"mixed intrinsics: RMS rel {abs(rg - ro) / ro:.2e}; f max {np.abs(gf - of).max():.2e} px = "
+          f"{df.max():.2e} sigma (sigma_f median {np.median(sf):.2e}); k1 max {np.abs(gk - ok).max():.2e} = "
+          f"{dk.max():.2e} sigma")
+    assert abs(rg - ro) <= 1e-6 * ro
+    assert df.max() <= 0.1 and dk.max() <= 0.1
+
+
+def test_noise_free_block_recovers_the_intrinsics_on_the_gpu(rp):
+    """One sub-block, noise-free, Gauss-Newton (tiny damping): every f and
+    k1 reaches the values the scene was rendered with."""
+    base = scenes.oblique_scene(3, n_strips=2, n_stations=6, n_pts=3000, n_blocks=1, size_range=(10, 60), noise=0.0)
+    s = scenes.with_intrinsics(base, 3)
+    gp, gh = rp.run_schedule(s, T=3, I=6, lam=1e-10)
+    assert gh[-1]["int_stats"][2] < 1e-9
+    f, k1 = gp.intrinsics()
+    assert np.abs(f - s.cam_f_true).max() < 1e-7 * scenes.F_PX
+    assert np.abs(k1 - s.cam_k1_true).max() < 1e-9
+
+
+@pytest.mark.parametrize("lam,bar", [(1e-4, TOL), (1e-6, 1e-8)])
+def test_covariances_with_intrinsics(rp, lam, bar):
+    """Camera covariances (8 x 8 blocks of S^-1) and copy covariances
+    against the oracle's.  With f and k1 the parameters of a camera differ
+    in scale by up to eight orders of magnitude (radians, the centre,
+    pixels, the distortion), so an entry is compared relative to the
+    geometric mean of its two variances, sqrt(C_rr C_cc).  Both sides invert
+    the same S in different orders: they agree to about kappa_s u, kappa_s
+    the condition number of S scaled to a unit diagonal.  On this block the
+    oracle's S gives kappa_s of about 3e4 at lambda = 1e-4 (bar 1e-9) and
+    1.1e6 to 1.8e6 at the lambda = 1e-6 of final covariances, where the
+    direction that trades f against the camera's distance is barely damped
+    (bar 1e-8, about 40 kappa_s u)."""
+    s = _scene()
+    gp, _ = rp.run_schedule(s, T=2, I=2, covariance=1)
+    op, _ = oracle.run_schedule(s, T=2, I=2)
+    gc, gx = gp.covariance(lam)
+    oc, ox = op.covariance(lam)
+    assert gc.shape == oc.shape == (s.M, 8, 8)
+    worst = 0.0
+    for i in range(s.M):
+        d = np.sqrt(np.diag(oc[i]))
+        err = np.abs(gc[i] - oc[i]) / np.outer(d, d)
+        worst = max(worst, err.max())
+    print(f"camera covariances at lambda {lam:g}: largest error {worst:.2e} of sqrt(C_rr C_cc)")
+    assert worst <= bar
+    gblk, gpt, _, _ = gp.copies()
+    oblk, opt_, _, _ = op.copies()
+    o_at = {(int(b), int(p)): q for q, (b, p) in enumerate(zip(oblk, opt_))}
+    for q, (b, p) in enumerate(zip(gblk, gpt)):
+        r = ox[o_at[(int(b), int(p))]]
+        if np.any(r != 0):
+            assert np.abs(gx[q] - r).max() <= bar * np.abs(r).max(), q

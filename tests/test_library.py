@@ -114,6 +114,33 @@ def test_validation_rejects_empty_subblock_and_bad_tile():
         binding.default_options(lamda=1e-3)
 
 
+def test_intrinsics_options_are_validated_and_size_the_camera_system():
+    """Intrinsics (f and k1 per camera, Sec. 6) need their start values, the
+    direct solver and the extended variant; the reduced camera systems then
+    have 8 rows per camera (the dense RCS grows by (8/6)^2)."""
+    s = scenes.config_scene(1, 0)
+    L = binding.load_library()
+    d, keep = _desc(s)
+    fake = ctypes.c_void_p(512)
+    n = ctypes.c_size_t(0)
+
+    def size(cam_intr, **kw):
+        d.cam_intr = cam_intr
+        rc = L.rpba_workspace_size(ctypes.byref(d), ctypes.byref(binding.default_options(**kw)), ctypes.byref(n))
+        return rc, n.value, L.rpba_last_error().decode()
+    rc, _, msg = size(None, intrinsics=1)
+    assert rc == 1 and "cam_intr" in msg
+    rc, _, msg = size(fake.value, intrinsics=1, solver=binding.RPBA_SOLVER_PCG_BJ)
+    assert rc == 1 and "RPBA_SOLVER_CHOL" in msg
+    rc, _, msg = size(fake.value, intrinsics=1, variant=binding.RPBA_VARIANT_PLAIN)
+    assert rc == 1 and "RPBA_VARIANT_EXTENDED" in msg
+    rc, _, msg = size(fake.value, intrinsics=2)
+    assert rc == 1 and "intrinsics" in msg
+    rc6, n6, _ = size(None)
+    rc8, n8, _ = size(fake.value, intrinsics=1)
+    assert rc6 == 0 and rc8 == 0 and n8 > n6
+
+
 def test_optional_arrays_take_workspace_only_when_asked():
     """The covariance array (one more dense RCS) and the adaptive-damping
     copy positions (24 bytes per copy) are laid out only with their options."""
