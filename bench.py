@@ -166,6 +166,24 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1910_0
                        "precond_config5.npy")
 
 
+def intrinsics_side(scene, seed, steps, warmup, log=print):
+    """The same block with every camera's focal length and radial
+    distortion estimated with its pose (Sec. 6: 8 x 8 camera blocks), the
+    observations rendered again with per-camera values: ms per step on both
+    paths (library defaults; the step as in the headline)."""
+    from paper_1910_08138_amd import binding, scenes
+    s = scenes.with_intrinsics(scene, seed)
+    out = {"workload": "oblique-strips-6000cam-2.5Mpt-64subblocks with f and k1 per camera",
+           "camera_parameters": 8}
+    for path, prec in (("mixed", binding.RPBA_MIXED), ("fp64", binding.RPBA_FP64)):
+        r = run_path(s, dict(precision=prec), steps, warmup)
+        out[path] = {"ms_per_step": r["ms_per_step"], "value": r["value"], "unit": "obs/s",
+                     "phase_ms_per_step": {k: v["ms"] / steps for k, v in r["phases"].items() if v["ms"] > 0}}
+        log(f"intrinsics {path}: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G obs/s; phases: " +
+            ", ".join(f"{k} {v:.3f}" for k, v in out[path]["phase_ms_per_step"].items()))
+    return out
+
+
 def learned_pcg(scene, steps=3):
     """LM step of the mixed path with PCG on the sub-blocks of at least 150
     cameras (Cholesky on the others), preconditioned by block-Jacobi and by
@@ -444,6 +462,9 @@ def main():
     if args.path == "mixed" and not args.small and not args.no_compare:
         lp = learned_pcg(scene)
         lp["cholesky_lm_step_ms"] = lm_ms
+    intr = None
+    if not args.small and not args.no_compare:
+        intr = intrinsics_side(scene, args.seed, args.steps, args.warmup, log=log)
     cpu = None
     if not args.no_cpu_baseline:
         model = "unknown"
@@ -516,6 +537,7 @@ def main():
         "tuning": head["tuning"],
         "final_rms_vs_oracle": oracle_rms,
         "learned_pcg": lp,
+        "intrinsics": intr,
     }
     if not args.no_compare:
         other = [p for p in out_paths if p != args.path][0]
