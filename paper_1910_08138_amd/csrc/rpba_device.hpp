@@ -204,8 +204,10 @@ __device__ __forceinline__ void rotate_left(const double w[3], const double* Rin
     a = 1.0;
     b = 0.5;
   } else {
-    a = sin(th) / th;
-    b = (1.0 - cos(th)) / th2;
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    a = sn / th;
+    b = (1.0 - cs) / th2;
   }
   // E = I + a K + b K^2 with K = [w]x, K^2 = w w^T - th2 I
   double E[9];

@@ -219,6 +219,7 @@ void launch_consensus(const Dev& d, double* stats, hipStream_t st);
 // PLAIN variants: every copy starts at its point's start value, duals zero
 void launch_init_copies(const Dev& d, hipStream_t st);
 void launch_zero(double* p, int64_t n, hipStream_t st);
+void launch_zero_wide(double* p, int64_t n, hipStream_t st);  // p 16-byte aligned
 void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 void launch_rcs_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);
 void launch_bsr_extract(const Dev& d, int l, double* S_out, double* e_out, hipStream_t st);

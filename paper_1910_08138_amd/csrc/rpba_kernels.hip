@@ -176,6 +176,19 @@ __global__ void k_gather_pts(Dev d) {
 __global__ void k_zero(double* p, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) p[t] = 0.0;
 }
+// the same for a large 16-byte aligned array: 16-byte stores, four per
+// thread and round
+__global__ void k_zero_wide(double* p, int64_t n) {
+  double2* q = reinterpret_cast<double2*>(p);
+  const int64_t n2 = n / 2, stride = (int64_t)gridDim.x * NT;
+  const double2 z = make_double2(0.0, 0.0);
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n2; t += 4 * stride) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (t + u * stride < n2) q[t + u * stride] = z;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) p[n - 1] = 0.0;
+}
 
 __global__ void k_zero_i32(int32_t* p, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) p[t] = 0;
@@ -1120,25 +1133,41 @@ __global__ __launch_bounds__(NT) void k_back_update(Dev d) {
 // per sub-block sums of the copy passes' slots: the cost before the step
 // (point-block pass, UPD false) or the cost after it and the squared step of
 // the copies (update pass, UPD true), from the slots of the workgroups that
-// hold the sub-block's copies (one wave per sub-block, lanes over the
-// workgroups); added to what is already there (the camera steps' squares,
+// hold the sub-block's copies (one workgroup per sub-block, threads over
+// those workgroups); added to what is already there (the camera steps' squares,
 // the cost before of fresh sub-blocks, and the rare overflow adds)
 template <bool UPD>
-__global__ void k_slots_reduce(Dev d) {
-  const int l = blockIdx.x * (NT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (l >= d.L) return;
+__global__ __launch_bounds__(NT) void k_slots_reduce(Dev d) {
+  __shared__ double sh[2 * (NT / 64)];
+  const int l = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // the point-block pass skipped every copy of a fresh sub-block whose
-  // records the intersection wrote: nothing to add
+  // records the intersection wrote: nothing to add (uniform over the workgroup)
   if (!UPD && *d.rec_valid != 0 && d.blk_fresh[l]) return;
   const int64_t c0 = d.blk_copy_off[l], c1 = d.blk_copy_off[l + 1];
   double a = 0.0, b = 0.0;
   if (c1 > c0) {
+    // one workgroup per sub-block, U workgroups' slots per thread in flight
+    constexpr int U = 4;
     const int64_t w0 = c0 / NT, w1 = (c1 - 1) / NT;
-    for (int64_t w = w0 + lane; w <= w1; w += 64) {
-      const int slot = l - d.copy_blk[w * NT];
-      if (slot >= 0 && slot < 8) {
-        a += d.upd_part[16 * w + slot];
-        if (UPD) b += d.upd_part[16 * w + 8 + slot];
+    for (int64_t wb = w0 + threadIdx.x; wb <= w1; wb += U * NT) {
+      int slot[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t w = wb + u * NT;
+        slot[u] = w <= w1 ? l - d.copy_blk[w * NT] : -1;
+      }
+      double va[U], vb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t w = wb + u * NT;
+        const bool in = slot[u] >= 0 && slot[u] < 8;
+        va[u] = in ? d.upd_part[16 * w + slot[u]] : 0.0;
+        vb[u] = UPD && in ? d.upd_part[16 * w + 8 + slot[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a += va[u];
+        b += vb[u];
       }
     }
   }
@@ -1147,11 +1176,21 @@ __global__ void k_slots_reduce(Dev d) {
     if (UPD) b += __shfl_xor(b, o);
   }
   if (lane == 0) {
+    sh[wv] = a;
+    sh[NT / 64 + wv] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      sa += sh[w];
+      sb += sh[NT / 64 + w];
+    }
     if (UPD) {
-      d.acc_blk[4 * l + 1] += a;
-      d.acc_blk[4 * l + 2] += b;
+      d.acc_blk[4 * l + 1] += sa;
+      d.acc_blk[4 * l + 2] += sb;
     } else {
-      d.acc_blk[4 * l + 0] += a;
+      d.acc_blk[4 * l + 0] += sa;
     }
   }
 }
@@ -1317,11 +1356,21 @@ __global__ __launch_bounds__(NT) void k_consensus_pts(Dev d) {
 
 // the four statistics of an intersection from the per-workgroup partials
 // (one workgroup of 1,024 threads, a fixed order: the sums are reproducible)
+// the intersection's per-workgroup partials, summed by INT_RED_WG
+// workgroups whose sums are added to acc_int[0..3] (zeroed with the launch):
+// a few dozen atomic adds per word instead of one workgroup reading them all
+constexpr int INT_RED_WG = 64;
 __global__ __launch_bounds__(1024) void k_int_reduce(Dev d, int nwg) {
   __shared__ double sh[4 * 16];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int t = threadIdx.x; t < nwg; t += blockDim.x)
-    for (int q = 0; q < 4; ++q) v[q] += d.int_part[4 * (int64_t)t + q];
+  const double4* p4 = reinterpret_cast<const double4*>(d.int_part);
+  for (int t = blockIdx.x * (int)blockDim.x + threadIdx.x; t < nwg; t += (int)(gridDim.x * blockDim.x)) {
+    const double4 a = p4[t];
+    v[0] += a.x;
+    v[1] += a.y;
+    v[2] += a.z;
+    v[3] += a.w;
+  }
   for (int q = 0; q < 4; ++q)
     for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1331,7 +1380,7 @@ __global__ __launch_bounds__(1024) void k_int_reduce(Dev d, int nwg) {
   if (threadIdx.x < 4) {
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[16 * threadIdx.x + w];
-    d.acc_int[threadIdx.x] = s;
+    atomicAdd(&d.acc_int[threadIdx.x], s);
   }
 }
 
@@ -1340,9 +1389,20 @@ __global__ __launch_bounds__(1024) void k_int_reduce(Dev d, int nwg) {
 __global__ __launch_bounds__(1024) void k_consensus_reduce(Dev d, int nwg) {
   __shared__ double sh[32];
   double mx = 0.0, sum = 0.0;
-  for (int t = threadIdx.x; t < nwg; t += blockDim.x) {
-    mx = fmax(mx, d.cons_part[2 * t]);
-    sum += d.cons_part[2 * t + 1];
+  constexpr int U = 8;  // partials in flight per thread
+  const double2* p2 = reinterpret_cast<const double2*>(d.cons_part);
+  for (int t0 = threadIdx.x; t0 < nwg; t0 += U * (int)blockDim.x) {
+    double2 a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      a[u] = t < nwg ? p2[t] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      mx = fmax(mx, a[u].x);
+      sum += a[u].y;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
     mx = fmax(mx, __shfl_xor(mx, o));
@@ -1545,6 +1605,13 @@ void launch_zero(double* p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3(g), dim3(NT), 0, st, p, n);
 }
 
+void launch_zero_wide(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned g = grid_for((n / 2 + 3) / 4);
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_zero_wide, dim3(g), dim3(NT), 0, st, p, n);
+}
+
 void launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   unsigned g = grid_for(n);
@@ -1589,7 +1656,7 @@ void launch_intersect(const Dev& d, bool want_cov, hipStream_t st) {
       else launch_intersect_var<RPBA_VARIANT_EXTENDED>(d, want_cov, st);
       break;
   }
-  hipLaunchKernelGGL(k_int_reduce, dim3(1), dim3(1024), 0, st, d, (int)grid_for(d.N, IT));
+  hipLaunchKernelGGL(k_int_reduce, dim3(INT_RED_WG), dim3(1024), 0, st, d, (int)grid_for(d.N, IT));
 }
 
 void launch_intersect_export(const Dev& d, double* cov, int32_t* status_out, double* stats, hipStream_t st) {
@@ -1611,7 +1678,7 @@ void launch_copy_prep(const Dev& d, hipStream_t st) {
     if (d.cpk_f32) hipLaunchKernelGGL((k_copy_prep<float, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
     else hipLaunchKernelGGL((k_copy_prep<double, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
   }
-  hipLaunchKernelGGL(k_slots_reduce<false>, dim3(grid_for(d.L, NT / 64)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_slots_reduce<false>, dim3(d.L), dim3(NT), 0, st, d);
 }
 
 void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
@@ -1623,7 +1690,7 @@ void launch_update(const Dev& d, double* block_stats, hipStream_t st) {
     if (d.cpk_f32) hipLaunchKernelGGL((k_back_update<float, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
     else hipLaunchKernelGGL((k_back_update<double, false>), dim3(grid_for(d.NC)), dim3(NT), 0, st, d);
   }
-  hipLaunchKernelGGL(k_slots_reduce<true>, dim3(grid_for(d.L, NT / 64)), dim3(NT), 0, st, d);
+  hipLaunchKernelGGL(k_slots_reduce<true>, dim3(d.L), dim3(NT), 0, st, d);
   hipLaunchKernelGGL(k_update_finish, dim3(grid_for(std::max<int64_t>((int64_t)CAM_STRIDE * d.M, d.L))), dim3(NT), 0,
                      st, d, block_stats);
   if (d.lam_blk) hipLaunchKernelGGL(k_restore_copies, dim3(grid_for(d.NC)), dim3(NT), 0, st, d);

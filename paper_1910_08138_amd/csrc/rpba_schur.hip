@@ -404,7 +404,7 @@ void launch_schur_diag(const Dev& d, bool fp32, bool dense, int64_t rcs_total, h
   if (dense) {
     // every lower element not covered by a pair block is zero; the padded
     // identity of the last diagonal tile is restored as well
-    launch_zero(d.S, rcs_total, st);
+    launch_zero_wide(d.S, rcs_total, st);
     launch_init_rcs(d, st);
   }
   const unsigned gd = (unsigned)((d.M + 3) / 4);
