@@ -161,3 +161,72 @@ def test_covariances_with_intrinsics(rp, lam, bar):
         r = ox[o_at[(int(b), int(p))]]
         if np.any(r != 0):
             assert np.abs(gx[q] - r).max() <= bar * np.abs(r).max(), q
+
+
+def _info(K, seed):
+    """Seeded SPD information matrices: W = R diag(1/s1^2, 1/s2^2) R^T with
+    s1, s2 ~ U[0.3, 0.8] px and R a rotation by an angle ~ U[0, pi)."""
+    rng = np.random.default_rng(seed)
+    s1, s2, th = rng.uniform(0.3, 0.8, K), rng.uniform(0.3, 0.8, K), rng.uniform(0.0, np.pi, K)
+    c, sn = np.cos(th), np.sin(th)
+    return np.stack([c * c / s1 ** 2 + sn * sn / s2 ** 2, c * sn * (1.0 / s1 ** 2 - 1.0 / s2 ** 2),
+                     sn * sn / s1 ** 2 + c * c / s2 ** 2])
+
+
+def test_intrinsics_with_information_matrices_and_robust_weights(rp):
+    """2% gross errors, per-observation information matrices and the robust
+    re-weighting from the second outer iteration: the intrinsic columns go
+    through the branches with non-unit weights of the Schur, point-block and
+    update passes."""
+    base = scenes.oblique_scene(6, n_strips=2, n_stations=10, n_pts=6000, n_blocks=3, size_range=(10, 60),
+                                outlier_frac=0.02)
+    s = scenes.with_intrinsics(base, 6)
+    W = _info(s.K, 6)
+    gp, gh = rp.run_schedule(s, T=4, I=2, robust=True, t_r=1, obs_info=W, graph=True)
+    op, oh = oracle.run_schedule(s, T=4, I=2, robust=True, t_r=1, obs_info=W)
+    for g, o in zip(gh, oh):
+        assert np.allclose(g["int_stats"], o["int_stats"], rtol=TOL, atol=0), (g["t"], g["int_stats"], o["int_stats"])
+        for bg, (bo, fails) in zip(g.get("steps", []), o.get("steps", [])):
+            assert fails == 0
+            assert np.allclose(bg[:, :2], bo[:, :2], rtol=TOL, atol=0)
+    _, wg = gp.robust_result()
+    assert np.array_equal(wg, op.weights()) and (wg < 1).sum() > 0
+    gf, gk = gp.intrinsics()
+    of, ok = op.intrinsics()
+    assert np.abs(gf - of).max() <= TOL * np.abs(of).max()
+    assert np.abs(gk - ok).max() <= TOL
+    _, gC = gp.cameras()
+    _, oC = op.cameras()
+    assert np.abs(gC - oC).max() <= TOL * _extent(s)
+
+
+def test_intrinsics_with_adaptive_damping(rp):
+    """f off by 5% at the start and lambda = 1e-8: some steps raise their
+    sub-block's cost and are taken back, f and k1 with the pose."""
+    base = scenes.oblique_scene(5, n_strips=2, n_stations=10, n_pts=6000, n_blocks=3, size_range=(10, 60))
+    s = scenes.with_intrinsics(base, 5, f_start_rel=0.05)
+    gp = rp.Problem(s, lam=1e-8, damping=rp.RPBA_DAMPING_ADAPTIVE)
+    op = oracle.OracleProblem(s, lam=1e-8)
+    op.set_damping(1)
+    n_rej = 0
+    for t in range(2):
+        g = gp.rpba_intersect()
+        o = op.intersect()
+        gp.sync()
+        assert np.allclose(g.cpu().numpy(), o, rtol=TOL, atol=0)
+        for i in range(4):
+            gb = gp.rpba_subblock_lm_step()
+            gp.sync()
+            ob, _ = op.lm_step()
+            gl, gr = gp.damping()
+            ol, orj = op.damping()
+            assert np.array_equal(gr, orj) and np.array_equal(gl, ol), (t, i, gl, ol, gr, orj)
+            assert np.allclose(gb.cpu().numpy()[:, :2], ob[:, :2], rtol=TOL, atol=0), (t, i)
+            n_rej += int(gr.sum())
+        gp.rpba_consensus()
+        op.consensus()
+    assert n_rej > 0
+    gf, gk = gp.intrinsics()
+    of, ok = op.intrinsics()
+    assert np.abs(gf - of).max() <= TOL * np.abs(of).max()
+    assert np.abs(gk - ok).max() <= TOL
