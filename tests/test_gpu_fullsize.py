@@ -49,7 +49,7 @@ def _gpu_run(s, **opts):
     st2 = binding._host(p, p.rpba_intersect())
     R, C = p.cameras()
     X, cov, status = p.intersection()
-    out = dict(st1=st1, bs=bs, cons=cons, st2=st2, R=R, C=C, X=X, cov=cov, status=status)
+    out = dict(st1=st1, bs=bs, cons=cons, st2=st2, R=R, C=C, X=X, cov=cov, status=status, intr=p.intrinsics())
     del p
     return out
 
@@ -189,3 +189,37 @@ def test_fullsize_config4_mixed_robust_against_oracle():
     assert np.quantile(dc, 0.99) <= 1e-6 and dc.max() <= 1e-5
     assert np.quantile(dr, 0.99) <= 1e-5 and dr.max() <= 1e-4
     assert np.quantile(rel, 0.9999) <= 1e-4 and rel.max() <= 2e-3
+
+
+def test_fullsize_intrinsics_fp64_parity():
+    """The same block with f and k1 estimated per camera (8 x 8 camera
+    blocks, reduced camera systems of up to 2,528 rows): one outer iteration
+    and the next intersection on the FP64 path against the oracle, 1e-9."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = scenes.with_intrinsics(scenes.config_scene(3, 0), 0)
+    op = oracle.OracleProblem(s)
+    o = dict(st1=op.intersect())
+    o["bs"], fails = op.lm_step()
+    o["cons"] = op.consensus()
+    o["st2"] = op.intersect()
+    o["R"], o["C"] = op.cameras()
+    o["X"], _, o["status"] = op.intersection()
+    of, ok1 = op.intrinsics()
+    del op
+    print("oracle done", flush=True)
+    g = _gpu_run(s)
+    assert fails == 0 and np.all(g["bs"][:, 3] >= 0)
+    assert np.allclose(g["st1"], o["st1"], rtol=TOL, atol=0), (g["st1"], o["st1"])
+    assert np.allclose(g["bs"][:, :3], o["bs"][:, :3], rtol=TOL, atol=0)
+    assert np.allclose(g["st2"], o["st2"], rtol=TOL, atol=0), (g["st2"], o["st2"])
+    assert np.abs(g["C"] - o["C"]).max() <= TOL * _extent(s)
+    assert np.abs(g["R"] - o["R"]).max() <= TOL
+    assert np.array_equal(g["status"], o["status"])
+    ok = o["status"] == 0
+    assert np.abs(g["X"][:, ok] - o["X"][:, ok]).max() <= TOL * _extent(s)
+    gf, gk = g["intr"]
+    print(f"f max rel {np.abs(gf - of).max() / of.max():.2e}, k1 max abs {np.abs(gk - ok1).max():.2e}", flush=True)
+    assert np.abs(gf - of).max() <= TOL * of.max()
+    assert np.abs(gk - ok1).max() <= TOL
