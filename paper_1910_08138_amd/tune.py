@@ -18,8 +18,9 @@ The search is coordinate-wise: each stage keeps the best configuration of
 the previous one and varies one choice.
 
 Results are cached in a JSON file keyed by a signature of the problem's shape
-(camera, point and observation counts and the sorted sub-block sizes) and the
-precision, so a second run on the same shape reuses the choice.
+(camera, point and observation counts and the sorted sub-block sizes), the
+precision and whether the cameras carry intrinsics, so a second run on the
+same shape reuses the choice.
 """
 from __future__ import annotations
 
@@ -38,17 +39,22 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "rpba_tune.json"
 def signature(scene, precision) -> str:
     sizes = np.sort(np.bincount(scene.cam_block, minlength=scene.L))
     h = hashlib.sha1()
-    h.update(np.asarray([scene.M, scene.N, scene.K, scene.L, int(precision)], dtype=np.int64).tobytes())
+    intr = int(getattr(scene, "cam_f", None) is not None)
+    h.update(np.asarray([scene.M, scene.N, scene.K, scene.L, int(precision), intr], dtype=np.int64).tobytes())
     h.update(sizes.astype(np.int64).tobytes())
     return h.hexdigest()[:20]
 
 
-def stages(precision):
+def stages(precision, intrinsics=False):
     """The candidate configurations of each search stage; a stage's entries
-    override the best configuration found so far."""
+    override the best configuration found so far.  With intrinsics (8 x 8
+    camera blocks) the pair pass always takes 8 lanes and every sub-block is
+    solved directly, so only the factorisation is searched."""
     out = [[dict(chol_tile=t, chol_schedule=sc, pair_lanes=8, pcg_min_cams=None)
-            for t in (64, 32) for sc in (binding.RPBA_CHOL_DATAFLOW, binding.RPBA_CHOL_STEPWISE)],
-           [dict(pair_lanes=g) for g in (4, 16)]]
+            for t in (64, 32) for sc in (binding.RPBA_CHOL_DATAFLOW, binding.RPBA_CHOL_STEPWISE)]]
+    if intrinsics:
+        return out
+    out.append([dict(pair_lanes=g) for g in (4, 16)])
     if precision == binding.RPBA_MIXED:
         out.append([dict(pcg_min_cams=c) for c in (300, 200, 150)])
     return out
@@ -106,7 +112,7 @@ def tune(scene, precision=binding.RPBA_FP64, cache_path=DEFAULT_CACHE, steps=5, 
         return _options(ent["choice"], precision), ent["table"]
     table = []
     best = None
-    for stage in stages(precision):
+    for stage in stages(precision, getattr(scene, "cam_f", None) is not None):
         base = dict(best) if best else {}
         for k in ("ms", "fails"):
             base.pop(k, None)

@@ -194,3 +194,14 @@ def test_library_ratio_rule_many_loops_at_once():
     assert n == 1
     assert act.tolist() == [1, 0, 0] and grace.tolist() == [1, 1, 0]
     assert best.tolist() == [99.5, 99.5, 5.0]
+
+
+def test_tuner_stages_with_intrinsics():
+    """With f and k1 per camera only the factorisation is searched (the pair
+    pass takes 8 lanes, every sub-block is solved directly)."""
+    from paper_1910_08138_amd import tune
+    st = tune.stages(binding.RPBA_MIXED, intrinsics=True)
+    assert len(st) == 1 and all(c["pcg_min_cams"] is None and c["pair_lanes"] == 8 for c in st[0])
+    assert len(tune.stages(binding.RPBA_MIXED)) == 3 and len(tune.stages(binding.RPBA_FP64)) == 2
+    s = scenes.config_scene(1, 0)
+    assert tune.signature(s, binding.RPBA_MIXED) != tune.signature(scenes.with_intrinsics(s, 0), binding.RPBA_MIXED)
