@@ -93,6 +93,32 @@ def test_schedule_with_intrinsics(rp, graph):
     assert np.abs(gX - oX).max() <= TOL * _extent(s)
 
 
+@pytest.mark.parametrize("tile", [64, 32])
+def test_stepwise_factorisation_with_intrinsics(rp, tile):
+    """The three-launches-per-tile-column schedule on the 8-row systems: two
+    LM steps against the oracle."""
+    s = _scene()
+    gp = rp.Problem(s, chol_tile=tile, chol_schedule=rp.RPBA_CHOL_STEPWISE)
+    op = oracle.OracleProblem(s)
+    gp.rpba_intersect()
+    op.intersect()
+    for _ in range(2):
+        gb = gp.rpba_subblock_lm_step()
+        gp.sync()
+        ob, fails = op.lm_step()
+        assert fails == 0
+        assert np.allclose(gb.cpu().numpy()[:, :3], ob[:, :3], rtol=TOL, atol=0)
+    # the caller's f and k1 are written by rpba_consensus only
+    gf, gk = gp.intrinsics()
+    assert np.array_equal(gf, s.cam_f) and np.all(gk == 0)
+    gp.rpba_consensus()
+    op.consensus()
+    gf, gk = gp.intrinsics()
+    of, ok = op.intrinsics()
+    assert np.abs(gf - of).max() <= TOL * np.abs(of).max() and np.abs(gk - ok).max() <= TOL
+    assert np.abs(gk).max() > 0
+
+
 def test_mixed_precision_with_intrinsics_against_fp64_oracle(rp):
     """FP32 Jacobians perturb the normal equations by about 1e-7 relative;
     along the nearly flat direction that trades a camera's f against its
