@@ -152,7 +152,7 @@ WsMap layout_for(const Plan& P, bool keep_res, bool plain, bool cov, bool adapti
   m.pm_w = L.add(P.has_info ? f8 * 3 * P.K : 0);
   m.cam_obs_c = L.add(i4 * P.cam_obs_c.size());
   m.df_tasks = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
-  m.df_flags = L.add(i4 * (P.rcs_total / ((int64_t)P.T * P.T)));
+  m.df_flags = L.add(i4 * 2 * (P.rcs_total / ((int64_t)P.T * P.T)));  // ready flags, then partial-sum flags
   m.df_ctl = L.add(i4 * 4);
   m.blk_fresh = L.add(i4 * P.L);
   m.dfb_tasks = L.add(i4 * (P.vec_total / P.T));
@@ -753,7 +753,7 @@ rpba_status rpba_create(const rpba_problem_desc* d, const rpba_options* o, void*
   launch_zero_i32(D.blk_fail, D.L, st);
   launch_zero_i32(D.blk_nc, D.L, st);
   launch_zero_i32(D.rec_valid, 1, st);
-  launch_zero_i32((int32_t*)(w + m.df_flags), p.rcs_total / ((int64_t)p.T * p.T), st);
+  launch_zero_i32((int32_t*)(w + m.df_flags), 2 * (p.rcs_total / ((int64_t)p.T * p.T)), st);
   launch_zero_i32((int32_t*)(w + m.df_ctl), 4, st);
   launch_df_reset((int32_t*)(w + m.df_ctl), st);
   launch_zero_i32(D.blk_fresh, D.L, st);
@@ -824,7 +824,8 @@ static rpba_status chol_forward(rpba_problem* h, const int32_t* pot, const int32
   hipStream_t st = h->stream;
   if (h->dataflow) {
     launch_chol_dataflow(h->d, (const int32_t*)(h->ws + h->map.df_tasks), h->df_ntask,
-                         (int*)(h->ws + h->map.df_flags), (int*)(h->ws + h->map.df_ctl), h->df_fwd_workers, st);
+                         (int*)(h->ws + h->map.df_flags), h->plan->rcs_total / ((int64_t)h->plan->T * h->plan->T),
+                         (int*)(h->ws + h->map.df_ctl), h->df_fwd_workers, st);
     return RPBA_OK;
   }
   for (int k = 0; k < h->nt_max_dense; ++k) {

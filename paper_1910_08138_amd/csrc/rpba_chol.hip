@@ -611,14 +611,21 @@ __global__ void k_df_finish(Dev d, int* ctl) {
   }
 }
 
+// A nonzero sub-diagonal tile (j, j-1) of the factor is solved by the task
+// of diagonal tile j: its own task only sums its products and publishes the
+// partial sums (second half of the flag array); the diagonal task solves it
+// with the inverse of diagonal tile j-1, publishes it, and subtracts its
+// product from its own sums in LDS.  One hand-over through memory less on
+// the chain diagonal (j-1) -> tile (j, j-1) -> diagonal (j).
 template <int T>
 __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* __restrict__ tasks, int ntask, int* flags,
-                                                      int* ctl) {
+                                                      int64_t nflags, int* ctl) {
   constexpr int LD = DiagLds<T>::LD;
   __shared__ DiagLds<T> sm;
   __shared__ int s_task, s_poll;
   const int epoch = ctl[1];
   int* err = ctl + 2;
+  int* pflags = flags + nflags;
   for (;;) {
     __syncthreads();  // the previous task is done with s_task and LDS
     if (threadIdx.x == 0) s_task = atomicAdd(ctl, 1);
@@ -630,6 +637,7 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
     if (d.active && !d.active[l]) continue;
     const int64_t tile0 = d.rcs_off[l] / (T * T);
     auto fl = [&](int r, int c) { return flags + tile0 + (int64_t)r * (r + 1) / 2 + c; };
+    auto pfl = [&](int r, int c) { return pflags + tile0 + (int64_t)r * (r + 1) / 2 + c; };
     double* C = tile_ptr<T>(d, l, i, j);
     Acc<T> acc;
 #pragma unroll
@@ -646,17 +654,36 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
     // products with a tile that stays zero are left out
     const uint8_t* nzi = d.tile_nz + tile0 + (int64_t)i * (i + 1) / 2;
     const uint8_t* nzj = d.tile_nz + tile0 + (int64_t)j * (j + 1) / 2;
+    const int nt = d.nt[l];
+    const bool partial = i == j + 1 && i < nt && nzi[j];  // sub-diagonal tile: products only
+    const bool fused = i == j && j >= 1 && nzj[j - 1];     // diagonal task that solves (j, j-1)
+    const int kend = fused ? j - 1 : j;
     int kready = 0;  // every k < kready is known to be ready
-    for (int k = 0; k < j; ++k) {
+    for (int k = 0; k < kend; ++k) {
       if (!nzi[k] || !nzj[k]) continue;
       if (k >= kready) {
-        kready = df_poll(fl(i, 0), i == j ? nullptr : fl(j, 0), nzi, nzj, k, j, epoch, &s_poll);
+        kready = df_poll(fl(i, 0), i == j ? nullptr : fl(j, 0), nzi, nzj, k, kend, epoch, &s_poll);
         if (kready == k) {
           df_wait(fl(i, k), i == j ? nullptr : fl(j, k), epoch, err);
           kready = k + 1;
         }
       }
       gemm_nt_mf_pipe<T, true, true, true>(tile_ptr<T>(d, l, i, k), tile_ptr<T>(d, l, j, k), acc);
+    }
+    if (partial) {
+      // the partial sums of tile (i, j), for the diagonal task i
+#pragma unroll
+      for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+        for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            int r, c;
+            acc_rc<T>(p, q, e, r, c);
+            coh_store(C + mf_idx(T, r, c), acc.v[p][q][e]);
+          }
+      df_publish(pfl(i, j), epoch);
+      continue;
     }
     if (i == j) {
       // diagonal: factor and inverse through LDS
@@ -671,6 +698,47 @@ __global__ __launch_bounds__(NT, 2) void k_chol_dataflow(Dev d, const int32_t* _
             acc_rc<T>(p, q, e, r, c);
             sm.A[r * LD + c] = acc.v[p][q][e];
           }
+      if (fused) {
+        // tile (j, j-1), its sums already in LDS as the diagonal's are:
+        // the partial sums staged (matrix-core layout), solved with the
+        // inverse of diagonal tile j-1, stored and published; then
+        // A(j,j) -= L(j,j-1) L(j,j-1)^T from the copy in LDS
+        double* Cs = tile_ptr<T>(d, l, j, j - 1);
+        // the partial sums are usually ready long before diagonal tile j-1:
+        // staged first, so that only the solve waits for it
+        df_wait(pfl(j, j - 1), nullptr, epoch, err);
+        for (int idx = threadIdx.x; idx < T * T; idx += NT) sm.X[idx] = coh_load(Cs + idx);
+        df_wait(fl(j - 1, j - 1), nullptr, epoch, err);  // (its barrier also orders the LDS stores)
+        const double* Lim = d.Li + d.diag_off[l] + (int64_t)(j - 1) * T * T;
+        Acc<T> out;
+        out.zero();
+        gemm_nt_mf_pipe<T, false, false, true>(sm.X, Lim, out);
+        __syncthreads();  // every wave has read the partial sums
+#pragma unroll
+        for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+          for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              int r, c;
+              acc_rc<T>(p, q, e, r, c);
+              coh_store(Cs + mf_idx(T, r, c), out.v[p][q][e]);
+              sm.X[mf_idx(T, r, c)] = out.v[p][q][e];
+            }
+        df_publish(fl(j, j - 1), epoch);  // (its barrier also orders the LDS stores)
+        out.zero();
+        gemm_nt_mf_pipe<T, true, false, false>(sm.X, sm.X, out);
+#pragma unroll
+        for (int p = 0; p < Acc<T>::NB; ++p)
+#pragma unroll
+          for (int q = 0; q < Acc<T>::NB; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              int r, c;
+              acc_rc<T>(p, q, e, r, c);
+              sm.A[r * LD + c] += out.v[p][q][e];
+            }
+      }
       __syncthreads();
       factor_inverse_tile<T>(sm);
       double* Li = d.Li + d.diag_off[l] + (int64_t)j * T * T;
@@ -902,14 +970,14 @@ int chol_dataflow_resident_per_cu(int T) {
   return e == hipSuccess ? n : 0;
 }
 
-void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
-                          hipStream_t st) {
+void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int64_t nflags, int* ctl,
+                          int nworkers, hipStream_t st) {
   if (ntask > 0) {
     const unsigned g = (unsigned)std::max(1, std::min(ntask, nworkers));
     if (d.T == 64)
-      hipLaunchKernelGGL(k_chol_dataflow<64>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, ctl);
+      hipLaunchKernelGGL(k_chol_dataflow<64>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, nflags, ctl);
     else
-      hipLaunchKernelGGL(k_chol_dataflow<32>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, ctl);
+      hipLaunchKernelGGL(k_chol_dataflow<32>, dim3(g), dim3(NT), 0, st, d, tasks, ntask, flags, nflags, ctl);
   }
 }
 

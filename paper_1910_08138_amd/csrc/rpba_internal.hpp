@@ -203,8 +203,8 @@ void launch_chol_update(const Dev& d, int k, const int32_t* upd, int64_t nupd, h
 // chol_dataflow_resident_per_cu: its workgroups that fit on one CU at once
 // (0 if the query fails)
 int chol_dataflow_resident_per_cu(int T);
-void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int* ctl, int nworkers,
-                          hipStream_t st);
+void launch_chol_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* flags, int64_t nflags, int* ctl,
+                          int nworkers, hipStream_t st);
 // the backward substitution as one persistent launch (ctl[3] = its ticket)
 void launch_chol_backward_dataflow(const Dev& d, const int32_t* tasks, int ntask, int* xflags, int* ctl,
                                    int nworkers, hipStream_t st);

@@ -541,23 +541,48 @@ std::vector<int32_t> dataflow_order(const Plan& P, const std::vector<int32_t>& b
     const int32_t l = blocks[b], n = P.nt[l];
     const uint8_t* z = P.tile_nz.data() + P.rcs_off[l] / T2;
     auto nz = [&](int32_t i, int32_t j) { return z[i * (i + 1) / 2 + j] != 0; };
+    // a nonzero sub-diagonal tile (j, j - 1) of the factor is solved by the
+    // task of diagonal tile j (fused): its own task only sums its products
+    // (partial), and tile (j, j - 1) is ready when the diagonal task has
+    // solved it
+    auto fused = [&](int32_t j) { return j >= 1 && j < n && nz(j, j - 1); };
+    auto producer = [&](int32_t r, int32_t c) { return r == c + 1 && fused(r) ? id(b, r, r) : id(b, r, c); };
     for (int32_t j = 0; j < n; ++j)
       for (int32_t i = j; i <= n; ++i) {
         if (!nz(i, j)) continue;
         const int64_t t = id(b, i, j);
         tasks[t] = {l, i, j};
         live[t] = 1;
-        int32_t nprod = 0;
-        for (int32_t k = 0; k < j; ++k) {
+        const bool partial = i == j + 1 && fused(i);
+        const bool fd = i == j && fused(j);
+        int32_t nprod = 0, ndep = 0;
+        for (int32_t k = 0; k < (fd ? j - 1 : j); ++k) {
           if (!nz(i, k) || !nz(j, k)) continue;
           ++nprod;
-          users[id(b, i, k)].push_back(t);
-          if (i != j) users[id(b, j, k)].push_back(t);
+          users[producer(i, k)].push_back(t);
+          ++ndep;
+          if (i != j) {
+            users[producer(j, k)].push_back(t);
+            ++ndep;
+          }
         }
-        if (i != j) users[id(b, j, j)].push_back(t);
-        indeg[t] = i == j ? nprod : 2 * nprod + 1;
-        const int depth = i == j ? 2 * j : 2 * j + 1;
-        prio[t] = (depth - (2 * n - 1)) * kHalfColumn - (nprod * kProduct + (i == j ? kFactor : kSolve));
+        if (fd) {
+          // the partial sums of tile (j, j - 1) and the inverse of diagonal
+          // tile j - 1; then one more product, with the solved tile
+          users[id(b, j, j - 1)].push_back(t);
+          users[id(b, j - 1, j - 1)].push_back(t);
+          ndep += 2;
+          ++nprod;
+        } else if (i != j && !partial) {
+          users[id(b, j, j)].push_back(t);
+          ++ndep;
+        }
+        indeg[t] = ndep;
+        // (the partial sums of tile (j + 1, j) are needed when diagonal tile
+        // j is done, like the inverse it publishes)
+        const int depth = i == j || partial ? 2 * j : 2 * j + 1;
+        const double own = i == j ? kFactor + (fd ? kSolve : 0.0) : partial ? 0.0 : kSolve;
+        prio[t] = (depth - (2 * n - 1)) * kHalfColumn - (nprod * kProduct + own);
       }
   }
   using Key = std::tuple<double, int32_t, int32_t, int32_t, int64_t>;

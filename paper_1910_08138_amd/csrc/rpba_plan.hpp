@@ -121,9 +121,12 @@ uint64_t topology_key(int32_t M, int32_t N, int32_t K, int32_t L, const int32_t*
 // Task list of the persistent forward factorisation: every tile (i, j),
 // j <= i <= nt, j < nt, of the listed sub-blocks, packed (l << 16) | (i << 8)
 // | j.  Tile (i, j) waits for the tiles (i, k) and (j, k), k < j, and for
-// i > j for the diagonal tile (j, j); the list is a topological order of
-// these dependencies (checked before it is returned: an empty list means a
-// broken order).
+// i > j for the diagonal tile (j, j).  A nonzero sub-diagonal tile (j, j-1)
+// of the factor is solved by the task of diagonal tile j: its own task only
+// sums its products, the diagonal task waits for those sums and for diagonal
+// tile j-1, and every other user of tile (j, j-1) waits for diagonal task j.
+// The list is a topological order of these dependencies (checked before it
+// is returned: an empty list means a broken order).
 // Tiles that stay zero in the factor (tile_nz) get no task, and products with
 // a zero tile are left out of the sums and of the dependencies.
 std::vector<int32_t> dataflow_order(const Plan& P, const std::vector<int32_t>& blocks);
