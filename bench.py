@@ -184,6 +184,34 @@ def intrinsics_side(scene, seed, steps, warmup, log=print):
     return out
 
 
+def aerial_side(seed, steps, warmup, T, I, with_oracle=True, log=print):
+    """The 500-camera aerial block at full size (20 x 25 nadir grid, 200k
+    points, 16 sub-blocks): ms per step of the mixed and FP64 paths (library
+    defaults, the step as in the headline) and the final RMS of each after
+    the fixed schedule, against the FP64 oracle's run of the same schedule."""
+    from paper_1910_08138_amd import binding, scenes
+    s = scenes.config_scene(2, seed)
+    out = {"workload": f"aerial-nadir-{s.M}cam-{s.N // 1000}kpt-{s.L}subblocks", "cameras": s.M, "points": s.N,
+           "observations": s.K, "subblocks": s.L}
+    for path, prec in (("mixed", binding.RPBA_MIXED), ("fp64", binding.RPBA_FP64)):
+        r = run_path(s, dict(precision=prec), steps, warmup)
+        rms, secs = schedule_rms(s, dict(precision=prec), T, I)
+        out[path] = {"ms_per_step": r["ms_per_step"], "value": r["value"], "unit": "obs/s", "final_rms_px": rms}
+        log(f"aerial {path}: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G obs/s; final RMS {rms:.9f} px")
+    out["throughput_ratio_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    if with_oracle:
+        import oracle
+        t0 = time.time()
+        op, oh = oracle.run_schedule(s, T=T, I=I)
+        rms_o = float(oh[-1]["int_stats"][2])
+        del op
+        out["oracle_fp64_final_rms_px"] = rms_o
+        out["final_rms_rel_diff"] = {p: abs(out[p]["final_rms_px"] - rms_o) / rms_o for p in ("mixed", "fp64")}
+        log(f"aerial oracle final RMS {rms_o:.9f} px ({time.time() - t0:.1f} s); rel diff " +
+            ", ".join(f"{p} {v:.2e}" for p, v in out["final_rms_rel_diff"].items()))
+    return out
+
+
 def learned_pcg(scene, steps=3):
     """LM step of the mixed path with PCG on the sub-blocks of at least 150
     cameras (Cholesky on the others), preconditioned by block-Jacobi and by
@@ -465,6 +493,10 @@ def main():
     intr = None
     if not args.small and not args.no_compare:
         intr = intrinsics_side(scene, args.seed, args.steps, args.warmup, log=log)
+    aerial = None
+    if not args.small and not args.no_compare:
+        aerial = aerial_side(args.seed, args.steps, args.warmup, *args.schedule,
+                             with_oracle=not args.no_oracle_rms, log=log)
     cpu = None
     if not args.no_cpu_baseline:
         model = "unknown"
@@ -538,6 +570,7 @@ def main():
         "final_rms_vs_oracle": oracle_rms,
         "learned_pcg": lp,
         "intrinsics": intr,
+        "aerial_500cam": aerial,
     }
     if not args.no_compare:
         other = [p for p in out_paths if p != args.path][0]

@@ -223,3 +223,62 @@ def test_fullsize_intrinsics_fp64_parity():
     print(f"f max rel {np.abs(gf - of).max() / of.max():.2e}, k1 max abs {np.abs(gk - ok1).max():.2e}", flush=True)
     assert np.abs(gf - of).max() <= TOL * of.max()
     assert np.abs(gk - ok1).max() <= TOL
+
+
+def test_fullsize_aerial_fp64_and_mixed_schedule_against_oracle():
+    """Config 2 at full size: the 500-camera aerial block (20 x 25 nadir grid
+    at 60% overlap over a terrain, 200k points, 16 sub-blocks) through the
+    fixed schedule (6 outer iterations of 4 LM steps, then the final
+    intersection) on the FP64 and on the mixed path (bench launch
+    configuration, HIP graphs), each against the FP64 oracle's run of the
+    same schedule.  Every result's error is reported and bounded per path:
+    final RMS, camera centres and rotations, points, point and camera
+    covariances, point status."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_08138_amd import binding
+    s = scenes.config_scene(2, 0)
+    print(f"scene M={s.M} N={s.N} K={s.K} L={s.L}", flush=True)
+    op, oh = oracle.run_schedule(s, T=6, I=4)
+    o = dict(rms=oh[-1]["int_stats"][2])
+    o["R"], o["C"] = op.cameras()
+    o["X"], o["cov"], o["status"] = op.intersection()
+    o["ccov"], _ = op.covariance(1e-4)
+    del op
+    print(f"oracle final RMS {o['rms']:.12f}", flush=True)
+    ext = _extent(s)
+    # per-result bounds (relative RMS, centres / extent, rotation entries,
+    # points / extent, point covariances (relative Frobenius norm) at the
+    # 99.99th percentile and largest, camera covariances at lambda 1e-4
+    # (largest entry error over sqrt(C_rr C_cc)))
+    # (1e-6 of the extent (1.2 km) in a centre is 1.2e-5 rad at the 100 m
+    # flying height: nadir views trade a tilt about a horizontal axis
+    # against a horizontal shift of the centre, so the mixed path's rotation
+    # bound follows its centre bound; measured fp64 1.1e-15 / 9.3e-17,
+    # mixed 2.9e-6 / 3.4e-7 (rotation / centres))
+    bounds = {binding.RPBA_FP64: dict(rms=1e-10, C=1e-9, R=1e-9, X=1e-9, cov=(1e-8, 1e-7), ccov=1e-7),
+              binding.RPBA_MIXED: dict(rms=1e-6, C=1e-6, R=1e-5, X=1e-6, cov=(1e-5, 1e-3), ccov=1e-3)}
+    for prec, b in bounds.items():
+        name = "fp64" if prec == binding.RPBA_FP64 else "mixed"
+        gp, gh = binding.run_schedule(s, T=6, I=4, graph=True, precision=prec, chol_tile=64,
+                                      chol_schedule=binding.RPBA_CHOL_DATAFLOW, covariance=1)
+        gR, gC = gp.cameras()
+        gX, gcov, gst = gp.intersection()
+        gccov, _ = gp.covariance(1e-4)
+        del gp
+        rms = abs(gh[-1]["int_stats"][2] - o["rms"]) / o["rms"]
+        dC = np.abs(gC - o["C"]).max() / ext
+        dR = np.abs(gR - o["R"]).max()
+        ok = (gst == 0) & (o["status"] == 0)
+        dX = np.abs(gX[:, ok] - o["X"][:, ok]).max() / ext
+        d = np.sqrt(np.diagonal(o["ccov"], axis1=1, axis2=2))
+        crel = (np.abs(gccov - o["ccov"]) / (d[:, :, None] * d[:, None, :])).max(axis=(1, 2))
+        print(f"aerial {name}: final RMS {gh[-1]['int_stats'][2]:.12f} (rel {rms:.2e}); centres / extent {dC:.2e}; "
+              f"rotation {dR:.2e}; points / extent {dX:.2e}; status differ {int((gst != o['status']).sum())}; "
+              f"camera covariance rel max {crel.max():.2e}", flush=True)
+        rel = _cov_report(gcov, o["cov"], ok)
+        assert np.array_equal(gst, o["status"])
+        assert rms <= b["rms"] and dC <= b["C"] and dR <= b["R"] and dX <= b["X"]
+        assert np.quantile(rel, 0.9999) <= b["cov"][0] and rel.max() <= b["cov"][1]
+        assert crel.max() <= b["ccov"]
