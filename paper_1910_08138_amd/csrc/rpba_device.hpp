@@ -40,6 +40,17 @@ struct Lin {
 // 1 / x: in FP64 the hardware reciprocal estimate refined by two Newton
 // steps (within an ulp or two for the depths met here, cheaper than the
 // correctly rounded division); in FP32 the plain division
+// Position of workgroup b of an n-workgroup grid in an order that gives each
+// of the 8 XCDs one contiguous run of the work: the dispatcher hands
+// workgroups to the XCDs round-robin (b runs on XCD b % 8), so position
+// (b % 8) * share + b / 8 keeps neighbouring work items, which read the same
+// records, on one XCD and in its L2.  A bijection of [0, n) for every n.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  constexpr int NX = 8;
+  const int q = n / NX, r = n % NX, x = b % NX, s = b / NX;
+  return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
 template <typename T>
 __device__ __forceinline__ T recip(T x) {
   return T(1) / x;

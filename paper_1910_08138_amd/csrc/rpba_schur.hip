@@ -211,12 +211,13 @@ __device__ __forceinline__ void obs_in_load(const Dev& d, int k, int c, bool in_
 }
 
 // One wave per camera: diagonal block S_(i,i) = U*_i - sum_k Y_k V*^-1 Y_k^T
-// and e_i.
+// and e_i.  Neighbouring cameras (which see the same points, so read the same
+// copy records) run on one XCD.
 template <typename T, int NP>
 __global__ __launch_bounds__(NT) void k_schur_diag(Dev d) {
   constexpr int NU = NP * (NP + 1) / 2;
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int i = xcd_block(blockIdx.x, gridDim.x) * (NT / 64) + (threadIdx.x >> 6);
   if (i >= d.M) return;
   const int l = d.cam_blk[i];
   if (d.active && !d.active[l]) return;
