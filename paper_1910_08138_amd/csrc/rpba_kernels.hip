@@ -465,14 +465,6 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
     const int c0 = d.pt_copy_off[j], c1 = d.pt_copy_off[j + 1], n = c1 - c0;
     const int i0 = d.pm_off[j], i1 = d.pm_off[j + 1];
     double X[3] = {d.P0[j], d.P0[(int64_t)d.N + j], d.P0[2 * (int64_t)d.N + j]};
-    // the point's first copies, loaded now and used after Gauss-Newton
-    constexpr int CU = 4;
-    int cpy[CU];
-#pragma unroll
-    for (int u = 0; u < CU; ++u) cpy[u] = n > 0 ? d.pt_copies[c0 + min(u, n - 1)] : 0;
-    auto copy_at = [&](int u) {
-      return u == 0 ? cpy[0] : u == 1 ? cpy[1] : u == 2 ? cpy[2] : u == 3 ? cpy[3] : d.pt_copies[c0 + u];
-    };
     int st = PLAIN ? 0 : 1;  // not converged (the plain variants evaluate at the consensus point)
     double h[6], g[3], lch[6];
     for (int it = 0; !PLAIN && it < d.int_maxit; ++it) {
@@ -536,19 +528,19 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         break;
       }
     }
-    // final pass at the converged point: normals, residuals, cost, and per
-    // copy the normals H^(l), gradient g^(l) and cost of its observations:
-    // those of the first and the last copy stay in registers, any in between
-    // are parked in their copy records until H is complete
+    // final pass at the converged point, two sweeps over the point's
+    // observations.  The first forms the normals H (summed copy by copy), the
+    // residuals, the cost and the statistics.  Once H is complete, the second
+    // forms each copy's normals H^(l), gradient g^(l) and cost again (the
+    // same arithmetic, so the same values) and finishes the copy at its last
+    // observation: refined weight, record and cost.  Recomputing the copies'
+    // sums costs less than keeping them in memory until H is known.
     double cost = 0.0, sq = 0.0, nobs = 0.0;
-    double hl0[6] = {0, 0, 0, 0, 0, 0}, hl[6] = {0, 0, 0, 0, 0, 0};
-    double gl0[3] = {0, 0, 0}, gl[3] = {0, 0, 0};
-    double cst0 = 0.0, cst1 = 0.0, cst2 = 0.0, ccur = 0.0;  // costs of copies 0, 1, 2 and of the current one
-    double vmax = 0.0;                                        // largest squared reprojection error (filters)
+    double vmax = 0.0;  // largest squared reprojection error (filters)
     if (st == 0) {
       for (int q = 0; q < 6; ++q) h[q] = 0.0;
+      double hl[6] = {0, 0, 0, 0, 0, 0}, gd[3] = {0, 0, 0};
       bool behind = false;
-      int u = 0;  // copy being summed
       for (int i = i0; i < i1; ++i) {
         double x, y, cm[CAL ? 14 : 12];
         W2<double> W;
@@ -558,42 +550,22 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         const bool live = W.a > 0.0;  // not deleted by the robust step
         if (!(L.z > 0.0) && live) behind = true;
         const double v0 = L.g0 - x, v1 = L.g1 - y;
-        add_point_normals<double>(L, W, v0, v1, hl, gl);
-        // the residual takes the place of the pixel in LDS (this pass reads
-        // it last), and the workgroup copies them out coalesced
+        add_point_normals<double>(L, W, v0, v1, hl, gd);
+        // the residual takes the place of the pixel in LDS (the second sweep
+        // reads it there, and the workgroup copies them out coalesced)
         if (OLDS) sg.xy[i - b0] = make_double2(v0, v1);
         else if (d.res) reinterpret_cast<double2*>(d.res)[i] = make_double2(v0, v1);
-        const double wq = wquad(W, v0, v1);
-        cost += wq;
-        ccur += wq;
+        cost += wquad(W, v0, v1);
         if (PLAIN && live) vmax = fmax(vmax, v0 * v0 + v1 * v1);
         if (live) {
           sq += v0 * v0 + v1 * v1;
           nobs += 1.0;
         }
-        if (code & PM_LAST) {  // copy u complete
-          for (int q = 0; q < 6; ++q) h[q] += hl[q];
-          if (u + 1 < n) {
-            if (u == 0) {
-              for (int q = 0; q < 6; ++q) hl0[q] = hl[q];
-              for (int q = 0; q < 3; ++q) gl0[q] = gl[q];
-              cst0 = ccur;
-            } else {
-              const int64_t c = copy_at(u);
-              double2* om = om_park(d, c);
-              om[0] = make_double2(hl[0], hl[1]);
-              om[1] = make_double2(hl[2], hl[3]);
-              om[2] = make_double2(hl[4], hl[5]);
-              park_g(d, c, gl);
-              if (u == 1) cst1 = ccur;
-              else if (u == 2) cst2 = ccur;
-              else if (!PLAIN) cost_add(d, cs, d.copy_blk[c], ccur);  // rare: a point in five or more sub-blocks
-            }
-            for (int q = 0; q < 6; ++q) hl[q] = 0.0;
-            for (int q = 0; q < 3; ++q) gl[q] = 0.0;
-            ccur = 0.0;
+        if (code & PM_LAST) {  // a copy complete: its normals join H
+          for (int q = 0; q < 6; ++q) {
+            h[q] += hl[q];
+            hl[q] = 0.0;
           }
-          ++u;
         }
       }
       if (behind) st = 2;
@@ -622,67 +594,67 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
         vok = chol3(hv, lv);
         if (vok) chol3_inverse(lv, vi);
       }
-      // Omega^l = H - H^(l): information from the cameras outside sub-block l
-      // (zero for a point seen by one sub-block only).  The copies themselves
-      // are reset to Xbar through the sub-blocks' fresh flags.
-      for (int u2 = 0; u2 < n; ++u2) {
-        const int64_t c = copy_at(u2);
-        double hu[6], g3[3];  // H^(l) and g^(l) of this copy
-        if (u2 == 0 && n > 1) {
-          for (int q = 0; q < 6; ++q) hu[q] = hl0[q];
-          for (int q = 0; q < 3; ++q) g3[q] = gl0[q];
-        } else if (u2 == n - 1) {
-          for (int q = 0; q < 6; ++q) hu[q] = hl[q];
-          for (int q = 0; q < 3; ++q) g3[q] = gl[q];
-        } else {
-          const double2* om = om_park(d, c);
-          const double2 a = om[0], b = om[1], e = om[2];
-          hu[0] = a.x;
-          hu[1] = a.y;
-          hu[2] = b.x;
-          hu[3] = b.y;
-          hu[4] = e.x;
-          hu[5] = e.y;
-          unpark_g(d, c, g3);
-        }
-        // Omega of a tie-point copy: information from the cameras outside l
-        // (EXTENDED, PLAIN_REFINED), from all cameras (ALL_CAMERAS), or rho_t I
-        // (SCALAR, PLAIN); zero for a point seen by one sub-block only
-        double o6[6];
-        for (int q = 0; q < 6; ++q) {
-          const double sc = (q == 0 || q == 3 || q == 5) ? rho : 0.0;
-          o6[q] = n == 1 ? 0.0
-                  : (VAR == RPBA_VARIANT_EXTENDED || VAR == RPBA_VARIANT_PLAIN_REFINED) ? h[q] - hu[q]
-                  : VAR == RPBA_VARIANT_ALL_CAMERAS ? h[q]
-                                                    : sc;
-        }
-        if (d.om_f32) {
-          float2* om = reinterpret_cast<float2*>(d.Omf + 6 * c);
-          om[0] = make_float2((float)o6[0], (float)o6[1]);
-          om[1] = make_float2((float)o6[2], (float)o6[3]);
-          om[2] = make_float2((float)o6[4], (float)o6[5]);
-        } else {
-          double2* om = reinterpret_cast<double2*>(d.Om + 6 * c);
-          om[0] = make_double2(o6[0], o6[1]);
-          om[1] = make_double2(o6[2], o6[3]);
-          om[2] = make_double2(o6[4], o6[5]);
-        }
-        if (!PLAIN) {
-          if (VAR == RPBA_VARIANT_EXTENDED) {
-            put_record(d, c, X, vi, g3, vok);
-          } else {
-            // the copy's own point block H^(l) + Omega^l, damped
-            double hv2[6], lv2[6], vi2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int q = 0; q < 6; ++q) hv2[q] = hu[q] + o6[q];
-            hv2[0] *= 1.0 + d.lambda;
-            hv2[3] *= 1.0 + d.lambda;
-            hv2[5] *= 1.0 + d.lambda;
-            const bool ok2 = chol3(hv2, lv2);
-            if (ok2) chol3_inverse(lv2, vi2);
-            put_record(d, c, X, vi2, g3, ok2);
+      // second sweep: copy by copy; the copies are reset to Xbar through the
+      // sub-blocks' fresh flags
+      double hu[6] = {0, 0, 0, 0, 0, 0}, g3[3] = {0, 0, 0}, cc = 0.0;  // H^(l), g^(l), cost of the copy
+      int u2 = 0;
+      int64_t c = n > 0 ? d.pt_copies[c0] : 0;
+      int lc = n > 0 ? d.copy_blk[c] : 0;
+      for (int i = i0; i < i1; ++i) {
+        const ObsHead o = obs_head<INFO, OLDS>(d, sg, b0, i);  // staged: (x, y) is the residual
+        double cm[CAL ? 14 : 12];
+        obs_cam<CAL>(d, sg, o.code, cm);
+        Lin<double> L;
+        linearise_cam<CAL, double>(cm, cm + CAM_F, X, d.f, d.cx, d.cy, L);
+        const double v0 = OLDS ? o.x : L.g0 - o.x, v1 = OLDS ? o.y : L.g1 - o.y;
+        add_point_normals<double>(L, o.W, v0, v1, hu, g3);
+        cc += wquad(o.W, v0, v1);
+        if (o.code & PM_LAST) {
+          // Omega of a tie-point copy: information from the cameras outside l
+          // (EXTENDED, PLAIN_REFINED), from all cameras (ALL_CAMERAS), or
+          // rho_t I (SCALAR, PLAIN); zero for a point seen by one sub-block only
+          double o6[6];
+          for (int q = 0; q < 6; ++q) {
+            const double sc = (q == 0 || q == 3 || q == 5) ? rho : 0.0;
+            o6[q] = n == 1 ? 0.0
+                    : (VAR == RPBA_VARIANT_EXTENDED || VAR == RPBA_VARIANT_PLAIN_REFINED) ? h[q] - hu[q]
+                    : VAR == RPBA_VARIANT_ALL_CAMERAS ? h[q]
+                                                      : sc;
           }
-          const double cc = u2 == n - 1 ? ccur : u2 == 0 ? cst0 : u2 == 1 ? cst1 : u2 == 2 ? cst2 : 0.0;
-          if (u2 == n - 1 || u2 < 3) cost_add(d, cs, d.copy_blk[c], cc);
+          if (d.om_f32) {
+            float2* om = reinterpret_cast<float2*>(d.Omf + 6 * c);
+            om[0] = make_float2((float)o6[0], (float)o6[1]);
+            om[1] = make_float2((float)o6[2], (float)o6[3]);
+            om[2] = make_float2((float)o6[4], (float)o6[5]);
+          } else {
+            double2* om = reinterpret_cast<double2*>(d.Om + 6 * c);
+            om[0] = make_double2(o6[0], o6[1]);
+            om[1] = make_double2(o6[2], o6[3]);
+            om[2] = make_double2(o6[4], o6[5]);
+          }
+          if (!PLAIN) {
+            if (VAR == RPBA_VARIANT_EXTENDED) {
+              put_record(d, c, X, vi, g3, vok);
+            } else {
+              // the copy's own point block H^(l) + Omega^l, damped
+              double hv2[6], lv2[6], vi2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+              for (int q = 0; q < 6; ++q) hv2[q] = hu[q] + o6[q];
+              hv2[0] *= 1.0 + d.lambda;
+              hv2[3] *= 1.0 + d.lambda;
+              hv2[5] *= 1.0 + d.lambda;
+              const bool ok2 = chol3(hv2, lv2);
+              if (ok2) chol3_inverse(lv2, vi2);
+              put_record(d, c, X, vi2, g3, ok2);
+            }
+            cost_add(d, cs, lc, cc);
+          }
+          for (int q = 0; q < 6; ++q) hu[q] = 0.0;
+          for (int q = 0; q < 3; ++q) g3[q] = 0.0;
+          cc = 0.0;
+          if (++u2 < n) {
+            c = d.pt_copies[c0 + u2];
+            lc = d.copy_blk[c];
+          }
         }
       }
       accv[0] = cost;
@@ -690,10 +662,9 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
       accv[2] = nobs;
       accv[3] = 1.0;
     } else if (!PLAIN) {
-      // a point that fails here: its copies drop out of the Schur pass (the
-      // costs of copies in five or more sub-blocks already added stay; a
+      // a point that fails here: its copies drop out of the Schur pass (a
       // point needs a degenerate geometry to fail after converging)
-      for (int u2 = 0; u2 < n; ++u2) zero_record(d, copy_at(u2));
+      for (int u2 = 0; u2 < n; ++u2) zero_record(d, d.pt_copies[c0 + u2]);
     }
     d.status[j] = st;
     put_pxs(d, j, X, st);
