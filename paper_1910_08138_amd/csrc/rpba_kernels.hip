@@ -369,41 +369,6 @@ __device__ __forceinline__ int32_t obs_get(const Dev& d, const Stage& sg, int b0
   return o.code;
 }
 
-// where the intersection parks the normals H^(l) (FP64, 6 doubles) and the
-// gradient g^(l) of a point's middle copies until H is complete: in the
-// copy's own record, which the intersection rewrites at the end (g^(l) in
-// FP64 on the FP64 path, in FP32 on the mixed path, the precision its record
-// keeps g_X in), so that H - H^(l) is still formed in FP64
-__device__ __forceinline__ double2* om_park(const Dev& d, int64_t c) {
-  return reinterpret_cast<double2*>(d.cpk + (d.cpk_f32 ? CPK32 : CPK) * c);
-}
-__device__ __forceinline__ void park_g(const Dev& d, int64_t c, const double (&g)[3]) {
-  if (d.cpk_f32) {
-    float* f = reinterpret_cast<float*>(d.cpk + CPK32 * c) + 12;
-    f[0] = (float)g[0];
-    f[1] = (float)g[1];
-    f[2] = (float)g[2];
-  } else {
-    double* q = d.cpk + CPK * c + 6;
-    q[0] = g[0];
-    q[1] = g[1];
-    q[2] = g[2];
-  }
-}
-__device__ __forceinline__ void unpark_g(const Dev& d, int64_t c, double (&g)[3]) {
-  if (d.cpk_f32) {
-    const float* f = reinterpret_cast<const float*>(d.cpk + CPK32 * c) + 12;
-    g[0] = f[0];
-    g[1] = f[1];
-    g[2] = f[2];
-  } else {
-    const double* q = d.cpk + CPK * c + 6;
-    g[0] = q[0];
-    g[1] = q[1];
-    g[2] = q[2];
-  }
-}
-
 // per-workgroup sums of the copies' costs by sub-block (the cost before the
 // next LM step of a fresh sub-block): a few LDS slots keyed by sub-block,
 // flushed with one atomic each; a sub-block that finds no slot adds to memory
@@ -531,10 +496,10 @@ __device__ __forceinline__ void intersect_point(const Dev& d, Stage& sg, CostSlo
     // final pass at the converged point, two sweeps over the point's
     // observations.  The first forms the normals H (summed copy by copy), the
     // residuals, the cost and the statistics.  Once H is complete, the second
-    // forms each copy's normals H^(l), gradient g^(l) and cost again (the
-    // same arithmetic, so the same values) and finishes the copy at its last
-    // observation: refined weight, record and cost.  Recomputing the copies'
-    // sums costs less than keeping them in memory until H is known.
+    // forms each copy's normals H^(l), gradient g^(l) and cost again and
+    // finishes the copy at its last observation: refined weight, record and
+    // cost.  Forming the copies' sums again costs less than keeping them in
+    // memory until H is known.
     double cost = 0.0, sq = 0.0, nobs = 0.0;
     double vmax = 0.0;  // largest squared reprojection error (filters)
     if (st == 0) {
