@@ -37,9 +37,6 @@ struct Lin {
   T Ai[2][2];    // with intrinsics: dg/df, dg/dk1
 };
 
-// 1 / x: in FP64 the hardware reciprocal estimate refined by two Newton
-// steps (within an ulp or two for the depths met here, cheaper than the
-// correctly rounded division); in FP32 the plain division
 // Position of workgroup b of an n-workgroup grid in an order that gives each
 // of the 8 XCDs one contiguous run of the work: the dispatcher hands
 // workgroups to the XCDs round-robin (b runs on XCD b % 8), so position
@@ -51,6 +48,10 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
+// 1 / x: in FP64 the hardware reciprocal estimate refined by two Newton
+// steps (within an ulp or two for the depths met here, cheaper than the
+// correctly rounded division); in FP32 the plain division (a refined
+// estimate there measured no faster and moved the mixed path's results)
 template <typename T>
 __device__ __forceinline__ T recip(T x) {
   return T(1) / x;
