@@ -147,3 +147,25 @@ def test_export_leaves_invalid_points_untouched(rp):
     gp.rpba_consensus()
     pts2 = gp.points()
     assert np.array_equal(pts2[:, bad], pts0[:, bad])
+
+
+def test_cost_sums_over_more_sub_blocks_than_workgroup_slots(rp):
+    """Every camera its own sub-block (24 sub-blocks): the copies of a
+    workgroup's points then lie in more sub-blocks than the 16 slots in
+    which the intersection sums the copies' costs per workgroup, and the
+    costs of the others go straight to memory.  The cost of every sub-block
+    before its first LM step (from those sums) and after it, and the
+    intersection statistics, against the oracle."""
+    s = scenes.ring_scene(9, n_cams=24, n_pts=2000)
+    s.cam_block = np.arange(s.M, dtype=np.int32)
+    cams, _ = _workgroup_extent(s)
+    assert cams > 16, cams   # sub-blocks seen by one workgroup
+    gp = rp.Problem(s)
+    op = oracle.OracleProblem(s)
+    gst = rp._host(gp, gp.rpba_intersect())
+    ost = op.intersect()
+    assert np.allclose(gst, ost, rtol=TOL, atol=0), (gst, ost)
+    gbs = rp._host(gp, gp.rpba_subblock_lm_step())
+    obs_, fails = op.lm_step()
+    assert fails == 0 and np.all(gbs[:, 3] >= 0)
+    assert np.allclose(gbs[:, :2], obs_[:, :2], rtol=TOL, atol=0), np.abs(gbs[:, :2] / obs_[:, :2] - 1).max()
