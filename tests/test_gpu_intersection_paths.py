@@ -165,6 +165,9 @@ def test_cost_sums_over_more_sub_blocks_than_workgroup_slots(rp):
     gst = rp._host(gp, gp.rpba_intersect())
     ost = op.intersect()
     assert np.allclose(gst, ost, rtol=TOL, atol=0), (gst, ost)
+    # points in up to eight sub-blocks: every copy's refined weight
+    assert np.bincount(np.unique(s.obs_pt.astype(np.int64) * s.M + s.obs_cam) // s.M).max() >= 6
+    _compare(gp, op, s)
     gbs = rp._host(gp, gp.rpba_subblock_lm_step())
     obs_, fails = op.lm_step()
     assert fails == 0 and np.all(gbs[:, 3] >= 0)
